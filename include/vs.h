@@ -1,0 +1,199 @@
+/*
+ * vs.h — C ABI of the MI355X (gfx950) library for the vorticity–stream-vector phase-field
+ * method (Gallen, Muñoz Biosca, Castro, Hernández-Machado, arXiv 2601.05031).
+ *
+ * One call of vs_step advances the coupled system of the main text, eq. (5a)–(5c)
+ * (supplementary eq. (29a)–(29c)) by forward Euler, in the segregated order of the
+ * "Numerical implementation" section: (1) advance phi, (2) solve the vorticity Poisson
+ * problem, (3) solve the stream-vector Poisson problem.
+ *
+ * Grid ("Numerical implementation"): nodes (i h, j h, k h), 0 <= i < nx, 0 <= j < ny,
+ * 0 <= k < nz, equal spacing h. x and z are periodic; the channel walls are the node planes
+ * j = 0 and j = ny-1 (height H = (ny-1) h); the imposed flow runs along +z.
+ *
+ * Layout of every scalar field in device memory: nx*ny*nz doubles, index (i*ny + j)*nz + k
+ * (z fastest). Vector fields are three such arrays (x, y, z components).
+ *
+ * Conventions shared by all calls:
+ *  - Every call returns a vs_status; 0 is success, negative values are errors. No call
+ *    aborts the process. vs_last_error() returns a message for the calling thread's last
+ *    failed call (valid until the next call on that thread).
+ *  - Ownership: the caller owns all device memory (the workspace, phi0, f, u, adjoint
+ *    buffers) and the HIP stream; the library owns the opaque vs_state (host memory only).
+ *    The workspace must outlive the state. Inputs are copied; outputs are read in place at
+ *    vs_field_offset() inside the workspace.
+ *  - Streams: all device work is enqueued on the stream given to vs_init, in order.
+ *    vs_step, vs_poisson_solve, vs_get_scalars and vs_save_state synchronise that stream
+ *    before they return.
+ *  - Threads: one vs_state per thread at a time; calls on one state are not re-entrant.
+ *  - Argument errors are detected on the host before anything is enqueued.
+ */
+#ifndef VS_H
+#define VS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VS_OK = 0,
+    VS_E_ARG = -1,          /* invalid argument (sizes, non-positive h, eta, M, eps, dt ...) */
+    VS_E_WORKSPACE = -2,    /* workspace missing, too small or misaligned (256 B)           */
+    VS_E_HIP = -3,          /* a HIP runtime call failed                                   */
+    VS_E_NOCONV = -4,       /* a Poisson solve missed rtol after max_cycles cycles         */
+    VS_E_NONFINITE = -5,    /* NaN or Inf seen in a residual norm or in V, A               */
+    VS_E_UNSTABLE = -6,     /* dt above the linear forward-Euler bound; nothing enqueued   */
+    VS_E_STATE = -7,        /* null or unusable state                                     */
+    VS_E_UNSUPPORTED = -8   /* feature not built (e.g. vs_grad_step) or size unsupported   */
+} vs_status;
+
+/* vs_walls.kind */
+enum { VS_POISEUILLE = 1, VS_COUETTE = 2 };
+/* vs_params.model */
+enum { VS_BENDING = 1, VS_CAHN_HILLIARD = 2 };
+/* vs_params.precision */
+enum { VS_FP64 = 1, VS_FP32_REFINED = 2 };
+/* vs_params.flags */
+enum { VS_ALLOW_UNSTABLE = 1 };
+/* vs_field_offset field ids */
+enum {
+    VS_PHI = 0, VS_MU = 1,
+    VS_OMEGA_X = 2, VS_OMEGA_Y = 3, VS_OMEGA_Z = 4,
+    VS_PSI_X = 5, VS_PSI_Y = 6, VS_PSI_Z = 7,
+    VS_NFIELDS = 8
+};
+/* vs_get_scalars slots */
+enum {
+    VS_S_V = 0, VS_S_A = 1, VS_S_V0 = 2, VS_S_A0 = 3, VS_S_LAMBDA_V = 4, VS_S_GAMMA_A = 5,
+    VS_S_RELRES = 6,   /* largest final relative residual of the Poisson solves of the last call */
+    VS_S_STEP = 7,     /* number of completed time steps since vs_init                            */
+    VS_NSCALARS = 8
+};
+
+/* Grid ("Numerical implementation"). ny counts both wall rows; ny >= 3.
+ * nx, nz >= 4, even, of the form 2^a 3^b, at most 512 (the periodic directions are
+ * diagonalised by fast transforms of these lengths). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double h;
+} vs_grid;
+
+/* Imposed channel flow along +z ("Boundary conditions"). The walls carry the flow without a
+ * body: Dirichlet values of psi and omega on j = 0 and j = ny-1 derived from v by
+ * v = curl psi (eq. (3)) and omega = curl v (eq. (4)):
+ *   VS_POISEUILLE, centreline speed u0:  v_z = 4 u0 y (H-y)/H^2,
+ *       psi_x = -(4 u0/H^2)(H y^2/2 - y^3/3), omega_x = (4 u0/H^2)(H - 2y);
+ *   VS_COUETTE, wall speeds u0 (y = 0) and u1 (y = H):  v_z = u0 + (u1-u0) y/H,
+ *       psi_x = -(u0 y + (u1-u0) y^2/(2H)), omega_x = (u1-u0)/H.
+ * All other components are zero on the walls. Wall nodes move with the wall. */
+typedef struct {
+    int32_t kind;
+    double u0, u1;
+} vs_walls;
+
+/* Physical and solver parameters.
+ *  eta       viscosity (eq. (5b), > 0)
+ *  mobility  M of eq. (5a) (> 0)
+ *  eps       interface width of the bending energy (SM eq. (30), > 0)
+ *  kappa     bending modulus (SM eq. (30), >= 0)
+ *  sigma     Cahn–Hilliard coefficient (eq. F_CH, SM (31), > 0 for that model)
+ *  gamma0    constant part of the surface-tension coefficient gamma_A of SM eq. (35)
+ *  rate_V    volume penalty: lambda_V = 2 rate_V (V0 - V)/(M |Omega|)   (0 = off)
+ *  k_A       area penalty:   gamma_A = gamma0 + k_A (A - A0)/A0          (0 = off)
+ *  bend_scale  multiplies C_b = 3 sqrt(2) kappa/(8 eps^3) of SM eq. (35) (1.0 = as printed)
+ *  poisson_rtol, poisson_max_cycles: each Poisson solve of vs_step runs up to max_cycles
+ *            refinement cycles until ||b - L_h u||_2 <= rtol ||b||_2 over the three
+ *            components (b includes the wall terms); max_cycles in [1, 16].
+ *  flags     VS_ALLOW_UNSTABLE skips the forward-Euler stability check of vs_step. */
+typedef struct {
+    int32_t model;
+    int32_t precision;
+    double eta, mobility, eps, kappa, sigma;
+    double gamma0;
+    double rate_V, k_A;
+    double bend_scale;
+    double poisson_rtol;
+    int32_t poisson_max_cycles;
+    int32_t flags;
+} vs_params;
+
+typedef struct vs_state vs_state;
+
+/* Size in bytes of the device workspace vs_init needs for this grid and parameters. */
+vs_status vs_workspace_bytes(const vs_grid* grid, const vs_params* params, size_t* bytes);
+
+/* Create a state. phi0: device pointer to nx*ny*nz doubles (initial phase field, copied).
+ * workspace: device memory of at least vs_workspace_bytes bytes, 256-byte aligned, owned by
+ * the caller. stream: a hipStream_t (NULL = default stream).
+ * Initialisation: V0 = V[phi0], A0 = A[phi0] (SM eq. (37), (32)), lambda_V = 0,
+ * gamma_A = gamma0, mu from phi0, then omega and psi solved from phi0 with the no-body
+ * fields as the initial guess. Synchronises the stream. */
+vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* params,
+                  const double* phi0, void* workspace, size_t bytes, void* stream,
+                  vs_state** out);
+
+/* Solve the discrete Poisson problem L_h u = f ("Numerical implementation"; the operator of
+ * eq. (5b), (5c)) on the interior rows 1 <= j <= ny-2 with the Dirichlet values stored in u
+ * on j = 0 and j = ny-1, periodic in x and z, for one scalar field.
+ * f: device, nx*ny*nz doubles, wall rows ignored. u: device, in: initial guess and wall
+ * values, out: solution (wall rows unchanged). Runs refinement cycles until
+ * ||f - L_h u||_2 <= rtol ||f~||_2 (f~ = f minus the wall terms) or max_cycles (1..16).
+ * cycles_out, relres_out may be NULL. Returns VS_E_NOCONV (u still written) if rtol was not
+ * reached. Uses the state's scratch space; does not touch the state's fields. Synchronises. */
+vs_status vs_poisson_solve(vs_state* state, const double* f, double* u, double rtol,
+                           int32_t max_cycles, int32_t* cycles_out, double* relres_out);
+
+/* Advance nsteps >= 1 time steps of size dt > 0 (main text eq. (5a)–(5c), forward Euler).
+ * Per step: phi^{n+1} = phi^n + dt [M (L_h mu^n + lambda_V^n) - (curl psi^n) . D phi^n];
+ * V, A, lambda_V, gamma_A and mu from phi^{n+1}; omega^{n+1} from
+ * L_h omega = (1/eta) D phi x D mu; psi^{n+1} from L_h psi = -omega.
+ * Returns VS_E_UNSTABLE before enqueuing anything if dt exceeds the linear bound
+ * 2 / (M (12/h^2) [C_b (2 + 12 eps^2/h^2)^2 + 12 |gamma_A|/h^2]) (bending) or
+ * 2 / (M (12/h^2)(2 + 12 sigma/h^2)) (Cahn–Hilliard), unless VS_ALLOW_UNSTABLE is set.
+ * Device-side failures (VS_E_NOCONV, VS_E_NONFINITE) are reported at the end of the call,
+ * after all nsteps have run. Synchronises the stream once, at the end. */
+vs_status vs_step(vs_state* state, double dt, int32_t nsteps);
+
+/* Reverse-mode step for the adjoint (not built: returns VS_E_UNSUPPORTED).
+ * adj_next: device, nx*ny*nz doubles, dL/dphi^{n+1}; adj_prev: device, out, dL/dphi^n;
+ * dparams: host, accumulated dL/dkappa and dL/du0. */
+vs_status vs_grad_step(vs_state* state, double dt, const double* adj_next, double* adj_prev,
+                       double dparams[2]);
+
+/* Byte offset, inside the workspace, of field `field` (VS_PHI ... VS_PSI_Z) as it stands
+ * now (phi moves between two buffers from step to step: query after each vs_step). */
+vs_status vs_field_offset(const vs_state* state, int32_t field, size_t* byte_offset);
+
+/* Copy the VS_NSCALARS global scalars (slots VS_S_*) to host memory `out`. Synchronises. */
+vs_status vs_get_scalars(vs_state* state, double out[VS_NSCALARS]);
+
+/* Checkpoint: write phi, mu, omega, psi, the scalars and the step count into host memory.
+ * With blob == NULL only *bytes is set to the size needed. Synchronises. */
+vs_status vs_save_state(vs_state* state, void* blob, size_t* bytes);
+/* Restore a checkpoint written by vs_save_state for the same grid. Synchronises. */
+vs_status vs_load_state(vs_state* state, const void* blob, size_t bytes);
+
+/* Per-kernel timing with HIP events on the state's stream, for measurement tools:
+ * vs_profile(state, 1) starts recording an event pair around every kernel launch,
+ * vs_profile(state, 0) stops, vs_profile_read returns, for kernel class `kernel`
+ * (0 <= kernel < vs_profile_count()), the summed duration in ms and the launch count since
+ * the last vs_profile(state, 1). vs_profile_name gives the class name. */
+vs_status vs_profile(vs_state* state, int32_t enable);
+int32_t vs_profile_count(void);
+const char* vs_profile_name(int32_t kernel);
+vs_status vs_profile_read(vs_state* state, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Free the host-side state (the workspace stays the caller's). NULL is ignored. */
+void vs_destroy(vs_state* state);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* vs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VS_H */

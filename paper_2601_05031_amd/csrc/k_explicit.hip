@@ -1,0 +1,285 @@
+// Explicit stencils of one time step on gfx950, FP64:
+//   phi-update (main text eq. (5a), SM (29a)/(38)) with the velocity v = curl psi (eq. (3))
+//   fused in registers; the chemical potential (SM eq. (35) bending, eq. F_CH / SM (31)
+//   Cahn-Hilliard); the volume and area integrals (SM eq. (37), (32)) with the penalty
+//   multipliers (SM "Lagrange multipliers").
+//
+// Launch shape of the node kernels: block = 256 lanes (four 64-wide waves) over the
+// contiguous (j, k) plane of one x-plane i = blockIdx.y, so a wave reads 64 consecutive z
+// values; the x and y neighbours of a block are other rows of the same or adjacent blocks
+// and are served by L2. Walls: mirror ghosts in y for phi, g and mu (no-flux walls).
+#include "vs_internal.h"
+
+namespace vs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void plane_index(const Dims& d, int& i, int& j, int& k, bool& ok) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    ok = t < d.ny * d.nz;
+    j = t / d.nz;
+    k = t - j * d.nz;
+    i = blockIdx.y;
+}
+
+struct Nbr {
+    int c, xp, xm, yp, ym, zp, zm;
+};
+
+// Neighbour indices, periodic in x and z, mirror ghosts in y (u[-1] = u[1], u[ny] = u[ny-2]).
+__device__ __forceinline__ Nbr neighbours_mirror(const Dims& d, int i, int j, int k) {
+    const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+    const int im = (i == 0) ? d.nx - 1 : i - 1;
+    const int jp = (j + 1 == d.ny) ? d.ny - 2 : j + 1;
+    const int jm = (j == 0) ? 1 : j - 1;
+    const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+    const int km = (k == 0) ? d.nz - 1 : k - 1;
+    Nbr n;
+    n.c = node(d, i, j, k);
+    n.xp = node(d, ip, j, k);
+    n.xm = node(d, im, j, k);
+    n.yp = node(d, i, jp, k);
+    n.ym = node(d, i, jm, k);
+    n.zp = n.c - k + kp;
+    n.zm = n.c - k + km;
+    return n;
+}
+
+__device__ __forceinline__ double lap7(const double* __restrict__ u, const Nbr& n, double inv_h2) {
+    return (u[n.xp] + u[n.xm] + u[n.yp] + u[n.ym] + u[n.zp] + u[n.zm] - 6.0 * u[n.c]) * inv_h2;
+}
+
+// g = phi^3 - phi - eps^2 L_h phi at node (i, j, k), mirror ghosts.
+__device__ __forceinline__ double g_at(const double* __restrict__ phi, const Dims& d, int i, int j,
+                                       int k, double eps2) {
+    const Nbr n = neighbours_mirror(d, i, j, k);
+    const double p = phi[n.c];
+    return p * p * p - p - eps2 * lap7(phi, n, d.inv_h2);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the block in a fixed order; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) sh[q * 16 + w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int i = 0; i < nw; ++i) s += sh[q * 16 + i];
+            v[q] = s;
+        }
+    }
+}
+
+// phi_out = phi + dt [ M (L_h mu + lambda_V) - v . D phi ], v = curl psi inside, wall speed on
+// the walls. Reads phi, mu, psi_x, psi_y, psi_z once (neighbours via cache), writes phi_out.
+__global__ __launch_bounds__(kBlock) void k_advance(
+    const double* __restrict__ phi, const double* __restrict__ mu,
+    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
+    double* __restrict__ out, Dims d, const double* __restrict__ scal, double dt, double mob,
+    double vz_lo, double vz_hi) {
+    int i, j, k;
+    bool ok;
+    plane_index(d, i, j, k, ok);
+    if (!ok) return;
+    const Nbr n = neighbours_mirror(d, i, j, k);
+    const double lam = scal[SC_LAMV];
+    const double lmu = lap7(mu, n, d.inv_h2);
+    const double dx = (phi[n.xp] - phi[n.xm]) * d.inv_2h;
+    const double dy = (phi[n.yp] - phi[n.ym]) * d.inv_2h;
+    const double dz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
+    double vx = 0.0, vy = 0.0, vz;
+    if (j == 0) {
+        vz = vz_lo;
+    } else if (j == d.ny - 1) {
+        vz = vz_hi;
+    } else {
+        // interior rows: the y neighbours are true rows (the mirror never applies here)
+        vx = ((pz[n.yp] - pz[n.ym]) - (py[n.zp] - py[n.zm])) * d.inv_2h;
+        vy = ((px[n.zp] - px[n.zm]) - (pz[n.xp] - pz[n.xm])) * d.inv_2h;
+        vz = ((py[n.xp] - py[n.xm]) - (px[n.yp] - px[n.ym])) * d.inv_2h;
+    }
+    out[n.c] = phi[n.c] + dt * (mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
+}
+
+// mu from phi. Bending (SM eq. (35)): g = phi^3 - phi - eps^2 L_h phi,
+// mu = C_b [(3 phi^2 - 1) g - eps^2 L_h g] - gamma_A L_h phi. Cahn-Hilliard:
+// mu = phi^3 - phi - sigma L_h phi. g at the six neighbours is recomputed from phi
+// (25-point footprint), so g never reaches HBM.
+__global__ __launch_bounds__(kBlock) void k_mu(const double* __restrict__ phi,
+                                              double* __restrict__ mu, Dims d,
+                                              const double* __restrict__ scal, int model,
+                                              double C_b, double eps, double sigma) {
+    int i, j, k;
+    bool ok;
+    plane_index(d, i, j, k, ok);
+    if (!ok) return;
+    const Nbr n = neighbours_mirror(d, i, j, k);
+    const double p = phi[n.c];
+    const double lphi = lap7(phi, n, d.inv_h2);
+    if (model == VS_CAHN_HILLIARD) {
+        mu[n.c] = p * p * p - p - sigma * lphi;
+        return;
+    }
+    const double eps2 = eps * eps;
+    const double gc = p * p * p - p - eps2 * lphi;
+    const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+    const int im = (i == 0) ? d.nx - 1 : i - 1;
+    const int jp = (j + 1 == d.ny) ? d.ny - 2 : j + 1;
+    const int jm = (j == 0) ? 1 : j - 1;
+    const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+    const int km = (k == 0) ? d.nz - 1 : k - 1;
+    const double gs = g_at(phi, d, ip, j, k, eps2) + g_at(phi, d, im, j, k, eps2) +
+                      g_at(phi, d, i, jp, k, eps2) + g_at(phi, d, i, jm, k, eps2) +
+                      g_at(phi, d, i, j, kp, eps2) + g_at(phi, d, i, j, km, eps2);
+    const double lg = (gs - 6.0 * gc) * d.inv_h2;
+    const double gamma = scal[SC_GAMMA];
+    mu[n.c] = C_b * ((3.0 * p * p - 1.0) * gc - eps2 * lg) - gamma * lphi;
+}
+
+// Block partials of sum_w phi and sum_w [(eps/2)|D phi|^2 + (phi^2-1)^2/(4 eps)]
+// (trapezoid weights w = 1/2 on the wall rows). Fixed grid, grid-stride: deterministic.
+__global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict__ phi, Dims d,
+                                                       double eps,
+                                                       double* __restrict__ partials) {
+    __shared__ double sh[2 * 16];
+    const int N = d.nx * d.ny * d.nz;
+    const int plane = d.ny * d.nz;
+    double acc[2] = {0.0, 0.0};
+    const double inv4e = 0.25 / eps;
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < N; t += gridDim.x * kBlock) {
+        const int i = t / plane;
+        const int r = t - i * plane;
+        const int j = r / d.nz;
+        const int k = r - j * d.nz;
+        const Nbr n = neighbours_mirror(d, i, j, k);
+        const double p = phi[n.c];
+        const double w = (j == 0 || j == d.ny - 1) ? 0.5 : 1.0;
+        const double dx = (phi[n.xp] - phi[n.xm]) * d.inv_2h;
+        const double dy = (phi[n.yp] - phi[n.ym]) * d.inv_2h;
+        const double dz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
+        const double q = p * p - 1.0;
+        acc[0] += w * p;
+        acc[1] += w * (0.5 * eps * (dx * dx + dy * dy + dz * dz) + q * q * inv4e);
+    }
+    block_sum<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x * kPartialStride + 0] = acc[0];
+        partials[blockIdx.x * kPartialStride + 1] = acc[1];
+    }
+}
+
+// V = (|Omega| + h^3 sum_w phi)/2, A = 3/(2 sqrt 2) h^3 sum_w(...); then
+// lambda_V = 2 rate_V (V0 - V)/(M |Omega|) and gamma_A = gamma0 + k_A (A - A0)/A0
+// (off when k_A = 0 or A0 = 0). init != 0 also sets V0 = V, A0 = A.
+__global__ __launch_bounds__(kBlock) void k_finalize_va(const double* __restrict__ partials,
+                                                       int nblocks, Dims d, double* scal,
+                                                       int* istat, int init, double rate_V,
+                                                       double k_A, double gamma0, double mob) {
+    __shared__ double sh[2 * 16];
+    double acc[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        acc[0] += partials[b * kPartialStride + 0];
+        acc[1] += partials[b * kPartialStride + 1];
+    }
+    block_sum<2>(acc, sh);
+    if (threadIdx.x != 0) return;
+    const double h3 = d.h * d.h * d.h;
+    const double vol = (double)d.nx * d.nz * (d.ny - 1) * h3;
+    const double V = 0.5 * (vol + h3 * acc[0]);
+    const double A = 3.0 / (2.0 * 1.4142135623730951) * h3 * acc[1];
+    if (init) {
+        scal[SC_V0] = V;
+        scal[SC_A0] = A;
+    }
+    const double V0 = scal[SC_V0], A0 = scal[SC_A0];
+    scal[SC_V] = V;
+    scal[SC_A] = A;
+    scal[SC_LAMV] = 2.0 * rate_V * (V0 - V) / (mob * vol);
+    double gamma = gamma0;
+    if (k_A != 0.0 && A0 > 0.0) gamma += k_A * (A - A0) / A0;
+    scal[SC_GAMMA] = gamma;
+    if (!isfinite(V) || !isfinite(A)) istat[IS_FLAGS] |= ST_NONFINITE;
+}
+
+// dst[(i, j, k)] = prof[j]: the no-body channel fields as initial guesses and wall rows.
+__global__ __launch_bounds__(kBlock) void k_fill_profile(double* __restrict__ dst, Dims d,
+                                                        const double* __restrict__ prof) {
+    int i, j, k;
+    bool ok;
+    plane_index(d, i, j, k, ok);
+    if (!ok) return;
+    dst[node(d, i, j, k)] = prof ? prof[j] : 0.0;
+}
+
+__global__ void k_reset_stats(double* scal, int* istat) {
+    if (threadIdx.x == 0) {
+        scal[SC_RELRES_MAX] = 0.0;
+        scal[SC_RELRES_LAST] = 0.0;
+        istat[IS_FLAGS] = 0;
+        istat[IS_CYCLES] = 0;
+        istat[IS_CONV] = 0;
+    }
+}
+
+dim3 plane_grid(const Dims& d) {
+    return dim3((unsigned)((d.ny * d.nz + kBlock - 1) / kBlock), (unsigned)d.nx, 1);
+}
+
+}  // namespace
+
+void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
+                    const double* const psi[3], double* phi_out, const double* scal, double dt,
+                    double mobility, double vz_lo, double vz_hi) {
+    hipLaunchKernelGGL(k_advance, plane_grid(d), dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
+                       psi[2], phi_out, d, scal, dt, mobility, vz_lo, vz_hi);
+}
+
+int va_partial_blocks(const Dims& d) {
+    const long N = (long)d.nx * d.ny * d.nz;
+    long b = (N + kBlock - 1) / kBlock;
+    if (b > kMaxPartialBlocks) b = kMaxPartialBlocks;
+    return (int)b;
+}
+
+void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
+                        double* partials, int nblocks) {
+    hipLaunchKernelGGL(k_va_partials, dim3(nblocks), dim3(kBlock), 0, s, phi, d, eps, partials);
+}
+
+void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
+                        double* scal, int* istat, int init, double rate_V, double k_A,
+                        double gamma0, double mobility) {
+    hipLaunchKernelGGL(k_finalize_va, dim3(1), dim3(kBlock), 0, s, partials, nblocks, d, scal,
+                       istat, init, rate_V, k_A, gamma0, mobility);
+}
+
+void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const double* scal,
+               int model, double C_b, double eps, double sigma) {
+    hipLaunchKernelGGL(k_mu, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, scal, model, C_b,
+                       eps, sigma);
+}
+
+void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof) {
+    hipLaunchKernelGGL(k_fill_profile, plane_grid(d), dim3(kBlock), 0, s, dst, d, prof);
+}
+
+void launch_reset_stats(hipStream_t s, double* scal, int* istat) {
+    hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, s, scal, istat);
+}
+
+}  // namespace vs

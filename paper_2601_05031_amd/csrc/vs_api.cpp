@@ -1,0 +1,626 @@
+// Host driver and C ABI of libvs: argument checks, workspace carve-up, the step sequence of
+// the segregated scheme ("Numerical implementation": advance phi, then the vorticity
+// Poisson problem, then the stream-vector Poisson problem), status handling, checkpoints
+// and per-kernel event timing. All device work is enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "vs_internal.h"
+
+using namespace vs;
+
+namespace {
+
+thread_local std::string g_err;
+
+vs_status fail(vs_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(VS_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+// Kernel classes for the event timer.
+enum KClass {
+    K_ADVANCE, K_VA_PARTIALS, K_FINALIZE_VA, K_MU, K_RHS_DHT_Z, K_DHT_X, K_TRIDIAG_Y,
+    K_DHT_Z_OUT, K_RESID_NORM, K_CHECK, K_FILL, K_RESET, K_NCLASS
+};
+const char* kClassNames[K_NCLASS] = {"advance",   "va_partials", "finalize_va", "mu",
+                                     "rhs_dht_z", "dht_x",       "tridiag_y",   "dht_z_out",
+                                     "resid_norm", "check",      "fill_profile", "reset_stats"};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool fft_plan(int n, FftPlan* pl) {
+    if (n < 4 || n > 512 || (n & 1)) return false;
+    pl->n = n;
+    pl->npass = 0;
+    int m = n;
+    while (m % 4 == 0) { pl->radix[pl->npass++] = 4; m /= 4; }
+    while (m % 2 == 0) { pl->radix[pl->npass++] = 2; m /= 2; }
+    while (m % 3 == 0) { pl->radix[pl->npass++] = 3; m /= 3; }
+    return m == 1 && pl->npass <= 12;
+}
+
+struct Layout {
+    size_t off_fields;      // 9 fields: phi(2), mu, omega(3), psi(3)
+    size_t off_spec;        // 3 spectral scratch fields
+    size_t off_twx, off_twz, off_tri, off_part, off_prof, off_scal, off_istat;
+    size_t total;
+};
+
+Layout make_layout(const vs_grid& g) {
+    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    const size_t fb = align_up(N * sizeof(double));
+    const size_t M = (size_t)g.ny - 2;
+    Layout L;
+    size_t o = 0;
+    L.off_fields = o; o += 9 * fb;
+    L.off_spec = o;   o += 3 * fb;
+    L.off_twx = o;    o += align_up((size_t)g.nx * sizeof(double2));
+    L.off_twz = o;    o += align_up((size_t)g.nz * sizeof(double2));
+    L.off_tri = o;    o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * M * sizeof(double));
+    L.off_part = o;   o += align_up((size_t)kMaxPartialBlocks * kPartialStride * sizeof(double));
+    L.off_prof = o;   o += align_up(2 * (size_t)g.ny * sizeof(double));
+    L.off_scal = o;   o += align_up(SC_NSCAL * sizeof(double));
+    L.off_istat = o;  o += align_up(IS_NSTAT * sizeof(int));
+    L.total = o;
+    return L;
+}
+
+vs_status check_grid(const vs_grid* g) {
+    if (!g) return fail(VS_E_ARG, "grid is NULL");
+    if (g->ny < 3) return fail(VS_E_ARG, "ny = %d: need at least 3 rows (two walls)", g->ny);
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(VS_E_ARG, "h must be > 0");
+    FftPlan p;
+    if (!fft_plan(g->nx, &p))
+        return fail(VS_E_UNSUPPORTED, "nx = %d: need even 4 <= nx <= 512 of the form 2^a 3^b", g->nx);
+    if (!fft_plan(g->nz, &p))
+        return fail(VS_E_UNSUPPORTED, "nz = %d: need even 4 <= nz <= 512 of the form 2^a 3^b", g->nz);
+    if ((long long)g->nx * g->ny * g->nz > (1ll << 30))
+        return fail(VS_E_ARG, "grid too large");
+    return VS_OK;
+}
+
+vs_status check_params(const vs_params* p) {
+    if (!p) return fail(VS_E_ARG, "params is NULL");
+    if (p->model != VS_BENDING && p->model != VS_CAHN_HILLIARD)
+        return fail(VS_E_ARG, "model must be VS_BENDING or VS_CAHN_HILLIARD");
+    if (p->precision != VS_FP64)
+        return fail(VS_E_UNSUPPORTED, "precision %d not built (VS_FP64 only)", p->precision);
+    if (!(p->eta > 0.0)) return fail(VS_E_ARG, "eta must be > 0");
+    if (!(p->mobility > 0.0)) return fail(VS_E_ARG, "mobility must be > 0");
+    if (!(p->eps > 0.0)) return fail(VS_E_ARG, "eps must be > 0");
+    if (!(p->kappa >= 0.0)) return fail(VS_E_ARG, "kappa must be >= 0");
+    if (p->model == VS_CAHN_HILLIARD && !(p->sigma > 0.0))
+        return fail(VS_E_ARG, "sigma must be > 0 for the Cahn-Hilliard model");
+    if (!(p->poisson_rtol > 0.0)) return fail(VS_E_ARG, "poisson_rtol must be > 0");
+    if (p->poisson_max_cycles < 1 || p->poisson_max_cycles > 16)
+        return fail(VS_E_ARG, "poisson_max_cycles must be in [1, 16]");
+    const double fin[] = {p->gamma0, p->rate_V, p->k_A, p->bend_scale};
+    for (double v : fin)
+        if (!std::isfinite(v)) return fail(VS_E_ARG, "non-finite parameter");
+    if (p->rate_V < 0.0 || p->k_A < 0.0) return fail(VS_E_ARG, "penalties must be >= 0");
+    return VS_OK;
+}
+
+vs_status check_walls(const vs_walls* w) {
+    if (!w) return fail(VS_E_ARG, "walls is NULL");
+    if (w->kind != VS_POISEUILLE && w->kind != VS_COUETTE)
+        return fail(VS_E_ARG, "walls.kind must be VS_POISEUILLE or VS_COUETTE");
+    if (!std::isfinite(w->u0) || !std::isfinite(w->u1)) return fail(VS_E_ARG, "wall speed not finite");
+    return VS_OK;
+}
+
+}  // namespace
+
+struct vs_state {
+    vs_grid g{};
+    vs_walls w{};
+    vs_params p{};
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L{};
+    Dims d{};
+    FftPlan px{}, pz{};
+    double* phi[2] = {nullptr, nullptr};
+    int cur = 0;
+    double* mu = nullptr;
+    double* om[3] = {};
+    double* ps[3] = {};
+    double* spec[3] = {};
+    double2* twx = nullptr;
+    double2* twz = nullptr;
+    double* tri = nullptr;
+    double* part = nullptr;
+    double* prof = nullptr;   // [0, ny): psi_x profile, [ny, 2 ny): omega_x profile
+    double* scal = nullptr;
+    int* istat = nullptr;
+    double vz_lo = 0.0, vz_hi = 0.0;
+    double gamma_host = 0.0;  // gamma_A as of the last synchronisation
+    long long step = 0;
+    double last_relres = 0.0;
+    // event timer
+    bool prof_on = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    std::vector<hipEvent_t> ev_pool;
+
+    double C_b() const { return p.bend_scale * 3.0 * std::sqrt(2.0) * p.kappa / (8.0 * p.eps * p.eps * p.eps); }
+};
+
+namespace {
+
+hipEvent_t take_event(vs_state* S) {
+    if (!S->ev_pool.empty()) {
+        hipEvent_t e = S->ev_pool.back();
+        S->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Run `launch` bracketed by an event pair when the timer is on.
+template <class F>
+void timed(vs_state* S, int cls, F&& launch) {
+    if (!S->prof_on) {
+        launch();
+        return;
+    }
+    hipEvent_t a = take_event(S), b = take_event(S);
+    if (a) (void)hipEventRecord(a, S->stream);
+    launch();
+    if (b) (void)hipEventRecord(b, S->stream);
+    if (a && b) S->ev_used.push_back({cls, {a, b}});
+}
+
+void release_events(vs_state* S) {
+    for (auto& u : S->ev_used) {
+        S->ev_pool.push_back(u.second.first);
+        S->ev_pool.push_back(u.second.second);
+    }
+    S->ev_used.clear();
+}
+
+// One vector (ncomp = 3) or scalar (ncomp = 1) Poisson solve, fully on the stream: cycle 0
+// solves directly from b and the wall rows; each later cycle is gated on the device flag
+// and solves for the correction of the current residual.
+void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncomp, double rtol,
+                   int max_cycles) {
+    const Dims& d = S->d;
+    const double* const cu[3] = {u[0], u[1], u[2]};
+    const int nb = resid_blocks(d);
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        const int* gate = cyc == 0 ? nullptr : S->istat + IS_CONV;
+        timed(S, K_RHS_DHT_Z, [&] {
+            launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rhs, cu, ncomp, cyc > 0, S->spec, gate);
+        });
+        timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
+        timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, ncomp, gate); });
+        timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
+        timed(S, K_DHT_Z_OUT, [&] {
+            launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, u, ncomp, cyc > 0, gate);
+        });
+        timed(S, K_RESID_NORM, [&] { launch_resid_norm(S->stream, d, rhs, cu, ncomp, S->part, nb, gate); });
+        timed(S, K_CHECK, [&] {
+            launch_check(S->stream, S->part, nb, rtol, cyc, cyc == max_cycles - 1, S->scal, S->istat, gate);
+        });
+    }
+}
+
+void enqueue_va_mu(vs_state* S, const double* phi, int init) {
+    const int nb = va_partial_blocks(S->d);
+    timed(S, K_VA_PARTIALS, [&] { launch_va_partials(S->stream, S->d, phi, S->p.eps, S->part, nb); });
+    timed(S, K_FINALIZE_VA, [&] {
+        launch_finalize_va(S->stream, S->d, S->part, nb, S->scal, S->istat, init, S->p.rate_V,
+                           S->p.k_A, S->p.gamma0, S->p.mobility);
+    });
+    timed(S, K_MU, [&] {
+        launch_mu(S->stream, S->d, phi, S->mu, S->scal, S->p.model, S->C_b(), S->p.eps, S->p.sigma);
+    });
+}
+
+void enqueue_flow(vs_state* S, const double* phi) {
+    RhsArgs rv{};
+    rv.mode = RHS_VORT;
+    rv.phi = phi;
+    rv.mu = S->mu;
+    rv.inv_eta = 1.0 / S->p.eta;
+    enqueue_solve(S, rv, S->om, 3, S->p.poisson_rtol, S->p.poisson_max_cycles);
+    RhsArgs rp{};
+    rp.mode = RHS_NEGW;
+    rp.f[0] = S->om[0];
+    rp.f[1] = S->om[1];
+    rp.f[2] = S->om[2];
+    enqueue_solve(S, rp, S->ps, 3, S->p.poisson_rtol, S->p.poisson_max_cycles);
+}
+
+void enqueue_step(vs_state* S, double dt) {
+    const double* phi = S->phi[S->cur];
+    double* out = S->phi[1 - S->cur];
+    const double* const psc[3] = {S->ps[0], S->ps[1], S->ps[2]};
+    timed(S, K_ADVANCE, [&] {
+        launch_advance(S->stream, S->d, phi, S->mu, psc, out, S->scal, dt, S->p.mobility,
+                       S->vz_lo, S->vz_hi);
+    });
+    S->cur = 1 - S->cur;
+    enqueue_va_mu(S, out, 0);
+    enqueue_flow(S, out);
+}
+
+// Reads the device status and scalars after a synchronisation; maps flags to a status.
+vs_status collect(vs_state* S, const char* what) {
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    int ist[IS_NSTAT];
+    double sc[SC_NSCAL];
+    HIP_TRY(hipMemcpy(ist, S->istat, sizeof ist, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    S->gamma_host = sc[SC_GAMMA];
+    S->last_relres = sc[SC_RELRES_MAX];
+    if (ist[IS_FLAGS] & ST_NONFINITE)
+        return fail(VS_E_NONFINITE, "%s: non-finite value in a residual norm or in V, A", what);
+    if (ist[IS_FLAGS] & ST_NOCONV)
+        return fail(VS_E_NOCONV, "%s: a Poisson solve missed rtol %.3g (relative residual %.3g)", what,
+                    S->p.poisson_rtol, sc[SC_RELRES_MAX]);
+    return VS_OK;
+}
+
+double stability_rate(const vs_state* S) {
+    const double h2 = S->g.h * S->g.h;
+    const double lmax = 12.0 / h2;
+    if (S->p.model == VS_CAHN_HILLIARD) return S->p.mobility * lmax * (2.0 + S->p.sigma * lmax);
+    const double e2 = S->p.eps * S->p.eps;
+    const double a = 2.0 + e2 * lmax;
+    return S->p.mobility * lmax * (S->C_b() * a * a + std::fabs(S->gamma_host) * lmax);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vs_last_error(void) { return g_err.c_str(); }
+
+vs_status vs_workspace_bytes(const vs_grid* grid, const vs_params* params, size_t* bytes) {
+    vs_status st = check_grid(grid);
+    if (st != VS_OK) return st;
+    if ((st = check_params(params)) != VS_OK) return st;
+    if (!bytes) return fail(VS_E_ARG, "bytes is NULL");
+    *bytes = make_layout(*grid).total;
+    return VS_OK;
+}
+
+vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* params,
+                  const double* phi0, void* workspace, size_t bytes, void* stream,
+                  vs_state** out) {
+    vs_status st;
+    if (!out) return fail(VS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if ((st = check_grid(grid)) != VS_OK) return st;
+    if ((st = check_walls(walls)) != VS_OK) return st;
+    if ((st = check_params(params)) != VS_OK) return st;
+    if (!phi0) return fail(VS_E_ARG, "phi0 is NULL");
+    const Layout L = make_layout(*grid);
+    if (!workspace) return fail(VS_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)workspace) & 255) return fail(VS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < L.total) return fail(VS_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+
+    vs_state* S = new vs_state();
+    S->g = *grid;
+    S->w = *walls;
+    S->p = *params;
+    S->stream = (hipStream_t)stream;
+    S->ws = (char*)workspace;
+    S->ws_bytes = bytes;
+    S->L = L;
+    S->d.nx = grid->nx;
+    S->d.ny = grid->ny;
+    S->d.nz = grid->nz;
+    S->d.M = grid->ny - 2;
+    S->d.h = grid->h;
+    S->d.inv_h2 = 1.0 / (grid->h * grid->h);
+    S->d.inv_2h = 0.5 / grid->h;
+    fft_plan(grid->nx, &S->px);
+    fft_plan(grid->nz, &S->pz);
+    const size_t N = (size_t)grid->nx * grid->ny * grid->nz;
+    const size_t fb = align_up(N * sizeof(double));
+    double* f = (double*)(S->ws + L.off_fields);
+    auto field = [&](int idx) { return (double*)((char*)f + idx * fb); };
+    S->phi[0] = field(0);
+    S->phi[1] = field(1);
+    S->mu = field(2);
+    for (int c = 0; c < 3; ++c) {
+        S->om[c] = field(3 + c);
+        S->ps[c] = field(6 + c);
+        S->spec[c] = (double*)(S->ws + L.off_spec + c * fb);
+    }
+    S->twx = (double2*)(S->ws + L.off_twx);
+    S->twz = (double2*)(S->ws + L.off_twz);
+    S->tri = (double*)(S->ws + L.off_tri);
+    S->part = (double*)(S->ws + L.off_part);
+    S->prof = (double*)(S->ws + L.off_prof);
+    S->scal = (double*)(S->ws + L.off_scal);
+    S->istat = (int*)(S->ws + L.off_istat);
+
+    // Host tables: twiddles exp(-2 pi i m/n), Thomas pivots per Hartley mode class, and the
+    // no-body channel profiles of psi_x and omega_x (main text "Boundary conditions").
+    auto twiddles = [](int n) {
+        std::vector<double2> t(n);
+        for (int m = 0; m < n; ++m) {
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * m / n;
+            t[m] = make_double2((double)cosl(a), (double)(-sinl(a)));
+        }
+        return t;
+    };
+    std::vector<double2> twx = twiddles(grid->nx), twz = twiddles(grid->nz);
+    const int M = grid->ny - 2, hx = grid->nx / 2 + 1, hz = grid->nz / 2 + 1;
+    std::vector<double> tri((size_t)hx * hz * M);
+    for (int pc = 0; pc < hx; ++pc)
+        for (int qc = 0; qc < hz; ++qc) {
+            const long double PI = 3.14159265358979323846264338327950288L;
+            const double beta = (double)(2.0L * cosl(2.0L * PI * pc / grid->nx) +
+                                         2.0L * cosl(2.0L * PI * qc / grid->nz) - 6.0L);
+            double* c = &tri[((size_t)pc * hz + qc) * M];
+            double prev = 0.0;
+            for (int j = 0; j < M; ++j) {
+                prev = 1.0 / (beta - prev);
+                c[j] = prev;
+            }
+        }
+    const double H = (grid->ny - 1) * grid->h;
+    std::vector<double> prof(2 * (size_t)grid->ny);
+    for (int j = 0; j < grid->ny; ++j) {
+        const double y = j * grid->h;
+        double psx, omx;
+        if (walls->kind == VS_POISEUILLE) {
+            const double U = walls->u0;
+            psx = -(4.0 * U / (H * H)) * (H * y * y / 2.0 - y * y * y / 3.0);
+            omx = (4.0 * U / (H * H)) * (H - 2.0 * y);
+        } else {
+            const double u0 = walls->u0, u1 = walls->u1;
+            psx = -(u0 * y + (u1 - u0) * y * y / (2.0 * H));
+            omx = (u1 - u0) / H;
+        }
+        prof[j] = psx;
+        prof[grid->ny + j] = omx;
+    }
+    if (walls->kind == VS_POISEUILLE) {
+        S->vz_lo = 0.0;
+        S->vz_hi = 0.0;
+    } else {
+        S->vz_lo = walls->u0;
+        S->vz_hi = walls->u1;
+    }
+    S->gamma_host = params->gamma0;
+
+    auto bail = [&](vs_status s) {
+        delete S;
+        return s;
+    };
+#define INIT_TRY(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return bail(fail(VS_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)));    \
+    } while (0)
+    INIT_TRY(hipMemcpyAsync(S->twx, twx.data(), twx.size() * sizeof(double2), hipMemcpyHostToDevice, S->stream));
+    INIT_TRY(hipMemcpyAsync(S->twz, twz.data(), twz.size() * sizeof(double2), hipMemcpyHostToDevice, S->stream));
+    INIT_TRY(hipMemcpyAsync(S->tri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice, S->stream));
+    INIT_TRY(hipMemcpyAsync(S->prof, prof.data(), prof.size() * sizeof(double), hipMemcpyHostToDevice, S->stream));
+    INIT_TRY(hipMemcpyAsync(S->phi[0], phi0, N * sizeof(double), hipMemcpyDeviceToDevice, S->stream));
+    INIT_TRY(hipMemsetAsync(S->scal, 0, SC_NSCAL * sizeof(double), S->stream));
+    INIT_TRY(hipMemsetAsync(S->istat, 0, IS_NSTAT * sizeof(int), S->stream));
+    launch_fill_profile(S->stream, S->d, S->ps[0], S->prof);
+    launch_fill_profile(S->stream, S->d, S->om[0], S->prof + grid->ny);
+    for (int c = 1; c < 3; ++c) {
+        launch_fill_profile(S->stream, S->d, S->ps[c], nullptr);
+        launch_fill_profile(S->stream, S->d, S->om[c], nullptr);
+    }
+    INIT_TRY(hipGetLastError());
+    enqueue_va_mu(S, S->phi[0], 1);
+    enqueue_flow(S, S->phi[0]);
+    INIT_TRY(hipGetLastError());
+    st = collect(S, "vs_init");
+    if (st != VS_OK) return bail(st);
+#undef INIT_TRY
+    *out = S;
+    return VS_OK;
+}
+
+vs_status vs_poisson_solve(vs_state* S, const double* f, double* u, double rtol, int32_t max_cycles,
+                           int32_t* cycles_out, double* relres_out) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!f || !u) return fail(VS_E_ARG, "f and u must be device pointers");
+    if (!(rtol > 0.0)) return fail(VS_E_ARG, "rtol must be > 0");
+    if (max_cycles < 1 || max_cycles > 16) return fail(VS_E_ARG, "max_cycles must be in [1, 16]");
+    timed(S, K_RESET, [&] { launch_reset_stats(S->stream, S->scal, S->istat); });
+    RhsArgs r{};
+    r.mode = RHS_FIELD;
+    r.f[0] = f;
+    double* const uu[3] = {u, nullptr, nullptr};
+    enqueue_solve(S, r, uu, 1, rtol, max_cycles);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    int ist[IS_NSTAT];
+    double sc[SC_NSCAL];
+    HIP_TRY(hipMemcpy(ist, S->istat, sizeof ist, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    if (cycles_out) *cycles_out = ist[IS_CYCLES];
+    if (relres_out) *relres_out = sc[SC_RELRES_LAST];
+    if (ist[IS_FLAGS] & ST_NONFINITE) return fail(VS_E_NONFINITE, "vs_poisson_solve: non-finite residual");
+    if (ist[IS_FLAGS] & ST_NOCONV)
+        return fail(VS_E_NOCONV, "vs_poisson_solve: relative residual %.3g above rtol %.3g after %d cycles",
+                    sc[SC_RELRES_LAST], rtol, ist[IS_CYCLES]);
+    return VS_OK;
+}
+
+vs_status vs_step(vs_state* S, double dt, int32_t nsteps) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(VS_E_ARG, "dt must be > 0");
+    if (nsteps < 1) return fail(VS_E_ARG, "nsteps must be >= 1");
+    if (!(S->p.flags & VS_ALLOW_UNSTABLE)) {
+        const double rate = stability_rate(S);
+        if (dt * rate > 2.0)
+            return fail(VS_E_UNSTABLE, "dt = %.4g exceeds the forward-Euler bound %.4g", dt, 2.0 / rate);
+    }
+    timed(S, K_RESET, [&] { launch_reset_stats(S->stream, S->scal, S->istat); });
+    for (int s = 0; s < nsteps; ++s) enqueue_step(S, dt);
+    HIP_TRY(hipGetLastError());
+    S->step += nsteps;
+    return collect(S, "vs_step");
+}
+
+vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* adj_prev,
+                       double dparams[2]) {
+    (void)dt;
+    (void)adj_next;
+    (void)adj_prev;
+    (void)dparams;
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    return fail(VS_E_UNSUPPORTED, "vs_grad_step: the adjoint step is not built");
+}
+
+vs_status vs_field_offset(const vs_state* S, int32_t field, size_t* byte_offset) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!byte_offset) return fail(VS_E_ARG, "byte_offset is NULL");
+    const double* p = nullptr;
+    switch (field) {
+        case VS_PHI: p = S->phi[S->cur]; break;
+        case VS_MU: p = S->mu; break;
+        case VS_OMEGA_X: case VS_OMEGA_Y: case VS_OMEGA_Z: p = S->om[field - VS_OMEGA_X]; break;
+        case VS_PSI_X: case VS_PSI_Y: case VS_PSI_Z: p = S->ps[field - VS_PSI_X]; break;
+        default: return fail(VS_E_ARG, "unknown field id %d", field);
+    }
+    *byte_offset = (size_t)((const char*)p - S->ws);
+    return VS_OK;
+}
+
+vs_status vs_get_scalars(vs_state* S, double out[VS_NSCALARS]) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!out) return fail(VS_E_ARG, "out is NULL");
+    double sc[SC_NSCAL];
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    out[VS_S_V] = sc[SC_V];
+    out[VS_S_A] = sc[SC_A];
+    out[VS_S_V0] = sc[SC_V0];
+    out[VS_S_A0] = sc[SC_A0];
+    out[VS_S_LAMBDA_V] = sc[SC_LAMV];
+    out[VS_S_GAMMA_A] = sc[SC_GAMMA];
+    out[VS_S_RELRES] = S->last_relres;
+    out[VS_S_STEP] = (double)S->step;
+    return VS_OK;
+}
+
+namespace {
+struct BlobHeader {
+    char magic[8];
+    int32_t nx, ny, nz, pad;
+    int64_t step;
+    double scal[SC_NSCAL];
+};
+}  // namespace
+
+vs_status vs_save_state(vs_state* S, void* blob, size_t* bytes) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!bytes) return fail(VS_E_ARG, "bytes is NULL");
+    const size_t N = (size_t)S->g.nx * S->g.ny * S->g.nz;
+    const size_t need = sizeof(BlobHeader) + 8 * N * sizeof(double);
+    if (!blob) {
+        *bytes = need;
+        return VS_OK;
+    }
+    if (*bytes < need) return fail(VS_E_ARG, "blob has %zu bytes, needs %zu", *bytes, need);
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    BlobHeader hd{};
+    std::memcpy(hd.magic, "VSSTATE1", 8);
+    hd.nx = S->g.nx;
+    hd.ny = S->g.ny;
+    hd.nz = S->g.nz;
+    hd.step = S->step;
+    HIP_TRY(hipMemcpy(hd.scal, S->scal, sizeof hd.scal, hipMemcpyDeviceToHost));
+    std::memcpy(blob, &hd, sizeof hd);
+    double* dst = (double*)((char*)blob + sizeof hd);
+    const double* src[8] = {S->phi[S->cur], S->mu, S->om[0], S->om[1], S->om[2], S->ps[0], S->ps[1], S->ps[2]};
+    for (int q = 0; q < 8; ++q) HIP_TRY(hipMemcpy(dst + q * N, src[q], N * sizeof(double), hipMemcpyDeviceToHost));
+    *bytes = need;
+    return VS_OK;
+}
+
+vs_status vs_load_state(vs_state* S, const void* blob, size_t bytes) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!blob) return fail(VS_E_ARG, "blob is NULL");
+    const size_t N = (size_t)S->g.nx * S->g.ny * S->g.nz;
+    const size_t need = sizeof(BlobHeader) + 8 * N * sizeof(double);
+    if (bytes < need) return fail(VS_E_ARG, "blob has %zu bytes, needs %zu", bytes, need);
+    BlobHeader hd;
+    std::memcpy(&hd, blob, sizeof hd);
+    if (std::memcmp(hd.magic, "VSSTATE1", 8) != 0) return fail(VS_E_ARG, "not a vs_save_state blob");
+    if (hd.nx != S->g.nx || hd.ny != S->g.ny || hd.nz != S->g.nz) return fail(VS_E_ARG, "grid mismatch");
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    const double* src = (const double*)((const char*)blob + sizeof hd);
+    double* dst[8] = {S->phi[S->cur], S->mu, S->om[0], S->om[1], S->om[2], S->ps[0], S->ps[1], S->ps[2]};
+    for (int q = 0; q < 8; ++q) HIP_TRY(hipMemcpy(dst[q], src + q * N, N * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(S->scal, hd.scal, sizeof hd.scal, hipMemcpyHostToDevice));
+    S->step = hd.step;
+    S->gamma_host = hd.scal[SC_GAMMA];
+    return VS_OK;
+}
+
+vs_status vs_profile(vs_state* S, int32_t enable) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    if (enable) release_events(S);
+    S->prof_on = enable != 0;
+    return VS_OK;
+}
+
+int32_t vs_profile_count(void) { return K_NCLASS; }
+
+const char* vs_profile_name(int32_t k) { return (k >= 0 && k < K_NCLASS) ? kClassNames[k] : ""; }
+
+vs_status vs_profile_read(vs_state* S, int32_t kernel, double* total_ms, int64_t* launches) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (kernel < 0 || kernel >= K_NCLASS) return fail(VS_E_ARG, "kernel class out of range");
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    double t = 0.0;
+    int64_t n = 0;
+    for (auto& u : S->ev_used) {
+        if (u.first != kernel) continue;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, u.second.first, u.second.second));
+        t += ms;
+        ++n;
+    }
+    if (total_ms) *total_ms = t;
+    if (launches) *launches = n;
+    return VS_OK;
+}
+
+void vs_destroy(vs_state* S) {
+    if (!S) return;
+    (void)hipStreamSynchronize(S->stream);
+    release_events(S);
+    for (hipEvent_t e : S->ev_pool) (void)hipEventDestroy(e);
+    delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the host driver and the kernel launchers of libvs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vs.h"
+
+namespace vs {
+
+// Geometry passed by value to every kernel.
+struct Dims {
+    int nx, ny, nz;   // nodes; walls at j = 0 and j = ny-1
+    int M;            // interior rows, ny - 2
+    double h, inv_h2, inv_2h;
+};
+
+static inline __host__ __device__ int node(const Dims& d, int i, int j, int k) {
+    return (i * d.ny + j) * d.nz + k;
+}
+
+// Slots of the device scalar array (doubles).
+enum {
+    SC_V = 0, SC_A = 1, SC_V0 = 2, SC_A0 = 3, SC_LAMV = 4, SC_GAMMA = 5,
+    SC_RELRES_MAX = 6,        // largest final relative residual since the last reset
+    SC_RELRES_LAST = 7,       // relative residual of the last check
+    SC_NSCAL = 16
+};
+// Slots of the device status array (ints).
+enum {
+    IS_FLAGS = 0,             // bit mask of ST_* below
+    IS_CONV = 1,              // 1 once the running Poisson solve met rtol (gates later cycles)
+    IS_CYCLES = 2,            // Poisson cycles run since the last reset
+    IS_NSTAT = 16
+};
+enum { ST_NOCONV = 1, ST_NONFINITE = 2 };
+
+// Source of the right-hand side b of a Poisson solve.
+enum RhsMode {
+    RHS_FIELD = 0,   // b_c = f_c (explicit arrays)
+    RHS_VORT = 1,    // b = (1/eta) D phi x D mu (three components), eq. (5b)
+    RHS_NEGW = 2     // b_c = -omega_c, eq. (5c)
+};
+
+struct RhsArgs {
+    int mode;
+    const double* f[3];      // RHS_FIELD arrays, or omega for RHS_NEGW
+    const double* phi;       // RHS_VORT
+    const double* mu;        // RHS_VORT
+    double inv_eta;
+};
+
+// Plan of a length-n transform: radices applied in order (Stockham passes).
+struct FftPlan {
+    int n;
+    int npass;
+    int radix[12];
+};
+
+constexpr int kMaxPartialBlocks = 1024;
+constexpr int kPartialStride = 8;    // doubles per block partial record
+
+// ---------------------------------------------------------------- explicit stencils
+void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
+                    const double* const psi[3], double* phi_out, const double* scal,
+                    double dt, double mobility, double vz_lo, double vz_hi);
+void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
+                        double* partials, int nblocks);
+int va_partial_blocks(const Dims& d);
+void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
+                        double* scal, int* istat, int init, double rate_V, double k_A,
+                        double gamma0, double mobility);
+void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const double* scal,
+               int model, double C_b, double eps, double sigma);
+void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof);
+void launch_reset_stats(hipStream_t s, double* scal, int* istat);
+
+// ---------------------------------------------------------------- spectral Poisson
+// Forward: b~ (direct) or r = b - L_h u (correct) on interior rows, 2D Hartley in z then x.
+void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                      const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
+                      double* const spec[3], const int* gate);
+void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
+                  double* const spec[3], int ncomp, const int* gate);
+void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
+                      int ncomp, const int* gate);
+void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                      double* const spec[3], double* const u[3], int ncomp, int add,
+                      const int* gate);
+int resid_blocks(const Dims& d);
+void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
+                       const double* const u[3], int ncomp, double* partials, int nblocks,
+                       const int* gate);
+void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
+                  int last_cycle, double* scal, int* istat, const int* gate);
+
+}  // namespace vs

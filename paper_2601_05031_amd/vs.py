@@ -1,0 +1,248 @@
+"""ctypes binding of libvs (include/vs.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of libvs. PyTorch provides the device
+workspace (one uint8 tensor) and the HIP stream; fields are exposed as torch views into the
+workspace. If libvs.so has not been built, loading fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvs.so")
+
+# status codes
+VS_OK = 0
+VS_E_ARG = -1
+VS_E_WORKSPACE = -2
+VS_E_HIP = -3
+VS_E_NOCONV = -4
+VS_E_NONFINITE = -5
+VS_E_UNSTABLE = -6
+VS_E_STATE = -7
+VS_E_UNSUPPORTED = -8
+STATUS_NAMES = {0: "VS_OK", -1: "VS_E_ARG", -2: "VS_E_WORKSPACE", -3: "VS_E_HIP", -4: "VS_E_NOCONV",
+                -5: "VS_E_NONFINITE", -6: "VS_E_UNSTABLE", -7: "VS_E_STATE", -8: "VS_E_UNSUPPORTED"}
+
+VS_POISEUILLE, VS_COUETTE = 1, 2
+VS_BENDING, VS_CAHN_HILLIARD = 1, 2
+VS_FP64, VS_FP32_REFINED = 1, 2
+VS_ALLOW_UNSTABLE = 1
+
+FIELDS = {"phi": 0, "mu": 1, "omega_x": 2, "omega_y": 3, "omega_z": 4, "psi_x": 5, "psi_y": 6, "psi_z": 7}
+SCALARS = ["V", "A", "V0", "A0", "lambda_V", "gamma_A", "relres", "step"]
+
+_WALL_KINDS = {"poiseuille": VS_POISEUILLE, "couette": VS_COUETTE}
+_MODELS = {"bending": VS_BENDING, "cahn_hilliard": VS_CAHN_HILLIARD}
+_PRECISIONS = {"fp64": VS_FP64, "fp32_refined": VS_FP32_REFINED}
+
+
+class VsGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double)]
+
+
+class VsWalls(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("u0", ctypes.c_double), ("u1", ctypes.c_double)]
+
+
+class VsParams(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("eta", ctypes.c_double), ("mobility", ctypes.c_double), ("eps", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("sigma", ctypes.c_double), ("gamma0", ctypes.c_double),
+                ("rate_V", ctypes.c_double), ("k_A", ctypes.c_double),
+                ("bend_scale", ctypes.c_double), ("poisson_rtol", ctypes.c_double),
+                ("poisson_max_cycles", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class VsError(RuntimeError):
+    def __init__(self, code: int, call: str, message: str):
+        self.code = code
+        self.call = call
+        super().__init__(f"{call}: {STATUS_NAMES.get(code, code)}: {message}")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvs.so from the package directory (built by paper_2601_05031_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_05031_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, sz, i32, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    sigs = {
+        "vs_workspace_bytes": (i32, [P(VsGrid), P(VsParams), P(sz)]),
+        "vs_init": (i32, [P(VsGrid), P(VsWalls), P(VsParams), vp, vp, sz, vp, P(vp)]),
+        "vs_poisson_solve": (i32, [vp, vp, vp, dbl, i32, P(i32), P(dbl)]),
+        "vs_step": (i32, [vp, dbl, i32]),
+        "vs_grad_step": (i32, [vp, dbl, vp, vp, P(dbl)]),
+        "vs_field_offset": (i32, [vp, i32, P(sz)]),
+        "vs_get_scalars": (i32, [vp, P(dbl)]),
+        "vs_save_state": (i32, [vp, vp, P(sz)]),
+        "vs_load_state": (i32, [vp, vp, sz]),
+        "vs_profile": (i32, [vp, i32]),
+        "vs_profile_count": (i32, []),
+        "vs_profile_name": (ctypes.c_char_p, [i32]),
+        "vs_profile_read": (i32, [vp, i32, P(dbl), P(ctypes.c_int64)]),
+        "vs_destroy": (None, [vp]),
+        "vs_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code: int, call: str):
+    if code != VS_OK:
+        raise VsError(code, call, lib().vs_last_error().decode())
+
+
+def make_params(model="bending", precision="fp64", eta=1.0, mobility=1.0, eps=1.0, kappa=1.0,
+                sigma=1.0, gamma0=0.0, rate_V=0.0, k_A=0.0, bend_scale=1.0, rtol=1e-10,
+                max_cycles=3, allow_unstable=False) -> VsParams:
+    return VsParams(_MODELS[model], _PRECISIONS[precision], eta, mobility, eps, kappa, sigma,
+                    gamma0, rate_V, k_A, bend_scale, rtol, max_cycles,
+                    VS_ALLOW_UNSTABLE if allow_unstable else 0)
+
+
+def workspace_bytes(grid, params: VsParams) -> int:
+    g = VsGrid(*grid) if not isinstance(grid, VsGrid) else grid
+    n = ctypes.c_size_t(0)
+    _check(lib().vs_workspace_bytes(ctypes.byref(g), ctypes.byref(params), ctypes.byref(n)),
+           "vs_workspace_bytes")
+    return n.value
+
+
+@dataclass
+class Grid:
+    nx: int
+    ny: int
+    nz: int
+    h: float = 1.0
+
+
+class Solver:
+    """One simulation on one GPU: owns a torch workspace tensor and a vs_state."""
+
+    def __init__(self, grid, walls: dict, params: dict, phi0, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.grid = VsGrid(grid[0], grid[1], grid[2], float(grid[3]) if len(grid) > 3 else 1.0)
+        self.walls = VsWalls(_WALL_KINDS[walls["kind"]], float(walls["u0"]), float(walls.get("u1", 0.0)))
+        p = dict(params)
+        self.params = make_params(**p)
+        nbytes = workspace_bytes(self.grid, self.params)
+        # 256 bytes of slack so the base can be aligned whatever the allocator returns
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._pad = (-base) % 256
+        self.ws_ptr = base + self._pad
+        self.ws_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        phi0_t = torch.as_tensor(phi0, dtype=torch.float64).to(self.device).contiguous()
+        shape = (self.grid.nx, self.grid.ny, self.grid.nz)
+        if tuple(phi0_t.shape) != shape:
+            raise ValueError(f"phi0 has shape {tuple(phi0_t.shape)}, grid is {shape}")
+        torch.cuda.current_stream(self.device).synchronize()
+        st = ctypes.c_void_p(0)
+        _check(lib().vs_init(ctypes.byref(self.grid), ctypes.byref(self.walls), ctypes.byref(self.params),
+                             ctypes.c_void_p(phi0_t.data_ptr()), ctypes.c_void_p(self.ws_ptr),
+                             ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
+                             ctypes.byref(st)), "vs_init")
+        self._st = st
+        self.shape = shape
+
+    # ------------------------------------------------------------------ core calls
+    def step(self, dt: float, nsteps: int = 1):
+        _check(lib().vs_step(self._st, float(dt), int(nsteps)), "vs_step")
+
+    def poisson_solve(self, f, u, rtol=1e-10, max_cycles=3):
+        """Solve L_h u = f in place in the torch float64 tensor u (walls held fixed)."""
+        cyc = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        for t in (f, u):
+            if t.dtype != self.torch.float64 or not t.is_contiguous() or tuple(t.shape) != self.shape:
+                raise ValueError("f and u must be contiguous float64 tensors of the grid shape")
+        code = lib().vs_poisson_solve(self._st, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                      float(rtol), int(max_cycles), ctypes.byref(cyc), ctypes.byref(rel))
+        if code not in (VS_OK, VS_E_NOCONV):
+            _check(code, "vs_poisson_solve")
+        return code, cyc.value, rel.value
+
+    def grad_step(self, dt, adj_next, adj_prev):
+        dp = (ctypes.c_double * 2)()
+        _check(lib().vs_grad_step(self._st, float(dt), ctypes.c_void_p(adj_next.data_ptr()),
+                                  ctypes.c_void_p(adj_prev.data_ptr()), dp), "vs_grad_step")
+        return dp[0], dp[1]
+
+    def field(self, name: str):
+        """Torch float64 view of a field inside the workspace (valid until the next step)."""
+        off = ctypes.c_size_t(0)
+        _check(lib().vs_field_offset(self._st, FIELDS[name], ctypes.byref(off)), "vs_field_offset")
+        n = self.shape[0] * self.shape[1] * self.shape[2]
+        start = self._pad + off.value
+        return self._ws[start:start + 8 * n].view(self.torch.float64).view(*self.shape)
+
+    def fields(self):
+        return {k: self.field(k).cpu().numpy() for k in FIELDS}
+
+    def scalars(self) -> dict:
+        out = (ctypes.c_double * 8)()
+        _check(lib().vs_get_scalars(self._st, out), "vs_get_scalars")
+        return dict(zip(SCALARS, list(out)))
+
+    def save(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        _check(lib().vs_save_state(self._st, None, ctypes.byref(n)), "vs_save_state")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().vs_save_state(self._st, buf, ctypes.byref(n)), "vs_save_state")
+        return buf.raw
+
+    def load(self, blob: bytes):
+        _check(lib().vs_load_state(self._st, blob, len(blob)), "vs_load_state")
+
+    # ---------------------------------------------------------------- measurement
+    def profile(self, on: bool):
+        _check(lib().vs_profile(self._st, 1 if on else 0), "vs_profile")
+
+    def profile_read(self) -> dict:
+        res = {}
+        for k in range(lib().vs_profile_count()):
+            ms = ctypes.c_double(0.0)
+            n = ctypes.c_int64(0)
+            _check(lib().vs_profile_read(self._st, k, ctypes.byref(ms), ctypes.byref(n)), "vs_profile_read")
+            res[lib().vs_profile_name(k).decode()] = (ms.value, n.value)
+        return res
+
+    def close(self):
+        if getattr(self, "_st", None):
+            lib().vs_destroy(self._st)
+            self._st = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(workload, device="cuda:0", **overrides) -> "Solver":
+    """Build a Solver from a workloads.Workload (seeded phi0 included)."""
+    w = workload.with_(**overrides) if overrides else workload
+    p = w.params()
+    rtol = p.pop("rtol")
+    mc = p.pop("max_cycles")
+    return Solver((w.grid.nx, w.grid.ny, w.grid.nz, w.grid.h), w.walls(),
+                  dict(p, rtol=rtol, max_cycles=mc), w.phi0(), device=device)

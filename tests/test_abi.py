@@ -1,0 +1,98 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function include/vs.h
+declares, and rejects bad arguments on the host before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2601_05031_amd as P
+from paper_2601_05031_amd import vs as V
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vs_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for must in ("vs_init", "vs_poisson_solve", "vs_step", "vs_grad_step", "vs_workspace_bytes",
+                 "vs_field_offset", "vs_get_scalars", "vs_save_state", "vs_load_state", "vs_destroy",
+                 "vs_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def test_workspace_bytes_and_layout():
+    n = P.workspace_bytes((128, 128, 128, 1.0), P.make_params())
+    N = 128**3
+    assert 12 * 8 * N <= n < 12 * 8 * N + 16 * 2**20
+
+
+@pytest.mark.parametrize("grid,code", [
+    ((128, 2, 128, 1.0), V.VS_E_ARG),          # no interior row
+    ((130, 16, 128, 1.0), V.VS_E_UNSUPPORTED),  # 130 = 2 * 5 * 13
+    ((128, 16, 1024, 1.0), V.VS_E_UNSUPPORTED),
+    ((128, 16, 128, 0.0), V.VS_E_ARG),
+    ((33, 16, 32, 1.0), V.VS_E_UNSUPPORTED),
+])
+def test_grid_validation(grid, code):
+    with pytest.raises(V.VsError) as e:
+        P.workspace_bytes(grid, P.make_params())
+    assert e.value.code == code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(eta=0.0), V.VS_E_ARG), (dict(mobility=-1.0), V.VS_E_ARG), (dict(eps=0.0), V.VS_E_ARG),
+    (dict(rtol=0.0), V.VS_E_ARG), (dict(max_cycles=0), V.VS_E_ARG), (dict(max_cycles=17), V.VS_E_ARG),
+    (dict(model="cahn_hilliard", sigma=0.0), V.VS_E_ARG), (dict(rate_V=-1.0), V.VS_E_ARG),
+])
+def test_param_validation(kw, code):
+    with pytest.raises(V.VsError) as e:
+        P.workspace_bytes((32, 32, 32, 1.0), P.make_params(**kw))
+    assert e.value.code == code
+
+
+def test_init_rejects_before_any_device_call():
+    L = P.lib()
+    g = V.VsGrid(32, 32, 32, 1.0)
+    w = V.VsWalls(V.VS_POISEUILLE, 0.05, 0.0)
+    p = P.make_params()
+    st = ctypes.c_void_p(0)
+    # NULL phi0
+    assert L.vs_init(ctypes.byref(g), ctypes.byref(w), ctypes.byref(p), None, ctypes.c_void_p(256),
+                     1 << 30, None, ctypes.byref(st)) == V.VS_E_ARG
+    # misaligned workspace
+    assert L.vs_init(ctypes.byref(g), ctypes.byref(w), ctypes.byref(p), ctypes.c_void_p(4096),
+                     ctypes.c_void_p(4100), 1 << 30, None, ctypes.byref(st)) == V.VS_E_WORKSPACE
+    # too small workspace
+    assert L.vs_init(ctypes.byref(g), ctypes.byref(w), ctypes.byref(p), ctypes.c_void_p(4096),
+                     ctypes.c_void_p(4096), 1024, None, ctypes.byref(st)) == V.VS_E_WORKSPACE
+    # bad wall kind
+    w2 = V.VsWalls(7, 0.0, 0.0)
+    assert L.vs_init(ctypes.byref(g), ctypes.byref(w2), ctypes.byref(p), ctypes.c_void_p(4096),
+                     ctypes.c_void_p(4096), 1 << 30, None, ctypes.byref(st)) == V.VS_E_ARG
+    assert b"kind" in L.vs_last_error()
+    assert st.value in (None, 0)
+
+
+def test_null_state_calls():
+    L = P.lib()
+    assert L.vs_step(None, 1e-3, 1) == V.VS_E_STATE
+    assert L.vs_poisson_solve(None, None, None, 1e-10, 1, None, None) == V.VS_E_STATE
+    assert L.vs_grad_step(None, 1e-3, None, None, None) == V.VS_E_STATE
+    off = ctypes.c_size_t(0)
+    assert L.vs_field_offset(None, 0, ctypes.byref(off)) == V.VS_E_STATE
+    L.vs_destroy(None)
+    assert L.vs_profile_count() >= 10
+    assert L.vs_profile_name(0) == b"advance"

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle, element by element.
+
+Bar (FP64): relative L2 error <= 1e-9 per field (phi, mu, omega, psi); Poisson solves alone
+<= 1e-12. Every case prints its name, shape and seed before it touches the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import workload
+from workloads.shapes import GridSpec, phi_sphere
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_2601_05031_amd as P  # noqa: E402
+from paper_2601_05031_amd import vs as V  # noqa: E402
+
+TOL = 1e-9
+FIELD_NAMES = ["phi", "mu", "omega_x", "omega_y", "omega_z", "psi_x", "psi_y", "psi_z"]
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+def oracle_objs(w):
+    g = O.Grid(*w.grid.shape, h=w.grid.h)
+    walls = O.Walls(w.wall_kind, w.u0, w.u1)
+    p = O.Params(model=w.model, eta=w.eta, mobility=w.mobility, eps=w.eps, kappa=w.kappa,
+                 sigma=w.sigma, gamma0=w.gamma0, rate_V=w.rate_V, k_A=w.k_A, bend_scale=w.bend_scale)
+    return g, walls, p
+
+
+def ref_fields(s):
+    d = {"phi": s.phi, "mu": s.mu}
+    for c, ax in enumerate("xyz"):
+        d["omega_" + ax] = s.omega[c]
+        d["psi_" + ax] = s.psi[c]
+    return d
+
+
+def compare(got, ref, tol=TOL, label=""):
+    errs = {k: rel_l2(got[k], ref[k]) for k in FIELD_NAMES}
+    say(f"  {label} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not (v <= tol)}
+    assert not bad, bad
+    return errs
+
+
+def run_both(w, nsteps):
+    say(f"case {w.name} grid={w.grid.shape} seed={w.seed} model={w.model} walls={w.wall_kind} "
+        f"nsteps={nsteps}")
+    s = P.solver_for(w)
+    if nsteps:
+        s.step(w.dt, nsteps)
+    got = s.fields()
+    sc = s.scalars()
+    s.close()
+    g, walls, p = oracle_objs(w)
+    ref = O.run(g, walls, p, w.phi0(), w.dt, nsteps)
+    return got, sc, ref
+
+
+# ------------------------------------------------------------------------- Poisson alone
+@pytest.mark.parametrize("shape,h", [((24, 7, 12), 1.0), ((32, 33, 48), 0.5), ((96, 19, 96), 1.3),
+                                     ((8, 3, 6), 1.0)])
+def test_poisson_solve_matches_oracle(shape, h):
+    say(f"case poisson shape={shape} h={h}")
+    w = workload("vesicle32").with_(grid=GridSpec(*shape, h=h), shape="sphere", R0=2.0)
+    s = P.solver_for(w)
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal(shape)
+    u0 = rng.standard_normal(shape)
+    ft = torch.tensor(f, device="cuda")
+    ut = torch.tensor(u0, device="cuda")
+    code, cycles, rel = s.poisson_solve(ft, ut, rtol=1e-12, max_cycles=3)
+    u = ut.cpu().numpy()
+    s.close()
+    g = O.Grid(*shape, h=h)
+    ref = O.poisson_solve(f[:, 1:-1, :], u0[:, 0, :], u0[:, -1, :], g)
+    err = rel_l2(u[:, 1:-1, :], ref)
+    say(f"  code={code} cycles={cycles} relres={rel:.2e} relL2={err:.2e}")
+    assert code == V.VS_OK and rel <= 1e-12 and cycles >= 1
+    assert err <= 1e-12
+    assert np.array_equal(u[:, 0, :], u0[:, 0, :]) and np.array_equal(u[:, -1, :], u0[:, -1, :])
+
+
+def test_poisson_zero_rhs_zero_walls_gives_zero():
+    say("case poisson zero rhs")
+    w = workload("vesicle32")
+    s = P.solver_for(w)
+    ft = torch.zeros(w.grid.shape, dtype=torch.float64, device="cuda")
+    ut = torch.ones(w.grid.shape, dtype=torch.float64, device="cuda")
+    ut[:, 0, :] = 0
+    ut[:, -1, :] = 0
+    code, cycles, rel = s.poisson_solve(ft, ut, rtol=1e-10, max_cycles=2)
+    s.close()
+    assert code == V.VS_OK and rel == 0.0
+    assert float(ut.abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------------- init and steps
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_init_parity_vesicle32(seed):
+    w = workload("vesicle32", seed=seed)
+    got, sc, ref = run_both(w, 0)
+    compare(got, ref_fields(ref), label="init")
+    assert sc["V0"] == pytest.approx(ref.V0, rel=1e-12)
+    assert sc["A0"] == pytest.approx(ref.A0, rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_step_parity_vesicle32(seed):
+    w = workload("vesicle32", seed=seed)
+    got, sc, ref = run_both(w, w.nsteps)
+    compare(got, ref_fields(ref), label="5 steps")
+    assert sc["V"] == pytest.approx(ref.V, rel=1e-12)
+    assert sc["A"] == pytest.approx(ref.A, rel=1e-11)
+    assert sc["relres"] <= w.rtol
+    assert sc["step"] == w.nsteps
+
+
+def test_step_parity_penalties_and_tension():
+    """Volume/area penalties and a surface tension on, ragged small grid, Couette walls."""
+    w = workload("vesicle32", grid=GridSpec(24, 21, 36), wall_kind="couette", u0=-0.03, u1=0.05,
+                 R0=6.0, gamma0=0.2, rate_V=10.0, k_A=1.0, kappa=0.5, seed=4, dt=5e-4)
+    got, sc, ref = run_both(w, 6)
+    compare(got, ref_fields(ref), label="6 steps")
+    assert sc["lambda_V"] == pytest.approx(ref.lam_V, rel=1e-7, abs=1e-14)
+    assert sc["gamma_A"] == pytest.approx(ref.gamma_A, rel=1e-9, abs=1e-14)
+
+
+def test_step_parity_cahn_hilliard_couette():
+    """Cahn-Hilliard droplet in plane Couette flow (walls at -/+0.05)."""
+    w = workload("droplet256", grid=GridSpec(48, 32, 96), R0=9.0, nsteps=5)
+    got, sc, ref = run_both(w, 5)
+    compare(got, ref_fields(ref), label="CH 5 steps")
+
+
+def test_step_parity_vesicle128_full_size():
+    """The 128^3 prolate vesicle at full size, kappa = 1, first 3 steps (the oracle takes
+    about two seconds per step)."""
+    w = workload("vesicle128", nsteps=3)
+    got, sc, ref = run_both(w, 3)
+    compare(got, ref_fields(ref), label="128^3 3 steps")
+
+
+def test_no_body_channel_is_exact():
+    """phi = -1: omega_x and psi_x are the linear and cubic wall profiles to roundoff."""
+    say("case no-body poiseuille 16x31x16")
+    w = workload("vesicle32", grid=GridSpec(16, 31, 16))
+    s = P.Solver((16, 31, 16, 1.0), w.walls(), dict(kappa=1.0), -np.ones((16, 31, 16)))
+    s.step(1e-3, 2)
+    got = s.fields()
+    s.close()
+    g, walls, _ = oracle_objs(w)
+    _, psx, omx = O.wall_profiles(g, walls)
+    assert np.max(np.abs(got["omega_x"] - omx[None, :, None])) < 1e-15
+    assert np.max(np.abs(got["psi_x"] - psx[None, :, None])) < 1e-13
+    for k in ("omega_y", "omega_z", "psi_y", "psi_z", "mu"):
+        assert np.max(np.abs(got[k])) < 1e-15
+    assert np.max(np.abs(got["phi"] + 1.0)) == 0.0
+
+
+def test_phi_budget_on_gpu():
+    """Delta(sum_w phi) over one GPU step = dt (M lambda_V W - sum_w v . D phi), with v and
+    D phi evaluated on the GPU's own psi and phi."""
+    w = workload("vesicle32", rate_V=10.0, k_A=1.0, seed=3)
+    say(f"case budget {w.grid.shape}")
+    s = P.solver_for(w)
+    g, walls, p = oracle_objs(w)
+    W = float(np.sum(g.weights() * np.ones(g.shape)))
+    for _ in range(3):
+        f0 = s.fields()
+        lam = s.scalars()["lambda_V"]
+        v = O.velocity(np.stack([f0["psi_x"], f0["psi_y"], f0["psi_z"]]), g, walls)
+        dx, dy, dz = O.grad_mirror(f0["phi"], g.h)
+        adv = float(np.sum(g.weights() * (v[0] * dx + v[1] * dy + v[2] * dz)))
+        before = float(np.sum(g.weights() * f0["phi"]))
+        s.step(w.dt, 1)
+        after = float(np.sum(g.weights() * s.field("phi").cpu().numpy()))
+        assert abs((after - before) - w.dt * (lam * W - adv)) < 1e-10 * abs(before)
+    s.close()
+
+
+# ------------------------------------------------------------- determinism and checkpoints
+def test_repeat_runs_bitwise_equal_and_checkpoint_resume():
+    w = workload("vesicle32", seed=1)
+    say("case determinism/checkpoint vesicle32")
+    a = P.solver_for(w)
+    a.step(w.dt, 4)
+    fa = a.fields()
+    b = P.solver_for(w)
+    b.step(w.dt, 2)
+    blob = b.save()
+    b.step(w.dt, 2)
+    fb = b.fields()
+    c = P.solver_for(w.with_(seed=2))
+    c.load(blob)
+    c.step(w.dt, 2)
+    fc = c.fields()
+    for k in FIELD_NAMES:
+        assert np.array_equal(fa[k], fb[k]), k
+        assert np.array_equal(fa[k], fc[k]), k
+    assert c.scalars()["step"] == 4
+    for s in (a, b, c):
+        s.close()
+
+
+# ------------------------------------------------------------------------- error paths
+def test_unstable_dt_rejected_before_enqueue():
+    w = workload("vesicle32")
+    say("case unstable dt")
+    s = P.solver_for(w)
+    before = s.fields()["phi"]
+    C_b = 3 * math.sqrt(2) / 8
+    bound = 2.0 / (12 * C_b * 14**2)
+    with pytest.raises(V.VsError) as e:
+        s.step(1.01 * bound, 1)
+    assert e.value.code == V.VS_E_UNSTABLE
+    assert np.array_equal(s.fields()["phi"], before)
+    s.step(0.99 * bound, 1)   # just below the bound is accepted
+    s.close()
+
+
+def test_unreachable_tolerance_reports_noconv():
+    w = workload("vesicle32")
+    say("case noconv")
+    s = P.solver_for(w)
+    f = torch.randn(w.grid.shape, dtype=torch.float64, device="cuda")
+    u = torch.zeros(w.grid.shape, dtype=torch.float64, device="cuda")
+    code, cycles, rel = s.poisson_solve(f, u, rtol=1e-30, max_cycles=2)
+    assert code == V.VS_E_NOCONV and cycles == 2 and 0 < rel < 1e-12
+    s.close()
+
+
+def test_nan_injection_reports_nonfinite():
+    w = workload("vesicle32")
+    say("case nan injection")
+    s = P.solver_for(w)
+    blob = bytearray(s.save())
+    hdr = len(blob) - 8 * 8 * w.grid.N
+    arr = np.frombuffer(blob, dtype=np.float64, count=w.grid.N, offset=hdr).copy()
+    arr[1000] = np.nan
+    blob[hdr:hdr + 8 * w.grid.N] = arr.tobytes()
+    s.load(bytes(blob))
+    with pytest.raises(V.VsError) as e:
+        s.step(w.dt, 1)
+    assert e.value.code == V.VS_E_NONFINITE
+    s.close()
+
+
+def test_grad_step_not_built():
+    w = workload("vesicle32")
+    s = P.solver_for(w)
+    a = torch.zeros(w.grid.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(V.VsError) as e:
+        s.grad_step(w.dt, a, a)
+    assert e.value.code == V.VS_E_UNSUPPORTED
+    s.close()
+
+
+def test_phi_sphere_helper_shapes():
+    g = GridSpec(8, 8, 8)
+    assert phi_sphere(g, 2.0, 1.0).shape == (8, 8, 8)
