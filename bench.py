@@ -1,0 +1,219 @@
+"""Benchmark of the FP64 time step on one MI355X.
+
+Workload (vesicle128): 128^3 grid, plane Poiseuille channel (centreline 0.05, walls at y = 0
+and y = 127), prolate vesicle of area-equivalent radius 24 and reduced volume 0.8, bending
+with volume/area penalties, dt = 5e-4. One benchmark step advances three instances, kappa =
+0.5, 1 and 2, by one time step each (three full passes of the hot path: phi update, mu,
+vorticity solve, stream-vector solve). Inputs are resident in HBM before the timed region.
+
+Prints one JSON line. `value` is cell-updates/s over the timed steps; `roofline` is the
+dominant kernel's algorithmic bytes per launch over its mean event-timed duration, against
+the 8 TB/s HBM peak; `cpu_baseline` is the CPU oracle on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s & steps/s at 128³: FP64 vs FP32-refined vs batched; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+KAPPAS = (0.5, 1.0, 2.0)
+
+
+def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
+    """Algorithmic HBM bytes of one launch: each input read once, each output written once
+    (FP64). Ni counts the interior rows the Poisson kernels touch. The two Poisson right-hand
+    sides differ (vorticity: phi, mu; stream vector: omega), so rhs_dht_z and resid_norm use
+    the mean of the two launches of a step."""
+    N = nx * ny * nz
+    Ni = nx * (ny - 2) * nz
+    table = {
+        "advance": 48 * N,            # phi, mu, psi_x, psi_y, psi_z in; phi' out
+        "va_partials": 8 * N,         # phi in
+        "mu": 16 * N,                 # phi in; mu out
+        "rhs_dht_z": 44 * Ni,         # (phi, mu) or omega(3) in; 3 spectral fields out
+        "dht_x": 48 * Ni,             # 3 spectral fields in and out
+        "tridiag_y": 48 * Ni,         # 3 spectral fields in and out
+        "dht_z_out": 48 * Ni,         # 3 spectral fields in; 3 solution fields out
+        "resid_norm": 44 * Ni,        # (phi, mu, omega(3)) or (omega(3), psi(3)) in
+    }
+    return table.get(name)
+
+
+def source_hash(kernel: str) -> str:
+    """Hash of the source file that holds a kernel, to tie stored counters to the code."""
+    fname = "k_explicit.hip" if kernel in ("advance", "va_partials", "mu") else "k_spectral.hip"
+    with open(os.path.join(ROOT, "paper_2601_05031_amd", "csrc", fname), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken on the
+    current source of that kernel; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"source_sha256_16:\s*(\w+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_b or m_hash.group(1) != source_hash(kernel):
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(workload, budget_s: float):
+    """The CPU oracle on the same 128^3 workload (kappa = 1): init, then as many steps as fit
+    in about budget_s seconds (at least 2)."""
+    import oracle as O
+
+    w = workload
+    g = O.Grid(*w.grid.shape, h=w.grid.h)
+    walls = O.Walls(w.wall_kind, w.u0, w.u1)
+    p = O.Params(model=w.model, eta=w.eta, mobility=w.mobility, eps=w.eps, kappa=1.0,
+                 sigma=w.sigma, gamma0=w.gamma0, rate_V=w.rate_V, k_A=w.k_A, bend_scale=w.bend_scale)
+    s = O.init_state(g, walls, p, w.phi0())
+    t0 = time.perf_counter()
+    n = 0
+    while n < 2 or (time.perf_counter() - t0) < budget_s:
+        s = O.step(s, w.dt, g, walls, p)
+        n += 1
+    t = time.perf_counter() - t0
+    N = w.grid.N
+    return {"value": N * n / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"vesicle128 kappa=1, {n} time steps at 128^3 after init, numpy/scipy FP64 "
+                      f"(single-threaded), {t:.1f} s",
+            "steps_per_s": n / t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--max-cycles", type=int, default=1,
+                    help="Poisson refinement cycles per solve (each solve is verified on the device)")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2601_05031_amd as P
+    from workloads import workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    base = workload("vesicle128", max_cycles=args.max_cycles)
+    nx, ny, nz = base.grid.shape
+    N = base.grid.N
+    print(f"bench: building {len(KAPPAS)} solvers for {base.name} {base.grid.shape}", file=sys.stderr,
+          flush=True)
+    solvers = [P.solver_for(base, kappa=k) for k in KAPPAS]
+    for s in solvers:
+        s.step(base.dt, args.warmup)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K benchmark steps = K time steps of each kappa instance
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    per_kappa = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k, s in zip(KAPPAS, solvers):
+        a = time.perf_counter()
+        s.step(base.dt, args.steps)
+        per_kappa[str(k)] = time.perf_counter() - a
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    total_cells = len(KAPPAS) * N * args.steps
+    value = total_cells / wall
+    relres = max(s.scalars()["relres"] for s in solvers)
+    print(f"bench: timed {args.steps} steps x {len(KAPPAS)} instances in {wall:.3f} s "
+          f"(events {gpu_ms:.1f} ms), max relres {relres:.2e}", file=sys.stderr, flush=True)
+
+    # ---- per-kernel event timing on the kappa = 1 instance (a separate pass)
+    s1 = solvers[1]
+    s1.profile(True)
+    s1.step(base.dt, args.profile_steps)
+    prof = s1.profile_read()
+    s1.profile(False)
+    kern = {}
+    for name, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        kern[name] = {"total_ms": ms, "launches": n, "mean_us": 1e3 * ms / n}
+    ranked = sorted(((v["total_ms"], k) for k, v in kern.items() if kernel_bytes(k, nx, ny, nz)),
+                    reverse=True)
+    dom = ranked[0][1]
+    dom_bytes = kernel_bytes(dom, nx, ny, nz)
+    dom_mean_s = kern[dom]["mean_us"] * 1e-6
+    achieved = dom_bytes / dom_mean_s / 1e9
+    traffic = stored_traffic(dom, base.name)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": dom_bytes, "mean_launch_us": round(kern[dom]["mean_us"], 2)}
+    step_bytes = sum(kernel_bytes(k, nx, ny, nz) * v["launches"] for k, v in kern.items()
+                     if kernel_bytes(k, nx, ny, nz)) / args.profile_steps
+    step_kernel_ms = sum(v["total_ms"] for v in kern.values()) / args.profile_steps
+
+    for s in solvers:
+        s.close()
+    del solvers
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(base, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": base.name, "grid": [nx, ny, nz], "kappa": list(KAPPAS),
+                   "instances_per_step": len(KAPPAS), "dt": base.dt, "precision": "fp64",
+                   "poisson_rtol": base.rtol, "poisson_max_cycles": args.max_cycles,
+                   "flow": "poiseuille u0=0.05", "penalties": {"rate_V": base.rate_V, "k_A": base.k_A}},
+        "steps_per_s_per_instance": len(KAPPAS) * args.steps / wall,
+        "max_relres": relres,
+        "per_kappa_cell_updates_per_s": {k: N * args.steps / t for k, t in per_kappa.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": {k: {"mean_us": round(v["mean_us"], 2), "launches_per_step": v["launches"] / args.profile_steps}
+                    for k, v in kern.items()},
+        "step_algorithmic_bytes": step_bytes,
+        "step_kernel_ms": step_kernel_ms,
+        "step_algorithmic_frac_hbm": (step_bytes / (step_kernel_ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
