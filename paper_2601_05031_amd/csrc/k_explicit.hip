@@ -178,8 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x * kPartialStride + 0] = acc[0];
-        partials[blockIdx.x * kPartialStride + 1] = acc[1];
+        partials[0 * kMaxPartialBlocks + blockIdx.x] = acc[0];
+        partials[1 * kMaxPartialBlocks + blockIdx.x] = acc[1];
     }
 }
 
@@ -193,8 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize_va(const double* __restrict
     __shared__ double sh[2 * 16];
     double acc[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        acc[0] += partials[b * kPartialStride + 0];
-        acc[1] += partials[b * kPartialStride + 1];
+        acc[0] += partials[0 * kMaxPartialBlocks + b];
+        acc[1] += partials[1 * kMaxPartialBlocks + b];
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x != 0) return;

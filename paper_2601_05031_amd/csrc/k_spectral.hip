@@ -70,52 +70,61 @@ __device__ __forceinline__ void butterfly<3>(double2 (&x)[3]) {
     x[2] = make_double2(m.x - c * e.y, m.y + c * e.x);   // m + i c e
 }
 
-// One radix-R Stockham pass over nlines lines of length n (line stride n), in -> out.
-// p is the product of the radices already applied.
+// One radix-R Stockham pass, in place in LDS, over nlines lines of length n (line stride n).
+// p is the product of the radices already applied. The tile holds at most 2 * R * blockDim
+// elements per pass, so each thread stages at most two butterflies in registers: all reads,
+// a barrier, then all writes.
 template <int R>
-__device__ __forceinline__ void stockham_pass(const double2* in, double2* out, int n, int p,
-                                              int nlines, const double2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(double2* A, int n, int p, int nlines,
+                                              const double2* __restrict__ tw) {
     const int T = n / R;
+    const int total = nlines * T;
     const int ts = n / (p * R);
-    for (int e = threadIdx.x; e < nlines * T; e += blockDim.x) {
-        const int line = e / T;
-        const int t = e - line * T;
-        const double2* X = in + line * n;
-        double2* Y = out + line * n;
-        const int kk = t % p;
-        double2 x[R];
+    double2 x[2][R];
+    int jo[2];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = X[t + r * T];
+    for (int b = 0; b < 2; ++b) {
+        const int e = threadIdx.x + b * blockDim.x;
+        jo[b] = -1;
+        if (e < total) {
+            const int line = e / T;
+            const int t = e - line * T;
+            const int kk = t % p;
+            const double2* X = A + line * n;
 #pragma unroll
-        for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * kk * ts]);
-        butterfly<R>(x);
-        const int jo = (t - kk) * R + kk;
+            for (int r = 0; r < R; ++r) x[b][r] = X[t + r * T];
 #pragma unroll
-        for (int r = 0; r < R; ++r) Y[jo + r * p] = x[r];
-    }
-}
-
-// Forward FFT of nlines lines held in A (B is scratch of the same size). Returns the buffer
-// with the result. Ends with a barrier.
-__device__ double2* fft_lines(double2* A, double2* B, const FftPlan& pl, int nlines,
-                              const double2* __restrict__ tw) {
-    int p = 1;
-    for (int s = 0; s < pl.npass; ++s) {
-        __syncthreads();
-        const int R = pl.radix[s];
-        if (R == 4)
-            stockham_pass<4>(A, B, pl.n, p, nlines, tw);
-        else if (R == 2)
-            stockham_pass<2>(A, B, pl.n, p, nlines, tw);
-        else
-            stockham_pass<3>(A, B, pl.n, p, nlines, tw);
-        p *= R;
-        double2* t = A;
-        A = B;
-        B = t;
+            for (int r = 1; r < R; ++r) x[b][r] = cmul(x[b][r], tw[r * kk * ts]);
+            butterfly<R>(x[b]);
+            jo[b] = line * n + (t - kk) * R + kk;
+        }
     }
     __syncthreads();
-    return A;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        if (jo[b] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) A[jo[b] + r * p] = x[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Forward FFT, in place, of nlines lines held in A (nlines * n <= kTileElems). Starts and
+// ends with a barrier.
+__device__ void fft_tile(double2* A, const FftPlan& pl, int nlines, const double2* __restrict__ tw) {
+    __syncthreads();
+    int p = 1;
+    for (int s = 0; s < pl.npass; ++s) {
+        const int R = pl.radix[s];
+        if (R == 4)
+            stockham_pass<4>(A, pl.n, p, nlines, tw);
+        else if (R == 2)
+            stockham_pass<2>(A, pl.n, p, nlines, tw);
+        else
+            stockham_pass<3>(A, pl.n, p, nlines, tw);
+        p *= R;
+    }
 }
 
 // Hartley value of the real line packed in the real (part = 0) or imaginary (part = 1) slot.
@@ -156,6 +165,37 @@ __device__ __forceinline__ void rhs_at(const RhsArgs& a, const Dims& d, int i, i
     for (int c = 0; c < ncomp; ++c) b[c] = sg * a.f[c][c0];
 }
 
+// Component c of the right-hand side at interior node (i, j, k).
+__device__ __forceinline__ double rhs_comp(const RhsArgs& a, const Dims& d, int i, int j, int k,
+                                           int c) {
+    const int c0 = node(d, i, j, k);
+    if (a.mode == RHS_VORT) {
+        const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+        const int im = (i == 0) ? d.nx - 1 : i - 1;
+        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+        const int km = (k == 0) ? d.nz - 1 : k - 1;
+        const double* f = a.phi;
+        const double* m = a.mu;
+        // (D phi x D mu)_c needs the two derivative directions other than c
+        double f1, f2, m1, m2;
+        if (c == 0) {        // y, z
+            f1 = f[c0 + d.nz] - f[c0 - d.nz]; m1 = m[c0 + d.nz] - m[c0 - d.nz];
+            f2 = f[c0 - k + kp] - f[c0 - k + km]; m2 = m[c0 - k + kp] - m[c0 - k + km];
+        } else if (c == 1) { // z, x
+            f1 = f[c0 - k + kp] - f[c0 - k + km]; m1 = m[c0 - k + kp] - m[c0 - k + km];
+            f2 = f[node(d, ip, j, k)] - f[node(d, im, j, k)];
+            m2 = m[node(d, ip, j, k)] - m[node(d, im, j, k)];
+        } else {             // x, y
+            f1 = f[node(d, ip, j, k)] - f[node(d, im, j, k)];
+            m1 = m[node(d, ip, j, k)] - m[node(d, im, j, k)];
+            f2 = f[c0 + d.nz] - f[c0 - d.nz]; m2 = m[c0 + d.nz] - m[c0 - d.nz];
+        }
+        return ((f1 * d.inv_2h) * (m2 * d.inv_2h) - (f2 * d.inv_2h) * (m1 * d.inv_2h)) * a.inv_eta;
+    }
+    const double v = a.f[c][c0];
+    return (a.mode == RHS_NEGW) ? -v : v;
+}
+
 // 7-point Laplacian at an interior node using the stored wall rows of u.
 __device__ __forceinline__ double lap_interior(const double* __restrict__ u, const Dims& d, int i,
                                                int j, int k) {
@@ -179,59 +219,58 @@ __device__ __forceinline__ double wall_term(const double* __restrict__ u, const 
 }
 
 // ---------------------------------------------------------------------------------------
-// rhs_dht_z: rows r = i*M + (j-1) of the interior, rpb rows per block, ncomp components.
+// Tiles: every transform kernel holds at most kTileElems complex values (16 KB) in one LDS
+// buffer, one component per block (blockIdx.y), so eight or more blocks fit on a CU.
+constexpr int kTileElems = 1024;
+
+// rhs_dht_z: block = (rows r0 .. r0+rpb-1 of the interior, r = i*M + (j-1); component c).
 // correct = 0: transform b - (wall terms); correct = 1: transform b - L_h u.
 __global__ __launch_bounds__(kBlock) void k_rhs_dht_z(Dims d, FftPlan pz,
                                                      const double2* __restrict__ tw, RhsArgs rhs,
-                                                     CPtr3 u, int ncomp, int correct, Ptr3 spec,
+                                                     CPtr3 u, int correct, Ptr3 spec,
                                                      const int* gate, int rpb) {
     if (gate && *gate) return;
-    extern __shared__ double2 lds[];
+    __shared__ double2 A[kTileElems];
     const int n = d.nz;
-    const int lpc = rpb >> 1;                 // complex lines per component
-    const int nlines = ncomp * lpc;
-    double2* A = lds;
-    double2* B = lds + nlines * n;
+    const int nlines = rpb >> 1;
+    const int c = blockIdx.y;
     const int nrows = d.nx * d.M;
     const int r0 = blockIdx.x * rpb;
+    const double* uc = u.p[c];
     for (int e = threadIdx.x; e < rpb * n; e += blockDim.x) {
         const int lr = e / n;
         const int k = e - lr * n;
         const int r = r0 + lr;
-        double b[3] = {0.0, 0.0, 0.0};
+        double b = 0.0;
         if (r < nrows) {
             const int i = r / d.M;
             const int j = 1 + (r - i * d.M);
-            rhs_at(rhs, d, i, j, k, ncomp, b);
-            for (int c = 0; c < ncomp; ++c)
-                b[c] -= correct ? lap_interior(u.p[c], d, i, j, k) : wall_term(u.p[c], d, i, j, k);
+            b = rhs_comp(rhs, d, i, j, k, c);
+            b -= correct ? lap_interior(uc, d, i, j, k) : wall_term(uc, d, i, j, k);
         }
-        for (int c = 0; c < ncomp; ++c) set_part(&A[(c * lpc + (lr >> 1)) * n + k], lr & 1, b[c]);
+        set_part(&A[(lr >> 1) * n + k], lr & 1, b);
     }
-    const double2* Z = fft_lines(A, B, pz, nlines, tw);
-    for (int e = threadIdx.x; e < ncomp * rpb * n; e += blockDim.x) {
-        const int c = e / (rpb * n);
-        const int rem = e - c * rpb * n;
-        const int lr = rem / n;
-        const int p = rem - lr * n;
+    fft_tile(A, pz, nlines, tw);
+    double* sc = spec.p[c];
+    for (int e = threadIdx.x; e < rpb * n; e += blockDim.x) {
+        const int lr = e / n;
+        const int p = e - lr * n;
         const int r = r0 + lr;
         if (r >= nrows) continue;
         const int i = r / d.M;
         const int j = 1 + (r - i * d.M);
-        spec.p[c][node(d, i, j, p)] = hartley(Z + (c * lpc + (lr >> 1)) * n, n, p, lr & 1);
+        sc[node(d, i, j, p)] = hartley(A + (lr >> 1) * n, n, p, lr & 1);
     }
 }
 
-// dht_x: block = (component, interior row j, block of kb consecutive z-modes q).
+// dht_x: block = (block of kb consecutive z-modes q, interior row j, component c).
 __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
                                                  const double2* __restrict__ tw, Ptr3 spec,
                                                  const int* gate, int kb) {
     if (gate && *gate) return;
-    extern __shared__ double2 lds[];
+    __shared__ double2 A[kTileElems];
     const int n = d.nx;
     const int nlines = kb >> 1;
-    double2* A = lds;
-    double2* B = lds + nlines * n;
     const int c = blockIdx.z;
     const int j = 1 + blockIdx.y;
     const int q0 = blockIdx.x * kb;
@@ -243,21 +282,23 @@ __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
         const double v = (q < d.nz) ? s[node(d, i, j, q)] : 0.0;
         set_part(&A[(kk >> 1) * n + i], kk & 1, v);
     }
-    const double2* Z = fft_lines(A, B, px, nlines, tw);
+    fft_tile(A, px, nlines, tw);
     for (int e = threadIdx.x; e < n * kb; e += blockDim.x) {
         const int p = e / kb;
         const int kk = e - p * kb;
         const int q = q0 + kk;
         if (q >= d.nz) continue;
-        s[node(d, p, j, q)] = hartley(Z + (kk >> 1) * n, n, p, kk & 1);
+        s[node(d, p, j, q)] = hartley(A + (kk >> 1) * n, n, p, kk & 1);
     }
 }
 
-// tridiag_y: one thread per (component, p, q). Solves
+// tridiag_y: one thread per (p, q), component blockIdx.y. Solves
 //   U_{j-1} + beta U_j + U_{j+1} = scale * B_j,  j = 1..M,  U_0 = U_{M+1} = 0,
 // beta = 2 cos(2 pi p/nx) + 2 cos(2 pi q/nz) - 6, with the forward-elimination pivots
-// c'_j = 1/(beta - c'_{j-1}) read from a table indexed by the mode class
-// (min(p, nx-p), min(q, nz-q)). In place; loads are issued in chunks of 8 rows.
+// c'_j = 1/(beta - c'_{j-1}) read from a table tri[(j-1) * nclass + class], class =
+// min(p, nx-p) * (nz/2+1) + min(q, nz-q): lanes with consecutive q read consecutive (or
+// reversed consecutive) entries. In place. Rows are processed in chunks of CH with the next
+// chunk's loads issued before the current chunk's dependent recurrence runs.
 __global__ __launch_bounds__(kBlock) void k_tridiag_y(Dims d, const double* __restrict__ tri,
                                                      Ptr3 spec, const int* gate, double scale) {
     if (gate && *gate) return;
@@ -268,91 +309,110 @@ __global__ __launch_bounds__(kBlock) void k_tridiag_y(Dims d, const double* __re
     const int q = t - p * d.nz;
     const int pc = min(p, d.nx - p);
     const int qc = min(q, d.nz - q);
-    const double* cp = tri + (size_t)(pc * (d.nz / 2 + 1) + qc) * d.M;
+    const size_t ncls = (size_t)(d.nx / 2 + 1) * (d.nz / 2 + 1);
+    const double* cp = tri + (size_t)(pc * (d.nz / 2 + 1) + qc);
     double* col = spec.p[c] + (size_t)p * d.ny * d.nz + q;
-    const int sj = d.nz;
+    const size_t sj = d.nz;
     const int M = d.M;
     constexpr int CH = 8;
+    double bv[CH], cv[CH];
+    // forward elimination, rows 1..M
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const int j = 1 + u;
+        bv[u] = (j <= M) ? col[j * sj] : 0.0;
+        cv[u] = (j <= M) ? cp[(size_t)(j - 1) * ncls] : 0.0;
+    }
     double dprev = 0.0;
-    int j = 1;
-    for (; j + CH - 1 <= M; j += CH) {
-        double bv[CH], cv[CH];
+    for (int j0 = 1; j0 <= M; j0 += CH) {
+        double nb[CH], nc[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            bv[u] = col[(size_t)(j + u) * sj];
-            cv[u] = cp[j + u - 1];
+            const int j = j0 + CH + u;
+            nb[u] = (j <= M) ? col[j * sj] : 0.0;
+            nc[u] = (j <= M) ? cp[(size_t)(j - 1) * ncls] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            dprev = cv[u] * (scale * bv[u] - dprev);
-            col[(size_t)(j + u) * sj] = dprev;
+            const int j = j0 + u;
+            if (j <= M) {
+                dprev = cv[u] * (scale * bv[u] - dprev);
+                col[j * sj] = dprev;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            bv[u] = nb[u];
+            cv[u] = nc[u];
         }
     }
-    for (; j <= M; ++j) {
-        dprev = cp[j - 1] * (scale * col[(size_t)j * sj] - dprev);
-        col[(size_t)j * sj] = dprev;
+    // back substitution, rows M..1
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const int j = M - u;
+        bv[u] = (j >= 1) ? col[j * sj] : 0.0;
+        cv[u] = (j >= 1) ? cp[(size_t)(j - 1) * ncls] : 0.0;
     }
     double unext = 0.0;
-    j = M;
-    for (; j - CH + 1 >= 1; j -= CH) {
-        double dv[CH], cv[CH];
+    for (int j0 = M; j0 >= 1; j0 -= CH) {
+        double nb[CH], nc[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            dv[u] = col[(size_t)(j - u) * sj];
-            cv[u] = cp[j - u - 1];
+            const int j = j0 - CH - u;
+            nb[u] = (j >= 1) ? col[j * sj] : 0.0;
+            nc[u] = (j >= 1) ? cp[(size_t)(j - 1) * ncls] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            unext = dv[u] - cv[u] * unext;
-            col[(size_t)(j - u) * sj] = unext;
+            const int j = j0 - u;
+            if (j >= 1) {
+                unext = bv[u] - cv[u] * unext;
+                col[j * sj] = unext;
+            }
         }
-    }
-    for (; j >= 1; --j) {
-        unext = col[(size_t)j * sj] - cp[j - 1] * unext;
-        col[(size_t)j * sj] = unext;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            bv[u] = nb[u];
+            cv[u] = nc[u];
+        }
     }
 }
 
 // dht_z_out: Hartley along z of the solved modes, then u = result (add = 0) or u += result.
 __global__ __launch_bounds__(kBlock) void k_dht_z_out(Dims d, FftPlan pz,
                                                      const double2* __restrict__ tw, Ptr3 spec,
-                                                     Ptr3 u, int ncomp, int add, const int* gate,
-                                                     int rpb) {
+                                                     Ptr3 u, int add, const int* gate, int rpb) {
     if (gate && *gate) return;
-    extern __shared__ double2 lds[];
+    __shared__ double2 A[kTileElems];
     const int n = d.nz;
-    const int lpc = rpb >> 1;
-    const int nlines = ncomp * lpc;
-    double2* A = lds;
-    double2* B = lds + nlines * n;
+    const int nlines = rpb >> 1;
+    const int c = blockIdx.y;
     const int nrows = d.nx * d.M;
     const int r0 = blockIdx.x * rpb;
-    for (int e = threadIdx.x; e < ncomp * rpb * n; e += blockDim.x) {
-        const int c = e / (rpb * n);
-        const int rem = e - c * rpb * n;
-        const int lr = rem / n;
-        const int k = rem - lr * n;
+    const double* sc = spec.p[c];
+    for (int e = threadIdx.x; e < rpb * n; e += blockDim.x) {
+        const int lr = e / n;
+        const int k = e - lr * n;
         const int r = r0 + lr;
         double v = 0.0;
         if (r < nrows) {
             const int i = r / d.M;
             const int j = 1 + (r - i * d.M);
-            v = spec.p[c][node(d, i, j, k)];
+            v = sc[node(d, i, j, k)];
         }
-        set_part(&A[(c * lpc + (lr >> 1)) * n + k], lr & 1, v);
+        set_part(&A[(lr >> 1) * n + k], lr & 1, v);
     }
-    const double2* Z = fft_lines(A, B, pz, nlines, tw);
-    for (int e = threadIdx.x; e < ncomp * rpb * n; e += blockDim.x) {
-        const int c = e / (rpb * n);
-        const int rem = e - c * rpb * n;
-        const int lr = rem / n;
-        const int p = rem - lr * n;
+    fft_tile(A, pz, nlines, tw);
+    double* uc = u.p[c];
+    for (int e = threadIdx.x; e < rpb * n; e += blockDim.x) {
+        const int lr = e / n;
+        const int p = e - lr * n;
         const int r = r0 + lr;
         if (r >= nrows) continue;
         const int i = r / d.M;
         const int j = 1 + (r - i * d.M);
-        const double v = hartley(Z + (c * lpc + (lr >> 1)) * n, n, p, lr & 1);
-        double* dst = u.p[c] + node(d, i, j, p);
+        const double v = hartley(A + (lr >> 1) * n, n, p, lr & 1);
+        double* dst = uc + node(d, i, j, p);
         *dst = add ? *dst + v : v;
     }
 }
@@ -397,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
     if (threadIdx.x < 6) {
         const double s = sh[threadIdx.x * 4 + 0] + sh[threadIdx.x * 4 + 1] +
                          sh[threadIdx.x * 4 + 2] + sh[threadIdx.x * 4 + 3];
-        partials[blockIdx.x * kPartialStride + threadIdx.x] = s;
+        partials[threadIdx.x * kMaxPartialBlocks + blockIdx.x] = s;
     }
 }
 
@@ -411,9 +471,9 @@ __global__ __launch_bounds__(kBlock) void k_check(const double* __restrict__ par
     __shared__ double sh[2 * 4];
     double rr = 0.0, bb = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        const double* pb = partials + b * kPartialStride;
-        rr += pb[0] + pb[1] + pb[2];
-        bb += pb[3] + pb[4] + pb[5];
+        const double* pb = partials + b;
+        rr += pb[0 * kMaxPartialBlocks] + pb[1 * kMaxPartialBlocks] + pb[2 * kMaxPartialBlocks];
+        bb += pb[3 * kMaxPartialBlocks] + pb[4 * kMaxPartialBlocks] + pb[5 * kMaxPartialBlocks];
     }
     rr = wave_sum(rr);
     bb = wave_sum(bb);
@@ -444,16 +504,17 @@ __global__ __launch_bounds__(kBlock) void k_check(const double* __restrict__ par
     if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
 }
 
-int z_rows_per_block(const Dims& d, int ncomp) {
-    int rpb = 2 * (1536 / (ncomp * d.nz));
-    if (rpb < 2) rpb = 2;
-    return rpb;
+// Rows per block of the z kernels: 2 * (kTileElems / nz), i.e. kTileElems / nz complex lines.
+int z_rows_per_block(const Dims& d) {
+    int lines = kTileElems / d.nz;
+    if (lines < 1) lines = 1;
+    return 2 * lines;
 }
 
+// z-modes per block of the x kernel: up to 32 consecutive q (256-byte runs), kb/2 lines of nx.
 int x_modes_per_block(const Dims& d) {
-    int kb = 4096 / d.nx;
-    if (kb > 16) kb = 16;
-    kb &= ~1;
+    int kb = 2 * (kTileElems / d.nx);
+    if (kb > 32) kb = 32;
     if (kb < 2) kb = 2;
     return kb;
 }
@@ -463,21 +524,19 @@ int x_modes_per_block(const Dims& d) {
 void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
                       double* const spec[3], const int* gate) {
-    const int rpb = z_rows_per_block(d, ncomp);
+    const int rpb = z_rows_per_block(d);
     const int nrows = d.nx * d.M;
-    const size_t lds = 2ull * ncomp * (rpb / 2) * d.nz * sizeof(double2);
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
     Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
-    hipLaunchKernelGGL(k_rhs_dht_z, dim3((nrows + rpb - 1) / rpb), dim3(kBlock), lds, s, d, pz,
-                       twz, rhs, uu, ncomp, correct, sp, gate, rpb);
+    hipLaunchKernelGGL(k_rhs_dht_z, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s, d,
+                       pz, twz, rhs, uu, correct, sp, gate, rpb);
 }
 
 void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
                   double* const spec[3], int ncomp, const int* gate) {
     const int kb = x_modes_per_block(d);
-    const size_t lds = 2ull * (kb / 2) * d.nx * sizeof(double2);
     Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
-    hipLaunchKernelGGL(k_dht_x, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), lds, s, d,
+    hipLaunchKernelGGL(k_dht_x, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), 0, s, d,
                        px, twx, sp, gate, kb);
 }
 
@@ -492,13 +551,12 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, double* c
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       double* const spec[3], double* const u[3], int ncomp, int add,
                       const int* gate) {
-    const int rpb = z_rows_per_block(d, ncomp);
+    const int rpb = z_rows_per_block(d);
     const int nrows = d.nx * d.M;
-    const size_t lds = 2ull * ncomp * (rpb / 2) * d.nz * sizeof(double2);
     Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
     Ptr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
-    hipLaunchKernelGGL(k_dht_z_out, dim3((nrows + rpb - 1) / rpb), dim3(kBlock), lds, s, d, pz,
-                       twz, sp, uu, ncomp, add, gate, rpb);
+    hipLaunchKernelGGL(k_dht_z_out, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s, d,
+                       pz, twz, sp, uu, add, gate, rpb);
 }
 
 int resid_blocks(const Dims& d) {

@@ -77,7 +77,7 @@ Layout make_layout(const vs_grid& g) {
     L.off_twx = o;    o += align_up((size_t)g.nx * sizeof(double2));
     L.off_twz = o;    o += align_up((size_t)g.nz * sizeof(double2));
     L.off_tri = o;    o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * M * sizeof(double));
-    L.off_part = o;   o += align_up((size_t)kMaxPartialBlocks * kPartialStride * sizeof(double));
+    L.off_part = o;   o += align_up((size_t)kMaxPartialBlocks * kPartialSlots * sizeof(double));
     L.off_prof = o;   o += align_up(2 * (size_t)g.ny * sizeof(double));
     L.off_scal = o;   o += align_up(SC_NSCAL * sizeof(double));
     L.off_istat = o;  o += align_up(IS_NSTAT * sizeof(int));
@@ -378,11 +378,11 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
             const long double PI = 3.14159265358979323846264338327950288L;
             const double beta = (double)(2.0L * cosl(2.0L * PI * pc / grid->nx) +
                                          2.0L * cosl(2.0L * PI * qc / grid->nz) - 6.0L);
-            double* c = &tri[((size_t)pc * hz + qc) * M];
+            const size_t cls = (size_t)pc * hz + qc, ncls = (size_t)hx * hz;
             double prev = 0.0;
             for (int j = 0; j < M; ++j) {
                 prev = 1.0 / (beta - prev);
-                c[j] = prev;
+                tri[(size_t)j * ncls + cls] = prev;
             }
         }
     const double H = (grid->ny - 1) * grid->h;

@@ -58,7 +58,7 @@ struct FftPlan {
 };
 
 constexpr int kMaxPartialBlocks = 1024;
-constexpr int kPartialStride = 8;    // doubles per block partial record
+constexpr int kPartialSlots = 8;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
 
 // ---------------------------------------------------------------- explicit stencils
 void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
