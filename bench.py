@@ -32,28 +32,34 @@ KAPPAS = (0.5, 1.0, 2.0)
 def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
     """Algorithmic HBM bytes of one launch: each input read once, each output written once
     (FP64). Ni counts the interior rows the Poisson kernels touch. The two Poisson right-hand
-    sides differ (vorticity: phi, mu; stream vector: omega), so rhs_dht_z and resid_norm use
-    the mean of the two launches of a step."""
+    sides differ (vorticity: phi, mu; stream vector: omega); their kernels are timed apart."""
     N = nx * ny * nz
     Ni = nx * (ny - 2) * nz
     table = {
         "advance": 48 * N,            # phi, mu, psi_x, psi_y, psi_z in; phi' out
         "va_partials": 8 * N,         # phi in
         "mu": 16 * N,                 # phi in; mu out
-        "rhs_dht_z": 44 * Ni,         # (phi, mu) or omega(3) in; 3 spectral fields out
+        "source": 16 * N + 24 * Ni,   # phi, mu in; S(3) out on the interior rows
+        "rhs_dht_z_omega": 48 * Ni,   # S(3) in; 3 spectral fields out
+        "rhs_dht_z_psi": 48 * Ni,     # omega(3) in; 3 spectral fields out
         "dht_x": 48 * Ni,             # 3 spectral fields in and out
         "tridiag_y": 48 * Ni,         # 3 spectral fields in and out
         "dht_z_out": 48 * Ni,         # 3 spectral fields in; 3 solution fields out
-        "resid_norm": 44 * Ni,        # (phi, mu, omega(3)) or (omega(3), psi(3)) in
+        "resid_norm_omega": 48 * Ni,  # S(3), omega(3) in
+        "resid_norm_psi": 48 * Ni,    # omega(3), psi(3) in
     }
     return table.get(name)
 
 
 def source_hash(kernel: str) -> str:
     """Hash of the source file that holds a kernel, to tie stored counters to the code."""
-    fname = "k_explicit.hip" if kernel in ("advance", "va_partials", "mu") else "k_spectral.hip"
-    with open(os.path.join(ROOT, "paper_2601_05031_amd", "csrc", fname), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    names = (["k_explicit.hip"] if kernel in ("advance", "va_partials", "mu", "source")
+             else ["k_spectral.hip", "fft_reg.h"])
+    h = hashlib.sha256()
+    for fname in names:
+        with open(os.path.join(ROOT, "paper_2601_05031_amd", "csrc", fname), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(kernel: str, workload: str):
@@ -104,6 +110,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -117,6 +125,12 @@ def main():
     from workloads import workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     base = workload("vesicle128", max_cycles=args.max_cycles)
     nx, ny, nz = base.grid.shape
     N = base.grid.N

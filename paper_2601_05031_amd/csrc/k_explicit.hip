@@ -16,12 +16,16 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Node of this thread in a plane grid (blockIdx.x over the (j, k) plane, blockIdx.y = i),
+// with the blocks ordered per XCD so that each XCD sweeps a contiguous range of x-planes.
 __device__ __forceinline__ void plane_index(const Dims& d, int& i, int& j, int& k, bool& ok) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int gx = gridDim.x;
+    const int lb = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
+    i = lb / gx;
+    const int t = (lb - i * gx) * kBlock + threadIdx.x;
     ok = t < d.ny * d.nz;
     j = t / d.nz;
     k = t - j * d.nz;
-    i = blockIdx.y;
 }
 
 struct Nbr {
@@ -152,29 +156,34 @@ __global__ __launch_bounds__(kBlock) void k_mu(const double* __restrict__ phi,
 }
 
 // Block partials of sum_w phi and sum_w [(eps/2)|D phi|^2 + (phi^2-1)^2/(4 eps)]
-// (trapezoid weights w = 1/2 on the wall rows). Fixed grid, grid-stride: deterministic.
+// (trapezoid weights w = 1/2 on the wall rows). Each thread owns one (j, k) and walks ci
+// consecutive x-planes (the i-1 plane it reads was the previous iteration's centre, still in
+// cache); the partial of block b is written to slot b: fixed order, deterministic.
 __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict__ phi, Dims d,
-                                                       double eps,
+                                                       double eps, SlabGrid sg,
                                                        double* __restrict__ partials) {
     __shared__ double sh[2 * 16];
-    const int N = d.nx * d.ny * d.nz;
-    const int plane = d.ny * d.nz;
+    const int nb = sg.gx * sg.gi;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int bi = lb / sg.gx;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
     double acc[2] = {0.0, 0.0};
-    const double inv4e = 0.25 / eps;
-    for (int t = blockIdx.x * kBlock + threadIdx.x; t < N; t += gridDim.x * kBlock) {
-        const int i = t / plane;
-        const int r = t - i * plane;
-        const int j = r / d.nz;
-        const int k = r - j * d.nz;
-        const Nbr n = neighbours_mirror(d, i, j, k);
-        const double p = phi[n.c];
+    if (t < d.ny * d.nz) {
+        const int j = t / d.nz;
+        const int k = t - j * d.nz;
         const double w = (j == 0 || j == d.ny - 1) ? 0.5 : 1.0;
-        const double dx = (phi[n.xp] - phi[n.xm]) * d.inv_2h;
-        const double dy = (phi[n.yp] - phi[n.ym]) * d.inv_2h;
-        const double dz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
-        const double q = p * p - 1.0;
-        acc[0] += w * p;
-        acc[1] += w * (0.5 * eps * (dx * dx + dy * dy + dz * dz) + q * q * inv4e);
+        const double inv4e = 0.25 / eps;
+        const int i1 = min(d.nx, (bi + 1) * sg.ci);
+        for (int i = bi * sg.ci; i < i1; ++i) {
+            const Nbr n = neighbours_mirror(d, i, j, k);
+            const double p = phi[n.c];
+            const double dx = (phi[n.xp] - phi[n.xm]) * d.inv_2h;
+            const double dy = (phi[n.yp] - phi[n.ym]) * d.inv_2h;
+            const double dz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
+            const double q = p * p - 1.0;
+            acc[0] += w * p;
+            acc[1] += w * (0.5 * eps * (dx * dx + dy * dy + dz * dz) + q * q * inv4e);
+        }
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
@@ -216,6 +225,26 @@ __global__ __launch_bounds__(kBlock) void k_finalize_va(const double* __restrict
     if (!isfinite(V) || !isfinite(A)) istat[IS_FLAGS] |= ST_NONFINITE;
 }
 
+// Vorticity source S = (1/eta) D phi x D mu (main text eq. (5b)) at the interior rows, stored
+// so that the transform and the residual of the vorticity solve read it as a plain field.
+__global__ __launch_bounds__(kBlock) void k_source(const double* __restrict__ phi,
+                                                  const double* __restrict__ mu, Dims d,
+                                                  double inv_eta, double* __restrict__ sx,
+                                                  double* __restrict__ sy, double* __restrict__ sz) {
+    int i, j, k;
+    bool ok;
+    plane_index(d, i, j, k, ok);
+    if (!ok || j == 0 || j == d.ny - 1) return;
+    const Nbr n = neighbours_mirror(d, i, j, k);
+    const double fx = (phi[n.xp] - phi[n.xm]) * d.inv_2h, fy = (phi[n.yp] - phi[n.ym]) * d.inv_2h,
+                 fz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
+    const double mx = (mu[n.xp] - mu[n.xm]) * d.inv_2h, my = (mu[n.yp] - mu[n.ym]) * d.inv_2h,
+                 mz = (mu[n.zp] - mu[n.zm]) * d.inv_2h;
+    sx[n.c] = (fy * mz - fz * my) * inv_eta;
+    sy[n.c] = (fz * mx - fx * mz) * inv_eta;
+    sz[n.c] = (fx * my - fy * mx) * inv_eta;
+}
+
 // dst[(i, j, k)] = prof[j]: the no-body channel fields as initial guesses and wall rows.
 __global__ __launch_bounds__(kBlock) void k_fill_profile(double* __restrict__ dst, Dims d,
                                                         const double* __restrict__ prof) {
@@ -250,15 +279,15 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
 }
 
 int va_partial_blocks(const Dims& d) {
-    const long N = (long)d.nx * d.ny * d.nz;
-    long b = (N + kBlock - 1) / kBlock;
-    if (b > kMaxPartialBlocks) b = kMaxPartialBlocks;
-    return (int)b;
+    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, 1024);
+    return g.gx * g.gi;
 }
 
 void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
-                        double* partials, int nblocks) {
-    hipLaunchKernelGGL(k_va_partials, dim3(nblocks), dim3(kBlock), 0, s, phi, d, eps, partials);
+                        double* partials) {
+    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, 1024);
+    hipLaunchKernelGGL(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
+                       partials);
 }
 
 void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
@@ -276,6 +305,12 @@ void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, cons
 
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof) {
     hipLaunchKernelGGL(k_fill_profile, plane_grid(d), dim3(kBlock), 0, s, dst, d, prof);
+}
+
+void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
+                   double inv_eta, double* const src[3]) {
+    hipLaunchKernelGGL(k_source, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0],
+                       src[1], src[2]);
 }
 
 void launch_reset_stats(hipStream_t s, double* scal, int* istat) {

@@ -18,6 +18,7 @@
 // (line a) + i (line b), then H_a(p) = Re A_p - Im A_p with A_p = (Z_p + conj Z_{n-p})/2,
 // and likewise for b. The FFT is a Stockham autosort transform in LDS with radix-4/2/3
 // passes (line lengths 2^a 3^b), twiddles from a table exp(-2 pi i m/n).
+#include "fft_reg.h"
 #include "vs_internal.h"
 
 namespace vs {
@@ -138,60 +139,8 @@ __device__ __forceinline__ void set_part(double2* slot, int part, double v) {
     reinterpret_cast<double*>(slot)[part] = v;
 }
 
-// Right-hand side b at interior node (i, j, k), 1 <= j <= ny-2.
-__device__ __forceinline__ void rhs_at(const RhsArgs& a, const Dims& d, int i, int j, int k,
-                                       int ncomp, double (&b)[3]) {
-    const int c0 = node(d, i, j, k);
-    if (a.mode == RHS_VORT) {
-        const int ip = (i + 1 == d.nx) ? 0 : i + 1;
-        const int im = (i == 0) ? d.nx - 1 : i - 1;
-        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
-        const int km = (k == 0) ? d.nz - 1 : k - 1;
-        const int xp = node(d, ip, j, k), xm = node(d, im, j, k);
-        const int yp = c0 + d.nz, ym = c0 - d.nz;
-        const int zp = c0 - k + kp, zm = c0 - k + km;
-        const double* f = a.phi;
-        const double* m = a.mu;
-        const double fx = (f[xp] - f[xm]) * d.inv_2h, fy = (f[yp] - f[ym]) * d.inv_2h,
-                     fz = (f[zp] - f[zm]) * d.inv_2h;
-        const double mx = (m[xp] - m[xm]) * d.inv_2h, my = (m[yp] - m[ym]) * d.inv_2h,
-                     mz = (m[zp] - m[zm]) * d.inv_2h;
-        b[0] = (fy * mz - fz * my) * a.inv_eta;
-        b[1] = (fz * mx - fx * mz) * a.inv_eta;
-        b[2] = (fx * my - fy * mx) * a.inv_eta;
-        return;
-    }
-    const double sg = (a.mode == RHS_NEGW) ? -1.0 : 1.0;
-    for (int c = 0; c < ncomp; ++c) b[c] = sg * a.f[c][c0];
-}
-
-// Component c of the right-hand side at interior node (i, j, k).
-__device__ __forceinline__ double rhs_comp(const RhsArgs& a, const Dims& d, int i, int j, int k,
-                                           int c) {
-    const int c0 = node(d, i, j, k);
-    if (a.mode == RHS_VORT) {
-        const int ip = (i + 1 == d.nx) ? 0 : i + 1;
-        const int im = (i == 0) ? d.nx - 1 : i - 1;
-        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
-        const int km = (k == 0) ? d.nz - 1 : k - 1;
-        const double* f = a.phi;
-        const double* m = a.mu;
-        // (D phi x D mu)_c needs the two derivative directions other than c
-        double f1, f2, m1, m2;
-        if (c == 0) {        // y, z
-            f1 = f[c0 + d.nz] - f[c0 - d.nz]; m1 = m[c0 + d.nz] - m[c0 - d.nz];
-            f2 = f[c0 - k + kp] - f[c0 - k + km]; m2 = m[c0 - k + kp] - m[c0 - k + km];
-        } else if (c == 1) { // z, x
-            f1 = f[c0 - k + kp] - f[c0 - k + km]; m1 = m[c0 - k + kp] - m[c0 - k + km];
-            f2 = f[node(d, ip, j, k)] - f[node(d, im, j, k)];
-            m2 = m[node(d, ip, j, k)] - m[node(d, im, j, k)];
-        } else {             // x, y
-            f1 = f[node(d, ip, j, k)] - f[node(d, im, j, k)];
-            m1 = m[node(d, ip, j, k)] - m[node(d, im, j, k)];
-            f2 = f[c0 + d.nz] - f[c0 - d.nz]; m2 = m[c0 + d.nz] - m[c0 - d.nz];
-        }
-        return ((f1 * d.inv_2h) * (m2 * d.inv_2h) - (f2 * d.inv_2h) * (m1 * d.inv_2h)) * a.inv_eta;
-    }
+// Component c of the right-hand side b at an interior node offset c0.
+__device__ __forceinline__ double rhs_val(const RhsArgs& a, int c, int c0) {
     const double v = a.f[c][c0];
     return (a.mode == RHS_NEGW) ? -v : v;
 }
@@ -245,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_dht_z(Dims d, FftPlan pz,
         if (r < nrows) {
             const int i = r / d.M;
             const int j = 1 + (r - i * d.M);
-            b = rhs_comp(rhs, d, i, j, k, c);
+            b = rhs_val(rhs, c, node(d, i, j, k));
             b -= correct ? lap_interior(uc, d, i, j, k) : wall_term(uc, d, i, j, k);
         }
         set_part(&A[(lr >> 1) * n + k], lr & 1, b);
@@ -292,87 +241,103 @@ __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
     }
 }
 
-// tridiag_y: one thread per (p, q), component blockIdx.y. Solves
+// tridiag_y: two lanes per mode (p, q) of component blockIdx.y solve
 //   U_{j-1} + beta U_j + U_{j+1} = scale * B_j,  j = 1..M,  U_0 = U_{M+1} = 0,
-// beta = 2 cos(2 pi p/nx) + 2 cos(2 pi q/nz) - 6, with the forward-elimination pivots
-// c'_j = 1/(beta - c'_{j-1}) read from a table tri[(j-1) * nclass + class], class =
-// min(p, nx-p) * (nz/2+1) + min(q, nz-q): lanes with consecutive q read consecutive (or
-// reversed consecutive) entries. In place. Rows are processed in chunks of CH with the next
-// chunk's loads issued before the current chunk's dependent recurrence runs.
-__global__ __launch_bounds__(kBlock) void k_tridiag_y(Dims d, const double* __restrict__ tri,
-                                                     Ptr3 spec, const int* gate, double scale) {
+// beta = 2 cos(2 pi p/nx) + 2 cos(2 pi q/nz) - 6, by a twisted factorisation: the even lane
+// eliminates rows 1..m downwards (pivots c'_s = 1/(beta - c'_{s-1}), rows read as
+// U_j + c'_j U_{j+1} = d'_j), the odd lane rows M..m+1 upwards with the same pivots counted
+// from the bottom (the matrix is symmetric Toeplitz), the two meet in a 2x2 system at rows
+// m, m+1 (values exchanged by a lane shuffle), then each back-substitutes away from the
+// middle. Pivots come from tri[s * nclass + class]; in place; loads run one chunk ahead.
+__global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restrict__ tri,
+                                                 Ptr3 spec, const int* gate, double scale) {
     if (gate && *gate) return;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= d.nx * d.nz) return;
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    const int pair = t >> 1;
+    const int half = t & 1;
+    const bool act = pair < d.nx * d.nz;
     const int c = blockIdx.y;
-    const int p = t / d.nz;
-    const int q = t - p * d.nz;
+    const int pp = act ? pair : 0;
+    const int p = pp / d.nz;
+    const int q = pp - p * d.nz;
     const int pc = min(p, d.nx - p);
     const int qc = min(q, d.nz - q);
     const size_t ncls = (size_t)(d.nx / 2 + 1) * (d.nz / 2 + 1);
     const double* cp = tri + (size_t)(pc * (d.nz / 2 + 1) + qc);
     double* col = spec.p[c] + (size_t)p * d.ny * d.nz + q;
-    const size_t sj = d.nz;
+    const long sj = d.nz;
     const int M = d.M;
+    const int m = (M + 1) / 2;
+    const int nr = act ? (half ? M - m : m) : 0;      // rows eliminated by this lane
+    // row of step s (s = 0 at the wall end), and its address step
+    const int j0 = half ? M : 1;
+    const long dj = half ? -sj : sj;
+    double* base = col + (long)j0 * sj;
     constexpr int CH = 8;
-    double bv[CH], cv[CH];
-    // forward elimination, rows 1..M
+    double fv[CH], cv[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-        const int j = 1 + u;
-        bv[u] = (j <= M) ? col[j * sj] : 0.0;
-        cv[u] = (j <= M) ? cp[(size_t)(j - 1) * ncls] : 0.0;
+        fv[u] = (u < nr) ? base[u * dj] : 0.0;
+        cv[u] = (u < nr) ? cp[(size_t)u * ncls] : 0.0;
     }
-    double dprev = 0.0;
-    for (int j0 = 1; j0 <= M; j0 += CH) {
-        double nb[CH], nc[CH];
+    double acc = 0.0, clast = 0.0;
+    for (int s0 = 0; s0 < nr; s0 += CH) {
+        double nf[CH], nc[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const int j = j0 + CH + u;
-            nb[u] = (j <= M) ? col[j * sj] : 0.0;
-            nc[u] = (j <= M) ? cp[(size_t)(j - 1) * ncls] : 0.0;
+            const int sn = s0 + CH + u;
+            nf[u] = (sn < nr) ? base[sn * dj] : 0.0;
+            nc[u] = (sn < nr) ? cp[(size_t)sn * ncls] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const int j = j0 + u;
-            if (j <= M) {
-                dprev = cv[u] * (scale * bv[u] - dprev);
-                col[j * sj] = dprev;
+            if (s0 + u < nr) {
+                acc = cv[u] * (scale * fv[u] - acc);
+                clast = cv[u];
+                base[(s0 + u) * dj] = acc;
             }
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            bv[u] = nb[u];
+            fv[u] = nf[u];
             cv[u] = nc[u];
         }
     }
-    // back substitution, rows M..1
+    // interface: top lane holds (d'_m, c'_m), bottom lane (g'_{m+1}, e'_{m+1}); a lane with no
+    // rows contributes (0, 0), i.e. the wall value U = 0.
+    const double oacc = __shfl_xor(acc, 1, 64);
+    const double oc = __shfl_xor(clast, 1, 64);
+    if (!act || nr == 0) return;
+    const double dm = half ? oacc : acc, cm = half ? oc : clast;
+    const double gm = half ? acc : oacc, em = half ? clast : oc;
+    const double Um = (dm - cm * gm) / (1.0 - cm * em);
+    double unext = half ? (gm - em * Um) : Um;        // U at this lane's last row
+    base[(nr - 1) * dj] = unext;
+    // back substitution from row s = nr-2 towards the wall: U_s = d'_s - c'_s U_{s+1}
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-        const int j = M - u;
-        bv[u] = (j >= 1) ? col[j * sj] : 0.0;
-        cv[u] = (j >= 1) ? cp[(size_t)(j - 1) * ncls] : 0.0;
+        const int sn = nr - 2 - u;
+        fv[u] = (sn >= 0) ? base[sn * dj] : 0.0;
+        cv[u] = (sn >= 0) ? cp[(size_t)(sn >= 0 ? sn : 0) * ncls] : 0.0;
     }
-    double unext = 0.0;
-    for (int j0 = M; j0 >= 1; j0 -= CH) {
-        double nb[CH], nc[CH];
+    for (int s0 = nr - 2; s0 >= 0; s0 -= CH) {
+        double nf[CH], nc[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const int j = j0 - CH - u;
-            nb[u] = (j >= 1) ? col[j * sj] : 0.0;
-            nc[u] = (j >= 1) ? cp[(size_t)(j - 1) * ncls] : 0.0;
+            const int sn = s0 - CH - u;
+            nf[u] = (sn >= 0) ? base[sn * dj] : 0.0;
+            nc[u] = (sn >= 0) ? cp[(size_t)(sn >= 0 ? sn : 0) * ncls] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const int j = j0 - u;
-            if (j >= 1) {
-                unext = bv[u] - cv[u] * unext;
-                col[j * sj] = unext;
+            if (s0 - u >= 0) {
+                unext = fv[u] - cv[u] * unext;
+                base[(s0 - u) * dj] = unext;
             }
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            bv[u] = nb[u];
+            fv[u] = nf[u];
             cv[u] = nc[u];
         }
     }
@@ -417,34 +382,289 @@ __global__ __launch_bounds__(kBlock) void k_dht_z_out(Dims d, FftPlan pz,
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Two-pass register transforms for line lengths n = B * A (B in {8, 16}; A in {3, 4, 6, 8,
+// 12, 16}). One 64-lane wave per block handles L = 64 / A complex lines (2L real lines):
+//  pass 1: item (line, k1), k1 < A: DFT_B over k2 of x[k1 + A k2] loaded from global memory,
+//          twiddle exp(-2 pi i k1 p2 / n), store Y[line][p2][k1] in LDS (padded rows);
+//  pass 2: item (line, s), s < B/2, owns the mode pair p2 = {s, B - s} ({0, B/2} for s = 0):
+//          DFT_A over k1 for both, giving X[p2 + B p1]; every X_p and its partner X_{n-p}
+//          sit in the same item, so both Hartley values are formed in registers and stored.
+template <int B, int A>
+struct TwoPass {
+    static constexpr int N = B * A;
+    static constexpr int L = (64 / A) > 0 ? (64 / A) : 1;
+    static constexpr int RS = A + 1;             // padded row of Y
+    static constexpr int LS = B * RS + 1;        // padded line of Y
+    static constexpr int LDS = L * LS;           // double2 elements
+};
+
+// Prep: Pre prep(line) (per-line row offsets, computed once per item).
+// Loader: double2 load(pre, k1, k2) -> (line a value, line b value) at position k1 + A k2.
+// Storer: void store(pre, p, ha, hb).
+template <int B, int A, bool LINE_FAST, class Prep, class Load, class Store>
+__device__ __forceinline__ void two_pass_hartley(double2* Y, const double2* __restrict__ tw,
+                                                 Prep prep, Load load, Store store) {
+    using P = TwoPass<B, A>;
+    constexpr int L = P::L;
+#pragma unroll 1
+    for (int it = threadIdx.x; it < L * A; it += 64) {
+        const int line = LINE_FAST ? (it % L) : (it / A);
+        const int k1 = LINE_FAST ? (it / L) : (it % A);
+        const auto pre = prep(line);
+        double2 x[B];
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) x[k2] = load(pre, k1, k2);
+        fftr::DFT<B>::run(x);
+#pragma unroll
+        for (int p2 = 1; p2 < B; ++p2) x[p2] = cmul(x[p2], tw[k1 * p2]);
+        double2* Yl = Y + line * P::LS + k1;
+#pragma unroll
+        for (int p2 = 0; p2 < B; ++p2) Yl[p2 * P::RS] = x[p2];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int it = threadIdx.x; it < L * (B / 2); it += 64) {
+        const int line = LINE_FAST ? (it % L) : (it / (B / 2));
+        const int s = LINE_FAST ? (it / L) : (it % (B / 2));
+        const auto pre = prep(line);
+        const int pa = s;                          // s = 0 gives p2 = 0
+        const int pb = (s == 0) ? B / 2 : B - s;
+        double2 xa[A], xb[A];
+        const double2* Ya = Y + line * P::LS + pa * P::RS;
+        const double2* Yb = Y + line * P::LS + pb * P::RS;
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            xa[k1] = Ya[k1];
+            xb[k1] = Yb[k1];
+        }
+        fftr::DFT<A>::run(xa);
+        fftr::DFT<A>::run(xb);
+#pragma unroll
+        for (int p1 = 0; p1 < A; ++p1) {
+            const double2 za = xa[p1];
+            const double2 ma = (s == 0) ? xa[(A - p1) % A] : xb[A - 1 - p1];
+            store(pre, pa + B * p1, 0.5 * (za.x + ma.x - za.y + ma.y), 0.5 * (za.x - ma.x + za.y + ma.y));
+            const double2 zb = xb[p1];
+            const double2 mb = (s == 0) ? xb[A - 1 - p1] : xa[A - 1 - p1];
+            store(pre, pb + B * p1, 0.5 * (zb.x + mb.x - zb.y + mb.y), 0.5 * (zb.x - mb.x + zb.y + mb.y));
+        }
+    }
+}
+
+// Node offsets of the first z node of interior rows r and r+1 (r = i*M + j-1), -1 if past
+// the last row.
+struct RowPair {
+    int a, b;
+};
+__device__ __forceinline__ int row_base(const Dims& d, int r, int nrows) {
+    if (r >= nrows) return -1;
+    const int i = r / d.M;
+    return node(d, i, 1 + (r - i * d.M), 0);
+}
+
+// Component c of the right-hand side minus the wall terms (correct = 0) or minus L_h u
+// (correct = 1), for the z index k of an interior row with node offset rb = node(i, j, 0) and
+// x-neighbour row offsets xpb, xmb.
+__device__ __forceinline__ double rhs_row(const RhsArgs& a, const Dims& d, const double* __restrict__ uc,
+                                          int c, int correct, int rb, int xpb, int xmb, int j, int k) {
+    const int c0 = rb + k;
+    double b = rhs_val(a, c, c0);
+    if (correct) {
+        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+        const int km = (k == 0) ? d.nz - 1 : k - 1;
+        b -= (uc[xpb + k] + uc[xmb + k] + uc[c0 + d.nz] + uc[c0 - d.nz] + uc[rb + kp] + uc[rb + km] -
+              6.0 * uc[c0]) * d.inv_h2;
+    } else {
+        double w = 0.0;
+        if (j == 1) w += uc[c0 - d.nz];
+        if (j == d.M) w += uc[c0 + d.nz];
+        b -= w * d.inv_h2;
+    }
+    return b;
+}
+
+// rhs_dht_z, two-pass form: block = (2L consecutive interior rows, component c), blocks
+// ordered per XCD. The right-hand side (a stencil for the vorticity source, the wall terms
+// or the residual) is first evaluated with lane-consecutive z indices (coalesced) into the
+// LDS tile, then pass 1 reads its strided inputs from there.
+template <int B, int A>
+__global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict__ tw,
+                                              RhsArgs rhs, CPtr3 u, int correct, Ptr3 spec,
+                                              const int* gate) {
+    if (gate && *gate) return;
+    using P = TwoPass<B, A>;
+    constexpr int N = P::N;
+    constexpr int L = P::L;
+    static_assert(L * N <= P::LDS, "input tile must fit in the exchange buffer");
+    static_assert(L * A <= 64, "one pass-1 round per lane");
+    __shared__ double2 Y[P::LDS];
+    const int gx = gridDim.x;
+    const int lb = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
+    const int c = lb / gx;
+    const int bx = lb - c * gx;
+    const int nrows = d.nx * d.M;
+    const int r0 = bx * 2 * L;
+    const double* uc = u.p[c];
+    double* sc = spec.p[c];
+#pragma unroll 4
+    for (int lr = 0; lr < 2 * L; ++lr) {
+        const int r = r0 + lr;
+        double2* row = &Y[(lr >> 1) * N];
+        if (r < nrows) {
+            const int i = r / d.M;
+            const int j = 1 + (r - i * d.M);
+            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+            const int im = (i == 0) ? d.nx - 1 : i - 1;
+            const int rb = node(d, i, j, 0), xpb = node(d, ip, j, 0), xmb = node(d, im, j, 0);
+#pragma unroll
+            for (int k = threadIdx.x; k < N; k += 64)
+                set_part(&row[k], lr & 1, rhs_row(rhs, d, uc, c, correct, rb, xpb, xmb, j, k));
+        } else {
+#pragma unroll
+            for (int k = threadIdx.x; k < N; k += 64) set_part(&row[k], lr & 1, 0.0);
+        }
+    }
+    __syncthreads();
+    double2 xin[B];
+    const int it = threadIdx.x;
+    const bool act = it < L * A;
+    const int line = act ? it / A : 0, k1 = act ? it % A : 0;
+    if (act) {
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) xin[k2] = Y[line * N + k1 + A * k2];
+    }
+    __syncthreads();
+    auto prep = [&](int ln) -> RowPair {
+        return RowPair{row_base(d, r0 + 2 * ln, nrows), row_base(d, r0 + 2 * ln + 1, nrows)};
+    };
+    auto load = [&](const RowPair&, int, int k2) -> double2 { return xin[k2]; };
+    auto store = [&](const RowPair& rp, int p, double ha, double hb) {
+        if (rp.a >= 0) sc[rp.a + p] = ha;
+        if (rp.b >= 0) sc[rp.b + p] = hb;
+    };
+    two_pass_hartley<B, A, false>(Y, tw, prep, load, store);
+}
+
+// dht_x, two-pass form: block = (2L consecutive z-modes q, interior row j, component c);
+// lines are the q-pairs (q, q+1), read and written as one 16-byte value.
+template <int B, int A>
+__global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ tw, Ptr3 spec,
+                                          const int* gate) {
+    if (gate && *gate) return;
+    using P = TwoPass<B, A>;
+    __shared__ double2 Y[P::LDS];
+    const int c = blockIdx.z;
+    const int j = 1 + blockIdx.y;
+    const int q0 = blockIdx.x * 2 * P::L;
+    double* s = spec.p[c];
+    const int pstride = d.ny * d.nz;
+    auto prep = [&](int line) -> int {
+        const int q = q0 + 2 * line;
+        return q < d.nz ? j * d.nz + q : -1;
+    };
+    auto load = [&](int o, int k1, int k2) -> double2 {
+        if (o < 0) return make_double2(0.0, 0.0);
+        return *reinterpret_cast<const double2*>(s + o + (k1 + A * k2) * pstride);
+    };
+    auto store = [&](int o, int p, double ha, double hb) {
+        if (o >= 0) *reinterpret_cast<double2*>(s + o + p * pstride) = make_double2(ha, hb);
+    };
+    two_pass_hartley<B, A, true>(Y, tw, prep, load, store);
+}
+
+// dht_z_out, two-pass form: block = (2L consecutive interior rows, component c).
+template <int B, int A>
+__global__ __launch_bounds__(64) void k_hz_out(Dims d, const double2* __restrict__ tw, Ptr3 spec,
+                                              Ptr3 u, int add, const int* gate) {
+    if (gate && *gate) return;
+    using P = TwoPass<B, A>;
+    __shared__ double2 Y[P::LDS];
+    const int c = blockIdx.y;
+    const int nrows = d.nx * d.M;
+    const int r0 = blockIdx.x * 2 * P::L;
+    const double* sc = spec.p[c];
+    double* uc = u.p[c];
+    auto prep = [&](int line) -> RowPair {
+        return RowPair{row_base(d, r0 + 2 * line, nrows), row_base(d, r0 + 2 * line + 1, nrows)};
+    };
+    auto load = [&](const RowPair& rp, int k1, int k2) -> double2 {
+        const int k = k1 + A * k2;
+        return make_double2(rp.a >= 0 ? sc[rp.a + k] : 0.0, rp.b >= 0 ? sc[rp.b + k] : 0.0);
+    };
+    auto store = [&](const RowPair& rp, int p, double ha, double hb) {
+        if (rp.a >= 0) {
+            double* dst = uc + rp.a + p;
+            *dst = add ? *dst + ha : ha;
+        }
+        if (rp.b >= 0) {
+            double* dst = uc + rp.b + p;
+            *dst = add ? *dst + hb : hb;
+        }
+    };
+    two_pass_hartley<B, A, false>(Y, tw, prep, load, store);
+}
+
+// Two-pass shape (B, A) for a line length, or (0, 0) if the LDS Stockham path is used.
+void two_pass_shape(int n, int& B, int& A) {
+    B = 16;
+    switch (n) {
+        case 32: B = 8; A = 4; return;
+        case 48: A = 3; return;
+        case 64: A = 4; return;
+        case 96: A = 6; return;
+        case 128: A = 8; return;
+        case 192: A = 12; return;
+        case 256: A = 16; return;
+        default: B = 0; A = 0; return;
+    }
+}
+
+#define VS_TWO_PASS_CASES(X) X(8, 4) X(16, 3) X(16, 4) X(16, 6) X(16, 8) X(16, 12) X(16, 16)
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return v;
 }
 
-// resid_norm: block partials of sum (b - L_h u)_c^2 and sum b~_c^2 over the interior.
+// resid_norm: block partials of sum (b - L_h u)_c^2 and sum b~_c^2 over the interior. Each
+// thread owns one interior (j, k) and walks ci consecutive x-planes; blocks ordered per XCD.
 __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr3 u, int ncomp,
-                                                      double* __restrict__ partials,
+                                                      SlabGrid sg, double* __restrict__ partials,
                                                       const int* gate) {
     if (gate && *gate) return;
     __shared__ double sh[6 * 4];
-    const int nint = d.nx * d.M * d.nz;
-    const int plane = d.M * d.nz;
+    const int nb = sg.gx * sg.gi;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int bi = lb / sg.gx;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = blockIdx.x * kBlock + threadIdx.x; t < nint; t += gridDim.x * kBlock) {
-        const int i = t / plane;
-        const int rem = t - i * plane;
-        const int jj = rem / d.nz;
-        const int k = rem - jj * d.nz;
+    if (t < d.M * d.nz) {
+        const int jj = t / d.nz;
+        const int k = t - jj * d.nz;
         const int j = jj + 1;
-        double b[3] = {0.0, 0.0, 0.0};
-        rhs_at(rhs, d, i, j, k, ncomp, b);
-        for (int c = 0; c < ncomp; ++c) {
-            const double r = b[c] - lap_interior(u.p[c], d, i, j, k);
-            const double bt = b[c] - wall_term(u.p[c], d, i, j, k);
-            acc[c] += r * r;
-            acc[3 + c] += bt * bt;
+        const int i1 = min(d.nx, (bi + 1) * sg.ci);
+#pragma unroll 2
+        for (int i = bi * sg.ci; i < i1; ++i) {
+            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+            const int im = (i == 0) ? d.nx - 1 : i - 1;
+            const int rb = node(d, i, j, 0), xpb = node(d, ip, j, 0), xmb = node(d, im, j, 0);
+            const int c0 = rb + k;
+            const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+            const int km = (k == 0) ? d.nz - 1 : k - 1;
+            for (int c = 0; c < ncomp; ++c) {
+                const double* uc = u.p[c];
+                const double b = rhs_val(rhs, c, c0);
+                const double ylo = uc[c0 - d.nz], yhi = uc[c0 + d.nz];
+                const double w = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
+                const double lap = (uc[xpb + k] + uc[xmb + k] + ylo + yhi + uc[rb + kp] +
+                                    uc[rb + km] - 6.0 * uc[c0]) * d.inv_h2;
+                const double r = b - lap;
+                const double bt = b - w * d.inv_h2;
+                acc[c] += r * r;
+                acc[3 + c] += bt * bt;
+            }
         }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -524,18 +744,40 @@ int x_modes_per_block(const Dims& d) {
 void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
                       double* const spec[3], const int* gate) {
-    const int rpb = z_rows_per_block(d);
     const int nrows = d.nx * d.M;
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
     Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
+    int B, A;
+    two_pass_shape(d.nz, B, A);
+#define VS_CASE(b, a)                                                                          \
+    if (B == b && A == a) {                                                                    \
+        const int rows = 2 * TwoPass<b, a>::L;                                                 \
+        hipLaunchKernelGGL((k_rhs_hz<b, a>), dim3((nrows + rows - 1) / rows, ncomp), dim3(64), \
+                           0, s, d, twz, rhs, uu, correct, sp, gate);                          \
+        return;                                                                                \
+    }
+    VS_TWO_PASS_CASES(VS_CASE)
+#undef VS_CASE
+    const int rpb = z_rows_per_block(d);
     hipLaunchKernelGGL(k_rhs_dht_z, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s, d,
                        pz, twz, rhs, uu, correct, sp, gate, rpb);
 }
 
 void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
                   double* const spec[3], int ncomp, const int* gate) {
-    const int kb = x_modes_per_block(d);
     Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
+    int B, A;
+    two_pass_shape(d.nx, B, A);
+#define VS_CASE(b, a)                                                                          \
+    if (B == b && A == a) {                                                                    \
+        const int qs = 2 * TwoPass<b, a>::L;                                                   \
+        hipLaunchKernelGGL((k_hx<b, a>), dim3((d.nz + qs - 1) / qs, d.M, ncomp), dim3(64), 0,  \
+                           s, d, twx, sp, gate);                                               \
+        return;                                                                                \
+    }
+    VS_TWO_PASS_CASES(VS_CASE)
+#undef VS_CASE
+    const int kb = x_modes_per_block(d);
     hipLaunchKernelGGL(k_dht_x, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), 0, s, d,
                        px, twx, sp, gate, kb);
 }
@@ -544,33 +786,43 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, double* c
                       int ncomp, const int* gate) {
     Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
-    hipLaunchKernelGGL(k_tridiag_y, dim3((d.nx * d.nz + kBlock - 1) / kBlock, ncomp),
-                       dim3(kBlock), 0, s, d, tri, sp, gate, scale);
+    const int threads = 2 * d.nx * d.nz;
+    hipLaunchKernelGGL(k_tridiag_y, dim3((threads + 63) / 64, ncomp), dim3(64), 0, s, d, tri, sp,
+                       gate, scale);
 }
 
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       double* const spec[3], double* const u[3], int ncomp, int add,
                       const int* gate) {
-    const int rpb = z_rows_per_block(d);
     const int nrows = d.nx * d.M;
     Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
     Ptr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
+    int B, A;
+    two_pass_shape(d.nz, B, A);
+#define VS_CASE(b, a)                                                                          \
+    if (B == b && A == a) {                                                                    \
+        const int rows = 2 * TwoPass<b, a>::L;                                                 \
+        hipLaunchKernelGGL((k_hz_out<b, a>), dim3((nrows + rows - 1) / rows, ncomp), dim3(64), \
+                           0, s, d, twz, sp, uu, add, gate);                                   \
+        return;                                                                                \
+    }
+    VS_TWO_PASS_CASES(VS_CASE)
+#undef VS_CASE
+    const int rpb = z_rows_per_block(d);
     hipLaunchKernelGGL(k_dht_z_out, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s, d,
                        pz, twz, sp, uu, add, gate, rpb);
 }
 
 int resid_blocks(const Dims& d) {
-    const long nint = (long)d.nx * d.M * d.nz;
-    long b = (nint + kBlock - 1) / kBlock;
-    if (b > kMaxPartialBlocks) b = kMaxPartialBlocks;
-    return (int)b;
+    const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
+    return g.gx * g.gi;
 }
 
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
-                       const double* const u[3], int ncomp, double* partials, int nblocks,
-                       const int* gate) {
+                       const double* const u[3], int ncomp, double* partials, const int* gate) {
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
-    hipLaunchKernelGGL(k_resid_norm, dim3(nblocks), dim3(kBlock), 0, s, d, rhs, uu, ncomp,
+    const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
+    hipLaunchKernelGGL(k_resid_norm, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, rhs, uu, ncomp, g,
                        partials, gate);
 }
 

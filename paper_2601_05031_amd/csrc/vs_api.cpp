@@ -39,12 +39,16 @@ vs_status fail(vs_status code, const char* fmt, ...) {
 
 // Kernel classes for the event timer.
 enum KClass {
-    K_ADVANCE, K_VA_PARTIALS, K_FINALIZE_VA, K_MU, K_RHS_DHT_Z, K_DHT_X, K_TRIDIAG_Y,
-    K_DHT_Z_OUT, K_RESID_NORM, K_CHECK, K_FILL, K_RESET, K_NCLASS
+    K_ADVANCE, K_VA_PARTIALS, K_FINALIZE_VA, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
+    K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI, K_RESID_FIELD,
+    K_CHECK, K_FILL, K_RESET, K_NCLASS
 };
-const char* kClassNames[K_NCLASS] = {"advance",   "va_partials", "finalize_va", "mu",
-                                     "rhs_dht_z", "dht_x",       "tridiag_y",   "dht_z_out",
-                                     "resid_norm", "check",      "fill_profile", "reset_stats"};
+const char* kClassNames[K_NCLASS] = {
+    "advance", "va_partials", "finalize_va", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
+    "rhs_dht_z_field", "dht_x", "tridiag_y", "dht_z_out", "resid_norm_omega", "resid_norm_psi",
+    "resid_norm_field", "check", "fill_profile", "reset_stats"};
+// Which solve a Poisson call belongs to (selects the timer classes).
+enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -62,6 +66,7 @@ bool fft_plan(int n, FftPlan* pl) {
 struct Layout {
     size_t off_fields;      // 9 fields: phi(2), mu, omega(3), psi(3)
     size_t off_spec;        // 3 spectral scratch fields
+    size_t off_src;         // 3 fields: the vorticity source S of the current step
     size_t off_twx, off_twz, off_tri, off_part, off_prof, off_scal, off_istat;
     size_t total;
 };
@@ -74,6 +79,7 @@ Layout make_layout(const vs_grid& g) {
     size_t o = 0;
     L.off_fields = o; o += 9 * fb;
     L.off_spec = o;   o += 3 * fb;
+    L.off_src = o;    o += 3 * fb;
     L.off_twx = o;    o += align_up((size_t)g.nx * sizeof(double2));
     L.off_twz = o;    o += align_up((size_t)g.nz * sizeof(double2));
     L.off_tri = o;    o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * M * sizeof(double));
@@ -147,6 +153,7 @@ struct vs_state {
     double* om[3] = {};
     double* ps[3] = {};
     double* spec[3] = {};
+    double* src[3] = {};
     double2* twx = nullptr;
     double2* twz = nullptr;
     double* tri = nullptr;
@@ -205,13 +212,15 @@ void release_events(vs_state* S) {
 // solves directly from b and the wall rows; each later cycle is gated on the device flag
 // and solves for the correction of the current residual.
 void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncomp, double rtol,
-                   int max_cycles) {
+                   int max_cycles, int tag) {
     const Dims& d = S->d;
     const double* const cu[3] = {u[0], u[1], u[2]};
     const int nb = resid_blocks(d);
+    const int k_rhs = tag == TAG_OMEGA ? K_RHS_Z_OMEGA : tag == TAG_PSI ? K_RHS_Z_PSI : K_RHS_Z_FIELD;
+    const int k_res = tag == TAG_OMEGA ? K_RESID_OMEGA : tag == TAG_PSI ? K_RESID_PSI : K_RESID_FIELD;
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
         const int* gate = cyc == 0 ? nullptr : S->istat + IS_CONV;
-        timed(S, K_RHS_DHT_Z, [&] {
+        timed(S, k_rhs, [&] {
             launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rhs, cu, ncomp, cyc > 0, S->spec, gate);
         });
         timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
@@ -220,7 +229,7 @@ void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncom
         timed(S, K_DHT_Z_OUT, [&] {
             launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, u, ncomp, cyc > 0, gate);
         });
-        timed(S, K_RESID_NORM, [&] { launch_resid_norm(S->stream, d, rhs, cu, ncomp, S->part, nb, gate); });
+        timed(S, k_res, [&] { launch_resid_norm(S->stream, d, rhs, cu, ncomp, S->part, gate); });
         timed(S, K_CHECK, [&] {
             launch_check(S->stream, S->part, nb, rtol, cyc, cyc == max_cycles - 1, S->scal, S->istat, gate);
         });
@@ -229,7 +238,7 @@ void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncom
 
 void enqueue_va_mu(vs_state* S, const double* phi, int init) {
     const int nb = va_partial_blocks(S->d);
-    timed(S, K_VA_PARTIALS, [&] { launch_va_partials(S->stream, S->d, phi, S->p.eps, S->part, nb); });
+    timed(S, K_VA_PARTIALS, [&] { launch_va_partials(S->stream, S->d, phi, S->p.eps, S->part); });
     timed(S, K_FINALIZE_VA, [&] {
         launch_finalize_va(S->stream, S->d, S->part, nb, S->scal, S->istat, init, S->p.rate_V,
                            S->p.k_A, S->p.gamma0, S->p.mobility);
@@ -240,18 +249,19 @@ void enqueue_va_mu(vs_state* S, const double* phi, int init) {
 }
 
 void enqueue_flow(vs_state* S, const double* phi) {
+    timed(S, K_SOURCE, [&] { launch_source(S->stream, S->d, phi, S->mu, 1.0 / S->p.eta, S->src); });
     RhsArgs rv{};
-    rv.mode = RHS_VORT;
-    rv.phi = phi;
-    rv.mu = S->mu;
-    rv.inv_eta = 1.0 / S->p.eta;
-    enqueue_solve(S, rv, S->om, 3, S->p.poisson_rtol, S->p.poisson_max_cycles);
+    rv.mode = RHS_FIELD;
+    rv.f[0] = S->src[0];
+    rv.f[1] = S->src[1];
+    rv.f[2] = S->src[2];
+    enqueue_solve(S, rv, S->om, 3, S->p.poisson_rtol, S->p.poisson_max_cycles, TAG_OMEGA);
     RhsArgs rp{};
     rp.mode = RHS_NEGW;
     rp.f[0] = S->om[0];
     rp.f[1] = S->om[1];
     rp.f[2] = S->om[2];
-    enqueue_solve(S, rp, S->ps, 3, S->p.poisson_rtol, S->p.poisson_max_cycles);
+    enqueue_solve(S, rp, S->ps, 3, S->p.poisson_rtol, S->p.poisson_max_cycles, TAG_PSI);
 }
 
 void enqueue_step(vs_state* S, double dt) {
@@ -351,6 +361,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
         S->om[c] = field(3 + c);
         S->ps[c] = field(6 + c);
         S->spec[c] = (double*)(S->ws + L.off_spec + c * fb);
+        S->src[c] = (double*)(S->ws + L.off_src + c * fb);
     }
     S->twx = (double2*)(S->ws + L.off_twx);
     S->twz = (double2*)(S->ws + L.off_twz);
@@ -456,7 +467,7 @@ vs_status vs_poisson_solve(vs_state* S, const double* f, double* u, double rtol,
     r.mode = RHS_FIELD;
     r.f[0] = f;
     double* const uu[3] = {u, nullptr, nullptr};
-    enqueue_solve(S, r, uu, 1, rtol, max_cycles);
+    enqueue_solve(S, r, uu, 1, rtol, max_cycles, TAG_FIELD);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(S->stream));
     int ist[IS_NSTAT];

@@ -19,6 +19,16 @@ static inline __host__ __device__ int node(const Dims& d, int i, int j, int k) {
     return (i * d.ny + j) * d.nz + k;
 }
 
+// Blocks are handed to the 8 XCDs round-robin by linear block id. This maps a linear id to a
+// logical block so that each XCD works through one contiguous range of logical blocks: the
+// neighbouring x-planes a stencil reads are then produced and consumed in the same 4 MB L2.
+// A bijection on [0, nblocks) for any nblocks.
+static inline __device__ int xcd_block(int bid, int nblocks) {
+    const int q = nblocks >> 3, rem = nblocks & 7;
+    const int x = bid & 7, slot = bid >> 3;
+    return x * q + (x < rem ? x : rem) + slot;
+}
+
 // Slots of the device scalar array (doubles).
 enum {
     SC_V = 0, SC_A = 1, SC_V0 = 2, SC_A0 = 3, SC_LAMV = 4, SC_GAMMA = 5,
@@ -37,17 +47,13 @@ enum { ST_NOCONV = 1, ST_NONFINITE = 2 };
 
 // Source of the right-hand side b of a Poisson solve.
 enum RhsMode {
-    RHS_FIELD = 0,   // b_c = f_c (explicit arrays)
-    RHS_VORT = 1,    // b = (1/eta) D phi x D mu (three components), eq. (5b)
+    RHS_FIELD = 0,   // b_c = f_c: explicit arrays, or the stored vorticity source of eq. (5b)
     RHS_NEGW = 2     // b_c = -omega_c, eq. (5c)
 };
 
 struct RhsArgs {
     int mode;
     const double* f[3];      // RHS_FIELD arrays, or omega for RHS_NEGW
-    const double* phi;       // RHS_VORT
-    const double* mu;        // RHS_VORT
-    double inv_eta;
 };
 
 // Plan of a length-n transform: radices applied in order (Stockham passes).
@@ -57,7 +63,21 @@ struct FftPlan {
     int radix[12];
 };
 
-constexpr int kMaxPartialBlocks = 1024;
+constexpr int kMaxPartialBlocks = 4096;
+
+// Reduction grids: block (bx, bi) covers 256 consecutive nodes of a (j, k) plane for the ci
+// consecutive x-planes [bi*ci, bi*ci + ci); gx * gi <= maxb <= kMaxPartialBlocks.
+struct SlabGrid {
+    int gx, ci, gi;
+};
+static inline SlabGrid slab_grid(int plane, int nx, int maxb) {
+    SlabGrid g;
+    g.gx = (plane + 255) / 256;
+    g.ci = 1;
+    while (g.gx * ((nx + g.ci - 1) / g.ci) > maxb && g.ci < nx) ++g.ci;
+    g.gi = (nx + g.ci - 1) / g.ci;
+    return g;
+}
 constexpr int kPartialSlots = 8;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
 
 // ---------------------------------------------------------------- explicit stencils
@@ -65,7 +85,7 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
                     const double* const psi[3], double* phi_out, const double* scal,
                     double dt, double mobility, double vz_lo, double vz_hi);
 void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
-                        double* partials, int nblocks);
+                        double* partials);
 int va_partial_blocks(const Dims& d);
 void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
                         double* scal, int* istat, int init, double rate_V, double k_A,
@@ -73,6 +93,9 @@ void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, in
 void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const double* scal,
                int model, double C_b, double eps, double sigma);
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof);
+// S = (1/eta) D phi x D mu on the interior rows (main text eq. (5b)), into src[0..2].
+void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
+                   double inv_eta, double* const src[3]);
 void launch_reset_stats(hipStream_t s, double* scal, int* istat);
 
 // ---------------------------------------------------------------- spectral Poisson
@@ -89,8 +112,7 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
                       const int* gate);
 int resid_blocks(const Dims& d);
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
-                       const double* const u[3], int ncomp, double* partials, int nblocks,
-                       const int* gate);
+                       const double* const u[3], int ncomp, double* partials, const int* gate);
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
                   int last_cycle, double* scal, int* istat, const int* gate);
 
