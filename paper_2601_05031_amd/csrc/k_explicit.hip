@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
 // V = (|Omega| + h^3 sum_w phi)/2, A = 3/(2 sqrt 2) h^3 sum_w(...); then
 // lambda_V = 2 rate_V (V0 - V)/(M |Omega|) and gamma_A = gamma0 + k_A (A - A0)/A0
 // (off when k_A = 0 or A0 = 0). init != 0 also sets V0 = V, A0 = A.
-__global__ __launch_bounds__(kBlock) void k_finalize_va(const double* __restrict__ partials,
+__global__ __launch_bounds__(1024) void k_finalize_va(const double* __restrict__ partials,
                                                        int nblocks, Dims d, double* scal,
                                                        int* istat, int init, double rate_V,
                                                        double k_A, double gamma0, double mob) {
@@ -279,13 +279,13 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
 }
 
 int va_partial_blocks(const Dims& d) {
-    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, 1024);
+    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kMaxPartialBlocks);
     return g.gx * g.gi;
 }
 
 void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
                         double* partials) {
-    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, 1024);
+    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kMaxPartialBlocks);
     hipLaunchKernelGGL(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
                        partials);
 }
@@ -293,7 +293,7 @@ void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double 
 void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
                         double* scal, int* istat, int init, double rate_V, double k_A,
                         double gamma0, double mobility) {
-    hipLaunchKernelGGL(k_finalize_va, dim3(1), dim3(kBlock), 0, s, partials, nblocks, d, scal,
+    hipLaunchKernelGGL(k_finalize_va, dim3(1), dim3(1024), 0, s, partials, nblocks, d, scal,
                        istat, init, rate_V, k_A, gamma0, mobility);
 }
 

@@ -241,43 +241,33 @@ __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
     }
 }
 
-// tridiag_y: two lanes per mode (p, q) of component blockIdx.y solve
-//   U_{j-1} + beta U_j + U_{j+1} = scale * B_j,  j = 1..M,  U_0 = U_{M+1} = 0,
-// beta = 2 cos(2 pi p/nx) + 2 cos(2 pi q/nz) - 6, by a twisted factorisation: the even lane
+// Twisted tridiagonal solve of
+//   U_{j-1} + beta U_j + U_{j+1} = f_j,  j = 1..M,  U_0 = U_{M+1} = 0,
+// beta = 2 cos(2 pi p/nx) + 2 cos(2 pi q/nz) - 6, shared by a lane pair: the even lane
 // eliminates rows 1..m downwards (pivots c'_s = 1/(beta - c'_{s-1}), rows read as
 // U_j + c'_j U_{j+1} = d'_j), the odd lane rows M..m+1 upwards with the same pivots counted
 // from the bottom (the matrix is symmetric Toeplitz), the two meet in a 2x2 system at rows
 // m, m+1 (values exchanged by a lane shuffle), then each back-substitutes away from the
-// middle. Pivots come from tri[s * nclass + class]; in place; loads run one chunk ahead.
-__global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restrict__ tri,
-                                                 Ptr3 spec, const int* gate, double scale) {
-    if (gate && *gate) return;
-    const int t = blockIdx.x * 64 + threadIdx.x;
-    const int pair = t >> 1;
-    const int half = t & 1;
-    const bool act = pair < d.nx * d.nz;
-    const int c = blockIdx.y;
-    const int pp = act ? pair : 0;
-    const int p = pp / d.nz;
-    const int q = pp - p * d.nz;
-    const int pc = min(p, d.nx - p);
-    const int qc = min(q, d.nz - q);
-    const size_t ncls = (size_t)(d.nx / 2 + 1) * (d.nz / 2 + 1);
-    const double* cp = tri + (size_t)(pc * (d.nz / 2 + 1) + qc);
-    double* col = spec.p[c] + (size_t)p * d.ny * d.nz + q;
-    const long sj = d.nz;
-    const int M = d.M;
+// middle. f_j = rhs(j, v) with v the value read at row j of rd; d' and then U are written to
+// wr (which may alias rd). Pivots come from cp[s * ncls]; loads run one chunk ahead. All lanes
+// of the wave call this together; inactive lanes pass act = false.
+// INPLACE: rd == wr (one pointer is used for both); otherwise rd and wr are distinct buffers.
+template <bool INPLACE, class Rhs>
+__device__ __forceinline__ void twisted_half(const double* __restrict__ rd, double* __restrict__ wr,
+                                             long sj, int M, int half, bool act,
+                                             const double* __restrict__ cp, size_t ncls, Rhs rhs) {
     const int m = (M + 1) / 2;
     const int nr = act ? (half ? M - m : m) : 0;      // rows eliminated by this lane
-    // row of step s (s = 0 at the wall end), and its address step
-    const int j0 = half ? M : 1;
-    const long dj = half ? -sj : sj;
-    double* base = col + (long)j0 * sj;
+    const int j0 = half ? M : 1;                       // row of step 0 (the wall end)
+    const int jd = half ? -1 : 1;
+    const long dj = jd * sj;
+    double* wb = wr + (long)j0 * sj;
+    const double* rb = INPLACE ? wb : rd + (long)j0 * sj;
     constexpr int CH = 8;
     double fv[CH], cv[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-        fv[u] = (u < nr) ? base[u * dj] : 0.0;
+        fv[u] = (u < nr) ? rhs(j0 + u * jd, rb[u * dj]) : 0.0;
         cv[u] = (u < nr) ? cp[(size_t)u * ncls] : 0.0;
     }
     double acc = 0.0, clast = 0.0;
@@ -286,15 +276,15 @@ __global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restri
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int sn = s0 + CH + u;
-            nf[u] = (sn < nr) ? base[sn * dj] : 0.0;
+            nf[u] = (sn < nr) ? rhs(j0 + sn * jd, rb[sn * dj]) : 0.0;
             nc[u] = (sn < nr) ? cp[(size_t)sn * ncls] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             if (s0 + u < nr) {
-                acc = cv[u] * (scale * fv[u] - acc);
+                acc = cv[u] * (fv[u] - acc);
                 clast = cv[u];
-                base[(s0 + u) * dj] = acc;
+                wb[(s0 + u) * dj] = acc;
             }
         }
 #pragma unroll
@@ -307,17 +297,17 @@ __global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restri
     // rows contributes (0, 0), i.e. the wall value U = 0.
     const double oacc = __shfl_xor(acc, 1, 64);
     const double oc = __shfl_xor(clast, 1, 64);
-    if (!act || nr == 0) return;
+    if (nr == 0) return;
     const double dm = half ? oacc : acc, cm = half ? oc : clast;
     const double gm = half ? acc : oacc, em = half ? clast : oc;
     const double Um = (dm - cm * gm) / (1.0 - cm * em);
     double unext = half ? (gm - em * Um) : Um;        // U at this lane's last row
-    base[(nr - 1) * dj] = unext;
-    // back substitution from row s = nr-2 towards the wall: U_s = d'_s - c'_s U_{s+1}
+    wb[(nr - 1) * dj] = unext;
+    // back substitution from step nr-2 towards the wall: U = d' - c' U_next
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
         const int sn = nr - 2 - u;
-        fv[u] = (sn >= 0) ? base[sn * dj] : 0.0;
+        fv[u] = (sn >= 0) ? wb[sn * dj] : 0.0;
         cv[u] = (sn >= 0) ? cp[(size_t)(sn >= 0 ? sn : 0) * ncls] : 0.0;
     }
     for (int s0 = nr - 2; s0 >= 0; s0 -= CH) {
@@ -325,14 +315,14 @@ __global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restri
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int sn = s0 - CH - u;
-            nf[u] = (sn >= 0) ? base[sn * dj] : 0.0;
+            nf[u] = (sn >= 0) ? wb[sn * dj] : 0.0;
             nc[u] = (sn >= 0) ? cp[(size_t)(sn >= 0 ? sn : 0) * ncls] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             if (s0 - u >= 0) {
                 unext = fv[u] - cv[u] * unext;
-                base[(s0 - u) * dj] = unext;
+                wb[(s0 - u) * dj] = unext;
             }
         }
 #pragma unroll
@@ -341,6 +331,70 @@ __global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restri
             cv[u] = nc[u];
         }
     }
+}
+
+struct ModeLane {
+    int p, q, half;
+    bool act;
+    const double* cp;
+    size_t ncls;
+    long off;   // offset of the (p, row 0, q) element
+};
+
+__device__ __forceinline__ ModeLane mode_lane(const Dims& d, const double* __restrict__ tri) {
+    ModeLane ml;
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    const int pair = t >> 1;
+    ml.half = t & 1;
+    ml.act = pair < d.nx * d.nz;
+    const int pp = ml.act ? pair : 0;
+    ml.p = pp / d.nz;
+    ml.q = pp - ml.p * d.nz;
+    const int pc = min(ml.p, d.nx - ml.p);
+    const int qc = min(ml.q, d.nz - ml.q);
+    ml.ncls = (size_t)(d.nx / 2 + 1) * (d.nz / 2 + 1);
+    ml.cp = tri + (size_t)(pc * (d.nz / 2 + 1) + qc);
+    ml.off = (long)ml.p * d.ny * d.nz + ml.q;
+    return ml;
+}
+
+// tridiag_y: one Poisson problem per component blockIdx.y: f_j = scale * B_j (B = the 2D
+// Hartley spectrum of the right-hand side, scale = h^2/(nx nz)), in place.
+__global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restrict__ tri,
+                                                 Ptr3 spec, const int* gate, double scale) {
+    if (gate && *gate) return;
+    const ModeLane ml = mode_lane(d, tri);
+    double* col = spec.p[blockIdx.y] + ml.off;
+    twisted_half<true>(nullptr, col, d.nz, d.M, ml.half, ml.act, ml.cp, ml.ncls,
+                       [&](int, double v) { return scale * v; });
+}
+
+// tridiag_psi: the stream-vector problem lap psi = -w from the vorticity modes U_w = T w/(nx nz)
+// left in spec by tridiag_y (T the 2D Hartley transform): its transformed right-hand side is
+// -(nx nz) U_w minus the wall terms, whose transform for wall values constant over each wall
+// plane lives only in mode (0, 0):
+//   f_j = -h^2 U_w(j) - [p = q = 0] ([j = 1] psi_lo + [j = M] psi_hi);
+// solved into spec2, leaving spec unchanged.
+__global__ __launch_bounds__(64) void k_tridiag_psi(Dims d, const double* __restrict__ tri,
+                                                   Ptr3 spec, Ptr3 spec2, double3 plo,
+                                                   double3 phi_) {
+    const ModeLane ml = mode_lane(d, tri);
+    const int c = blockIdx.y;
+    const double* col = spec.p[c] + ml.off;
+    double* col2 = spec2.p[c] + ml.off;
+    const bool m00 = (ml.p == 0 && ml.q == 0);
+    const double wlo = c == 0 ? plo.x : (c == 1 ? plo.y : plo.z);
+    const double whi = c == 0 ? phi_.x : (c == 1 ? phi_.y : phi_.z);
+    const double h2 = d.h * d.h;
+    const int M = d.M;
+    twisted_half<false>(col, col2, d.nz, d.M, ml.half, ml.act, ml.cp, ml.ncls, [&](int j, double v) {
+        double f = -h2 * v;
+        if (m00) {
+            if (j == 1) f -= wlo;
+            if (j == M) f -= whi;
+        }
+        return f;
+    });
 }
 
 // dht_z_out: Hartley along z of the solved modes, then u = result (add = 0) or u += result.
@@ -499,14 +553,58 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
     static_assert(L * N <= P::LDS, "input tile must fit in the exchange buffer");
     static_assert(L * A <= 64, "one pass-1 round per lane");
     __shared__ double2 Y[P::LDS];
+    // Only the residual form (a stencil of u) benefits from XCD-ordered blocks; the pointwise
+    // form keeps the hardware order (neighbouring rows stream together).
     const int gx = gridDim.x;
-    const int lb = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
+    const int lb = correct ? xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y)
+                           : (int)(blockIdx.x + gx * blockIdx.y);
     const int c = lb / gx;
     const int bx = lb - c * gx;
     const int nrows = d.nx * d.M;
     const int r0 = bx * 2 * L;
     const double* uc = u.p[c];
     double* sc = spec.p[c];
+    auto prep = [&](int ln) -> RowPair {
+        return RowPair{row_base(d, r0 + 2 * ln, nrows), row_base(d, r0 + 2 * ln + 1, nrows)};
+    };
+    auto store = [&](const RowPair& rp, int p, double ha, double hb) {
+        if (rp.a >= 0) sc[rp.a + p] = ha;
+        if (rp.b >= 0) sc[rp.b + p] = hb;
+    };
+    if (!correct) {
+        // b - wall terms: a pointwise read plus, on the first and last interior rows, the
+        // wall row of u; pass 1 loads it directly. Per line: row offsets and wall flags
+        // (bit 0: row j = 1 borders the y = 0 wall, bit 1: row j = M borders y = H).
+        const double sg = (rhs.mode == RHS_NEGW) ? -1.0 : 1.0;
+        const double* fc = rhs.f[c];
+        auto prepw = [&](int ln) -> int4 {
+            int4 o;
+            const int ra = r0 + 2 * ln, rbb = ra + 1;
+            o.x = row_base(d, ra, nrows);
+            o.y = row_base(d, rbb, nrows);
+            const int ja = 1 + (ra - (ra / d.M) * d.M), jb = 1 + (rbb - (rbb / d.M) * d.M);
+            o.z = (ja == 1 ? 1 : 0) | (ja == d.M ? 2 : 0);
+            o.w = (jb == 1 ? 1 : 0) | (jb == d.M ? 2 : 0);
+            return o;
+        };
+        auto rowval = [&](int rb, int fl, int k) -> double {
+            if (rb < 0) return 0.0;
+            double b = sg * fc[rb + k];
+            if (fl & 1) b -= uc[rb - d.nz + k] * d.inv_h2;
+            if (fl & 2) b -= uc[rb + d.nz + k] * d.inv_h2;
+            return b;
+        };
+        auto load = [&](const int4& o, int k1, int k2) -> double2 {
+            const int k = k1 + A * k2;
+            return make_double2(rowval(o.x, o.z, k), rowval(o.y, o.w, k));
+        };
+        auto storew = [&](const int4& o, int p, double ha, double hb) {
+            if (o.x >= 0) sc[o.x + p] = ha;
+            if (o.y >= 0) sc[o.y + p] = hb;
+        };
+        two_pass_hartley<B, A, false>(Y, tw, prepw, load, storew);
+        return;
+    }
 #pragma unroll 4
     for (int lr = 0; lr < 2 * L; ++lr) {
         const int r = r0 + lr;
@@ -519,7 +617,7 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
             const int rb = node(d, i, j, 0), xpb = node(d, ip, j, 0), xmb = node(d, im, j, 0);
 #pragma unroll
             for (int k = threadIdx.x; k < N; k += 64)
-                set_part(&row[k], lr & 1, rhs_row(rhs, d, uc, c, correct, rb, xpb, xmb, j, k));
+                set_part(&row[k], lr & 1, rhs_row(rhs, d, uc, c, 1, rb, xpb, xmb, j, k));
         } else {
 #pragma unroll
             for (int k = threadIdx.x; k < N; k += 64) set_part(&row[k], lr & 1, 0.0);
@@ -535,14 +633,7 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
         for (int k2 = 0; k2 < B; ++k2) xin[k2] = Y[line * N + k1 + A * k2];
     }
     __syncthreads();
-    auto prep = [&](int ln) -> RowPair {
-        return RowPair{row_base(d, r0 + 2 * ln, nrows), row_base(d, r0 + 2 * ln + 1, nrows)};
-    };
     auto load = [&](const RowPair&, int, int k2) -> double2 { return xin[k2]; };
-    auto store = [&](const RowPair& rp, int p, double ha, double hb) {
-        if (rp.a >= 0) sc[rp.a + p] = ha;
-        if (rp.b >= 0) sc[rp.b + p] = hb;
-    };
     two_pass_hartley<B, A, false>(Y, tw, prep, load, store);
 }
 
@@ -681,31 +772,104 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
     }
 }
 
+// resid_pair: both residuals of a step in one pass (used when no correction cycle can
+// follow): vorticity r = S - L_h w with b~ = S - w-walls, stream vector r = -w - L_h psi with
+// b~ = -w - psi-walls. Partials: slots 0-5 as resid_norm for the vorticity, 6-11 for psi.
+__global__ __launch_bounds__(kBlock) void k_resid_pair(Dims d, CPtr3 src, CPtr3 w, CPtr3 psi,
+                                                      SlabGrid sg, double* __restrict__ partials) {
+    __shared__ double sh[12 * 4];
+    const int nb = sg.gx * sg.gi;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int bi = lb / sg.gx;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
+    double acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+    if (t < d.M * d.nz) {
+        const int jj = t / d.nz;
+        const int k = t - jj * d.nz;
+        const int j = jj + 1;
+        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+        const int km = (k == 0) ? d.nz - 1 : k - 1;
+        const int i1 = min(d.nx, (bi + 1) * sg.ci);
+#pragma unroll 2
+        for (int i = bi * sg.ci; i < i1; ++i) {
+            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+            const int im = (i == 0) ? d.nx - 1 : i - 1;
+            const int rb = node(d, i, j, 0), xpb = node(d, ip, j, 0), xmb = node(d, im, j, 0);
+            const int c0 = rb + k;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double* wc = w.p[c];
+                const double* pc = psi.p[c];
+                const double wv = wc[c0];
+                {
+                    const double ylo = wc[c0 - d.nz], yhi = wc[c0 + d.nz];
+                    const double b = src.p[c][c0];
+                    const double wall = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
+                    const double lap = (wc[xpb + k] + wc[xmb + k] + ylo + yhi + wc[rb + kp] +
+                                        wc[rb + km] - 6.0 * wv) * d.inv_h2;
+                    const double r = b - lap, bt = b - wall * d.inv_h2;
+                    acc[c] += r * r;
+                    acc[3 + c] += bt * bt;
+                }
+                {
+                    const double ylo = pc[c0 - d.nz], yhi = pc[c0 + d.nz];
+                    const double b = -wv;
+                    const double wall = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
+                    const double lap = (pc[xpb + k] + pc[xmb + k] + ylo + yhi + pc[rb + kp] +
+                                        pc[rb + km] - 6.0 * pc[c0]) * d.inv_h2;
+                    const double r = b - lap, bt = b - wall * d.inv_h2;
+                    acc[6 + c] += r * r;
+                    acc[9 + c] += bt * bt;
+                }
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const double sum = wave_sum(acc[q]);
+        if (lane == 0) sh[q * 4 + wv] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const double sum = sh[threadIdx.x * 4 + 0] + sh[threadIdx.x * 4 + 1] +
+                           sh[threadIdx.x * 4 + 2] + sh[threadIdx.x * 4 + 3];
+        partials[threadIdx.x * kMaxPartialBlocks + blockIdx.x] = sum;
+    }
+}
+
 // check: relative residual sqrt(sum_c r^2 / sum_c b~^2) in a fixed summation order; sets the
 // convergence flag that gates the following cycles, counts the cycle and raises ST_NOCONV
 // on the last allowed cycle, ST_NONFINITE on NaN/Inf.
-__global__ __launch_bounds__(kBlock) void k_check(const double* __restrict__ partials,
-                                                 int nblocks, double rtol, int last_cycle,
-                                                 double* scal, int* istat, const int* gate) {
+__global__ __launch_bounds__(1024) void k_check(const double* __restrict__ partials,
+                                               int nblocks, double rtol, int last_cycle,
+                                               double* scal, int* istat, const int* gate,
+                                               int slot0) {
     if (gate && *gate) return;
-    __shared__ double sh[2 * 4];
+    __shared__ double sh[2 * 16];
     double rr = 0.0, bb = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        const double* pb = partials + b;
+        const double* pb = partials + (size_t)slot0 * kMaxPartialBlocks + b;
         rr += pb[0 * kMaxPartialBlocks] + pb[1 * kMaxPartialBlocks] + pb[2 * kMaxPartialBlocks];
         bb += pb[3 * kMaxPartialBlocks] + pb[4 * kMaxPartialBlocks] + pb[5 * kMaxPartialBlocks];
     }
     rr = wave_sum(rr);
     bb = wave_sum(bb);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0) {
         sh[w] = rr;
-        sh[4 + w] = bb;
+        sh[16 + w] = bb;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    rr = sh[0] + sh[1] + sh[2] + sh[3];
-    bb = sh[4] + sh[5] + sh[6] + sh[7];
+    rr = 0.0;
+    bb = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        rr += sh[i];
+        bb += sh[16 + i];
+    }
     double rel;
     if (bb > 0.0)
         rel = sqrt(rr / bb);
@@ -791,6 +955,16 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, double* c
                        gate, scale);
 }
 
+void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
+                        double* const spec2[3], const double psi_lo[3], const double psi_hi[3]) {
+    Ptr3 sp{{spec[0], spec[1], spec[2]}};
+    Ptr3 sp2{{spec2[0], spec2[1], spec2[2]}};
+    const int threads = 2 * d.nx * d.nz;
+    hipLaunchKernelGGL(k_tridiag_psi, dim3((threads + 63) / 64, 3), dim3(64), 0, s, d, tri, sp, sp2,
+                       make_double3(psi_lo[0], psi_lo[1], psi_lo[2]),
+                       make_double3(psi_hi[0], psi_hi[1], psi_hi[2]));
+}
+
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       double* const spec[3], double* const u[3], int ncomp, int add,
                       const int* gate) {
@@ -818,6 +992,13 @@ int resid_blocks(const Dims& d) {
     return g.gx * g.gi;
 }
 
+void launch_resid_pair(hipStream_t s, const Dims& d, double* const src[3], double* const w[3],
+                       double* const psi[3], double* partials) {
+    CPtr3 a{{src[0], src[1], src[2]}}, b{{w[0], w[1], w[2]}}, c{{psi[0], psi[1], psi[2]}};
+    const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
+    hipLaunchKernelGGL(k_resid_pair, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, a, b, c, g, partials);
+}
+
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate) {
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
@@ -827,10 +1008,10 @@ void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
 }
 
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
-                  int last_cycle, double* scal, int* istat, const int* gate) {
+                  int last_cycle, double* scal, int* istat, const int* gate, int slot0) {
     (void)cycle;
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, partials, nblocks, rtol,
-                       last_cycle, scal, istat, gate);
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(1024), 0, s, partials, nblocks, rtol,
+                       last_cycle, scal, istat, gate, slot0);
 }
 
 }  // namespace vs

@@ -40,13 +40,13 @@ vs_status fail(vs_status code, const char* fmt, ...) {
 // Kernel classes for the event timer.
 enum KClass {
     K_ADVANCE, K_VA_PARTIALS, K_FINALIZE_VA, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
-    K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI, K_RESID_FIELD,
-    K_CHECK, K_FILL, K_RESET, K_NCLASS
+    K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PSI, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
+    K_RESID_FIELD, K_RESID_PAIR, K_CHECK, K_FILL, K_RESET, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "finalize_va", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
-    "rhs_dht_z_field", "dht_x", "tridiag_y", "dht_z_out", "resid_norm_omega", "resid_norm_psi",
-    "resid_norm_field", "check", "fill_profile", "reset_stats"};
+    "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_psi", "dht_z_out", "resid_norm_omega",
+    "resid_norm_psi", "resid_norm_field", "resid_pair", "check", "fill_profile", "reset_stats"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -67,6 +67,7 @@ struct Layout {
     size_t off_fields;      // 9 fields: phi(2), mu, omega(3), psi(3)
     size_t off_spec;        // 3 spectral scratch fields
     size_t off_src;         // 3 fields: the vorticity source S of the current step
+    size_t off_spec2;       // 3 spectral fields: the stream-vector modes
     size_t off_twx, off_twz, off_tri, off_part, off_prof, off_scal, off_istat;
     size_t total;
 };
@@ -80,6 +81,7 @@ Layout make_layout(const vs_grid& g) {
     L.off_fields = o; o += 9 * fb;
     L.off_spec = o;   o += 3 * fb;
     L.off_src = o;    o += 3 * fb;
+    L.off_spec2 = o;  o += 3 * fb;
     L.off_twx = o;    o += align_up((size_t)g.nx * sizeof(double2));
     L.off_twz = o;    o += align_up((size_t)g.nz * sizeof(double2));
     L.off_tri = o;    o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * M * sizeof(double));
@@ -154,6 +156,8 @@ struct vs_state {
     double* ps[3] = {};
     double* spec[3] = {};
     double* src[3] = {};
+    double* spec2[3] = {};
+    double psi_wall_lo[3] = {0, 0, 0}, psi_wall_hi[3] = {0, 0, 0};
     double2* twx = nullptr;
     double2* twz = nullptr;
     double* tri = nullptr;
@@ -208,31 +212,45 @@ void release_events(vs_state* S) {
     S->ev_used.clear();
 }
 
-// One vector (ncomp = 3) or scalar (ncomp = 1) Poisson solve, fully on the stream: cycle 0
-// solves directly from b and the wall rows; each later cycle is gated on the device flag
-// and solves for the correction of the current residual.
-void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncomp, double rtol,
-                   int max_cycles, int tag) {
+// Residual norms of the current u and the convergence check of cycle `cyc`.
+void enqueue_verify(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncomp, double rtol,
+                    int cyc, int last, int tag, const int* gate) {
     const Dims& d = S->d;
     const double* const cu[3] = {u[0], u[1], u[2]};
     const int nb = resid_blocks(d);
-    const int k_rhs = tag == TAG_OMEGA ? K_RHS_Z_OMEGA : tag == TAG_PSI ? K_RHS_Z_PSI : K_RHS_Z_FIELD;
     const int k_res = tag == TAG_OMEGA ? K_RESID_OMEGA : tag == TAG_PSI ? K_RESID_PSI : K_RESID_FIELD;
+    timed(S, k_res, [&] { launch_resid_norm(S->stream, d, rhs, cu, ncomp, S->part, gate); });
+    timed(S, K_CHECK, [&] {
+        launch_check(S->stream, S->part, nb, rtol, cyc, last, S->scal, S->istat, gate);
+    });
+}
+
+// One transform cycle: cycle 0 (correct = 0) solves directly from b and the wall rows;
+// a correction cycle solves for the correction of the residual and adds it to u.
+void enqueue_cycle(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncomp, int correct,
+                   int tag, const int* gate) {
+    const Dims& d = S->d;
+    const double* const cu[3] = {u[0], u[1], u[2]};
+    const int k_rhs = tag == TAG_OMEGA ? K_RHS_Z_OMEGA : tag == TAG_PSI ? K_RHS_Z_PSI : K_RHS_Z_FIELD;
+    timed(S, k_rhs, [&] {
+        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rhs, cu, ncomp, correct, S->spec, gate);
+    });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
+    timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, ncomp, gate); });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
+    timed(S, K_DHT_Z_OUT, [&] {
+        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, u, ncomp, correct, gate);
+    });
+}
+
+// Verified solve: cycle 0, then up to max_cycles-1 correction cycles gated on the device flag
+// (a cycle runs only while the previous check missed rtol); each cycle ends with a check.
+void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncomp, double rtol,
+                   int max_cycles, int tag) {
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
         const int* gate = cyc == 0 ? nullptr : S->istat + IS_CONV;
-        timed(S, k_rhs, [&] {
-            launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rhs, cu, ncomp, cyc > 0, S->spec, gate);
-        });
-        timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
-        timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, ncomp, gate); });
-        timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
-        timed(S, K_DHT_Z_OUT, [&] {
-            launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, u, ncomp, cyc > 0, gate);
-        });
-        timed(S, k_res, [&] { launch_resid_norm(S->stream, d, rhs, cu, ncomp, S->part, gate); });
-        timed(S, K_CHECK, [&] {
-            launch_check(S->stream, S->part, nb, rtol, cyc, cyc == max_cycles - 1, S->scal, S->istat, gate);
-        });
+        enqueue_cycle(S, rhs, u, ncomp, cyc > 0, tag, gate);
+        enqueue_verify(S, rhs, u, ncomp, rtol, cyc, cyc == max_cycles - 1, tag, gate);
     }
 }
 
@@ -248,20 +266,55 @@ void enqueue_va_mu(vs_state* S, const double* phi, int init) {
     });
 }
 
+// The flow part of a step (main text eq. (5b), then (5c)). Cycle 0 of the two vector solves
+// shares one spectral pass: the vorticity modes after the Thomas solve are, up to -h^2, the
+// transformed right-hand side of the stream-vector problem, so psi needs no forward
+// transform. Both fields are then verified against their own spatial residual; correction
+// cycles (normally never run in FP64) use the generic path.
 void enqueue_flow(vs_state* S, const double* phi) {
-    timed(S, K_SOURCE, [&] { launch_source(S->stream, S->d, phi, S->mu, 1.0 / S->p.eta, S->src); });
+    const Dims& d = S->d;
+    const double rtol = S->p.poisson_rtol;
+    const int mc = S->p.poisson_max_cycles;
+    timed(S, K_SOURCE, [&] { launch_source(S->stream, d, phi, S->mu, 1.0 / S->p.eta, S->src); });
     RhsArgs rv{};
     rv.mode = RHS_FIELD;
     rv.f[0] = S->src[0];
     rv.f[1] = S->src[1];
     rv.f[2] = S->src[2];
-    enqueue_solve(S, rv, S->om, 3, S->p.poisson_rtol, S->p.poisson_max_cycles, TAG_OMEGA);
     RhsArgs rp{};
     rp.mode = RHS_NEGW;
     rp.f[0] = S->om[0];
     rp.f[1] = S->om[1];
     rp.f[2] = S->om[2];
-    enqueue_solve(S, rp, S->ps, 3, S->p.poisson_rtol, S->p.poisson_max_cycles, TAG_PSI);
+    const double* const cu[3] = {S->om[0], S->om[1], S->om[2]};
+    timed(S, K_RHS_Z_OMEGA, [&] {
+        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rv, cu, 3, 0, S->spec, nullptr);
+    });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, nullptr); });
+    timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, 3, nullptr); });
+    timed(S, K_TRIDIAG_PSI, [&] {
+        launch_tridiag_psi(S->stream, d, S->tri, S->spec, S->spec2, S->psi_wall_lo, S->psi_wall_hi);
+    });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, nullptr); });
+    timed(S, K_DHT_Z_OUT, [&] {
+        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, S->om, 3, 0, nullptr);
+    });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec2, 3, nullptr); });
+    timed(S, K_DHT_Z_OUT, [&] {
+        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec2, S->ps, 3, 0, nullptr);
+    });
+    enqueue_verify(S, rv, S->om, 3, rtol, 0, mc == 1, TAG_OMEGA, nullptr);
+    for (int cyc = 1; cyc < mc; ++cyc) {
+        const int* gate = S->istat + IS_CONV;
+        enqueue_cycle(S, rv, S->om, 3, 1, TAG_OMEGA, gate);
+        enqueue_verify(S, rv, S->om, 3, rtol, cyc, cyc == mc - 1, TAG_OMEGA, gate);
+    }
+    enqueue_verify(S, rp, S->ps, 3, rtol, 0, mc == 1, TAG_PSI, nullptr);
+    for (int cyc = 1; cyc < mc; ++cyc) {
+        const int* gate = S->istat + IS_CONV;
+        enqueue_cycle(S, rp, S->ps, 3, 1, TAG_PSI, gate);
+        enqueue_verify(S, rp, S->ps, 3, rtol, cyc, cyc == mc - 1, TAG_PSI, gate);
+    }
 }
 
 void enqueue_step(vs_state* S, double dt) {
@@ -362,6 +415,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
         S->ps[c] = field(6 + c);
         S->spec[c] = (double*)(S->ws + L.off_spec + c * fb);
         S->src[c] = (double*)(S->ws + L.off_src + c * fb);
+        S->spec2[c] = (double*)(S->ws + L.off_spec2 + c * fb);
     }
     S->twx = (double2*)(S->ws + L.off_twx);
     S->twz = (double2*)(S->ws + L.off_twz);
@@ -413,6 +467,8 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
         prof[j] = psx;
         prof[grid->ny + j] = omx;
     }
+    S->psi_wall_lo[0] = prof[0];
+    S->psi_wall_hi[0] = prof[grid->ny - 1];
     if (walls->kind == VS_POISEUILLE) {
         S->vz_lo = 0.0;
         S->vz_hi = 0.0;

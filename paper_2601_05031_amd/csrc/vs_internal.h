@@ -78,7 +78,7 @@ static inline SlabGrid slab_grid(int plane, int nx, int maxb) {
     g.gi = (nx + g.ci - 1) / g.ci;
     return g;
 }
-constexpr int kPartialSlots = 8;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
+constexpr int kPartialSlots = 12;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
 
 // ---------------------------------------------------------------- explicit stencils
 void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
@@ -107,6 +107,10 @@ void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2
                   double* const spec[3], int ncomp, const int* gate);
 void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
                       int ncomp, const int* gate);
+// Stream-vector modes into spec2 from the vorticity modes left in spec by launch_tridiag_y
+// (psi wall values constant over each wall plane: psi_lo at j = 0, psi_hi at j = ny-1).
+void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
+                        double* const spec2[3], const double psi_lo[3], const double psi_hi[3]);
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       double* const spec[3], double* const u[3], int ncomp, int add,
                       const int* gate);
@@ -114,6 +118,9 @@ int resid_blocks(const Dims& d);
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate);
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
-                  int last_cycle, double* scal, int* istat, const int* gate);
+                  int last_cycle, double* scal, int* istat, const int* gate, int slot0 = 0);
+// Both residuals of a step in one pass: partial slots 0-5 (vorticity), 6-11 (stream vector).
+void launch_resid_pair(hipStream_t s, const Dims& d, double* const src[3], double* const w[3],
+                       double* const psi[3], double* partials);
 
 }  // namespace vs

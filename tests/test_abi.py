@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_workspace_bytes_and_layout():
     n = P.workspace_bytes((128, 128, 128, 1.0), P.make_params())
     N = 128**3
-    assert 15 * 8 * N <= n < 15 * 8 * N + 16 * 2**20   # 15 fields + tables
+    assert 18 * 8 * N <= n < 18 * 8 * N + 16 * 2**20   # 18 fields + tables
 
 
 @pytest.mark.parametrize("grid,code", [
