@@ -102,6 +102,46 @@ def cpu_baseline(workload, budget_s: float):
             "steps_per_s": n / t}
 
 
+def compare_precisions(P, torch, steps: int) -> dict:
+    """droplet256 (128 x 128 x 256 Cahn-Hilliard droplet in Couette flow): the same steps in
+    FP64 and in the FP32-refined mode (FP32-stored spectral solves, FP64 defect correction to
+    the same rtol), timed alike; the refined fields are compared with the FP64 ones."""
+    from workloads import workload
+
+    w = workload("droplet256", max_cycles=1)
+    N = w.grid.N
+    out = {"workload": w.name, "grid": list(w.grid.shape), "steps": steps, "poisson_rtol": w.rtol}
+    fields = {}
+    for prec, mc in (("fp64", 1), ("fp32_refined", 4)):
+        s = P.solver_for(w, precision=prec, max_cycles=mc)
+        s.step(w.dt, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(w.dt, steps)
+        t = time.perf_counter() - t0
+        sc = s.scalars()
+        fields[prec] = s.fields()
+        out[prec] = {"cell_updates_per_s": N * steps / t, "ms_per_step": 1e3 * t / steps,
+                     "max_relres": sc["relres"], "cycles_per_solve": sc["cycles"] / (2.0 * steps)}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    import numpy as np
+
+    errs = {}
+    for k, ref in fields["fp64"].items():
+        nb = float(np.linalg.norm(ref))
+        errs[k] = float(np.linalg.norm(fields["fp32_refined"][k] - ref)) / (nb if nb > 0 else 1.0)
+    out["fp32_refined_rel_l2_vs_fp64"] = errs
+    out["speedup_fp32_refined_over_fp64"] = (out["fp32_refined"]["cell_updates_per_s"]
+                                             / out["fp64"]["cell_updates_per_s"])
+    print(f"bench: droplet256 fp64 {out['fp64']['ms_per_step']:.3f} ms/step, fp32-refined "
+          f"{out['fp32_refined']['ms_per_step']:.3f} ms/step "
+          f"({out['fp32_refined']['cycles_per_solve']:.2f} cycles/solve), max field error "
+          f"{max(errs.values()):.2e}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +152,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-steps", type=int, default=500,
+                    help="steps of the FP64 vs FP32-refined comparison on droplet256 (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -195,6 +237,10 @@ def main():
     del solvers
     torch.cuda.empty_cache()
 
+    precision = None
+    if args.precision_steps > 0:
+        precision = compare_precisions(P, torch, args.precision_steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
@@ -227,6 +273,7 @@ def main():
         "step_algorithmic_bytes": step_bytes,
         "step_kernel_ms": step_kernel_ms,
         "step_algorithmic_frac_hbm": (step_bytes / (step_kernel_ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
+        "fp64_vs_fp32_refined": precision,
     }
     print(json.dumps(out), flush=True)
 

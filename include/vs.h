@@ -54,7 +54,11 @@ typedef enum {
 enum { VS_POISEUILLE = 1, VS_COUETTE = 2 };
 /* vs_params.model */
 enum { VS_BENDING = 1, VS_CAHN_HILLIARD = 2 };
-/* vs_params.precision */
+/* vs_params.precision: VS_FP64 solves each Poisson problem by one exact spectral pass in FP64;
+ * VS_FP32_REFINED stores every spectral intermediate (transform outputs, tridiagonal data) in
+ * FP32 and wraps each solve in FP64 defect correction (residual in FP64 from the previous
+ * step's field, FP32-stored correction solve, FP64 update) until the FP64 relative residual
+ * meets poisson_rtol. Stencils, fields and the volume/area integrals stay FP64 in both. */
 enum { VS_FP64 = 1, VS_FP32_REFINED = 2 };
 /* vs_params.flags */
 enum { VS_ALLOW_UNSTABLE = 1 };
@@ -70,7 +74,8 @@ enum {
     VS_S_V = 0, VS_S_A = 1, VS_S_V0 = 2, VS_S_A0 = 3, VS_S_LAMBDA_V = 4, VS_S_GAMMA_A = 5,
     VS_S_RELRES = 6,   /* largest final relative residual of the Poisson solves of the last call */
     VS_S_STEP = 7,     /* number of completed time steps since vs_init                            */
-    VS_NSCALARS = 8
+    VS_S_CYCLES = 8,   /* Poisson refinement cycles run by the last vs_step call (all solves)      */
+    VS_NSCALARS = 9
 };
 
 /* Grid ("Numerical implementation"). ny counts both wall rows; ny >= 3.

@@ -33,6 +33,28 @@ struct Ptr3 {
 struct CPtr3 {
     const double* p[3];
 };
+// Pointers to the spectral intermediates, stored as ST (double, or float in the refined mode).
+template <class ST>
+struct SPtr3 {
+    ST* p[3];
+};
+
+// Loads widen to double and stores narrow from double: inside a kernel all arithmetic is FP64.
+__device__ __forceinline__ double ld(const double* p) { return *p; }
+__device__ __forceinline__ double ld(const float* p) { return (double)*p; }
+__device__ __forceinline__ void st(double* p, double v) { *p = v; }
+__device__ __forceinline__ void st(float* p, double v) { *p = (float)v; }
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ __forceinline__ double2 ld2(const float* p) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double* p, double a, double b) {
+    *reinterpret_cast<double2*>(p) = make_double2(a, b);
+}
+__device__ __forceinline__ void st2(float* p, double a, double b) {
+    *reinterpret_cast<float2*>(p) = make_float2((float)a, (float)b);
+}
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -174,9 +196,10 @@ constexpr int kTileElems = 1024;
 
 // rhs_dht_z: block = (rows r0 .. r0+rpb-1 of the interior, r = i*M + (j-1); component c).
 // correct = 0: transform b - (wall terms); correct = 1: transform b - L_h u.
+template <class ST>
 __global__ __launch_bounds__(kBlock) void k_rhs_dht_z(Dims d, FftPlan pz,
                                                      const double2* __restrict__ tw, RhsArgs rhs,
-                                                     CPtr3 u, int correct, Ptr3 spec,
+                                                     CPtr3 u, int correct, SPtr3<ST> spec,
                                                      const int* gate, int rpb) {
     if (gate && *gate) return;
     __shared__ double2 A[kTileElems];
@@ -200,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_dht_z(Dims d, FftPlan pz,
         set_part(&A[(lr >> 1) * n + k], lr & 1, b);
     }
     fft_tile(A, pz, nlines, tw);
-    double* sc = spec.p[c];
+    ST* sc = spec.p[c];
     for (int e = threadIdx.x; e < rpb * n; e += blockDim.x) {
         const int lr = e / n;
         const int p = e - lr * n;
@@ -208,13 +231,14 @@ __global__ __launch_bounds__(kBlock) void k_rhs_dht_z(Dims d, FftPlan pz,
         if (r >= nrows) continue;
         const int i = r / d.M;
         const int j = 1 + (r - i * d.M);
-        sc[node(d, i, j, p)] = hartley(A + (lr >> 1) * n, n, p, lr & 1);
+        st(sc + node(d, i, j, p), hartley(A + (lr >> 1) * n, n, p, lr & 1));
     }
 }
 
 // dht_x: block = (block of kb consecutive z-modes q, interior row j, component c).
+template <class ST>
 __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
-                                                 const double2* __restrict__ tw, Ptr3 spec,
+                                                 const double2* __restrict__ tw, SPtr3<ST> spec,
                                                  const int* gate, int kb) {
     if (gate && *gate) return;
     __shared__ double2 A[kTileElems];
@@ -223,12 +247,12 @@ __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
     const int c = blockIdx.z;
     const int j = 1 + blockIdx.y;
     const int q0 = blockIdx.x * kb;
-    double* s = spec.p[c];
+    ST* s = spec.p[c];
     for (int e = threadIdx.x; e < n * kb; e += blockDim.x) {
         const int i = e / kb;
         const int kk = e - i * kb;
         const int q = q0 + kk;
-        const double v = (q < d.nz) ? s[node(d, i, j, q)] : 0.0;
+        const double v = (q < d.nz) ? ld(s + node(d, i, j, q)) : 0.0;
         set_part(&A[(kk >> 1) * n + i], kk & 1, v);
     }
     fft_tile(A, px, nlines, tw);
@@ -237,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
         const int kk = e - p * kb;
         const int q = q0 + kk;
         if (q >= d.nz) continue;
-        s[node(d, p, j, q)] = hartley(A + (kk >> 1) * n, n, p, kk & 1);
+        st(s + node(d, p, j, q), hartley(A + (kk >> 1) * n, n, p, kk & 1));
     }
 }
 
@@ -252,8 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_dht_x(Dims d, FftPlan px,
 // wr (which may alias rd). Pivots come from cp[s * ncls]; loads run one chunk ahead. All lanes
 // of the wave call this together; inactive lanes pass act = false.
 // INPLACE: rd == wr (one pointer is used for both); otherwise rd and wr are distinct buffers.
-template <bool INPLACE, class Rhs>
-__device__ __forceinline__ void twisted_half(const double* __restrict__ rd, double* __restrict__ wr,
+template <bool INPLACE, class ST, class Rhs>
+__device__ __forceinline__ void twisted_half(const ST* __restrict__ rd, ST* __restrict__ wr,
                                              long sj, int M, int half, bool act,
                                              const double* __restrict__ cp, size_t ncls, Rhs rhs) {
     const int m = (M + 1) / 2;
@@ -261,13 +285,13 @@ __device__ __forceinline__ void twisted_half(const double* __restrict__ rd, doub
     const int j0 = half ? M : 1;                       // row of step 0 (the wall end)
     const int jd = half ? -1 : 1;
     const long dj = jd * sj;
-    double* wb = wr + (long)j0 * sj;
-    const double* rb = INPLACE ? wb : rd + (long)j0 * sj;
+    ST* wb = wr + (long)j0 * sj;
+    const ST* rb = INPLACE ? wb : rd + (long)j0 * sj;
     constexpr int CH = 8;
     double fv[CH], cv[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
-        fv[u] = (u < nr) ? rhs(j0 + u * jd, rb[u * dj]) : 0.0;
+        fv[u] = (u < nr) ? rhs(j0 + u * jd, ld(rb + u * dj)) : 0.0;
         cv[u] = (u < nr) ? cp[(size_t)u * ncls] : 0.0;
     }
     double acc = 0.0, clast = 0.0;
@@ -276,7 +300,7 @@ __device__ __forceinline__ void twisted_half(const double* __restrict__ rd, doub
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int sn = s0 + CH + u;
-            nf[u] = (sn < nr) ? rhs(j0 + sn * jd, rb[sn * dj]) : 0.0;
+            nf[u] = (sn < nr) ? rhs(j0 + sn * jd, ld(rb + sn * dj)) : 0.0;
             nc[u] = (sn < nr) ? cp[(size_t)sn * ncls] : 0.0;
         }
 #pragma unroll
@@ -284,7 +308,7 @@ __device__ __forceinline__ void twisted_half(const double* __restrict__ rd, doub
             if (s0 + u < nr) {
                 acc = cv[u] * (fv[u] - acc);
                 clast = cv[u];
-                wb[(s0 + u) * dj] = acc;
+                st(wb + (s0 + u) * dj, acc);
             }
         }
 #pragma unroll
@@ -302,12 +326,12 @@ __device__ __forceinline__ void twisted_half(const double* __restrict__ rd, doub
     const double gm = half ? acc : oacc, em = half ? clast : oc;
     const double Um = (dm - cm * gm) / (1.0 - cm * em);
     double unext = half ? (gm - em * Um) : Um;        // U at this lane's last row
-    wb[(nr - 1) * dj] = unext;
+    st(wb + (nr - 1) * dj, unext);
     // back substitution from step nr-2 towards the wall: U = d' - c' U_next
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
         const int sn = nr - 2 - u;
-        fv[u] = (sn >= 0) ? wb[sn * dj] : 0.0;
+        fv[u] = (sn >= 0) ? ld(wb + sn * dj) : 0.0;
         cv[u] = (sn >= 0) ? cp[(size_t)(sn >= 0 ? sn : 0) * ncls] : 0.0;
     }
     for (int s0 = nr - 2; s0 >= 0; s0 -= CH) {
@@ -315,14 +339,14 @@ __device__ __forceinline__ void twisted_half(const double* __restrict__ rd, doub
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int sn = s0 - CH - u;
-            nf[u] = (sn >= 0) ? wb[sn * dj] : 0.0;
+            nf[u] = (sn >= 0) ? ld(wb + sn * dj) : 0.0;
             nc[u] = (sn >= 0) ? cp[(size_t)(sn >= 0 ? sn : 0) * ncls] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             if (s0 - u >= 0) {
                 unext = fv[u] - cv[u] * unext;
-                wb[(s0 - u) * dj] = unext;
+                st(wb + (s0 - u) * dj, unext);
             }
         }
 #pragma unroll
@@ -360,12 +384,13 @@ __device__ __forceinline__ ModeLane mode_lane(const Dims& d, const double* __res
 
 // tridiag_y: one Poisson problem per component blockIdx.y: f_j = scale * B_j (B = the 2D
 // Hartley spectrum of the right-hand side, scale = h^2/(nx nz)), in place.
+template <class ST>
 __global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restrict__ tri,
-                                                 Ptr3 spec, const int* gate, double scale) {
+                                                 SPtr3<ST> spec, const int* gate, double scale) {
     if (gate && *gate) return;
     const ModeLane ml = mode_lane(d, tri);
-    double* col = spec.p[blockIdx.y] + ml.off;
-    twisted_half<true>(nullptr, col, d.nz, d.M, ml.half, ml.act, ml.cp, ml.ncls,
+    ST* col = spec.p[blockIdx.y] + ml.off;
+    twisted_half<true, ST>(nullptr, col, d.nz, d.M, ml.half, ml.act, ml.cp, ml.ncls,
                        [&](int, double v) { return scale * v; });
 }
 
@@ -375,19 +400,20 @@ __global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restri
 // plane lives only in mode (0, 0):
 //   f_j = -h^2 U_w(j) - [p = q = 0] ([j = 1] psi_lo + [j = M] psi_hi);
 // solved into spec2, leaving spec unchanged.
+template <class ST>
 __global__ __launch_bounds__(64) void k_tridiag_psi(Dims d, const double* __restrict__ tri,
-                                                   Ptr3 spec, Ptr3 spec2, double3 plo,
+                                                   SPtr3<ST> spec, SPtr3<ST> spec2, double3 plo,
                                                    double3 phi_) {
     const ModeLane ml = mode_lane(d, tri);
     const int c = blockIdx.y;
-    const double* col = spec.p[c] + ml.off;
-    double* col2 = spec2.p[c] + ml.off;
+    const ST* col = spec.p[c] + ml.off;
+    ST* col2 = spec2.p[c] + ml.off;
     const bool m00 = (ml.p == 0 && ml.q == 0);
     const double wlo = c == 0 ? plo.x : (c == 1 ? plo.y : plo.z);
     const double whi = c == 0 ? phi_.x : (c == 1 ? phi_.y : phi_.z);
     const double h2 = d.h * d.h;
     const int M = d.M;
-    twisted_half<false>(col, col2, d.nz, d.M, ml.half, ml.act, ml.cp, ml.ncls, [&](int j, double v) {
+    twisted_half<false, ST>(col, col2, d.nz, d.M, ml.half, ml.act, ml.cp, ml.ncls, [&](int j, double v) {
         double f = -h2 * v;
         if (m00) {
             if (j == 1) f -= wlo;
@@ -398,8 +424,9 @@ __global__ __launch_bounds__(64) void k_tridiag_psi(Dims d, const double* __rest
 }
 
 // dht_z_out: Hartley along z of the solved modes, then u = result (add = 0) or u += result.
+template <class ST>
 __global__ __launch_bounds__(kBlock) void k_dht_z_out(Dims d, FftPlan pz,
-                                                     const double2* __restrict__ tw, Ptr3 spec,
+                                                     const double2* __restrict__ tw, SPtr3<ST> spec,
                                                      Ptr3 u, int add, const int* gate, int rpb) {
     if (gate && *gate) return;
     __shared__ double2 A[kTileElems];
@@ -408,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_dht_z_out(Dims d, FftPlan pz,
     const int c = blockIdx.y;
     const int nrows = d.nx * d.M;
     const int r0 = blockIdx.x * rpb;
-    const double* sc = spec.p[c];
+    const ST* sc = spec.p[c];
     for (int e = threadIdx.x; e < rpb * n; e += blockDim.x) {
         const int lr = e / n;
         const int k = e - lr * n;
@@ -417,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_dht_z_out(Dims d, FftPlan pz,
         if (r < nrows) {
             const int i = r / d.M;
             const int j = 1 + (r - i * d.M);
-            v = sc[node(d, i, j, k)];
+            v = ld(sc + node(d, i, j, k));
         }
         set_part(&A[(lr >> 1) * n + k], lr & 1, v);
     }
@@ -542,9 +569,9 @@ __device__ __forceinline__ double rhs_row(const RhsArgs& a, const Dims& d, const
 // ordered per XCD. The right-hand side (a stencil for the vorticity source, the wall terms
 // or the residual) is first evaluated with lane-consecutive z indices (coalesced) into the
 // LDS tile, then pass 1 reads its strided inputs from there.
-template <int B, int A>
+template <int B, int A, class ST>
 __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict__ tw,
-                                              RhsArgs rhs, CPtr3 u, int correct, Ptr3 spec,
+                                              RhsArgs rhs, CPtr3 u, int correct, SPtr3<ST> spec,
                                               const int* gate) {
     if (gate && *gate) return;
     using P = TwoPass<B, A>;
@@ -563,13 +590,13 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
     const int nrows = d.nx * d.M;
     const int r0 = bx * 2 * L;
     const double* uc = u.p[c];
-    double* sc = spec.p[c];
+    ST* sc = spec.p[c];
     auto prep = [&](int ln) -> RowPair {
         return RowPair{row_base(d, r0 + 2 * ln, nrows), row_base(d, r0 + 2 * ln + 1, nrows)};
     };
     auto store = [&](const RowPair& rp, int p, double ha, double hb) {
-        if (rp.a >= 0) sc[rp.a + p] = ha;
-        if (rp.b >= 0) sc[rp.b + p] = hb;
+        if (rp.a >= 0) st(sc + rp.a + p, ha);
+        if (rp.b >= 0) st(sc + rp.b + p, hb);
     };
     if (!correct) {
         // b - wall terms: a pointwise read plus, on the first and last interior rows, the
@@ -599,8 +626,8 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
             return make_double2(rowval(o.x, o.z, k), rowval(o.y, o.w, k));
         };
         auto storew = [&](const int4& o, int p, double ha, double hb) {
-            if (o.x >= 0) sc[o.x + p] = ha;
-            if (o.y >= 0) sc[o.y + p] = hb;
+            if (o.x >= 0) st(sc + o.x + p, ha);
+            if (o.y >= 0) st(sc + o.y + p, hb);
         };
         two_pass_hartley<B, A, false>(Y, tw, prepw, load, storew);
         return;
@@ -639,8 +666,8 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
 
 // dht_x, two-pass form: block = (2L consecutive z-modes q, interior row j, component c);
 // lines are the q-pairs (q, q+1), read and written as one 16-byte value.
-template <int B, int A>
-__global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ tw, Ptr3 spec,
+template <int B, int A, class ST>
+__global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ tw, SPtr3<ST> spec,
                                           const int* gate) {
     if (gate && *gate) return;
     using P = TwoPass<B, A>;
@@ -648,7 +675,7 @@ __global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ t
     const int c = blockIdx.z;
     const int j = 1 + blockIdx.y;
     const int q0 = blockIdx.x * 2 * P::L;
-    double* s = spec.p[c];
+    ST* s = spec.p[c];
     const int pstride = d.ny * d.nz;
     auto prep = [&](int line) -> int {
         const int q = q0 + 2 * line;
@@ -656,17 +683,17 @@ __global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ t
     };
     auto load = [&](int o, int k1, int k2) -> double2 {
         if (o < 0) return make_double2(0.0, 0.0);
-        return *reinterpret_cast<const double2*>(s + o + (k1 + A * k2) * pstride);
+        return ld2(s + o + (k1 + A * k2) * pstride);
     };
     auto store = [&](int o, int p, double ha, double hb) {
-        if (o >= 0) *reinterpret_cast<double2*>(s + o + p * pstride) = make_double2(ha, hb);
+        if (o >= 0) st2(s + o + p * pstride, ha, hb);
     };
     two_pass_hartley<B, A, true>(Y, tw, prep, load, store);
 }
 
 // dht_z_out, two-pass form: block = (2L consecutive interior rows, component c).
-template <int B, int A>
-__global__ __launch_bounds__(64) void k_hz_out(Dims d, const double2* __restrict__ tw, Ptr3 spec,
+template <int B, int A, class ST>
+__global__ __launch_bounds__(64) void k_hz_out(Dims d, const double2* __restrict__ tw, SPtr3<ST> spec,
                                               Ptr3 u, int add, const int* gate) {
     if (gate && *gate) return;
     using P = TwoPass<B, A>;
@@ -674,14 +701,14 @@ __global__ __launch_bounds__(64) void k_hz_out(Dims d, const double2* __restrict
     const int c = blockIdx.y;
     const int nrows = d.nx * d.M;
     const int r0 = blockIdx.x * 2 * P::L;
-    const double* sc = spec.p[c];
+    const ST* sc = spec.p[c];
     double* uc = u.p[c];
     auto prep = [&](int line) -> RowPair {
         return RowPair{row_base(d, r0 + 2 * line, nrows), row_base(d, r0 + 2 * line + 1, nrows)};
     };
     auto load = [&](const RowPair& rp, int k1, int k2) -> double2 {
         const int k = k1 + A * k2;
-        return make_double2(rp.a >= 0 ? sc[rp.a + k] : 0.0, rp.b >= 0 ? sc[rp.b + k] : 0.0);
+        return make_double2(rp.a >= 0 ? ld(sc + rp.a + k) : 0.0, rp.b >= 0 ? ld(sc + rp.b + k) : 0.0);
     };
     auto store = [&](const RowPair& rp, int p, double ha, double hb) {
         if (rp.a >= 0) {
@@ -903,88 +930,129 @@ int x_modes_per_block(const Dims& d) {
     return kb;
 }
 
-}  // namespace
+template <class ST>
+SPtr3<ST> sptr(void* const spec[3], int ncomp) {
+    return SPtr3<ST>{{static_cast<ST*>(spec[0]), ncomp > 1 ? static_cast<ST*>(spec[1]) : nullptr,
+                      ncomp > 2 ? static_cast<ST*>(spec[2]) : nullptr}};
+}
 
-void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
-                      const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
-                      double* const spec[3], const int* gate) {
+template <class ST>
+void rhs_dht_z_t(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                 const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
+                 void* const spec[3], const int* gate) {
     const int nrows = d.nx * d.M;
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
-    Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
+    const SPtr3<ST> sp = sptr<ST>(spec, ncomp);
     int B, A;
     two_pass_shape(d.nz, B, A);
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int rows = 2 * TwoPass<b, a>::L;                                                 \
-        hipLaunchKernelGGL((k_rhs_hz<b, a>), dim3((nrows + rows - 1) / rows, ncomp), dim3(64), \
-                           0, s, d, twz, rhs, uu, correct, sp, gate);                          \
+        hipLaunchKernelGGL((k_rhs_hz<b, a, ST>), dim3((nrows + rows - 1) / rows, ncomp),       \
+                           dim3(64), 0, s, d, twz, rhs, uu, correct, sp, gate);                \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int rpb = z_rows_per_block(d);
-    hipLaunchKernelGGL(k_rhs_dht_z, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s, d,
-                       pz, twz, rhs, uu, correct, sp, gate, rpb);
+    hipLaunchKernelGGL(k_rhs_dht_z<ST>, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s,
+                       d, pz, twz, rhs, uu, correct, sp, gate, rpb);
 }
 
-void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
-                  double* const spec[3], int ncomp, const int* gate) {
-    Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
+template <class ST>
+void dht_x_t(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
+             void* const spec[3], int ncomp, const int* gate) {
+    const SPtr3<ST> sp = sptr<ST>(spec, ncomp);
     int B, A;
     two_pass_shape(d.nx, B, A);
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int qs = 2 * TwoPass<b, a>::L;                                                   \
-        hipLaunchKernelGGL((k_hx<b, a>), dim3((d.nz + qs - 1) / qs, d.M, ncomp), dim3(64), 0,  \
-                           s, d, twx, sp, gate);                                               \
+        hipLaunchKernelGGL((k_hx<b, a, ST>), dim3((d.nz + qs - 1) / qs, d.M, ncomp), dim3(64), \
+                           0, s, d, twx, sp, gate);                                            \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int kb = x_modes_per_block(d);
-    hipLaunchKernelGGL(k_dht_x, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), 0, s, d,
+    hipLaunchKernelGGL(k_dht_x<ST>, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), 0, s, d,
                        px, twx, sp, gate, kb);
 }
 
-void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
-                      int ncomp, const int* gate) {
-    Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
-    const double scale = d.h * d.h / ((double)d.nx * d.nz);
-    const int threads = 2 * d.nx * d.nz;
-    hipLaunchKernelGGL(k_tridiag_y, dim3((threads + 63) / 64, ncomp), dim3(64), 0, s, d, tri, sp,
-                       gate, scale);
-}
-
-void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
-                        double* const spec2[3], const double psi_lo[3], const double psi_hi[3]) {
-    Ptr3 sp{{spec[0], spec[1], spec[2]}};
-    Ptr3 sp2{{spec2[0], spec2[1], spec2[2]}};
-    const int threads = 2 * d.nx * d.nz;
-    hipLaunchKernelGGL(k_tridiag_psi, dim3((threads + 63) / 64, 3), dim3(64), 0, s, d, tri, sp, sp2,
-                       make_double3(psi_lo[0], psi_lo[1], psi_lo[2]),
-                       make_double3(psi_hi[0], psi_hi[1], psi_hi[2]));
-}
-
-void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
-                      double* const spec[3], double* const u[3], int ncomp, int add,
-                      const int* gate) {
+template <class ST>
+void dht_z_out_t(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                 void* const spec[3], double* const u[3], int ncomp, int add, const int* gate) {
     const int nrows = d.nx * d.M;
-    Ptr3 sp{{spec[0], ncomp > 1 ? spec[1] : nullptr, ncomp > 2 ? spec[2] : nullptr}};
+    const SPtr3<ST> sp = sptr<ST>(spec, ncomp);
     Ptr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
     int B, A;
     two_pass_shape(d.nz, B, A);
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int rows = 2 * TwoPass<b, a>::L;                                                 \
-        hipLaunchKernelGGL((k_hz_out<b, a>), dim3((nrows + rows - 1) / rows, ncomp), dim3(64), \
-                           0, s, d, twz, sp, uu, add, gate);                                   \
+        hipLaunchKernelGGL((k_hz_out<b, a, ST>), dim3((nrows + rows - 1) / rows, ncomp),       \
+                           dim3(64), 0, s, d, twz, sp, uu, add, gate);                         \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int rpb = z_rows_per_block(d);
-    hipLaunchKernelGGL(k_dht_z_out, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s, d,
-                       pz, twz, sp, uu, add, gate, rpb);
+    hipLaunchKernelGGL(k_dht_z_out<ST>, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s,
+                       d, pz, twz, sp, uu, add, gate, rpb);
+}
+
+}  // namespace
+
+void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                      const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
+                      void* const spec[3], bool f32, const int* gate) {
+    if (f32)
+        rhs_dht_z_t<float>(s, d, pz, twz, rhs, u, ncomp, correct, spec, gate);
+    else
+        rhs_dht_z_t<double>(s, d, pz, twz, rhs, u, ncomp, correct, spec, gate);
+}
+
+void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
+                  void* const spec[3], int ncomp, bool f32, const int* gate) {
+    if (f32)
+        dht_x_t<float>(s, d, px, twx, spec, ncomp, gate);
+    else
+        dht_x_t<double>(s, d, px, twx, spec, ncomp, gate);
+}
+
+void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                      int ncomp, bool f32, const int* gate) {
+    const double scale = d.h * d.h / ((double)d.nx * d.nz);
+    const dim3 grid((2 * d.nx * d.nz + 63) / 64, ncomp);
+    if (f32)
+        hipLaunchKernelGGL(k_tridiag_y<float>, grid, dim3(64), 0, s, d, tri, sptr<float>(spec, ncomp),
+                           gate, scale);
+    else
+        hipLaunchKernelGGL(k_tridiag_y<double>, grid, dim3(64), 0, s, d, tri,
+                           sptr<double>(spec, ncomp), gate, scale);
+}
+
+void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                        void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
+                        bool f32) {
+    const dim3 grid((2 * d.nx * d.nz + 63) / 64, 3);
+    const double3 lo = make_double3(psi_lo[0], psi_lo[1], psi_lo[2]);
+    const double3 hi = make_double3(psi_hi[0], psi_hi[1], psi_hi[2]);
+    if (f32)
+        hipLaunchKernelGGL(k_tridiag_psi<float>, grid, dim3(64), 0, s, d, tri, sptr<float>(spec, 3),
+                           sptr<float>(spec2, 3), lo, hi);
+    else
+        hipLaunchKernelGGL(k_tridiag_psi<double>, grid, dim3(64), 0, s, d, tri,
+                           sptr<double>(spec, 3), sptr<double>(spec2, 3), lo, hi);
+}
+
+void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                      void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
+                      const int* gate) {
+    if (f32)
+        dht_z_out_t<float>(s, d, pz, twz, spec, u, ncomp, add, gate);
+    else
+        dht_z_out_t<double>(s, d, pz, twz, spec, u, ncomp, add, gate);
 }
 
 int resid_blocks(const Dims& d) {

@@ -111,8 +111,8 @@ vs_status check_params(const vs_params* p) {
     if (!p) return fail(VS_E_ARG, "params is NULL");
     if (p->model != VS_BENDING && p->model != VS_CAHN_HILLIARD)
         return fail(VS_E_ARG, "model must be VS_BENDING or VS_CAHN_HILLIARD");
-    if (p->precision != VS_FP64)
-        return fail(VS_E_UNSUPPORTED, "precision %d not built (VS_FP64 only)", p->precision);
+    if (p->precision != VS_FP64 && p->precision != VS_FP32_REFINED)
+        return fail(VS_E_ARG, "precision must be VS_FP64 or VS_FP32_REFINED");
     if (!(p->eta > 0.0)) return fail(VS_E_ARG, "eta must be > 0");
     if (!(p->mobility > 0.0)) return fail(VS_E_ARG, "mobility must be > 0");
     if (!(p->eps > 0.0)) return fail(VS_E_ARG, "eps must be > 0");
@@ -154,9 +154,10 @@ struct vs_state {
     double* mu = nullptr;
     double* om[3] = {};
     double* ps[3] = {};
-    double* spec[3] = {};
+    void* spec[3] = {};
     double* src[3] = {};
-    double* spec2[3] = {};
+    void* spec2[3] = {};
+    bool f32 = false;         // refined mode: spectral intermediates stored as float
     double psi_wall_lo[3] = {0, 0, 0}, psi_wall_hi[3] = {0, 0, 0};
     double2* twx = nullptr;
     double2* twz = nullptr;
@@ -169,6 +170,7 @@ struct vs_state {
     double gamma_host = 0.0;  // gamma_A as of the last synchronisation
     long long step = 0;
     double last_relres = 0.0;
+    int last_cycles = 0;
     // event timer
     bool prof_on = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
@@ -233,23 +235,25 @@ void enqueue_cycle(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncom
     const double* const cu[3] = {u[0], u[1], u[2]};
     const int k_rhs = tag == TAG_OMEGA ? K_RHS_Z_OMEGA : tag == TAG_PSI ? K_RHS_Z_PSI : K_RHS_Z_FIELD;
     timed(S, k_rhs, [&] {
-        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rhs, cu, ncomp, correct, S->spec, gate);
+        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rhs, cu, ncomp, correct, S->spec, S->f32, gate);
     });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
-    timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, ncomp, gate); });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, gate); });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, S->f32, gate); });
+    timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, ncomp, S->f32, gate); });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, ncomp, S->f32, gate); });
     timed(S, K_DHT_Z_OUT, [&] {
-        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, u, ncomp, correct, gate);
+        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, u, ncomp, correct, S->f32, gate);
     });
 }
 
 // Verified solve: cycle 0, then up to max_cycles-1 correction cycles gated on the device flag
 // (a cycle runs only while the previous check missed rtol); each cycle ends with a check.
+// warm = 1: cycle 0 too solves for the correction of the residual of the incoming u (the
+// refined mode's defect correction from the previous time step's field).
 void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncomp, double rtol,
-                   int max_cycles, int tag) {
+                   int max_cycles, int tag, int warm = 0) {
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
         const int* gate = cyc == 0 ? nullptr : S->istat + IS_CONV;
-        enqueue_cycle(S, rhs, u, ncomp, cyc > 0, tag, gate);
+        enqueue_cycle(S, rhs, u, ncomp, (cyc > 0 || warm) ? 1 : 0, tag, gate);
         enqueue_verify(S, rhs, u, ncomp, rtol, cyc, cyc == max_cycles - 1, tag, gate);
     }
 }
@@ -286,22 +290,29 @@ void enqueue_flow(vs_state* S, const double* phi) {
     rp.f[0] = S->om[0];
     rp.f[1] = S->om[1];
     rp.f[2] = S->om[2];
+    if (S->f32) {
+        // refined mode: FP32-stored spectral corrections of the FP64 residual, from the warm
+        // start, until the FP64 relative residual meets rtol
+        enqueue_solve(S, rv, S->om, 3, rtol, mc, TAG_OMEGA, 1);
+        enqueue_solve(S, rp, S->ps, 3, rtol, mc, TAG_PSI, 1);
+        return;
+    }
     const double* const cu[3] = {S->om[0], S->om[1], S->om[2]};
     timed(S, K_RHS_Z_OMEGA, [&] {
-        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rv, cu, 3, 0, S->spec, nullptr);
+        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rv, cu, 3, 0, S->spec, false, nullptr);
     });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, nullptr); });
-    timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, 3, nullptr); });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
+    timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, 3, false, nullptr); });
     timed(S, K_TRIDIAG_PSI, [&] {
-        launch_tridiag_psi(S->stream, d, S->tri, S->spec, S->spec2, S->psi_wall_lo, S->psi_wall_hi);
+        launch_tridiag_psi(S->stream, d, S->tri, S->spec, S->spec2, S->psi_wall_lo, S->psi_wall_hi, false);
     });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, nullptr); });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
     timed(S, K_DHT_Z_OUT, [&] {
-        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, S->om, 3, 0, nullptr);
+        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, S->om, 3, 0, false, nullptr);
     });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec2, 3, nullptr); });
+    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec2, 3, false, nullptr); });
     timed(S, K_DHT_Z_OUT, [&] {
-        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec2, S->ps, 3, 0, nullptr);
+        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec2, S->ps, 3, 0, false, nullptr);
     });
     enqueue_verify(S, rv, S->om, 3, rtol, 0, mc == 1, TAG_OMEGA, nullptr);
     for (int cyc = 1; cyc < mc; ++cyc) {
@@ -339,6 +350,7 @@ vs_status collect(vs_state* S, const char* what) {
     HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
     S->gamma_host = sc[SC_GAMMA];
     S->last_relres = sc[SC_RELRES_MAX];
+    S->last_cycles = ist[IS_CYCLES];
     if (ist[IS_FLAGS] & ST_NONFINITE)
         return fail(VS_E_NONFINITE, "%s: non-finite value in a residual norm or in V, A", what);
     if (ist[IS_FLAGS] & ST_NOCONV)
@@ -413,10 +425,11 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     for (int c = 0; c < 3; ++c) {
         S->om[c] = field(3 + c);
         S->ps[c] = field(6 + c);
-        S->spec[c] = (double*)(S->ws + L.off_spec + c * fb);
+        S->spec[c] = (void*)(S->ws + L.off_spec + c * fb);
         S->src[c] = (double*)(S->ws + L.off_src + c * fb);
-        S->spec2[c] = (double*)(S->ws + L.off_spec2 + c * fb);
+        S->spec2[c] = (void*)(S->ws + L.off_spec2 + c * fb);
     }
+    S->f32 = params->precision == VS_FP32_REFINED;
     S->twx = (double2*)(S->ws + L.off_twx);
     S->twz = (double2*)(S->ws + L.off_twz);
     S->tri = (double*)(S->ws + L.off_tri);
@@ -594,6 +607,7 @@ vs_status vs_get_scalars(vs_state* S, double out[VS_NSCALARS]) {
     out[VS_S_GAMMA_A] = sc[SC_GAMMA];
     out[VS_S_RELRES] = S->last_relres;
     out[VS_S_STEP] = (double)S->step;
+    out[VS_S_CYCLES] = (double)S->last_cycles;
     return VS_OK;
 }
 

@@ -99,20 +99,23 @@ void launch_source(hipStream_t s, const Dims& d, const double* phi, const double
 void launch_reset_stats(hipStream_t s, double* scal, int* istat);
 
 // ---------------------------------------------------------------- spectral Poisson
+// Spectral pipeline. The spectral intermediates (spec, spec2) are stored as double, or as
+// float when f32 is set (the refined mode); kernel arithmetic is FP64 either way.
 // Forward: b~ (direct) or r = b - L_h u (correct) on interior rows, 2D Hartley in z then x.
 void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
-                      double* const spec[3], const int* gate);
+                      void* const spec[3], bool f32, const int* gate);
 void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
-                  double* const spec[3], int ncomp, const int* gate);
-void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
-                      int ncomp, const int* gate);
+                  void* const spec[3], int ncomp, bool f32, const int* gate);
+void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                      int ncomp, bool f32, const int* gate);
 // Stream-vector modes into spec2 from the vorticity modes left in spec by launch_tridiag_y
 // (psi wall values constant over each wall plane: psi_lo at j = 0, psi_hi at j = ny-1).
-void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, double* const spec[3],
-                        double* const spec2[3], const double psi_lo[3], const double psi_hi[3]);
+void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                        void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
+                        bool f32);
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
-                      double* const spec[3], double* const u[3], int ncomp, int add,
+                      void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
                       const int* gate);
 int resid_blocks(const Dims& d);
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,

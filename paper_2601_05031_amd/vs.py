@@ -8,7 +8,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvs.so")
@@ -32,7 +31,7 @@ VS_FP64, VS_FP32_REFINED = 1, 2
 VS_ALLOW_UNSTABLE = 1
 
 FIELDS = {"phi": 0, "mu": 1, "omega_x": 2, "omega_y": 3, "omega_z": 4, "psi_x": 5, "psi_y": 6, "psi_z": 7}
-SCALARS = ["V", "A", "V0", "A0", "lambda_V", "gamma_A", "relres", "step"]
+SCALARS = ["V", "A", "V0", "A0", "lambda_V", "gamma_A", "relres", "step", "cycles"]
 
 _WALL_KINDS = {"poiseuille": VS_POISEUILLE, "couette": VS_COUETTE}
 _MODELS = {"bending": VS_BENDING, "cahn_hilliard": VS_CAHN_HILLIARD}
@@ -123,14 +122,6 @@ def workspace_bytes(grid, params: VsParams) -> int:
     return n.value
 
 
-@dataclass
-class Grid:
-    nx: int
-    ny: int
-    nz: int
-    h: float = 1.0
-
-
 class Solver:
     """One simulation on one GPU: owns a torch workspace tensor and a vs_state."""
 
@@ -199,7 +190,7 @@ class Solver:
         return {k: self.field(k).cpu().numpy() for k in FIELDS}
 
     def scalars(self) -> dict:
-        out = (ctypes.c_double * 8)()
+        out = (ctypes.c_double * len(SCALARS))()
         _check(lib().vs_get_scalars(self._st, out), "vs_get_scalars")
         return dict(zip(SCALARS, list(out)))
 
@@ -238,11 +229,11 @@ class Solver:
             pass
 
 
-def solver_for(workload, device="cuda:0", **overrides) -> "Solver":
+def solver_for(workload, device="cuda:0", precision="fp64", **overrides) -> "Solver":
     """Build a Solver from a workloads.Workload (seeded phi0 included)."""
     w = workload.with_(**overrides) if overrides else workload
     p = w.params()
     rtol = p.pop("rtol")
     mc = p.pop("max_cycles")
     return Solver((w.grid.nx, w.grid.ny, w.grid.nz, w.grid.h), w.walls(),
-                  dict(p, rtol=rtol, max_cycles=mc), w.phi0(), device=device)
+                  dict(p, rtol=rtol, max_cycles=mc, precision=precision), w.phi0(), device=device)

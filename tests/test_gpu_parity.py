@@ -283,3 +283,62 @@ def test_grad_step_not_built():
 def test_phi_sphere_helper_shapes():
     g = GridSpec(8, 8, 8)
     assert phi_sphere(g, 2.0, 1.0).shape == (8, 8, 8)
+
+
+# ------------------------------------------------------------------ FP32-refined mode
+TOL_REFINED = 1e-6
+
+
+def test_refined_poisson_needs_and_gets_refinement():
+    """FP32-stored spectral solves inside FP64 defect correction reach rtol = 1e-12 after a
+    few cycles; one cycle alone stops near FP32 accuracy."""
+    shape = (32, 33, 48)
+    say(f"case refined poisson {shape}")
+    w = workload("vesicle32").with_(grid=GridSpec(*shape, h=0.5), shape="sphere", R0=4.0)
+    s = P.solver_for(w, precision="fp32_refined")
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(shape)
+    u0 = rng.standard_normal(shape)
+    g = O.Grid(*shape, h=0.5)
+    ref = O.poisson_solve(f[:, 1:-1, :], u0[:, 0, :], u0[:, -1, :], g)
+    ft = torch.tensor(f, device="cuda")
+    ut = torch.tensor(u0, device="cuda")
+    code1, cyc1, rel1 = s.poisson_solve(ft, ut, rtol=1e-12, max_cycles=1)
+    ut = torch.tensor(u0, device="cuda")
+    code, cycles, rel = s.poisson_solve(ft, ut, rtol=1e-12, max_cycles=6)
+    err = rel_l2(ut.cpu().numpy()[:, 1:-1, :], ref)
+    s.close()
+    say(f"  one cycle: relres={rel1:.2e}; refined: cycles={cycles} relres={rel:.2e} relL2={err:.2e}")
+    assert code1 == V.VS_E_NOCONV and 1e-9 < rel1 < 1e-5
+    assert code == V.VS_OK and 2 <= cycles <= 6 and rel <= 1e-12 and err <= 1e-10
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_refined_step_parity_vesicle32(seed):
+    w = workload("vesicle32", seed=seed, max_cycles=4)
+    say(f"case refined vesicle32 seed={seed}")
+    s = P.solver_for(w, precision="fp32_refined")
+    s.step(w.dt, w.nsteps)
+    got = s.fields()
+    sc = s.scalars()
+    s.close()
+    g, walls, p = oracle_objs(w)
+    ref = O.run(g, walls, p, w.phi0(), w.dt, w.nsteps)
+    compare(got, ref_fields(ref), tol=TOL_REFINED, label="refined 5 steps")
+    assert sc["relres"] <= w.rtol
+
+
+def test_refined_droplet256_full_size():
+    """The Cahn-Hilliard droplet in Couette flow at its full 128 x 128 x 256 size, first 2
+    steps, refined mode against the FP64 oracle."""
+    w = workload("droplet256", nsteps=2, max_cycles=4)
+    say(f"case refined droplet256 {w.grid.shape}")
+    s = P.solver_for(w, precision="fp32_refined")
+    s.step(w.dt, 2)
+    got = s.fields()
+    sc = s.scalars()
+    s.close()
+    g, walls, p = oracle_objs(w)
+    ref = O.run(g, walls, p, w.phi0(), w.dt, 2)
+    compare(got, ref_fields(ref), tol=TOL_REFINED, label="refined droplet256 2 steps")
+    assert sc["relres"] <= w.rtol
