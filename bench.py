@@ -142,6 +142,58 @@ def compare_precisions(P, torch, steps: int) -> dict:
     return out
 
 
+def batched_run(P, torch, steps: int, nstreams: int) -> dict:
+    """The 64-instance batch (grids drawn from 48^3..128^3, instance i seeded with 1000 + i):
+    every instance advanced `steps` time steps through one captured HIP graph per two steps,
+    against the same instances stepped one after another with vs_step."""
+    from collections import Counter
+
+    from workloads import batch_instances
+
+    ws = batch_instances(64)
+    t0 = time.perf_counter()
+    phis = [w.phi0() for w in ws]
+    print(f"bench: batch seed shapes built in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    cells = sum(w.grid.N for w in ws)
+    dts = [w.dt for w in ws]
+    out = {"workload": "batch64", "instances": len(ws), "steps": steps, "streams": nstreams,
+           "grids": {f"{n}^3": c for n, c in sorted(Counter(w.grid.nx for w in ws).items())},
+           "cells_per_batch_step": cells, "poisson_rtol": ws[0].rtol}
+    for prec, mc in (("fp32_refined", 4), ("fp64", 1)):
+        solvers = [P.solver_for(w, precision=prec, max_cycles=mc, phi0=phi) for w, phi in zip(ws, phis)]
+        b = P.Batch(solvers, nstreams=nstreams)
+        b.step(dts, 2)                        # capture + first replay, untimed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(dts, steps)
+        tb = time.perf_counter() - t0
+        b.close()
+        sc = [s.scalars() for s in solvers]
+        for s, dt in zip(solvers, dts):       # the same work, one instance after another
+            s.step(dt, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, dt in zip(solvers, dts):
+            s.step(dt, steps)
+        ts = time.perf_counter() - t0
+        out[prec] = {"cell_updates_per_s": cells * steps / tb, "ms_per_batch_step": 1e3 * tb / steps,
+                     "instance_steps_per_s": len(ws) * steps / tb,
+                     "sequential_cell_updates_per_s": cells * steps / ts,
+                     "speedup_over_sequential": ts / tb,
+                     "max_relres": max(x["relres"] for x in sc),
+                     "cycles_per_solve": sum(x["cycles"] for x in sc) / (2.0 * steps * len(ws)),
+                     "poisson_max_cycles": mc}
+        print(f"bench: batch64 {prec}: {1e3 * tb / steps:.2f} ms/batch step "
+              f"({cells * steps / tb:.3e} cell-updates/s), sequential {1e3 * ts / steps:.2f} ms",
+              file=sys.stderr, flush=True)
+        for s in solvers:
+            s.close()
+        del solvers, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +206,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=500,
                     help="steps of the FP64 vs FP32-refined comparison on droplet256 (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="steps of the 64-instance batch (0 = skip)")
+    ap.add_argument("--batch-streams", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -241,6 +296,10 @@ def main():
     if args.precision_steps > 0:
         precision = compare_precisions(P, torch, args.precision_steps)
 
+    batched = None
+    if args.batch_steps > 0:
+        batched = batched_run(P, torch, args.batch_steps + (args.batch_steps & 1), args.batch_streams)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
@@ -274,6 +333,7 @@ def main():
         "step_kernel_ms": step_kernel_ms,
         "step_algorithmic_frac_hbm": (step_bytes / (step_kernel_ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
         "fp64_vs_fp32_refined": precision,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

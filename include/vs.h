@@ -191,6 +191,24 @@ int32_t vs_profile_count(void);
 const char* vs_profile_name(int32_t kernel);
 vs_status vs_profile_read(vs_state* state, int32_t kernel, double* total_ms, int64_t* launches);
 
+/* Batches (many independent instances, e.g. vesicles of different grids and parameters).
+ * vs_batch_create groups n states made by vs_init (each keeps its own workspace). It creates
+ * nstreams HIP streams (instance i runs on stream i % nstreams) and moves every state onto its
+ * stream; `stream` (a hipStream_t, NULL = default) is the origin the batch forks from and
+ * joins to. vs_batch_step captures two time steps of every instance into one HIP graph (the
+ * capture is redone when dt changes) and replays it nsteps/2 times on the origin stream, so a
+ * whole batch step is one graph launch and independent instances run concurrently on the
+ * GPU. nsteps must be even. dt: host array of n time steps. Each instance is checked against
+ * its stability bound first; statuses are collected after one synchronisation (the first
+ * failing instance's status is returned). vs_batch_destroy frees the batch and moves the
+ * states back to the origin stream; the states stay valid and are destroyed by vs_destroy.
+ * A state belongs to at most one batch; do not call vs_step on it while the batch exists. */
+typedef struct vs_batch vs_batch;
+vs_status vs_batch_create(vs_state* const* states, int32_t n, void* stream, int32_t nstreams,
+                          vs_batch** out);
+vs_status vs_batch_step(vs_batch* batch, const double* dt, int32_t nsteps);
+void vs_batch_destroy(vs_batch* batch);
+
 /* Free the host-side state (the workspace stays the caller's). NULL is ignored. */
 void vs_destroy(vs_state* state);
 

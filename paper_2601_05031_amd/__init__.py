@@ -2,6 +2,7 @@
 (arXiv 2601.05031): HIP kernels behind the C ABI of include/vs.h, with a ctypes binding."""
 from .vs import (  # noqa: F401
     FIELDS,
+    Batch,
     SCALARS,
     Solver,
     VsError,

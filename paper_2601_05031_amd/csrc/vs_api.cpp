@@ -696,6 +696,165 @@ vs_status vs_profile_read(vs_state* S, int32_t kernel, double* total_ms, int64_t
     return VS_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------------------ batches
+struct vs_batch {
+    std::vector<vs_state*> st;
+    std::vector<hipStream_t> streams;   // instance i runs on streams[i % streams.size()]
+    std::vector<hipEvent_t> ev;         // fork event + one join event per stream
+    hipStream_t origin = nullptr;       // the caller's stream: graph launches go here
+    hipStream_t cap = nullptr;          // private stream the graph is captured from (the
+                                        // caller's may be the null stream, which cannot capture)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double> dt;             // time steps baked into the captured graph
+};
+
+namespace {
+
+void batch_release_graph(vs_batch* B) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+}
+
+// Capture two time steps of every instance: fork from the origin stream to the instance
+// streams, enqueue, join back. Two steps return each state's phi buffer to its start, so the
+// graph can be replayed.
+vs_status batch_capture(vs_batch* B, const double* dt) {
+    batch_release_graph(B);
+    const int ns = (int)B->streams.size();
+    HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    vs_status st = VS_OK;
+    auto body = [&]() -> hipError_t {
+        hipError_t e = hipEventRecord(B->ev[0], B->cap);
+        if (e != hipSuccess) return e;
+        for (int k = 0; k < ns; ++k)
+            if ((e = hipStreamWaitEvent(B->streams[k], B->ev[0], 0)) != hipSuccess) return e;
+        for (size_t i = 0; i < B->st.size(); ++i) {
+            vs_state* S = B->st[i];
+            enqueue_step(S, dt[i]);
+            enqueue_step(S, dt[i]);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int k = 0; k < ns; ++k) {
+            if ((e = hipEventRecord(B->ev[1 + k], B->streams[k])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(B->cap, B->ev[1 + k], 0)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const hipError_t eb = body();
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(B->cap, &g);
+    if (eb != hipSuccess) st = fail(VS_E_HIP, "batch capture failed: %s", hipGetErrorString(eb));
+    else if (ee != hipSuccess) st = fail(VS_E_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+    if (st != VS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    B->graph = g;
+    HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    B->dt.assign(dt, dt + B->st.size());
+    return VS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vs_status vs_batch_create(vs_state* const* states, int32_t n, void* stream, int32_t nstreams,
+                          vs_batch** out) {
+    if (!out) return fail(VS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!states || n < 1) return fail(VS_E_ARG, "need n >= 1 states");
+    if (nstreams < 1) return fail(VS_E_ARG, "nstreams must be >= 1");
+    for (int i = 0; i < n; ++i) {
+        if (!states[i]) return fail(VS_E_STATE, "state %d is NULL", i);
+        for (int k = 0; k < i; ++k)
+            if (states[k] == states[i]) return fail(VS_E_ARG, "state %d appears twice", i);
+    }
+    vs_batch* B = new vs_batch();
+    B->st.assign(states, states + n);
+    B->origin = (hipStream_t)stream;
+    const int ns = nstreams < n ? nstreams : n;
+    auto bail = [&](vs_status e) {
+        if (B->cap) (void)hipStreamDestroy(B->cap);
+        for (hipStream_t q : B->streams) (void)hipStreamDestroy(q);
+        for (hipEvent_t x : B->ev) (void)hipEventDestroy(x);
+        delete B;
+        return e;
+    };
+    if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(VS_E_HIP, "hipStreamCreate failed"));
+    for (int k = 0; k < ns; ++k) {
+        hipStream_t q = nullptr;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(VS_E_HIP, "hipStreamCreate failed"));
+        B->streams.push_back(q);
+    }
+    for (int k = 0; k <= ns; ++k) {
+        hipEvent_t x = nullptr;
+        if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(VS_E_HIP, "hipEventCreate failed"));
+        B->ev.push_back(x);
+    }
+    // finish each state's pending work, then move it onto its batch stream
+    for (int i = 0; i < n; ++i) {
+        vs_state* S = B->st[i];
+        if (hipStreamSynchronize(S->stream) != hipSuccess) return bail(fail(VS_E_HIP, "sync failed"));
+        S->prof_on = false;
+        S->stream = B->streams[i % ns];
+    }
+    *out = B;
+    return VS_OK;
+}
+
+vs_status vs_batch_step(vs_batch* B, const double* dt, int32_t nsteps) {
+    if (!B) return fail(VS_E_STATE, "batch is NULL");
+    if (!dt) return fail(VS_E_ARG, "dt is NULL");
+    if (nsteps < 2 || (nsteps & 1)) return fail(VS_E_ARG, "nsteps must be even and >= 2");
+    const size_t n = B->st.size();
+    for (size_t i = 0; i < n; ++i) {
+        vs_state* S = B->st[i];
+        if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(VS_E_ARG, "dt[%zu] must be > 0", i);
+        if (!(S->p.flags & VS_ALLOW_UNSTABLE) && dt[i] * stability_rate(S) > 2.0)
+            return fail(VS_E_UNSTABLE, "instance %zu: dt = %.4g exceeds the forward-Euler bound %.4g",
+                        i, dt[i], 2.0 / stability_rate(S));
+    }
+    bool same = B->exec && B->dt.size() == n;
+    for (size_t i = 0; same && i < n; ++i) same = B->dt[i] == dt[i];
+    if (!same) {
+        const vs_status st = batch_capture(B, dt);
+        if (st != VS_OK) return st;
+    }
+    for (size_t i = 0; i < n; ++i) launch_reset_stats(B->origin, B->st[i]->scal, B->st[i]->istat);
+    HIP_TRY(hipGetLastError());
+    for (int r = 0; r < nsteps / 2; ++r) HIP_TRY(hipGraphLaunch(B->exec, B->origin));
+    HIP_TRY(hipStreamSynchronize(B->origin));
+    vs_status worst = VS_OK;
+    for (size_t i = 0; i < n; ++i) {
+        B->st[i]->step += nsteps;
+        const vs_status st = collect(B->st[i], "vs_batch_step");
+        if (st != VS_OK && worst == VS_OK) worst = st;
+    }
+    return worst;
+}
+
+void vs_batch_destroy(vs_batch* B) {
+    if (!B) return;
+    (void)hipStreamSynchronize(B->origin);
+    for (hipStream_t q : B->streams) (void)hipStreamSynchronize(q);
+    batch_release_graph(B);
+    for (hipEvent_t x : B->ev) (void)hipEventDestroy(x);
+    // states keep working after the batch: give them back a valid stream (the origin)
+    for (vs_state* S : B->st) S->stream = B->origin;
+    for (hipStream_t q : B->streams) (void)hipStreamDestroy(q);
+    (void)hipStreamDestroy(B->cap);
+    delete B;
+}
+
 void vs_destroy(vs_state* S) {
     if (!S) return;
     (void)hipStreamSynchronize(S->stream);

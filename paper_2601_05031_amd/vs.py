@@ -91,6 +91,9 @@ def lib() -> ctypes.CDLL:
         "vs_profile_name": (ctypes.c_char_p, [i32]),
         "vs_profile_read": (i32, [vp, i32, P(dbl), P(ctypes.c_int64)]),
         "vs_destroy": (None, [vp]),
+        "vs_batch_create": (i32, [P(vp), i32, vp, i32, P(vp)]),
+        "vs_batch_step": (i32, [vp, P(dbl), i32]),
+        "vs_batch_destroy": (None, [vp]),
         "vs_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sigs.items():
@@ -229,11 +232,47 @@ class Solver:
             pass
 
 
-def solver_for(workload, device="cuda:0", precision="fp64", **overrides) -> "Solver":
-    """Build a Solver from a workloads.Workload (seeded phi0 included)."""
+class Batch:
+    """Many Solvers stepped together: their steps are captured into one HIP graph (each
+    instance on its own stream, forked from and joined to the origin stream) and replayed."""
+
+    def __init__(self, solvers, nstreams=8, stream=None):
+        import torch
+
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        origin = stream if stream is not None else torch.cuda.current_stream()
+        arr = (ctypes.c_void_p * n)(*[s._st for s in self.solvers])
+        b = ctypes.c_void_p(0)
+        _check(lib().vs_batch_create(arr, n, ctypes.c_void_p(origin.cuda_stream), int(nstreams),
+                                     ctypes.byref(b)), "vs_batch_create")
+        self._b = b
+
+    def step(self, dts, nsteps: int):
+        n = len(self.solvers)
+        if not hasattr(dts, "__len__"):
+            dts = [dts] * n
+        arr = (ctypes.c_double * n)(*[float(x) for x in dts])
+        _check(lib().vs_batch_step(self._b, arr, int(nsteps)), "vs_batch_step")
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().vs_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(workload, device="cuda:0", precision="fp64", phi0=None, **overrides) -> "Solver":
+    """Build a Solver from a workloads.Workload (its seeded phi0 unless one is given)."""
     w = workload.with_(**overrides) if overrides else workload
     p = w.params()
     rtol = p.pop("rtol")
     mc = p.pop("max_cycles")
     return Solver((w.grid.nx, w.grid.ny, w.grid.nz, w.grid.h), w.walls(),
-                  dict(p, rtol=rtol, max_cycles=mc, precision=precision), w.phi0(), device=device)
+                  dict(p, rtol=rtol, max_cycles=mc, precision=precision),
+                  w.phi0() if phi0 is None else phi0, device=device)

@@ -1,0 +1,116 @@
+"""GPU batches: many independent instances stepped through one captured HIP graph.
+
+A batch runs exactly the kernels vs_step runs, on other streams, so every instance must come
+out bit-identical to the same instance stepped alone, and within the FP64 bar of the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import batch_instances
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_2601_05031_amd as P  # noqa: E402
+from paper_2601_05031_amd import vs as V  # noqa: E402
+
+FIELD_NAMES = ["phi", "mu", "omega_x", "omega_y", "omega_z", "psi_x", "psi_y", "psi_z"]
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel_l2(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+def small_instances(k):
+    """The first k batch instances with a 48^3 or 64^3 grid (the oracle runs them in seconds)."""
+    out = [w for w in batch_instances(64) if w.grid.nx <= 64]
+    return out[:k]
+
+
+def test_batch_instances_recipe():
+    ws = batch_instances(64)
+    assert len(ws) == 64
+    assert {w.grid.nx for w in ws} == {48, 64, 96, 128}
+    assert {w.wall_kind for w in ws} == {"poiseuille", "couette"}
+    for w in ws:
+        assert 0.15 * w.grid.H <= w.R0 <= 0.25 * w.grid.H
+        assert 0.5 <= w.kappa <= 2.0 and 0.7 <= w.prolate_Vr <= 0.95
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_batch_bitwise_equals_single_instances(precision):
+    ws = small_instances(5)
+    nsteps = 4
+    say(f"case batch-vs-single precision={precision} n={len(ws)} "
+        f"grids={[w.grid.nx for w in ws]} seeds={[w.seed for w in ws]} nsteps={nsteps}")
+    singles = []
+    for w in ws:
+        s = P.solver_for(w, precision=precision)
+        s.step(w.dt, nsteps)
+        singles.append((s.fields(), s.scalars()))
+        s.close()
+    solvers = [P.solver_for(w, precision=precision) for w in ws]
+    b = V.Batch(solvers, nstreams=4)
+    b.step([w.dt for w in ws], 2)
+    b.step([w.dt for w in ws], nsteps - 2)      # replays the captured graph
+    b.close()
+    for w, s, (ref, rsc) in zip(ws, solvers, singles):
+        got = s.fields()
+        sc = s.scalars()
+        for k in FIELD_NAMES:
+            assert np.array_equal(got[k], ref[k]), (w.name, k)
+        assert sc["step"] == nsteps and sc["V"] == rsc["V"] and sc["A"] == rsc["A"]
+        # the states keep working after the batch is gone
+        s.step(w.dt, 1)
+        s.close()
+
+
+def test_batch_matches_oracle():
+    ws = small_instances(3)
+    nsteps = 2
+    say(f"case batch-vs-oracle n={len(ws)} grids={[w.grid.nx for w in ws]} nsteps={nsteps}")
+    solvers = [P.solver_for(w) for w in ws]
+    b = V.Batch(solvers, nstreams=8)
+    b.step([w.dt for w in ws], nsteps)
+    b.close()
+    for w, s in zip(ws, solvers):
+        got = s.fields()
+        s.close()
+        g = O.Grid(*w.grid.shape, h=w.grid.h)
+        walls = O.Walls(w.wall_kind, w.u0, w.u1)
+        p = O.Params(model=w.model, eta=w.eta, mobility=w.mobility, eps=w.eps, kappa=w.kappa,
+                     sigma=w.sigma, gamma0=w.gamma0, rate_V=w.rate_V, k_A=w.k_A,
+                     bend_scale=w.bend_scale)
+        ref = O.run(g, walls, p, w.phi0(), w.dt, nsteps)
+        refd = {"phi": ref.phi, "mu": ref.mu}
+        for c, ax in enumerate("xyz"):
+            refd["omega_" + ax] = ref.omega[c]
+            refd["psi_" + ax] = ref.psi[c]
+        errs = {k: rel_l2(got[k], refd[k]) for k in FIELD_NAMES}
+        say(f"  {w.name} n={w.grid.nx} " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+        assert max(errs.values()) <= 1e-9, errs
+
+
+def test_batch_rejects_odd_steps_and_unstable_dt():
+    ws = small_instances(2)
+    say(f"case batch-errors n={len(ws)}")
+    solvers = [P.solver_for(w) for w in ws]
+    b = V.Batch(solvers)
+    with pytest.raises(V.VsError) as e:
+        b.step([w.dt for w in ws], 3)
+    assert e.value.code == V.VS_E_ARG
+    with pytest.raises(V.VsError) as e:
+        b.step([ws[0].dt, 10.0], 2)
+    assert e.value.code == V.VS_E_UNSTABLE
+    b.close()
+    for s in solvers:
+        assert s.scalars()["step"] == 0
+        s.close()

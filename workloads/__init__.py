@@ -12,8 +12,9 @@ from .shapes import (  # noqa: F401
     real_sph_harm,
     phi_sh_vesicle,
     phi_prolate,
+    phi_prolate_sh,
     phi_sphere,
     prolate_axes,
     prolate_area,
 )
-from .configs import Workload, WORKLOADS, workload  # noqa: F401
+from .configs import Workload, WORKLOADS, batch_instances, workload  # noqa: F401

@@ -20,7 +20,8 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from .shapes import GridSpec, alm_coefficients, phi_prolate, phi_sh_vesicle, phi_sphere, prolate_axes
+from .shapes import (GridSpec, alm_coefficients, phi_prolate, phi_prolate_sh, phi_sh_vesicle,
+                     phi_sphere, prolate_axes)
 
 BENDING = "bending"
 CAHN_HILLIARD = "cahn_hilliard"
@@ -74,6 +75,9 @@ class Workload:
             return phi_prolate(g, a, b, self.width, self.center)
         if self.shape == "sphere":
             return phi_sphere(g, self.R0, self.width, self.center)
+        if self.shape == "prolate_sh":
+            a, b = prolate_axes(self.R0, self.prolate_Vr)
+            return phi_prolate_sh(g, a, b, np.asarray(self.extra["alm"]), self.width, self.center)
         raise ValueError(self.shape)
 
     def params(self) -> dict:
@@ -98,6 +102,30 @@ WORKLOADS = {
         name="droplet256", grid=GridSpec(128, 128, 256), wall_kind=COUETTE, u0=-0.05, u1=0.05,
         model=CAHN_HILLIARD, sigma=1.0, dt=1e-3, nsteps=500, shape="sphere", R0=20.0),
 }
+
+
+def batch_instances(count: int = 64, seed_base: int = 1000) -> list[Workload]:
+    """The batched workload: instance i draws from default_rng(seed_base + i) a cubic grid
+    from {48, 64, 96, 128}, a plane Poiseuille (centreline 0.05) or Couette (-/+0.05) channel
+    by coin flip, an area-equivalent vesicle radius U(0.15, 0.25) of the channel width,
+    kappa ~ U(0.5, 2), reduced volume ~ U(0.7, 0.95) and l <= 3 shape coefficients
+    N(0, 0.02^2); membrane with volume/area penalties, dt = 5e-4."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed_base + i)
+        n = int(rng.choice([48, 64, 96, 128]))
+        couette = bool(rng.integers(0, 2))
+        frac = float(rng.uniform(0.15, 0.25))
+        kappa = float(rng.uniform(0.5, 2.0))
+        vr = float(rng.uniform(0.7, 0.95))
+        alm = rng.normal(0.0, 0.02, 16)
+        g = GridSpec(n, n, n)
+        out.append(Workload(
+            name=f"batch{i}", grid=g, wall_kind=COUETTE if couette else POISEUILLE,
+            u0=-0.05 if couette else 0.05, u1=0.05 if couette else 0.0, model=BENDING,
+            kappa=kappa, rate_V=10.0, k_A=1.0, dt=5e-4, nsteps=100, shape="prolate_sh",
+            R0=frac * g.H, prolate_Vr=vr, seed=seed_base + i, extra={"alm": alm.tolist()}))
+    return out
 
 
 def workload(name: str, **overrides) -> Workload:

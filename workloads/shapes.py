@@ -95,6 +95,22 @@ def phi_sphere(g: GridSpec, R: float, width: float, center=None) -> np.ndarray:
     return np.tanh((R - r) / width)
 
 
+def phi_prolate_sh(g: GridSpec, a: float, b: float, alm: np.ndarray, width: float,
+                   center=None) -> np.ndarray:
+    """Spheroid (semi-axis a along z, b in x, y) with a spherical-harmonic perturbation:
+    R(theta, varphi) = R_spheroid(theta) (1 + sum a_lm Y_lm)."""
+    r, theta, varphi = _coords(g, center)
+    Rs = 1.0 / np.sqrt(np.cos(theta) ** 2 / a**2 + np.sin(theta) ** 2 / b**2)
+    lmax = int(round(math.sqrt(len(alm)))) - 1
+    s = np.zeros_like(r)
+    idx = 0
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            s += alm[idx] * real_sph_harm(l, m, theta, varphi)
+            idx += 1
+    return np.tanh((Rs * (1.0 + s) - r) / width)
+
+
 def phi_prolate(g: GridSpec, a: float, b: float, width: float, center=None) -> np.ndarray:
     """Spheroid with semi-axis a along z and b in x, y: R(theta) = (cos^2/a^2 + sin^2/b^2)^(-1/2)."""
     r, theta, _ = _coords(g, center)
