@@ -44,7 +44,7 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
         "rhs_dht_z_psi": 48 * Ni,     # omega(3) in; 3 spectral fields out
         "dht_x": 48 * Ni,             # 3 spectral fields in and out
         "tridiag_y": 48 * Ni,         # 3 spectral fields in and out
-        "tridiag_psi": 48 * Ni,       # vorticity modes in; stream-vector modes out
+        "tridiag_pair": 72 * Ni,      # source modes in; vorticity and stream-vector modes out
         "resid_pair": 72 * Ni,        # S(3), omega(3), psi(3) in
         "dht_z_out": 48 * Ni,         # 3 spectral fields in; 3 solution fields out
         "resid_norm_omega": 48 * Ni,  # S(3), omega(3) in

@@ -423,6 +423,284 @@ __global__ __launch_bounds__(64) void k_tridiag_psi(Dims d, const double* __rest
     });
 }
 
+// ---------------------------------------------------------------- segmented tridiagonal solve
+// Partition solve of T x = f for one mode, T = tridiag(1, beta, 1) of size M with zero ends
+// (the walls are folded into f). The column is cut into S consecutive segments, one lane each
+// (the S lanes of a mode are adjacent in the wave); a segment of L rows lives in registers.
+// With G = T_L^{-1}, segment k obeys x_k = G (f_k - E_{k-1} e_1 - F_{k+1} e_L), where F_k, E_k
+// are the first and last unknowns of segment k (E_{-1} = F_S = 0). Its ends give the coupled
+// relations  F_k = p_k - g11 E_{k-1} - g1L F_{k+1},  E_k = q_k - g1L E_{k-1} - g11 F_{k+1}
+// (p, q: ends of G f_k; g11 = G_11 = G_LL, g1L = G_1L = G_L1 since T_L is symmetric and
+// persymmetric). A forward sweep over the segments, E_k = a_k - b_k F_{k+1},
+// F_k = phi_k - chi_k F_{k+1}, runs redundantly in every lane of the mode; the back sweep
+// passes F down the lanes. The segment is then finished from its forward-eliminated rows d'_j:
+// the corrections of f enter d' as -E_{k-1} pi_j (pi = forward elimination of e_1) and
+// -F_{k+1} c'_L at the last row. Pivots c'_j = 1/(beta - c'_{j-1}) come from the class table,
+// so no lane divides in the row loops; beta itself is the table's last row.
+//
+// Segments have Lm rows (the first nlong of them) or Lm - 1 rows. Every lane walks Lm rows so
+// that the row loops depend on wave-uniform values only; a short segment's extra last row is a
+// phantom whose value is forced to zero by selects on the last two rows.
+// Buffer-instruction access for the segmented solve (see seg_load).
+typedef __amdgpu_buffer_rsrc_t BufRes;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ BufRes buf_res(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(BufRes r, unsigned voff, unsigned soff, const double*) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_ld(BufRes r, unsigned voff, unsigned soff, const float*) {
+    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st(BufRes r, unsigned voff, unsigned soff, double v, double*) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_st(BufRes r, unsigned voff, unsigned soff, double v, float*) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), r, voff, soff, 0);
+}
+
+template <int LMAX>
+struct SegCoef {
+    double c[LMAX];
+    double beta, g11l, g11s, g1ll, g1ls;   // G_11 and G_1L for Lm and Lm - 1 rows
+};
+
+template <int LMAX>
+__device__ __forceinline__ void seg_coef(SegCoef<LMAX>& cf, const double* __restrict__ tri,
+                                         unsigned cls, unsigned ncls, int M, int Lm) {
+    const BufRes r = buf_res(tri, (unsigned)(M + 1) * ncls * 8u);
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) cf.c[u] = (u < Lm) ? buf_ld(r, cls * 8u, u * ncls * 8u, tri) : 0.0;
+    cf.beta = buf_ld(r, cls * 8u, (unsigned)M * ncls * 8u, tri);
+    // G_11(L) = c'_L; G_1L(L) = (-1)^(L-1) c'_1 ... c'_L
+    double prod = 1.0;
+    cf.g11l = cf.g11s = cf.g1ll = cf.g1ls = 0.0;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) {
+        if (u < Lm) {
+            prod *= -cf.c[u];
+            if (u == Lm - 2) {
+                cf.g1ls = -prod;
+                cf.g11s = cf.c[u];
+            }
+            if (u == Lm - 1) {
+                cf.g1ll = -prod;
+                cf.g11l = cf.c[u];
+            }
+        }
+    }
+}
+
+template <int S, int LMAX>
+__device__ __forceinline__ void seg_solve(double (&x)[LMAX], const SegCoef<LMAX>& cf, int k,
+                                          bool shortl, int Lm, int nlong) {
+    const double* c = cf.c;
+    // forward elimination in place; q = last d', piL = pi at the last row (phantom row zeroed)
+    double acc = 0.0, pi = 0.0, q = 0.0, piL = 0.0;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) {
+        if (u < Lm) {
+            acc = c[u] * (x[u] - acc);
+            pi = (u == 0) ? c[0] : -c[u] * pi;
+            if (u == Lm - 2) {
+                q = acc;
+                piL = pi;
+            }
+            if (u == Lm - 1) {
+                q = shortl ? q : acc;
+                piL = shortl ? piL : pi;
+                x[u] = shortl ? 0.0 : acc;
+            } else {
+                x[u] = acc;
+            }
+        }
+    }
+    // p = first unknown of the zero-end segment solve (back substitution, nothing stored)
+    double p = 0.0;
+#pragma unroll
+    for (int u = LMAX - 1; u >= 0; --u)
+        if (u < Lm) p = x[u] - c[u] * p;
+    // reduced system: forward sweep in every lane, keeping this lane's coefficients
+    double a = 0.0, b = 0.0, mph = 0.0, mch = 0.0, mal = 0.0, mbe = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < S; ++kk) {
+        const double pk = __shfl(p, kk, S);
+        const double qk = __shfl(q, kk, S);
+        const bool lng = nlong == 0 || kk < nlong;   // nlong = 0: all segments have Lm rows
+        const double g11 = lng ? cf.g11l : cf.g11s;
+        const double g1l = lng ? cf.g1ll : cf.g1ls;
+        const double rden = 1.0 / (1.0 - g11 * b);
+        const double ph = (pk - g11 * a) * rden;
+        const double ch = g1l * rden;
+        const double an = qk - g1l * a + g1l * b * ph;
+        const double bn = g11 + g1l * b * ch;
+        if (kk == k) {
+            mph = ph;
+            mch = ch;
+            mal = an;
+            mbe = bn;
+        }
+        a = an;
+        b = bn;
+    }
+    // back sweep down the lanes: F_k = phi_k - chi_k F_{k+1}
+    double Fk = mph;
+#pragma unroll
+    for (int it = 1; it < S; ++it) {
+        const double up = __shfl(Fk, k + 1 < S ? k + 1 : k, S);
+        Fk = mph - mch * (k + 1 < S ? up : 0.0);
+    }
+    const double fup = __shfl(Fk, k + 1 < S ? k + 1 : k, S);
+    const double Fnext = k + 1 < S ? fup : 0.0;
+    const double Ek = mal - mbe * Fnext;
+    const double eup = __shfl(Ek, k > 0 ? k - 1 : k, S);
+    const double Eprev = k > 0 ? eup : 0.0;
+    // finish the segment bottom up
+    double xn = 0.0, pc = 0.0;
+#pragma unroll
+    for (int u = LMAX - 1; u >= 0; --u) {
+        if (u < Lm) {
+            double f;
+            if (u == Lm - 1) {
+                pc = shortl ? 0.0 : piL;
+                f = shortl ? 0.0 : Fnext * c[u];
+            } else if (u == Lm - 2) {
+                pc = shortl ? piL : -pc * (cf.beta - c[u]);
+                f = shortl ? Fnext * c[u] : 0.0;
+            } else {
+                pc = -pc * (cf.beta - c[u]);
+                f = 0.0;
+            }
+            xn = (x[u] - Eprev * pc - f) - c[u] * xn;
+            x[u] = xn;
+        }
+    }
+}
+
+template <int S>
+struct SegLane {
+    int p, q, k, Lm, nlong;
+    bool act, shortl;
+    unsigned cls, ncls;
+    unsigned off;   // offset of (p, first row of the segment, q); grids stay below 2^31 nodes
+};
+
+template <int S>
+__device__ __forceinline__ SegLane<S> seg_lane(const Dims& d) {
+    SegLane<S> sl;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mode = t / S;
+    sl.k = t % S;
+    sl.act = mode < d.nx * d.nz;
+    const int mm = sl.act ? mode : 0;
+    sl.p = mm / d.nz;
+    sl.q = mm - sl.p * d.nz;
+    const int base = d.M / S;
+    sl.nlong = d.M - base * S;
+    sl.Lm = base + (sl.nlong > 0);
+    sl.shortl = sl.nlong > 0 && sl.k >= sl.nlong;
+    const int a = sl.k * base + min(sl.k, sl.nlong);
+    const int pc = min(sl.p, d.nx - sl.p);
+    const int qc = min(sl.q, d.nz - sl.q);
+    sl.ncls = (unsigned)((d.nx / 2 + 1) * (d.nz / 2 + 1));
+    sl.cls = (unsigned)(pc * (d.nz / 2 + 1) + qc);
+    sl.off = (unsigned)(sl.p * d.ny * d.nz + (1 + a) * d.nz + sl.q);
+    return sl;
+}
+
+// Segment rows go through buffer instructions: one buffer resource per array (wave-uniform),
+// the lane's 32-bit byte offset in a VGPR and the row offset u * sj in an SGPR, so no lane
+// keeps an address per row. Accesses beyond the array's extent read zero and drop stores.
+// A short segment's phantom row reads the next segment's first row, or the wall row
+// j = ny-1: in bounds, and zeroed by the solve.
+template <int S, int LMAX, class ST>
+__device__ __forceinline__ void seg_load(double (&x)[LMAX], const ST* base, unsigned nelem,
+                                         unsigned off, unsigned sj, int Lm, double scale) {
+    const BufRes r = buf_res(base, nelem * (unsigned)sizeof(ST));
+    const unsigned vo = off * (unsigned)sizeof(ST);
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u)
+        x[u] = (u < Lm) ? scale * buf_ld(r, vo, u * sj * (unsigned)sizeof(ST), base) : 0.0;
+}
+
+template <int S, int LMAX, class ST>
+__device__ __forceinline__ void seg_store(const double (&x)[LMAX], ST* base, unsigned nelem,
+                                          unsigned sj, const SegLane<S>& sl) {
+    const BufRes r = buf_res(base, nelem * (unsigned)sizeof(ST));
+    const unsigned vo = sl.off * (unsigned)sizeof(ST);
+    if (!sl.act) return;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) {
+        const unsigned so = u * sj * (unsigned)sizeof(ST);
+        if (u < sl.Lm - 1) buf_st(r, vo, so, x[u], base);
+        if (u == sl.Lm - 1 && !sl.shortl) buf_st(r, vo, so, x[u], base);
+    }
+}
+
+// Segmented tridiag_y: f_j = scale * B_j per component blockIdx.y, solved in place.
+// LMF, NLF: the segment length Lm and long-segment count nlong fixed at compile time for the
+// common row counts (LMF = 0: taken from M at run time).
+template <int S, int LMAX, class ST, int LMF, int NLF>
+__global__ __launch_bounds__(256) void k_tridiag_seg(Dims d, const double* __restrict__ tri,
+                                                    SPtr3<ST> spec, const int* gate, double scale) {
+    if (gate && *gate) return;
+    SegLane<S> sl = seg_lane<S>(d);
+    if (LMF) {
+        sl.Lm = LMF;
+        sl.nlong = NLF;
+        sl.shortl = NLF > 0 && sl.k >= NLF;
+    }
+    SegCoef<LMAX> cf;
+    seg_coef<LMAX>(cf, tri, sl.cls, sl.ncls, d.M, sl.Lm);
+    ST* col = spec.p[blockIdx.y];
+    const unsigned N = (unsigned)(d.nx * d.ny * d.nz);
+    double x[LMAX];
+    seg_load<S, LMAX, ST>(x, col, N, sl.off, d.nz, sl.Lm, scale);
+    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
+    seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
+}
+
+// Segmented vorticity + stream-vector pair: the vorticity modes U_w (f = scale * B) are solved
+// and stored in spec, then the stream-vector problem lap psi = -w is solved from them in
+// registers, f_j = -h^2 U_w(j) - [p = q = 0]([j = 1] psi_lo + [j = M] psi_hi), into spec2.
+template <int S, int LMAX, class ST, int LMF, int NLF>
+__global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* __restrict__ tri,
+                                                         SPtr3<ST> spec, SPtr3<ST> spec2,
+                                                         double3 plo, double3 phi_, double scale) {
+    SegLane<S> sl = seg_lane<S>(d);
+    if (LMF) {
+        sl.Lm = LMF;
+        sl.nlong = NLF;
+        sl.shortl = NLF > 0 && sl.k >= NLF;
+    }
+    const int c3 = blockIdx.y;
+    SegCoef<LMAX> cf;
+    seg_coef<LMAX>(cf, tri, sl.cls, sl.ncls, d.M, sl.Lm);
+    ST* col = spec.p[c3];
+    const unsigned N = (unsigned)(d.nx * d.ny * d.nz);
+    double x[LMAX];
+    seg_load<S, LMAX, ST>(x, col, N, sl.off, d.nz, sl.Lm, scale);
+    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
+    seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
+    const double h2 = d.h * d.h;
+    const bool m00 = sl.p == 0 && sl.q == 0;
+    const double wlo = c3 == 0 ? plo.x : (c3 == 1 ? plo.y : plo.z);
+    const double whi = c3 == 0 ? phi_.x : (c3 == 1 ? phi_.y : phi_.z);
+    // the row j = M is the last real row of segment S - 1 (short if nlong > 0)
+    const int ulast = sl.nlong > 0 ? sl.Lm - 2 : sl.Lm - 1;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u) {
+        double f = -h2 * x[u];
+        if (m00 && sl.k == 0 && u == 0) f -= wlo;
+        if (m00 && sl.k == S - 1 && u == ulast) f -= whi;
+        x[u] = f;
+    }
+    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
+    seg_store<S, LMAX, ST>(x, spec2.p[c3], N, d.nz, sl);
+}
+
 // dht_z_out: Hartley along z of the solved modes, then u = result (add = 0) or u += result.
 template <class ST>
 __global__ __launch_bounds__(kBlock) void k_dht_z_out(Dims d, FftPlan pz,
@@ -1020,30 +1298,97 @@ void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2
         dht_x_t<double>(s, d, px, twx, spec, ncomp, gate);
 }
 
-void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                      int ncomp, bool f32, const int* gate) {
-    const double scale = d.h * d.h / ((double)d.nx * d.nz);
-    const dim3 grid((2 * d.nx * d.nz + 63) / 64, ncomp);
-    if (f32)
-        hipLaunchKernelGGL(k_tridiag_y<float>, grid, dim3(64), 0, s, d, tri, sptr<float>(spec, ncomp),
-                           gate, scale);
-    else
-        hipLaunchKernelGGL(k_tridiag_y<double>, grid, dim3(64), 0, s, d, tri,
-                           sptr<double>(spec, ncomp), gate, scale);
+// Segment layout for M interior rows: S lanes per mode, at most LMAX rows per lane.
+// 0 = the twisted two-lane solve (M < 4 or M > 256).
+int seg_shape(int M) {
+    if (M < 4 || M > 256) return 0;
+    if (M <= 32) return 8;
+    if (M <= 64) return 16;
+    if (M <= 128) return 32;
+    return 832;   // S = 8, LMAX = 32
 }
 
-void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                        void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
-                        bool f32) {
+// Launches the segmented solve with S lanes per mode; PAIR selects the vorticity +
+// stream-vector kernel. Grids with ny = n in {32, 48, 64, 96, 128, 256} (M = n - 2) get
+// their segment lengths as compile-time constants.
+template <bool PAIR, int S, int LMAX, class ST, int LMF, int NLF>
+void seg_launch(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                void* const spec2[3], int ncomp, const int* gate, double3 lo, double3 hi,
+                double scale) {
+    const dim3 grid((unsigned)(((long)d.nx * d.nz * S + 255) / 256), ncomp);
+    if (PAIR)
+        hipLaunchKernelGGL((k_tridiag_pair_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d,
+                           tri, sptr<ST>(spec, 3), sptr<ST>(spec2, 3), lo, hi, scale);
+    else
+        hipLaunchKernelGGL((k_tridiag_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d, tri,
+                           sptr<ST>(spec, ncomp), gate, scale);
+}
+
+template <bool PAIR, class ST>
+bool seg_dispatch(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                  void* const spec2[3], int ncomp, const int* gate, double3 lo, double3 hi) {
+    const double scale = d.h * d.h / ((double)d.nx * d.nz);
+#define VS_SEG(S_, LMAX_, LMF_, NLF_) \
+    seg_launch<PAIR, S_, LMAX_, ST, LMF_, NLF_>(s, d, tri, spec, spec2, ncomp, gate, lo, hi, scale)
+    switch (d.M) {
+    case 30: VS_SEG(4, 8, 8, 2); return true;
+    case 46: VS_SEG(4, 16, 12, 2); return true;
+    case 62: VS_SEG(4, 16, 16, 2); return true;
+    case 94: VS_SEG(4, 32, 24, 2); return true;
+    case 126: VS_SEG(4, 32, 32, 2); return true;
+    case 254: VS_SEG(8, 32, 32, 6); return true;
+    default: break;
+    }
+    switch (seg_shape(d.M)) {
+    case 8: VS_SEG(4, 8, 0, 0); return true;
+    case 16: VS_SEG(4, 16, 0, 0); return true;
+    case 32: VS_SEG(4, 32, 0, 0); return true;
+    case 832: VS_SEG(8, 32, 0, 0); return true;
+    default: return false;
+    }
+#undef VS_SEG
+}
+
+template <class ST>
+void tridiag_y_t(hipStream_t s, const Dims& d, const double* tri, void* const spec[3], int ncomp,
+                 const int* gate) {
+    const double3 z = make_double3(0.0, 0.0, 0.0);
+    if (seg_dispatch<false, ST>(s, d, tri, spec, nullptr, ncomp, gate, z, z)) return;
+    const double scale = d.h * d.h / ((double)d.nx * d.nz);
+    const dim3 grid((2 * d.nx * d.nz + 63) / 64, ncomp);
+    hipLaunchKernelGGL(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, ncomp), gate,
+                       scale);
+}
+
+template <class ST>
+void tridiag_pair_t(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                    void* const spec2[3], double3 lo, double3 hi) {
+    if (seg_dispatch<true, ST>(s, d, tri, spec, spec2, 3, nullptr, lo, hi)) return;
+    const double scale = d.h * d.h / ((double)d.nx * d.nz);
     const dim3 grid((2 * d.nx * d.nz + 63) / 64, 3);
+    hipLaunchKernelGGL(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
+                       (const int*)nullptr, scale);
+    hipLaunchKernelGGL(k_tridiag_psi<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
+                       sptr<ST>(spec2, 3), lo, hi);
+}
+
+void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                      int ncomp, bool f32, const int* gate) {
+    if (f32)
+        tridiag_y_t<float>(s, d, tri, spec, ncomp, gate);
+    else
+        tridiag_y_t<double>(s, d, tri, spec, ncomp, gate);
+}
+
+void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                         void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
+                         bool f32) {
     const double3 lo = make_double3(psi_lo[0], psi_lo[1], psi_lo[2]);
     const double3 hi = make_double3(psi_hi[0], psi_hi[1], psi_hi[2]);
     if (f32)
-        hipLaunchKernelGGL(k_tridiag_psi<float>, grid, dim3(64), 0, s, d, tri, sptr<float>(spec, 3),
-                           sptr<float>(spec2, 3), lo, hi);
+        tridiag_pair_t<float>(s, d, tri, spec, spec2, lo, hi);
     else
-        hipLaunchKernelGGL(k_tridiag_psi<double>, grid, dim3(64), 0, s, d, tri,
-                           sptr<double>(spec, 3), sptr<double>(spec2, 3), lo, hi);
+        tridiag_pair_t<double>(s, d, tri, spec, spec2, lo, hi);
 }
 
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,

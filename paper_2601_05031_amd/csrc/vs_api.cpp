@@ -40,12 +40,12 @@ vs_status fail(vs_status code, const char* fmt, ...) {
 // Kernel classes for the event timer.
 enum KClass {
     K_ADVANCE, K_VA_PARTIALS, K_FINALIZE_VA, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
-    K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PSI, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
+    K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
     K_RESID_FIELD, K_RESID_PAIR, K_CHECK, K_FILL, K_RESET, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "finalize_va", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
-    "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_psi", "dht_z_out", "resid_norm_omega",
+    "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
     "resid_norm_psi", "resid_norm_field", "resid_pair", "check", "fill_profile", "reset_stats"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
@@ -84,7 +84,7 @@ Layout make_layout(const vs_grid& g) {
     L.off_spec2 = o;  o += 3 * fb;
     L.off_twx = o;    o += align_up((size_t)g.nx * sizeof(double2));
     L.off_twz = o;    o += align_up((size_t)g.nz * sizeof(double2));
-    L.off_tri = o;    o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * M * sizeof(double));
+    L.off_tri = o;    o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * (M + 1) * sizeof(double));
     L.off_part = o;   o += align_up((size_t)kMaxPartialBlocks * kPartialSlots * sizeof(double));
     L.off_prof = o;   o += align_up(2 * (size_t)g.ny * sizeof(double));
     L.off_scal = o;   o += align_up(SC_NSCAL * sizeof(double));
@@ -302,9 +302,8 @@ void enqueue_flow(vs_state* S, const double* phi) {
         launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rv, cu, 3, 0, S->spec, false, nullptr);
     });
     timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
-    timed(S, K_TRIDIAG_Y, [&] { launch_tridiag_y(S->stream, d, S->tri, S->spec, 3, false, nullptr); });
-    timed(S, K_TRIDIAG_PSI, [&] {
-        launch_tridiag_psi(S->stream, d, S->tri, S->spec, S->spec2, S->psi_wall_lo, S->psi_wall_hi, false);
+    timed(S, K_TRIDIAG_PAIR, [&] {
+        launch_tridiag_pair(S->stream, d, S->tri, S->spec, S->spec2, S->psi_wall_lo, S->psi_wall_hi, false);
     });
     timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
     timed(S, K_DHT_Z_OUT, [&] {
@@ -450,7 +449,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     };
     std::vector<double2> twx = twiddles(grid->nx), twz = twiddles(grid->nz);
     const int M = grid->ny - 2, hx = grid->nx / 2 + 1, hz = grid->nz / 2 + 1;
-    std::vector<double> tri((size_t)hx * hz * M);
+    std::vector<double> tri((size_t)hx * hz * (M + 1));
     for (int pc = 0; pc < hx; ++pc)
         for (int qc = 0; qc < hz; ++qc) {
             const long double PI = 3.14159265358979323846264338327950288L;
@@ -462,6 +461,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
                 prev = 1.0 / (beta - prev);
                 tri[(size_t)j * ncls + cls] = prev;
             }
+            tri[(size_t)M * ncls + cls] = beta;
         }
     const double H = (grid->ny - 1) * grid->h;
     std::vector<double> prof(2 * (size_t)grid->ny);

@@ -109,11 +109,12 @@ void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2
                   void* const spec[3], int ncomp, bool f32, const int* gate);
 void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
                       int ncomp, bool f32, const int* gate);
-// Stream-vector modes into spec2 from the vorticity modes left in spec by launch_tridiag_y
-// (psi wall values constant over each wall plane: psi_lo at j = 0, psi_hi at j = ny-1).
-void launch_tridiag_psi(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                        void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
-                        bool f32);
+// Vorticity modes solved in place in spec (as launch_tridiag_y), then the stream-vector modes
+// into spec2 from them (psi wall values constant over each wall plane: psi_lo at j = 0,
+// psi_hi at j = ny-1).
+void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
+                         void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
+                         bool f32);
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
                       const int* gate);

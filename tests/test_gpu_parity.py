@@ -72,8 +72,12 @@ def run_both(w, nsteps):
 
 
 # ------------------------------------------------------------------------- Poisson alone
+# row counts M = ny - 2 that select each tridiagonal layout: the two-lane twisted solve
+# (M = 1, 258), and 4 or 8 register segments per mode with every segment length bound
+# (M = 4: one row each; 5, 17, 31: ragged; 68; 148)
 @pytest.mark.parametrize("shape,h", [((24, 7, 12), 1.0), ((32, 33, 48), 0.5), ((96, 19, 96), 1.3),
-                                     ((8, 3, 6), 1.0)])
+                                     ((8, 3, 6), 1.0), ((16, 6, 12), 1.0), ((16, 70, 18), 0.7),
+                                     ((12, 150, 8), 1.0), ((8, 260, 6), 1.0)])
 def test_poisson_solve_matches_oracle(shape, h):
     say(f"case poisson shape={shape} h={h}")
     w = workload("vesicle32").with_(grid=GridSpec(*shape, h=h), shape="sphere", R0=2.0)
@@ -154,6 +158,15 @@ def test_step_parity_cahn_hilliard_couette():
     w = workload("droplet256", grid=GridSpec(48, 32, 96), R0=9.0, nsteps=5)
     got, sc, ref = run_both(w, 5)
     compare(got, ref_fields(ref), label="CH 5 steps")
+
+
+@pytest.mark.parametrize("ny", [6, 40, 140, 260])
+def test_step_parity_tall_channels(ny):
+    """Cahn-Hilliard droplet in Couette flow across the tridiagonal layouts (M = ny - 2)."""
+    R = min(4.0, 0.3 * (ny - 1))
+    w = workload("droplet256", grid=GridSpec(16, ny, 24), R0=R, nsteps=3)
+    got, sc, ref = run_both(w, 3)
+    compare(got, ref_fields(ref), label=f"ny={ny}")
 
 
 def test_step_parity_vesicle128_full_size():
