@@ -274,7 +274,7 @@ dim3 plane_grid(const Dims& d) {
 void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
                     const double* const psi[3], double* phi_out, const double* scal, double dt,
                     double mobility, double vz_lo, double vz_hi) {
-    hipLaunchKernelGGL(k_advance, plane_grid(d), dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
+    launch_kernel(k_advance, plane_grid(d), dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
                        psi[2], phi_out, d, scal, dt, mobility, vz_lo, vz_hi);
 }
 
@@ -286,35 +286,35 @@ int va_partial_blocks(const Dims& d) {
 void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
                         double* partials) {
     const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kMaxPartialBlocks);
-    hipLaunchKernelGGL(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
+    launch_kernel(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
                        partials);
 }
 
 void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
                         double* scal, int* istat, int init, double rate_V, double k_A,
                         double gamma0, double mobility) {
-    hipLaunchKernelGGL(k_finalize_va, dim3(1), dim3(1024), 0, s, partials, nblocks, d, scal,
+    launch_kernel(k_finalize_va, dim3(1), dim3(1024), 0, s, partials, nblocks, d, scal,
                        istat, init, rate_V, k_A, gamma0, mobility);
 }
 
 void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const double* scal,
                int model, double C_b, double eps, double sigma) {
-    hipLaunchKernelGGL(k_mu, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, scal, model, C_b,
+    launch_kernel(k_mu, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, scal, model, C_b,
                        eps, sigma);
 }
 
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof) {
-    hipLaunchKernelGGL(k_fill_profile, plane_grid(d), dim3(kBlock), 0, s, dst, d, prof);
+    launch_kernel(k_fill_profile, plane_grid(d), dim3(kBlock), 0, s, dst, d, prof);
 }
 
 void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
                    double inv_eta, double* const src[3]) {
-    hipLaunchKernelGGL(k_source, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0],
+    launch_kernel(k_source, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0],
                        src[1], src[2]);
 }
 
 void launch_reset_stats(hipStream_t s, double* scal, int* istat) {
-    hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, s, scal, istat);
+    launch_kernel(k_reset_stats, dim3(1), dim3(64), 0, s, scal, istat);
 }
 
 }  // namespace vs

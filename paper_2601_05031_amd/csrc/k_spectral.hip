@@ -1226,14 +1226,14 @@ void rhs_dht_z_t(hipStream_t s, const Dims& d, const FftPlan& pz, const double2*
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int rows = 2 * TwoPass<b, a>::L;                                                 \
-        hipLaunchKernelGGL((k_rhs_hz<b, a, ST>), dim3((nrows + rows - 1) / rows, ncomp),       \
+        launch_kernel((k_rhs_hz<b, a, ST>), dim3((nrows + rows - 1) / rows, ncomp),       \
                            dim3(64), 0, s, d, twz, rhs, uu, correct, sp, gate);                \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int rpb = z_rows_per_block(d);
-    hipLaunchKernelGGL(k_rhs_dht_z<ST>, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s,
+    launch_kernel(k_rhs_dht_z<ST>, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s,
                        d, pz, twz, rhs, uu, correct, sp, gate, rpb);
 }
 
@@ -1246,14 +1246,14 @@ void dht_x_t(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int qs = 2 * TwoPass<b, a>::L;                                                   \
-        hipLaunchKernelGGL((k_hx<b, a, ST>), dim3((d.nz + qs - 1) / qs, d.M, ncomp), dim3(64), \
+        launch_kernel((k_hx<b, a, ST>), dim3((d.nz + qs - 1) / qs, d.M, ncomp), dim3(64), \
                            0, s, d, twx, sp, gate);                                            \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int kb = x_modes_per_block(d);
-    hipLaunchKernelGGL(k_dht_x<ST>, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), 0, s, d,
+    launch_kernel(k_dht_x<ST>, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), 0, s, d,
                        px, twx, sp, gate, kb);
 }
 
@@ -1268,14 +1268,14 @@ void dht_z_out_t(hipStream_t s, const Dims& d, const FftPlan& pz, const double2*
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int rows = 2 * TwoPass<b, a>::L;                                                 \
-        hipLaunchKernelGGL((k_hz_out<b, a, ST>), dim3((nrows + rows - 1) / rows, ncomp),       \
+        launch_kernel((k_hz_out<b, a, ST>), dim3((nrows + rows - 1) / rows, ncomp),       \
                            dim3(64), 0, s, d, twz, sp, uu, add, gate);                         \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int rpb = z_rows_per_block(d);
-    hipLaunchKernelGGL(k_dht_z_out<ST>, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s,
+    launch_kernel(k_dht_z_out<ST>, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s,
                        d, pz, twz, sp, uu, add, gate, rpb);
 }
 
@@ -1317,10 +1317,10 @@ void seg_launch(hipStream_t s, const Dims& d, const double* tri, void* const spe
                 double scale) {
     const dim3 grid((unsigned)(((long)d.nx * d.nz * S + 255) / 256), ncomp);
     if (PAIR)
-        hipLaunchKernelGGL((k_tridiag_pair_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d,
+        launch_kernel((k_tridiag_pair_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d,
                            tri, sptr<ST>(spec, 3), sptr<ST>(spec2, 3), lo, hi, scale);
     else
-        hipLaunchKernelGGL((k_tridiag_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d, tri,
+        launch_kernel((k_tridiag_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d, tri,
                            sptr<ST>(spec, ncomp), gate, scale);
 }
 
@@ -1334,9 +1334,9 @@ bool seg_dispatch(hipStream_t s, const Dims& d, const double* tri, void* const s
     case 30: VS_SEG(4, 8, 8, 2); return true;
     case 46: VS_SEG(4, 16, 12, 2); return true;
     case 62: VS_SEG(4, 16, 16, 2); return true;
-    case 94: VS_SEG(4, 32, 24, 2); return true;
-    case 126: VS_SEG(4, 32, 32, 2); return true;
-    case 254: VS_SEG(8, 32, 32, 6); return true;
+    case 94: VS_SEG(8, 16, 12, 6); return true;
+    case 126: VS_SEG(8, 16, 16, 6); return true;
+    case 254: VS_SEG(16, 16, 16, 14); return true;
     default: break;
     }
     switch (seg_shape(d.M)) {
@@ -1356,7 +1356,7 @@ void tridiag_y_t(hipStream_t s, const Dims& d, const double* tri, void* const sp
     if (seg_dispatch<false, ST>(s, d, tri, spec, nullptr, ncomp, gate, z, z)) return;
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
     const dim3 grid((2 * d.nx * d.nz + 63) / 64, ncomp);
-    hipLaunchKernelGGL(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, ncomp), gate,
+    launch_kernel(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, ncomp), gate,
                        scale);
 }
 
@@ -1366,9 +1366,9 @@ void tridiag_pair_t(hipStream_t s, const Dims& d, const double* tri, void* const
     if (seg_dispatch<true, ST>(s, d, tri, spec, spec2, 3, nullptr, lo, hi)) return;
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
     const dim3 grid((2 * d.nx * d.nz + 63) / 64, 3);
-    hipLaunchKernelGGL(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
+    launch_kernel(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
                        (const int*)nullptr, scale);
-    hipLaunchKernelGGL(k_tridiag_psi<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
+    launch_kernel(k_tridiag_psi<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
                        sptr<ST>(spec2, 3), lo, hi);
 }
 
@@ -1409,21 +1409,21 @@ void launch_resid_pair(hipStream_t s, const Dims& d, double* const src[3], doubl
                        double* const psi[3], double* partials) {
     CPtr3 a{{src[0], src[1], src[2]}}, b{{w[0], w[1], w[2]}}, c{{psi[0], psi[1], psi[2]}};
     const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
-    hipLaunchKernelGGL(k_resid_pair, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, a, b, c, g, partials);
+    launch_kernel(k_resid_pair, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, a, b, c, g, partials);
 }
 
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate) {
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
     const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
-    hipLaunchKernelGGL(k_resid_norm, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, rhs, uu, ncomp, g,
+    launch_kernel(k_resid_norm, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, rhs, uu, ncomp, g,
                        partials, gate);
 }
 
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
                   int last_cycle, double* scal, int* istat, const int* gate, int slot0) {
     (void)cycle;
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(1024), 0, s, partials, nblocks, rtol,
+    launch_kernel(k_check, dim3(1), dim3(1024), 0, s, partials, nblocks, rtol,
                        last_cycle, scal, istat, gate, slot0);
 }
 

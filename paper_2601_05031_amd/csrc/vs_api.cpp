@@ -192,7 +192,16 @@ hipEvent_t take_event(vs_state* S) {
     return e;
 }
 
-// Run `launch` bracketed by an event pair when the timer is on.
+}  // namespace
+
+LaunchProbe& vs::launch_probe() {
+    static thread_local LaunchProbe probe;
+    return probe;
+}
+
+namespace {
+
+// Run `launch` with its kernels timed by an event pair when the timer is on.
 template <class F>
 void timed(vs_state* S, int cls, F&& launch) {
     if (!S->prof_on) {
@@ -200,10 +209,18 @@ void timed(vs_state* S, int cls, F&& launch) {
         return;
     }
     hipEvent_t a = take_event(S), b = take_event(S);
-    if (a) (void)hipEventRecord(a, S->stream);
+    if (!a || !b) {
+        launch();
+        return;
+    }
+    LaunchProbe& p = vs::launch_probe();
+    p.start = a;
+    p.stop = b;
+    p.launches = 0;
     launch();
-    if (b) (void)hipEventRecord(b, S->stream);
-    if (a && b) S->ev_used.push_back({cls, {a, b}});
+    const int n = p.launches;
+    p = LaunchProbe{};
+    if (n > 0) S->ev_used.push_back({cls, {a, b}});
 }
 
 void release_events(vs_state* S) {

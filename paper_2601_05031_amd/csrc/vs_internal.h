@@ -1,6 +1,7 @@
 // Internal declarations shared by the host driver and the kernel launchers of libvs.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -27,6 +28,29 @@ static inline __device__ int xcd_block(int bid, int nblocks) {
     const int q = nblocks >> 3, rem = nblocks & 7;
     const int x = bid & 7, slot = bid >> 3;
     return x * q + (x < rem ? x : rem) + slot;
+}
+
+// Per-thread profiling probe. While `stop` is set, launch_kernel dispatches through
+// hipExtLaunchKernelGGL so that the dispatch packet itself records `start` when the first
+// kernel begins and `stop` when each kernel ends: the elapsed time covers the kernels alone,
+// as a kernel tracer reports it, without the event packets' own dispatch latency.
+struct LaunchProbe {
+    hipEvent_t start = nullptr, stop = nullptr;
+    int launches = 0;
+};
+LaunchProbe& launch_probe();
+
+template <class... KArgs, class... Args>
+inline void launch_kernel(void (*k)(KArgs...), dim3 grid, dim3 block, unsigned shmem,
+                          hipStream_t s, Args&&... args) {
+    LaunchProbe& p = launch_probe();
+    if (p.stop) {
+        hipExtLaunchKernelGGL(k, grid, block, shmem, s, p.launches == 0 ? p.start : nullptr,
+                              p.stop, 0u, static_cast<KArgs>(args)...);
+        ++p.launches;
+    } else {
+        hipLaunchKernelGGL(k, grid, block, shmem, s, static_cast<KArgs>(args)...);
+    }
 }
 
 // Slots of the device scalar array (doubles).

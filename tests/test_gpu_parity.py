@@ -160,7 +160,7 @@ def test_step_parity_cahn_hilliard_couette():
     compare(got, ref_fields(ref), label="CH 5 steps")
 
 
-@pytest.mark.parametrize("ny", [6, 40, 140, 260])
+@pytest.mark.parametrize("ny", [6, 40, 96, 128, 140, 256, 260])
 def test_step_parity_tall_channels(ny):
     """Cahn-Hilliard droplet in Couette flow across the tridiagonal layouts (M = ny - 2)."""
     R = min(4.0, 0.3 * (ny - 1))
