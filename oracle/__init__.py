@@ -3,6 +3,7 @@
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the CPU-baseline leg
 of the benchmark may import this package. The HIP library never calls it and
 shares no code with it; the two meet only in the seeded inputs of ``workloads``.
+The reverse (adjoint) step lives in ``oracle.adjoint``.
 """
 from .vsref import (  # noqa: F401
     BENDING,
