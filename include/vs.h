@@ -162,9 +162,21 @@ vs_status vs_poisson_solve(vs_state* state, const double* f, double* u, double r
  * after all nsteps have run. Synchronises the stream once, at the end. */
 vs_status vs_step(vs_state* state, double dt, int32_t nsteps);
 
-/* Reverse-mode step for the adjoint (not built: returns VS_E_UNSUPPORTED).
- * adj_next: device, nx*ny*nz doubles, dL/dphi^{n+1}; adj_prev: device, out, dL/dphi^n;
- * dparams: host, accumulated dL/dkappa and dL/du0. */
+/* Reverse step of one time step (the discrete adjoint of vs_step's update, FP64 mode only;
+ * VS_E_UNSUPPORTED in VS_FP32_REFINED). The state must hold level n as vs_step leaves it
+ * (phi^n with its mu^n, omega^n, psi^n and multipliers), e.g. reloaded from a vs_save_state
+ * checkpoint and advanced to n. With a = dL/dphi^{n+1}:
+ *   adj_prev = (d phi^{n+1} / d phi^n)^T a, where mu^n, psi^n (through the vorticity and
+ *              stream-vector problems, main text eq. (5b), (5c)), lambda_V^n and gamma_A^n
+ *              are differentiated as functions of phi^n (SM eq. (32), (35), (37), (38)) and
+ *              V0, A0 are held fixed;
+ *   dparams[0] += a^T d phi^{n+1} / d kappa;
+ *   dparams[1] += a^T d phi^{n+1} / d s, where s scales both wall speeds (u0, u1) -> (s u0,
+ *              s u1) at s = 1 (every wall table is linear in the wall speeds).
+ * adj_next, adj_prev: device, nx*ny*nz doubles each, z fastest, must not alias; dparams: host,
+ * 2 doubles, accumulated. The two adjoint Poisson solves are verified to poisson_rtol like the
+ * forward ones (VS_E_NOCONV otherwise). The state's fields are left unchanged (the reverse
+ * step uses the spectral scratch and the spare phi buffer). Synchronises the stream once. */
 vs_status vs_grad_step(vs_state* state, double dt, const double* adj_next, double* adj_prev,
                        double dparams[2]);
 

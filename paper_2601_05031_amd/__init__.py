@@ -8,6 +8,8 @@ from .vs import (  # noqa: F401
     VsError,
     lib,
     make_params,
+    rollout_gradient,
+    rollout_loss,
     solver_for,
     workspace_bytes,
 )

@@ -587,12 +587,63 @@ vs_status vs_step(vs_state* S, double dt, int32_t nsteps) {
 
 vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* adj_prev,
                        double dparams[2]) {
-    (void)dt;
-    (void)adj_next;
-    (void)adj_prev;
-    (void)dparams;
     if (!S) return fail(VS_E_STATE, "state is NULL");
-    return fail(VS_E_UNSUPPORTED, "vs_grad_step: the adjoint step is not built");
+    if (!adj_next || !adj_prev || !dparams) return fail(VS_E_ARG, "adj_next, adj_prev and dparams are required");
+    if (adj_next == adj_prev) return fail(VS_E_ARG, "adj_next and adj_prev must not alias");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(VS_E_ARG, "dt must be > 0");
+    if (S->f32) return fail(VS_E_UNSUPPORTED, "vs_grad_step: the reverse step runs in the FP64 mode only");
+    const Dims& d = S->d;
+    hipStream_t st = S->stream;
+    const double rtol = S->p.poisson_rtol;
+    const int mc = S->p.poisson_max_cycles;
+    const double* phi = S->phi[S->cur];
+    double* mubar = S->phi[1 - S->cur];     // free between steps
+    double* const q[3] = {S->src[0], S->src[1], S->src[2]};
+    double* const u1[3] = {(double*)S->spec2[0], (double*)S->spec2[1], (double*)S->spec2[2]};
+    const double* const cps[3] = {S->ps[0], S->ps[1], S->ps[2]};
+    timed(S, K_RESET, [&] { launch_reset_stats(st, S->scal, S->istat); });
+    // advection, L_h mu and lambda_V terms; q = psi_bar
+    launch_adj_advect(st, d, adj_next, phi, cps, dt, S->p.mobility, S->vz_lo, S->vz_hi, adj_prev,
+                      mubar, q, S->part, S->scal);
+    // psi_int = P(-omega_int; psi walls): first adjoint solve, homogeneous walls
+    for (int c = 0; c < 3; ++c) launch_fill_profile(st, d, u1[c], nullptr);
+    RhsArgs r1{};
+    r1.mode = RHS_FIELD;
+    for (int c = 0; c < 3; ++c) r1.f[c] = q[c];
+    enqueue_solve(S, r1, u1, 3, rtol, mc, TAG_FIELD);
+    launch_adj_wall_couple(st, d, u1, S->ps, S->part, S->scal, SC_ADJ_PSIC);
+    // omega_int = P(S; omega walls): second adjoint solve of -u1, into q = S_bar
+    for (int c = 0; c < 3; ++c) launch_fill_profile(st, d, q[c], nullptr);
+    RhsArgs r2{};
+    r2.mode = RHS_NEGW;
+    for (int c = 0; c < 3; ++c) r2.f[c] = u1[c];
+    enqueue_solve(S, r2, q, 3, rtol, mc, TAG_FIELD);
+    launch_adj_wall_couple(st, d, q, S->om, S->part, S->scal, SC_ADJ_OMC);
+    // S = (1/eta) D phi x D mu
+    launch_adj_source(st, d, phi, S->mu, q, 1.0 / S->p.eta, adj_prev, mubar);
+    // mu(phi)
+    double* gbar = (double*)S->spec[0];
+    const double dCb = S->p.bend_scale * 3.0 * std::sqrt(2.0) / (8.0 * S->p.eps * S->p.eps * S->p.eps);
+    if (S->p.model == VS_BENDING)
+        launch_adj_mu1(st, d, phi, mubar, S->C_b(), dCb, S->p.eps, gbar, S->part, S->scal);
+    launch_adj_mu2(st, d, phi, mubar, gbar, S->scal, S->p.model, S->C_b(), S->p.eps, S->p.sigma, dt,
+                   S->p.mobility, S->p.rate_V, S->p.k_A, adj_prev);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    int ist[IS_NSTAT];
+    double sc[SC_NSCAL];
+    HIP_TRY(hipMemcpy(ist, S->istat, sizeof ist, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    if (ist[IS_FLAGS] & ST_NONFINITE) return fail(VS_E_NONFINITE, "vs_grad_step: non-finite residual");
+    if (ist[IS_FLAGS] & ST_NOCONV)
+        return fail(VS_E_NOCONV, "vs_grad_step: an adjoint Poisson solve missed rtol %.3g", rtol);
+    const double kbar = S->p.model == VS_BENDING ? sc[SC_ADJ_KAPPA] : 0.0;
+    const double sbar = -dt * sc[SC_ADJ_WALLV] + sc[SC_ADJ_PSIW] + sc[SC_ADJ_PSIC] + sc[SC_ADJ_OMC];
+    if (!std::isfinite(kbar) || !std::isfinite(sbar))
+        return fail(VS_E_NONFINITE, "vs_grad_step: non-finite parameter gradient");
+    dparams[0] += kbar;
+    dparams[1] += sbar;
+    return VS_OK;
 }
 
 vs_status vs_field_offset(const vs_state* S, int32_t field, size_t* byte_offset) {

@@ -58,6 +58,14 @@ enum {
     SC_V = 0, SC_A = 1, SC_V0 = 2, SC_A0 = 3, SC_LAMV = 4, SC_GAMMA = 5,
     SC_RELRES_MAX = 6,        // largest final relative residual since the last reset
     SC_RELRES_LAST = 7,       // relative residual of the last check
+    // reverse step: sums gathered by its reduction kernels
+    SC_ADJ_SUM_A = 8,         // sum a (the adjoint of lambda_V over dt M)
+    SC_ADJ_WALLV = 9,         // sum over wall nodes of a v_wall D_z phi
+    SC_ADJ_PSIW = 10,         // sum over wall rows of psi_bar . psi
+    SC_ADJ_PSIC = 11,         // wall coupling of the first adjoint solve with the psi walls
+    SC_ADJ_OMC = 12,          // wall coupling of the second adjoint solve with the omega walls
+    SC_ADJ_KAPPA = 13,        // sum mu_bar d mu / d kappa
+    SC_ADJ_GAMMA = 14,        // sum mu_bar d mu / d gamma_A = -sum mu_bar L_h phi
     SC_NSCAL = 16
 };
 // Slots of the device status array (ints).
@@ -143,6 +151,31 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
                       void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
                       const int* gate);
 int resid_blocks(const Dims& d);
+
+// ---------------------------------------------------------------- reverse step (k_adjoint.hip)
+// a = dL/dphi^{n+1}; writes phibar (dL/dphi^n, partial), mubar and psibar(3); gathers
+// SC_ADJ_SUM_A, SC_ADJ_WALLV, SC_ADJ_PSIW.
+void launch_adj_advect(hipStream_t s, const Dims& d, const double* a, const double* phi,
+                       const double* const psi[3], double dt, double mobility, double vz_lo,
+                       double vz_hi, double* phibar, double* mubar, double* const psibar[3],
+                       double* part, double* scal);
+// scal[slot] = -(1/h^2) sum_c sum_{i,k} [u_c(i,1,k) wall_c(i,0,k) + u_c(i,M,k) wall_c(i,ny-1,k)]
+void launch_adj_wall_couple(hipStream_t s, const Dims& d, double* const u[3],
+                            double* const wall[3], double* part, double* scal, int slot);
+// phibar += sum_c D_c^T abar_c, mubar += sum_c D_c^T bbar_c with abar = (1/eta) D mu x Sbar,
+// bbar = (1/eta) Sbar x D phi on the interior rows.
+void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
+                       double* const sbar[3], double inv_eta, double* phibar, double* mubar);
+// Bending: gbar = C_b [(3 phi^2 - 1) mubar - eps^2 L^T mubar]; gathers SC_ADJ_KAPPA,
+// SC_ADJ_GAMMA.
+void launch_adj_mu1(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
+                    double C_b, double dCb_dkappa, double eps, double* gbar, double* part,
+                    double* scal);
+// phibar += (d mu/d phi)^T mubar + the volume and area multiplier terms.
+void launch_adj_mu2(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
+                    const double* gbar, const double* scal, int model, double C_b, double eps,
+                    double sigma, double dt, double mobility, double rate_V, double k_A,
+                    double* phibar);
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate);
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,

@@ -176,6 +176,11 @@ class Solver:
         return code, cyc.value, rel.value
 
     def grad_step(self, dt, adj_next, adj_prev):
+        """Reverse step at the state's level n: adj_prev = (d phi^{n+1}/d phi^n)^T adj_next;
+        returns this step's (dL/dkappa, dL/ds) terms (s scales the wall speeds)."""
+        for t in (adj_next, adj_prev):
+            if t.dtype != self.torch.float64 or not t.is_contiguous() or tuple(t.shape) != self.shape:
+                raise ValueError("adjoints must be contiguous float64 tensors of the grid shape")
         dp = (ctypes.c_double * 2)()
         _check(lib().vs_grad_step(self._st, float(dt), ctypes.c_void_p(adj_next.data_ptr()),
                                   ctypes.c_void_p(adj_prev.data_ptr()), dp), "vs_grad_step")
@@ -265,6 +270,64 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def rollout_gradient(solver: "Solver", dt: float, nsteps: int, target, checkpoint_every: int = 10):
+    """L = ||phi^N - target||^2 (sum over nodes) of an nsteps rollout from the solver's current
+    state, and (L, dL/dkappa, dL/ds, dL/dphi^0 with V0, A0 fixed). The forward pass keeps a
+    vs_save_state checkpoint every checkpoint_every steps; the reverse sweep reloads the nearest
+    checkpoint and recomputes forward to each level (bit-identical to the first pass) before
+    its vs_grad_step. The solver is left at the initial state."""
+    torch = solver.torch
+    ce = max(1, int(checkpoint_every))
+    ckpt = {0: solver.save()}
+    for n in range(nsteps):
+        solver.step(dt, 1)
+        if (n + 1) % ce == 0:
+            ckpt[n + 1] = solver.save()
+    r = solver.field("phi") - target
+    loss = float((r * r).sum())
+    a = (2.0 * r).contiguous()
+    b = torch.empty_like(a)
+    kb = sb = 0.0
+    for n in range(nsteps - 1, -1, -1):
+        base = max(k for k in ckpt if k <= n)
+        solver.load(ckpt[base])
+        if n > base:
+            solver.step(dt, n - base)
+        dk, ds = solver.grad_step(dt, a, b)
+        kb += dk
+        sb += ds
+        a, b = b, a
+    solver.load(ckpt[0])
+    return loss, kb, sb, a
+
+
+def rollout_loss(workload, kappa, scale, target, nsteps=None, checkpoint_every=10, device="cuda:0"):
+    """torch.autograd.Function form of rollout_gradient: kappa and scale are 0-d float64 CPU
+    tensors (the bending modulus and the wall-speed scale); returns the loss as a 0-d tensor
+    whose backward gives dL/dkappa and dL/dscale."""
+    import torch
+
+    class _Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, k, sc):
+            w = workload.with_(kappa=float(k), u0=float(sc) * workload.u0, u1=float(sc) * workload.u1)
+            sol = solver_for(w, device=device)
+            try:
+                L, kb, sb, _ = rollout_gradient(sol, w.dt, nsteps or w.nsteps, target, checkpoint_every)
+            finally:
+                sol.close()
+            # dL/dscale: s scales the walls of w, whose speeds are scale * u; d/dscale = (1/scale) d/ds
+            ctx.save_for_backward(torch.tensor([kb, sb / float(sc)], dtype=torch.float64))
+            return torch.tensor(L, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            (gr,) = ctx.saved_tensors
+            return g * gr[0], g * gr[1]
+
+    return _Rollout.apply(kappa, scale)
 
 
 def solver_for(workload, device="cuda:0", precision="fp64", phi0=None, **overrides) -> "Solver":

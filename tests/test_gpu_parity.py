@@ -283,16 +283,6 @@ def test_nan_injection_reports_nonfinite():
     s.close()
 
 
-def test_grad_step_not_built():
-    w = workload("vesicle32")
-    s = P.solver_for(w)
-    a = torch.zeros(w.grid.shape, dtype=torch.float64, device="cuda")
-    with pytest.raises(V.VsError) as e:
-        s.grad_step(w.dt, a, a)
-    assert e.value.code == V.VS_E_UNSUPPORTED
-    s.close()
-
-
 def test_phi_sphere_helper_shapes():
     g = GridSpec(8, 8, 8)
     assert phi_sphere(g, 2.0, 1.0).shape == (8, 8, 8)

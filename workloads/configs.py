@@ -12,6 +12,10 @@ along +z, the walls are normal to y, x and z are periodic.
   droplet256  : 128 x 128 x 256 (256 along the flow), plane Couette with walls at
                 -0.05 / +0.05, Cahn-Hilliard droplet R = 20, sigma = 1, 500 steps of
                 dt = 1e-3.
+  adjoint96   : 96^3, plane Poiseuille (centreline 0.05), membrane kappa = 1 with a
+                seeded l <= 3 shape perturbation of radius 16, 50 steps of dt = 5e-4; the
+                differentiation workload (loss ||phi^50 - phi_target||^2, the target from
+                kappa = 1.5 and 1.2 times the wall speed, checkpoints every 10 steps).
 """
 from __future__ import annotations
 
@@ -101,6 +105,9 @@ WORKLOADS = {
     "droplet256": Workload(
         name="droplet256", grid=GridSpec(128, 128, 256), wall_kind=COUETTE, u0=-0.05, u1=0.05,
         model=CAHN_HILLIARD, sigma=1.0, dt=1e-3, nsteps=500, shape="sphere", R0=20.0),
+    "adjoint96": Workload(
+        name="adjoint96", grid=GridSpec(96, 96, 96), wall_kind=POISEUILLE, u0=0.05, u1=0.0,
+        model=BENDING, kappa=1.0, dt=5e-4, nsteps=50, shape="sh", R0=16.0, seed=0),
 }
 
 
