@@ -180,6 +180,30 @@ vs_status vs_step(vs_state* state, double dt, int32_t nsteps);
 vs_status vs_grad_step(vs_state* state, double dt, const double* adj_next, double* adj_prev,
                        double dparams[2]);
 
+/* Time-dependent walls (SM "Time-dependency and inertial flow": only the boundary data
+ * change). New wall speeds of the same kind (Poiseuille: u0 = centreline speed; Couette:
+ * u0, u1 = wall speeds) take effect now: the Poisson problems are linear in the wall data and
+ * the no-body channel fields solve them exactly, so omega_x and psi_x shift by the difference
+ * of the no-body fields (equal to re-solving the flow with the new walls), and the next steps
+ * use the new wall speeds. An oscillatory flow calls this before each vs_step. A batch that
+ * holds the state re-captures its graph on its next vs_batch_step. Checkpoints carry the
+ * walls. VS_E_ARG if the kind differs. Synchronises the stream. */
+vs_status vs_set_walls(vs_state* state, const vs_walls* walls);
+
+/* Diagnostics of the current state, on the device (synchronises the stream):
+ *   out[0] = int |omega - omega_0|^2, out[1] = int |psi - psi_0|^2: the flow observables of
+ *            the results section, about the no-body channel fields omega_0, psi_0 of the
+ *            current walls (trapezoid rule in y);
+ *   out[2] = free energy: bending, SM eq. (30) without the area term,
+ *            3 sqrt(2) kappa/(8 eps^3) int g^2; Cahn-Hilliard, eq. F_CH,
+ *            int 1/4 (phi^2 - 1)^2 + (sigma/2) |grad phi|^2;
+ *   out[3] = max sigma_t.
+ * sigma_t: device, nx*ny*nz doubles, or NULL: the in-plane shear-stress intensity of the
+ * section "In plane shear", sqrt(s_xy^2 + s_yz^2 + s_xz^2) with s_ij = eta (d_j v_i + d_i v_j)
+ * by central differences of v (curl psi inside, the wall speed on the walls), on the interior
+ * rows; 0 on the wall rows. */
+vs_status vs_diagnostics(vs_state* state, double* sigma_t, double out[4]);
+
 /* Byte offset, inside the workspace, of field `field` (VS_PHI ... VS_PSI_Z) as it stands
  * now (phi moves between two buffers from step to step: query after each vs_step). */
 vs_status vs_field_offset(const vs_state* state, int32_t field, size_t* byte_offset);

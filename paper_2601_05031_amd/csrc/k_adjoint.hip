@@ -18,85 +18,11 @@ namespace vs {
 
 namespace {
 
-__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-// Velocity components at a node: curl psi on the interior rows, the wall speed on the walls.
-struct Vel {
-    const double *px, *py, *pz;
-    double vz_lo, vz_hi;
-};
-
-__device__ __forceinline__ double vx_at(const Vel& v, const Dims& d, int i, int j, int k) {
-    if (j == 0 || j == d.ny - 1) return 0.0;
-    const int kp = wrap(k + 1, d.nz), km = wrap(k - 1, d.nz);
-    return ((v.pz[node(d, i, j + 1, k)] - v.pz[node(d, i, j - 1, k)]) -
-            (v.py[node(d, i, j, kp)] - v.py[node(d, i, j, km)])) * d.inv_2h;
-}
-__device__ __forceinline__ double vy_at(const Vel& v, const Dims& d, int i, int j, int k) {
-    if (j == 0 || j == d.ny - 1) return 0.0;
-    const int ip = wrap(i + 1, d.nx), im = wrap(i - 1, d.nx);
-    const int kp = wrap(k + 1, d.nz), km = wrap(k - 1, d.nz);
-    return ((v.px[node(d, i, j, kp)] - v.px[node(d, i, j, km)]) -
-            (v.pz[node(d, ip, j, k)] - v.pz[node(d, im, j, k)])) * d.inv_2h;
-}
-__device__ __forceinline__ double vz_at(const Vel& v, const Dims& d, int i, int j, int k) {
-    if (j == 0) return v.vz_lo;
-    if (j == d.ny - 1) return v.vz_hi;
-    const int ip = wrap(i + 1, d.nx), im = wrap(i - 1, d.nx);
-    return ((v.py[node(d, ip, j, k)] - v.py[node(d, im, j, k)]) -
-            (v.px[node(d, i, j + 1, k)] - v.px[node(d, i, j - 1, k)])) * d.inv_2h;
-}
-
-__device__ __forceinline__ double wrow(const Dims& d, int j) {
-    return (j == 0 || j == d.ny - 1) ? 0.5 : 1.0;
-}
-
-// (L_h^T u)_m = w_m (L_h (u / w))_m, mirror ghosts in y.
-__device__ __forceinline__ double lapT(const double* __restrict__ u, const Dims& d, int i, int j,
-                                       int k) {
-    const int jp = (j + 1 == d.ny) ? d.ny - 2 : j + 1;
-    const int jm = (j == 0) ? 1 : j - 1;
-    const double xz = u[node(d, wrap(i + 1, d.nx), j, k)] + u[node(d, wrap(i - 1, d.nx), j, k)] +
-                      u[node(d, i, j, wrap(k + 1, d.nz))] + u[node(d, i, j, wrap(k - 1, d.nz))];
-    const double yy = u[node(d, i, jp, k)] / wrow(d, jp) + u[node(d, i, jm, k)] / wrow(d, jm);
-    return (xz + wrow(d, j) * yy - 6.0 * u[node(d, i, j, k)]) * d.inv_h2;
-}
-
-// Central difference of u along axis c at an interior or any node (true neighbours in y; the
-// callers use it on the rows where the forward difference is evaluated).
-__device__ __forceinline__ double dcen(const double* __restrict__ u, const Dims& d, int c, int i,
-                                       int j, int k) {
-    if (c == 0) return (u[node(d, wrap(i + 1, d.nx), j, k)] - u[node(d, wrap(i - 1, d.nx), j, k)]) * d.inv_2h;
-    if (c == 1) return (u[node(d, i, j + 1, k)] - u[node(d, i, j - 1, k)]) * d.inv_2h;
-    return (u[node(d, i, j, wrap(k + 1, d.nz))] - u[node(d, i, j, wrap(k - 1, d.nz))]) * d.inv_2h;
-}
-
-__device__ __forceinline__ bool interior(const Dims& d, int j) { return j >= 1 && j <= d.ny - 2; }
-
 // b_c = -dt a D_c phi at an interior node, 0 on the wall rows and outside the grid.
 __device__ __forceinline__ double bcur(const double* __restrict__ a, const double* __restrict__ phi,
                                        const Dims& d, double dt, int c, int i, int j, int k) {
     if (j < 1 || j > d.ny - 2) return 0.0;
     return -dt * a[node(d, i, j, k)] * dcen(phi, d, c, i, j, k);
-}
-
-// Walks a slab of x-planes per thread (the block-partial layout of the forward reductions).
-struct SlabIter {
-    int j, k, i0, i1;
-    bool ok;
-};
-__device__ __forceinline__ SlabIter slab_iter(const Dims& d, const SlabGrid& sg) {
-    const int nb = sg.gx * sg.gi;
-    const int lb = xcd_block(blockIdx.x, nb);
-    const int bi = lb / sg.gx;
-    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
-    SlabIter it;
-    it.ok = t < d.ny * d.nz;
-    it.j = it.ok ? t / d.nz : 0;
-    it.k = it.ok ? t - it.j * d.nz : 0;
-    it.i0 = bi * sg.ci;
-    it.i1 = min(d.nx, (bi + 1) * sg.ci);
-    return it;
 }
 
 // Reverse of phi' = phi + dt [M (L_h mu + lambda_V) - v . D phi] with respect to phi (through

@@ -86,7 +86,7 @@ Layout make_layout(const vs_grid& g) {
     L.off_twz = o;    o += align_up((size_t)g.nz * sizeof(double2));
     L.off_tri = o;    o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * (M + 1) * sizeof(double));
     L.off_part = o;   o += align_up((size_t)kMaxPartialBlocks * kPartialSlots * sizeof(double));
-    L.off_prof = o;   o += align_up(2 * (size_t)g.ny * sizeof(double));
+    L.off_prof = o;   o += align_up(4 * (size_t)g.ny * sizeof(double));   // tables + a change
     L.off_scal = o;   o += align_up(SC_NSCAL * sizeof(double));
     L.off_istat = o;  o += align_up(IS_NSTAT * sizeof(int));
     L.total = o;
@@ -167,6 +167,8 @@ struct vs_state {
     double* scal = nullptr;
     int* istat = nullptr;
     double vz_lo = 0.0, vz_hi = 0.0;
+    std::vector<double> prof_host;   // the device wall tables prof[0, 2 ny), host copy
+    long long walls_gen = 0;  // bumped on every wall change (a batch re-captures its graph)
     double gamma_host = 0.0;  // gamma_A as of the last synchronisation
     long long step = 0;
     double last_relres = 0.0;
@@ -357,6 +359,46 @@ void enqueue_step(vs_state* S, double dt) {
     enqueue_flow(S, out);
 }
 
+// No-body channel tables on the node rows (the wall data of "Boundary conditions", reading
+// R11): prof[j] = psi_x(y_j), prof[ny + j] = omega_x(y_j).
+std::vector<double> wall_tables(const vs_grid& g, const vs_walls& w) {
+    const double H = (g.ny - 1) * g.h;
+    std::vector<double> prof(2 * (size_t)g.ny);
+    for (int j = 0; j < g.ny; ++j) {
+        const double y = j * g.h;
+        double psx, omx;
+        if (w.kind == VS_POISEUILLE) {
+            const double U = w.u0;
+            psx = -(4.0 * U / (H * H)) * (H * y * y / 2.0 - y * y * y / 3.0);
+            omx = (4.0 * U / (H * H)) * (H - 2.0 * y);
+        } else {
+            const double u0 = w.u0, u1 = w.u1;
+            psx = -(u0 * y + (u1 - u0) * y * y / (2.0 * H));
+            omx = (u1 - u0) / H;
+        }
+        prof[j] = psx;
+        prof[g.ny + j] = omx;
+    }
+    return prof;
+}
+
+// Host-side wall state: the wall speeds the advection uses on the wall nodes and the psi wall
+// values folded into mode (0, 0) of the stream-vector solve.
+void set_wall_state(vs_state* S, const vs_walls& w, const std::vector<double>& prof) {
+    S->w = w;
+    S->prof_host = prof;
+    S->psi_wall_lo[0] = prof[0];
+    S->psi_wall_hi[0] = prof[S->g.ny - 1];
+    if (w.kind == VS_POISEUILLE) {
+        S->vz_lo = 0.0;
+        S->vz_hi = 0.0;
+    } else {
+        S->vz_lo = w.u0;
+        S->vz_hi = w.u1;
+    }
+    ++S->walls_gen;
+}
+
 // Reads the device status and scalars after a synchronisation; maps flags to a status.
 vs_status collect(vs_state* S, const char* what) {
     HIP_TRY(hipStreamSynchronize(S->stream));
@@ -480,32 +522,8 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
             }
             tri[(size_t)M * ncls + cls] = beta;
         }
-    const double H = (grid->ny - 1) * grid->h;
-    std::vector<double> prof(2 * (size_t)grid->ny);
-    for (int j = 0; j < grid->ny; ++j) {
-        const double y = j * grid->h;
-        double psx, omx;
-        if (walls->kind == VS_POISEUILLE) {
-            const double U = walls->u0;
-            psx = -(4.0 * U / (H * H)) * (H * y * y / 2.0 - y * y * y / 3.0);
-            omx = (4.0 * U / (H * H)) * (H - 2.0 * y);
-        } else {
-            const double u0 = walls->u0, u1 = walls->u1;
-            psx = -(u0 * y + (u1 - u0) * y * y / (2.0 * H));
-            omx = (u1 - u0) / H;
-        }
-        prof[j] = psx;
-        prof[grid->ny + j] = omx;
-    }
-    S->psi_wall_lo[0] = prof[0];
-    S->psi_wall_hi[0] = prof[grid->ny - 1];
-    if (walls->kind == VS_POISEUILLE) {
-        S->vz_lo = 0.0;
-        S->vz_hi = 0.0;
-    } else {
-        S->vz_lo = walls->u0;
-        S->vz_hi = walls->u1;
-    }
+    std::vector<double> prof = wall_tables(*grid, *walls);
+    set_wall_state(S, *walls, prof);
     S->gamma_host = params->gamma0;
 
     auto bail = [&](vs_status s) {
@@ -646,6 +664,45 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
     return VS_OK;
 }
 
+vs_status vs_set_walls(vs_state* S, const vs_walls* walls) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    vs_status st = check_walls(walls);
+    if (st != VS_OK) return st;
+    if (walls->kind != S->w.kind) return fail(VS_E_ARG, "vs_set_walls: the wall kind cannot change");
+    const std::vector<double> prof = wall_tables(S->g, *walls);
+    const int ny = S->g.ny;
+    std::vector<double> dprof(2 * (size_t)ny);
+    for (size_t q = 0; q < dprof.size(); ++q) dprof[q] = prof[q] - S->prof_host[q];
+    HIP_TRY(hipMemcpyAsync(S->prof + 2 * ny, dprof.data(), dprof.size() * sizeof(double),
+                           hipMemcpyHostToDevice, S->stream));
+    launch_shift_profiles(S->stream, S->d, S->om[0], S->ps[0], S->prof + 2 * ny);
+    HIP_TRY(hipMemcpyAsync(S->prof, prof.data(), prof.size() * sizeof(double), hipMemcpyHostToDevice,
+                           S->stream));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(S->stream));   // the host tables above are copied from
+    set_wall_state(S, *walls, prof);
+    return VS_OK;
+}
+
+vs_status vs_diagnostics(vs_state* S, double* sigma_t, double out[4]) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!out) return fail(VS_E_ARG, "out is NULL");
+    const Dims& d = S->d;
+    launch_diagnostics(S->stream, d, S->phi[S->cur], S->om, S->ps, S->prof, S->vz_lo, S->vz_hi,
+                       S->p.eta, S->p.model, S->p.eps, S->p.sigma, sigma_t, S->part, S->scal);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    double sc[SC_NSCAL];
+    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    const double h3 = d.h * d.h * d.h;
+    const double cF = 3.0 * std::sqrt(2.0) * S->p.kappa / (8.0 * S->p.eps * S->p.eps * S->p.eps);
+    out[0] = h3 * sc[SC_DG_OMEGA];
+    out[1] = h3 * sc[SC_DG_PSI];
+    out[2] = (S->p.model == VS_BENDING ? cF : 1.0) * h3 * sc[SC_DG_ENERGY];
+    out[3] = sc[SC_DG_SMAX];
+    return VS_OK;
+}
+
 vs_status vs_field_offset(const vs_state* S, int32_t field, size_t* byte_offset) {
     if (!S) return fail(VS_E_STATE, "state is NULL");
     if (!byte_offset) return fail(VS_E_ARG, "byte_offset is NULL");
@@ -682,8 +739,9 @@ vs_status vs_get_scalars(vs_state* S, double out[VS_NSCALARS]) {
 namespace {
 struct BlobHeader {
     char magic[8];
-    int32_t nx, ny, nz, pad;
+    int32_t nx, ny, nz, kind;
     int64_t step;
+    double u0, u1;            // wall speeds
     double scal[SC_NSCAL];
 };
 }  // namespace
@@ -700,11 +758,14 @@ vs_status vs_save_state(vs_state* S, void* blob, size_t* bytes) {
     if (*bytes < need) return fail(VS_E_ARG, "blob has %zu bytes, needs %zu", *bytes, need);
     HIP_TRY(hipStreamSynchronize(S->stream));
     BlobHeader hd{};
-    std::memcpy(hd.magic, "VSSTATE1", 8);
+    std::memcpy(hd.magic, "VSSTATE2", 8);
     hd.nx = S->g.nx;
     hd.ny = S->g.ny;
     hd.nz = S->g.nz;
+    hd.kind = S->w.kind;
     hd.step = S->step;
+    hd.u0 = S->w.u0;
+    hd.u1 = S->w.u1;
     HIP_TRY(hipMemcpy(hd.scal, S->scal, sizeof hd.scal, hipMemcpyDeviceToHost));
     std::memcpy(blob, &hd, sizeof hd);
     double* dst = (double*)((char*)blob + sizeof hd);
@@ -722,8 +783,9 @@ vs_status vs_load_state(vs_state* S, const void* blob, size_t bytes) {
     if (bytes < need) return fail(VS_E_ARG, "blob has %zu bytes, needs %zu", bytes, need);
     BlobHeader hd;
     std::memcpy(&hd, blob, sizeof hd);
-    if (std::memcmp(hd.magic, "VSSTATE1", 8) != 0) return fail(VS_E_ARG, "not a vs_save_state blob");
+    if (std::memcmp(hd.magic, "VSSTATE2", 8) != 0) return fail(VS_E_ARG, "not a vs_save_state blob");
     if (hd.nx != S->g.nx || hd.ny != S->g.ny || hd.nz != S->g.nz) return fail(VS_E_ARG, "grid mismatch");
+    if (hd.kind != S->w.kind) return fail(VS_E_ARG, "wall kind mismatch");
     HIP_TRY(hipStreamSynchronize(S->stream));
     const double* src = (const double*)((const char*)blob + sizeof hd);
     double* dst[8] = {S->phi[S->cur], S->mu, S->om[0], S->om[1], S->om[2], S->ps[0], S->ps[1], S->ps[2]};
@@ -731,6 +793,15 @@ vs_status vs_load_state(vs_state* S, const void* blob, size_t bytes) {
     HIP_TRY(hipMemcpy(S->scal, hd.scal, sizeof hd.scal, hipMemcpyHostToDevice));
     S->step = hd.step;
     S->gamma_host = hd.scal[SC_GAMMA];
+    if (hd.u0 != S->w.u0 || hd.u1 != S->w.u1) {
+        // the fields carry the saved walls: restore the wall tables with them
+        vs_walls w = S->w;
+        w.u0 = hd.u0;
+        w.u1 = hd.u1;
+        const std::vector<double> prof = wall_tables(S->g, w);
+        HIP_TRY(hipMemcpy(S->prof, prof.data(), prof.size() * sizeof(double), hipMemcpyHostToDevice));
+        set_wall_state(S, w, prof);
+    }
     return VS_OK;
 }
 
@@ -777,6 +848,7 @@ struct vs_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<double> dt;             // time steps baked into the captured graph
+    std::vector<long long> gen;         // each instance's walls_gen at capture
 };
 
 namespace {
@@ -825,6 +897,8 @@ vs_status batch_capture(vs_batch* B, const double* dt) {
     B->graph = g;
     HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     B->dt.assign(dt, dt + B->st.size());
+    B->gen.clear();
+    for (vs_state* S : B->st) B->gen.push_back(S->walls_gen);
     return VS_OK;
 }
 
@@ -891,8 +965,8 @@ vs_status vs_batch_step(vs_batch* B, const double* dt, int32_t nsteps) {
             return fail(VS_E_UNSTABLE, "instance %zu: dt = %.4g exceeds the forward-Euler bound %.4g",
                         i, dt[i], 2.0 / stability_rate(S));
     }
-    bool same = B->exec && B->dt.size() == n;
-    for (size_t i = 0; same && i < n; ++i) same = B->dt[i] == dt[i];
+    bool same = B->exec && B->dt.size() == n && B->gen.size() == n;
+    for (size_t i = 0; same && i < n; ++i) same = B->dt[i] == dt[i] && B->gen[i] == B->st[i]->walls_gen;
     if (!same) {
         const vs_status st = batch_capture(B, dt);
         if (st != VS_OK) return st;

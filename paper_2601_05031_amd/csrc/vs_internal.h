@@ -66,7 +66,12 @@ enum {
     SC_ADJ_OMC = 12,          // wall coupling of the second adjoint solve with the omega walls
     SC_ADJ_KAPPA = 13,        // sum mu_bar d mu / d kappa
     SC_ADJ_GAMMA = 14,        // sum mu_bar d mu / d gamma_A = -sum mu_bar L_h phi
-    SC_NSCAL = 16
+    // diagnostics: sums over the nodes with trapezoid weights, and the largest sigma_t
+    SC_DG_OMEGA = 16,         // sum_w |omega - omega_0|^2
+    SC_DG_PSI = 17,           // sum_w |psi - psi_0|^2
+    SC_DG_ENERGY = 18,        // sum_w of the free-energy density (g^2 for bending)
+    SC_DG_SMAX = 19,          // max sigma_t
+    SC_NSCAL = 24
 };
 // Slots of the device status array (ints).
 enum {
@@ -171,6 +176,14 @@ void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const do
 void launch_adj_mu1(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
                     double C_b, double dCb_dkappa, double eps, double* gbar, double* part,
                     double* scal);
+// Diagnostics (k_diag.hip): sigma_t (device field or NULL) and SC_DG_* sums.
+void launch_diagnostics(hipStream_t s, const Dims& d, const double* phi, double* const omega[3],
+                        double* const psi[3], const double* prof, double vz_lo, double vz_hi,
+                        double eta, int model, double eps, double sigma, double* sigma_t,
+                        double* part, double* scal);
+// omega_x += dprof[ny + j], psi_x += dprof[j] at every node (a wall-speed change).
+void launch_shift_profiles(hipStream_t s, const Dims& d, double* omega_x, double* psi_x,
+                           const double* dprof);
 // phibar += (d mu/d phi)^T mubar + the volume and area multiplier terms.
 void launch_adj_mu2(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
                     const double* gbar, const double* scal, int model, double C_b, double eps,

@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         "vs_profile_name": (ctypes.c_char_p, [i32]),
         "vs_profile_read": (i32, [vp, i32, P(dbl), P(ctypes.c_int64)]),
         "vs_destroy": (None, [vp]),
+        "vs_set_walls": (i32, [vp, P(VsWalls)]),
+        "vs_diagnostics": (i32, [vp, vp, P(dbl)]),
         "vs_batch_create": (i32, [P(vp), i32, vp, i32, P(vp)]),
         "vs_batch_step": (i32, [vp, P(dbl), i32]),
         "vs_batch_destroy": (None, [vp]),
@@ -201,6 +203,23 @@ class Solver:
         out = (ctypes.c_double * len(SCALARS))()
         _check(lib().vs_get_scalars(self._st, out), "vs_get_scalars")
         return dict(zip(SCALARS, list(out)))
+
+    def set_walls(self, u0: float, u1: float = 0.0):
+        """New wall speeds (same kind) from now on: the time-dependent-walls hook."""
+        w = VsWalls(self.walls.kind, float(u0), float(u1))
+        _check(lib().vs_set_walls(self._st, ctypes.byref(w)), "vs_set_walls")
+        self.walls = w
+
+    def diagnostics(self, sigma_t=None) -> dict:
+        """Observables, free energy and max shear-stress intensity; fills sigma_t (a float64
+        tensor of the grid shape) with the shear-stress intensity if given."""
+        if sigma_t is not None and (sigma_t.dtype != self.torch.float64 or not sigma_t.is_contiguous()
+                                    or tuple(sigma_t.shape) != self.shape):
+            raise ValueError("sigma_t must be a contiguous float64 tensor of the grid shape")
+        out = (ctypes.c_double * 4)()
+        ptr = ctypes.c_void_p(sigma_t.data_ptr()) if sigma_t is not None else None
+        _check(lib().vs_diagnostics(self._st, ptr, out), "vs_diagnostics")
+        return {"obs_omega": out[0], "obs_psi": out[1], "energy": out[2], "sigma_t_max": out[3]}
 
     def save(self) -> bytes:
         n = ctypes.c_size_t(0)

@@ -156,6 +156,6 @@ def test_adjoint96_gradient_against_finite_differences():
     sc = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
     loss = P.rollout_loss(w, k, sc, target)
     loss.backward()
-    assert float(loss) == pytest.approx(L, rel=1e-12)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-12)
     assert float(k.grad) == pytest.approx(kb, rel=1e-12)
     assert float(sc.grad) == pytest.approx(sb, rel=1e-12)
