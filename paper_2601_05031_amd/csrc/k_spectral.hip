@@ -384,14 +384,28 @@ __device__ __forceinline__ ModeLane mode_lane(const Dims& d, const double* __res
 
 // tridiag_y: one Poisson problem per component blockIdx.y: f_j = scale * B_j (B = the 2D
 // Hartley spectrum of the right-hand side, scale = h^2/(nx nz)), in place.
+// wlo, whi: wall terms folded into mode (0, 0) (zero when the right-hand side holds them).
 template <class ST>
 __global__ __launch_bounds__(64) void k_tridiag_y(Dims d, const double* __restrict__ tri,
-                                                 SPtr3<ST> spec, const int* gate, double scale) {
+                                                 SPtr3<ST> spec, const int* gate, double scale,
+                                                 double3 wlo, double3 whi) {
     if (gate && *gate) return;
     const ModeLane ml = mode_lane(d, tri);
-    ST* col = spec.p[blockIdx.y] + ml.off;
+    const int c = blockIdx.y;
+    ST* col = spec.p[c] + ml.off;
+    const bool m00 = (ml.p == 0 && ml.q == 0);
+    const double a = c == 0 ? wlo.x : (c == 1 ? wlo.y : wlo.z);
+    const double b = c == 0 ? whi.x : (c == 1 ? whi.y : whi.z);
+    const int M = d.M;
     twisted_half<true, ST>(nullptr, col, d.nz, d.M, ml.half, ml.act, ml.cp, ml.ncls,
-                       [&](int, double v) { return scale * v; });
+                           [&](int j, double v) {
+                               double f = scale * v;
+                               if (m00) {
+                                   if (j == 1) f -= a;
+                                   if (j == M) f -= b;
+                               }
+                               return f;
+                           });
 }
 
 // tridiag_psi: the stream-vector problem lap psi = -w from the vorticity modes U_w = T w/(nx nz)
@@ -668,7 +682,8 @@ __global__ __launch_bounds__(256) void k_tridiag_seg(Dims d, const double* __res
 template <int S, int LMAX, class ST, int LMF, int NLF>
 __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* __restrict__ tri,
                                                          SPtr3<ST> spec, SPtr3<ST> spec2,
-                                                         double3 plo, double3 phi_, double scale) {
+                                                         double3 olo, double3 ohi, double3 plo,
+                                                         double3 phi_, double scale) {
     SegLane<S> sl = seg_lane<S>(d);
     if (LMF) {
         sl.Lm = LMF;
@@ -682,14 +697,24 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
     const unsigned N = (unsigned)(d.nx * d.ny * d.nz);
     double x[LMAX];
     seg_load<S, LMAX, ST>(x, col, N, sl.off, d.nz, sl.Lm, scale);
+    const bool m00 = sl.p == 0 && sl.q == 0;
+    // the row j = M is the last real row of segment S - 1 (short if nlong > 0)
+    const int ulast = sl.nlong > 0 ? sl.Lm - 2 : sl.Lm - 1;
+    {
+        // vorticity wall terms, constant over each wall plane: mode (0, 0) only
+        const double a = c3 == 0 ? olo.x : (c3 == 1 ? olo.y : olo.z);
+        const double b = c3 == 0 ? ohi.x : (c3 == 1 ? ohi.y : ohi.z);
+#pragma unroll
+        for (int u = 0; u < LMAX; ++u) {
+            if (m00 && sl.k == 0 && u == 0) x[u] -= a;
+            if (m00 && sl.k == S - 1 && u == ulast) x[u] -= b;
+        }
+    }
     seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
     seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
     const double h2 = d.h * d.h;
-    const bool m00 = sl.p == 0 && sl.q == 0;
     const double wlo = c3 == 0 ? plo.x : (c3 == 1 ? plo.y : plo.z);
     const double whi = c3 == 0 ? phi_.x : (c3 == 1 ? phi_.y : phi_.z);
-    // the row j = M is the last real row of segment S - 1 (short if nlong > 0)
-    const int ulast = sl.nlong > 0 ? sl.Lm - 2 : sl.Lm - 1;
 #pragma unroll
     for (int u = 0; u < LMAX; ++u) {
         double f = -h2 * x[u];
@@ -907,6 +932,16 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
             if (o.x >= 0) st(sc + o.x + p, ha);
             if (o.y >= 0) st(sc + o.y + p, hb);
         };
+        if (rhs.fold_walls) {
+            // f alone: one unconditional load per element
+            auto loadf = [&](const RowPair& rp, int k1, int k2) -> double2 {
+                const int k = k1 + A * k2;
+                return make_double2(rp.a >= 0 ? sg * fc[rp.a + k] : 0.0,
+                                    rp.b >= 0 ? sg * fc[rp.b + k] : 0.0);
+            };
+            two_pass_hartley<B, A, false>(Y, tw, prep, loadf, store);
+            return;
+        }
         two_pass_hartley<B, A, false>(Y, tw, prepw, load, storew);
         return;
     }
@@ -1313,12 +1348,12 @@ int seg_shape(int M) {
 // their segment lengths as compile-time constants.
 template <bool PAIR, int S, int LMAX, class ST, int LMF, int NLF>
 void seg_launch(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                void* const spec2[3], int ncomp, const int* gate, double3 lo, double3 hi,
-                double scale) {
+                void* const spec2[3], int ncomp, const int* gate, double3 olo, double3 ohi,
+                double3 lo, double3 hi, double scale) {
     const dim3 grid((unsigned)(((long)d.nx * d.nz * S + 255) / 256), ncomp);
     if (PAIR)
         launch_kernel((k_tridiag_pair_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d,
-                           tri, sptr<ST>(spec, 3), sptr<ST>(spec2, 3), lo, hi, scale);
+                           tri, sptr<ST>(spec, 3), sptr<ST>(spec2, 3), olo, ohi, lo, hi, scale);
     else
         launch_kernel((k_tridiag_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d, tri,
                            sptr<ST>(spec, ncomp), gate, scale);
@@ -1326,10 +1361,12 @@ void seg_launch(hipStream_t s, const Dims& d, const double* tri, void* const spe
 
 template <bool PAIR, class ST>
 bool seg_dispatch(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                  void* const spec2[3], int ncomp, const int* gate, double3 lo, double3 hi) {
+                  void* const spec2[3], int ncomp, const int* gate, double3 olo, double3 ohi,
+                  double3 lo, double3 hi) {
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
 #define VS_SEG(S_, LMAX_, LMF_, NLF_) \
-    seg_launch<PAIR, S_, LMAX_, ST, LMF_, NLF_>(s, d, tri, spec, spec2, ncomp, gate, lo, hi, scale)
+    seg_launch<PAIR, S_, LMAX_, ST, LMF_, NLF_>(s, d, tri, spec, spec2, ncomp, gate, olo, ohi, lo, \
+                                                hi, scale)
     switch (d.M) {
     case 30: VS_SEG(4, 8, 8, 2); return true;
     case 46: VS_SEG(4, 16, 12, 2); return true;
@@ -1353,21 +1390,21 @@ template <class ST>
 void tridiag_y_t(hipStream_t s, const Dims& d, const double* tri, void* const spec[3], int ncomp,
                  const int* gate) {
     const double3 z = make_double3(0.0, 0.0, 0.0);
-    if (seg_dispatch<false, ST>(s, d, tri, spec, nullptr, ncomp, gate, z, z)) return;
+    if (seg_dispatch<false, ST>(s, d, tri, spec, nullptr, ncomp, gate, z, z, z, z)) return;
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
     const dim3 grid((2 * d.nx * d.nz + 63) / 64, ncomp);
     launch_kernel(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, ncomp), gate,
-                       scale);
+                  scale, z, z);
 }
 
 template <class ST>
 void tridiag_pair_t(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                    void* const spec2[3], double3 lo, double3 hi) {
-    if (seg_dispatch<true, ST>(s, d, tri, spec, spec2, 3, nullptr, lo, hi)) return;
+                    void* const spec2[3], double3 olo, double3 ohi, double3 lo, double3 hi) {
+    if (seg_dispatch<true, ST>(s, d, tri, spec, spec2, 3, nullptr, olo, ohi, lo, hi)) return;
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
     const dim3 grid((2 * d.nx * d.nz + 63) / 64, 3);
     launch_kernel(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
-                       (const int*)nullptr, scale);
+                  (const int*)nullptr, scale, olo, ohi);
     launch_kernel(k_tridiag_psi<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
                        sptr<ST>(spec2, 3), lo, hi);
 }
@@ -1381,14 +1418,16 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* con
 }
 
 void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                         void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
-                         bool f32) {
+                         void* const spec2[3], const double om_lo[3], const double om_hi[3],
+                         const double psi_lo[3], const double psi_hi[3], bool f32) {
+    const double3 olo = make_double3(om_lo[0], om_lo[1], om_lo[2]);
+    const double3 ohi = make_double3(om_hi[0], om_hi[1], om_hi[2]);
     const double3 lo = make_double3(psi_lo[0], psi_lo[1], psi_lo[2]);
     const double3 hi = make_double3(psi_hi[0], psi_hi[1], psi_hi[2]);
     if (f32)
-        tridiag_pair_t<float>(s, d, tri, spec, spec2, lo, hi);
+        tridiag_pair_t<float>(s, d, tri, spec, spec2, olo, ohi, lo, hi);
     else
-        tridiag_pair_t<double>(s, d, tri, spec, spec2, lo, hi);
+        tridiag_pair_t<double>(s, d, tri, spec, spec2, olo, ohi, lo, hi);
 }
 
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,

@@ -159,6 +159,7 @@ struct vs_state {
     void* spec2[3] = {};
     bool f32 = false;         // refined mode: spectral intermediates stored as float
     double psi_wall_lo[3] = {0, 0, 0}, psi_wall_hi[3] = {0, 0, 0};
+    double om_wall_lo[3] = {0, 0, 0}, om_wall_hi[3] = {0, 0, 0};
     double2* twx = nullptr;
     double2* twz = nullptr;
     double* tri = nullptr;
@@ -317,12 +318,15 @@ void enqueue_flow(vs_state* S, const double* phi) {
         return;
     }
     const double* const cu[3] = {S->om[0], S->om[1], S->om[2]};
+    RhsArgs rvf = rv;
+    rvf.fold_walls = 1;   // the omega wall terms go into mode (0, 0) of the tridiagonal solve
     timed(S, K_RHS_Z_OMEGA, [&] {
-        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rv, cu, 3, 0, S->spec, false, nullptr);
+        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rvf, cu, 3, 0, S->spec, false, nullptr);
     });
     timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
     timed(S, K_TRIDIAG_PAIR, [&] {
-        launch_tridiag_pair(S->stream, d, S->tri, S->spec, S->spec2, S->psi_wall_lo, S->psi_wall_hi, false);
+        launch_tridiag_pair(S->stream, d, S->tri, S->spec, S->spec2, S->om_wall_lo, S->om_wall_hi,
+                            S->psi_wall_lo, S->psi_wall_hi, false);
     });
     timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
     timed(S, K_DHT_Z_OUT, [&] {
@@ -389,6 +393,8 @@ void set_wall_state(vs_state* S, const vs_walls& w, const std::vector<double>& p
     S->prof_host = prof;
     S->psi_wall_lo[0] = prof[0];
     S->psi_wall_hi[0] = prof[S->g.ny - 1];
+    S->om_wall_lo[0] = prof[S->g.ny];
+    S->om_wall_hi[0] = prof[2 * S->g.ny - 1];
     if (w.kind == VS_POISEUILLE) {
         S->vz_lo = 0.0;
         S->vz_hi = 0.0;

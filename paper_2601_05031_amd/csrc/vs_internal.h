@@ -91,6 +91,9 @@ enum RhsMode {
 struct RhsArgs {
     int mode;
     const double* f[3];      // RHS_FIELD arrays, or omega for RHS_NEGW
+    // 1: the direct transform reads f alone; the wall terms (wall values constant over each
+    // wall plane) are added in mode (0, 0) by the tridiagonal solve instead
+    int fold_walls;
 };
 
 // Plan of a length-n transform: radices applied in order (Stockham passes).
@@ -149,9 +152,11 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* con
 // Vorticity modes solved in place in spec (as launch_tridiag_y), then the stream-vector modes
 // into spec2 from them (psi wall values constant over each wall plane: psi_lo at j = 0,
 // psi_hi at j = ny-1).
+// The vorticity right-hand side's wall terms, om_lo at j = 0 and om_hi at j = ny-1 (constant
+// over each wall plane), are added in mode (0, 0) (the transform read S alone).
 void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                         void* const spec2[3], const double psi_lo[3], const double psi_hi[3],
-                         bool f32);
+                         void* const spec2[3], const double om_lo[3], const double om_hi[3],
+                         const double psi_lo[3], const double psi_hi[3], bool f32);
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
                       const int* gate);
