@@ -42,37 +42,120 @@ __global__ __launch_bounds__(kBlock) void k_advance(
 
 // mu from phi. Bending (SM eq. (35)): g = phi^3 - phi - eps^2 L_h phi,
 // mu = C_b [(3 phi^2 - 1) g - eps^2 L_h g] - gamma_A L_h phi. Cahn-Hilliard:
-// mu = phi^3 - phi - sigma L_h phi. g at the six neighbours is recomputed from phi
-// (25-point footprint), so g never reaches HBM.
-__global__ __launch_bounds__(kBlock) void k_mu(const double* __restrict__ phi,
-                                              double* __restrict__ mu, Dims d,
-                                              const double* __restrict__ scal, int model,
-                                              double C_b, double eps, double sigma) {
-    int i, j, k;
-    bool ok;
-    plane_index(d, i, j, k, ok);
-    if (!ok) return;
-    const Nbr n = neighbours_mirror(d, i, j, k);
-    const double p = phi[n.c];
-    const double lphi = lap7(phi, n, d.inv_h2);
-    if (model == VS_CAHN_HILLIARD) {
-        mu[n.c] = p * p * p - p - sigma * lphi;
-        return;
+// mu = phi^3 - phi - sigma L_h phi. g never reaches HBM.
+//
+// mu by x-marching tiles. A block owns a kMuTY x kMuTZ tile of (j, k) and walks kMuNI
+// consecutive x-planes: a 4-plane ring of phi (halo 2 in y and z) and a 3-plane ring of g
+// (halo 1) live in LDS, the next phi plane is prefetched into registers while the current
+// one is computed, and every x-neighbour comes from the rings instead of L2. Rows beyond the
+// walls are filled with the mirror image (j -> -j, ny-1+m -> ny-1-m), so g computed there is
+// the mirror ghost of g. Sums run in the order of lap7, so the result equals the plain
+// stencil's bit for bit.
+constexpr int kMuTY = 4, kMuTZ = 64, kMuNI = 8;
+constexpr int kPY = kMuTY + 4, kPZ = kMuTZ + 4, kPN = kPY * kPZ;
+constexpr int kGY = kMuTY + 2, kGZ = kMuTZ + 2, kGN = kGY * kGZ;
+constexpr int kPre = (kPN + kBlock - 1) / kBlock;
+
+__device__ __forceinline__ int mirror_row(int j, int ny) {
+    j = j < 0 ? -j : (j > ny - 1 ? 2 * (ny - 1) - j : j);
+    return j < 0 ? 0 : (j > ny - 1 ? ny - 1 : j);   // only rows no output needs get clamped
+}
+__device__ __forceinline__ int wrap_mod(int k, int n) {
+    k %= n;
+    return k < 0 ? k + n : k;
+}
+
+template <bool BEND>
+__global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ phi,
+                                                   double* __restrict__ mu, Dims d,
+                                                   const double* __restrict__ scal, double C_b,
+                                                   double eps, double sigma) {
+    __shared__ double P[4][kPN];
+    __shared__ double G[BEND ? 3 : 1][BEND ? kGN : 1];
+    const int tz_n = (d.nz + kMuTZ - 1) / kMuTZ;
+    const int ty_n = (d.ny + kMuTY - 1) / kMuTY;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int ic = lb / (ty_n * tz_n);
+    const int rem = lb - ic * ty_n * tz_n;
+    const int j0 = (rem / tz_n) * kMuTY, k0 = (rem - (rem / tz_n) * tz_n) * kMuTZ;
+    const int i0 = ic * kMuNI, i1 = min(d.nx, i0 + kMuNI);
+    const int plane = d.ny * d.nz;
+    // region element e -> node offset inside a plane (mirror rows, periodic z)
+    int roff[kPre];
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        const int r = e / kPZ, c = e - (e / kPZ) * kPZ;
+        roff[q] = (e < kPN) ? mirror_row(j0 - 2 + r, d.ny) * d.nz + wrap_mod(k0 - 2 + c, d.nz) : 0;
     }
+    auto fetch = [&](int i, double (&v)[kPre]) {
+        const double* src = phi + (size_t)wrap_mod(i, d.nx) * plane;
+#pragma unroll
+        for (int q = 0; q < kPre; ++q)
+            if (threadIdx.x + q * kBlock < kPN) v[q] = src[roff[q]];
+    };
+    auto put = [&](double* dst, const double (&v)[kPre]) {
+#pragma unroll
+        for (int q = 0; q < kPre; ++q)
+            if (threadIdx.x + q * kBlock < kPN) dst[threadIdx.x + q * kBlock] = v[q];
+    };
+    auto slot = [](int m) { return m & 3; };   // m >= -2 + 4 below
     const double eps2 = eps * eps;
-    const double gc = p * p * p - p - eps2 * lphi;
-    const int ip = (i + 1 == d.nx) ? 0 : i + 1;
-    const int im = (i == 0) ? d.nx - 1 : i - 1;
-    const int jp = (j + 1 == d.ny) ? d.ny - 2 : j + 1;
-    const int jm = (j == 0) ? 1 : j - 1;
-    const int kp = (k + 1 == d.nz) ? 0 : k + 1;
-    const int km = (k == 0) ? d.nz - 1 : k - 1;
-    const double gs = g_at(phi, d, ip, j, k, eps2) + g_at(phi, d, im, j, k, eps2) +
-                      g_at(phi, d, i, jp, k, eps2) + g_at(phi, d, i, jm, k, eps2) +
-                      g_at(phi, d, i, j, kp, eps2) + g_at(phi, d, i, j, km, eps2);
-    const double lg = (gs - 6.0 * gc) * d.inv_h2;
+    auto make_g = [&](int m) {
+        const double* pc = P[slot(m + 4)];
+        const double* pm = P[slot(m + 3)];
+        const double* pp = P[slot(m + 5)];
+        double* g = G[BEND ? (m + 3) % 3 : 0];
+        for (int e = threadIdx.x; e < kGN; e += kBlock) {
+            const int r = e / kGZ, c = e - (e / kGZ) * kGZ;
+            const int x = (r + 1) * kPZ + (c + 1);
+            const double p = pc[x];
+            const double l = (pp[x] + pm[x] + pc[x + kPZ] + pc[x - kPZ] + pc[x + 1] + pc[x - 1] - 6.0 * p) * d.inv_h2;
+            g[e] = p * p * p - p - eps2 * l;
+        }
+    };
+    double v[kPre];
+    // prologue: phi planes i0-2 .. i0+1, g planes i0-1 and i0
+    for (int m = -2; m <= 1; ++m) {
+        fetch(i0 + m, v);
+        put(P[slot(i0 + m + 4)], v);
+    }
+    __syncthreads();
+    if (BEND) {
+        make_g(i0 - 1);
+        make_g(i0);
+    }
+    fetch(i0 + 2, v);
+    const int tj = threadIdx.x / kMuTZ, tk = threadIdx.x - (threadIdx.x / kMuTZ) * kMuTZ;
+    const int j = j0 + tj, k = k0 + tk;
+    const bool out = j < d.ny && k < d.nz;
     const double gamma = scal[SC_GAMMA];
-    mu[n.c] = C_b * ((3.0 * p * p - 1.0) * gc - eps2 * lg) - gamma * lphi;
+    for (int i = i0; i < i1; ++i) {
+        __syncthreads();                         // the slot of phi(i-2) and g(i-2) are free
+        put(P[slot(i + 6)], v);                  // phi(i+2)
+        __syncthreads();
+        if (i + 1 < i1) fetch(i + 3, v);         // in flight during the computation below
+        if (BEND) make_g(i + 1);
+        __syncthreads();
+        if (!out) continue;
+        const double* pc = P[slot(i + 4)];
+        const int x = (tj + 2) * kPZ + (tk + 2);
+        const double p = pc[x];
+        const double lphi = (P[slot(i + 5)][x] + P[slot(i + 3)][x] + pc[x + kPZ] + pc[x - kPZ] +
+                             pc[x + 1] + pc[x - 1] - 6.0 * p) * d.inv_h2;
+        const size_t o = (size_t)i * plane + (size_t)j * d.nz + k;
+        if (!BEND) {
+            mu[o] = p * p * p - p - sigma * lphi;
+            continue;
+        }
+        const double* gc = G[(i + 3) % 3];
+        const int y = (tj + 1) * kGZ + (tk + 1);
+        const double g0 = gc[y];
+        const double gs = G[(i + 4) % 3][y] + G[(i + 2) % 3][y] + gc[y + kGZ] + gc[y - kGZ] +
+                          gc[y + 1] + gc[y - 1];
+        const double lg = (gs - 6.0 * g0) * d.inv_h2;
+        mu[o] = C_b * ((3.0 * p * p - 1.0) * g0 - eps2 * lg) - gamma * lphi;
+    }
 }
 
 // Block partials of sum_w phi and sum_w [(eps/2)|D phi|^2 + (phi^2-1)^2/(4 eps)]
@@ -216,8 +299,12 @@ void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, in
 
 void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const double* scal,
                int model, double C_b, double eps, double sigma) {
-    launch_kernel(k_mu, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, scal, model, C_b,
-                       eps, sigma);
+    const int nb = ((d.ny + kMuTY - 1) / kMuTY) * ((d.nz + kMuTZ - 1) / kMuTZ) *
+                   ((d.nx + kMuNI - 1) / kMuNI);
+    if (model == VS_CAHN_HILLIARD)
+        launch_kernel(k_mu_tile<false>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, scal, C_b, eps, sigma);
+    else
+        launch_kernel(k_mu_tile<true>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, scal, C_b, eps, sigma);
 }
 
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof) {
