@@ -45,7 +45,6 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
         "dht_x": 48 * Ni,             # 3 spectral fields in and out
         "tridiag_y": 48 * Ni,         # 3 spectral fields in and out
         "tridiag_pair": 72 * Ni,      # source modes in; vorticity and stream-vector modes out
-        "resid_pair": 72 * Ni,        # S(3), omega(3), psi(3) in
         "dht_z_out": 48 * Ni,         # 3 spectral fields in; 3 solution fields out
         "resid_norm_omega": 48 * Ni,  # S(3), omega(3) in
         "resid_norm_psi": 48 * Ni,    # omega(3), psi(3) in

@@ -1112,74 +1112,6 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
     }
 }
 
-// resid_pair: both residuals of a step in one pass (used when no correction cycle can
-// follow): vorticity r = S - L_h w with b~ = S - w-walls, stream vector r = -w - L_h psi with
-// b~ = -w - psi-walls. Partials: slots 0-5 as resid_norm for the vorticity, 6-11 for psi.
-__global__ __launch_bounds__(kBlock) void k_resid_pair(Dims d, CPtr3 src, CPtr3 w, CPtr3 psi,
-                                                      SlabGrid sg, double* __restrict__ partials) {
-    __shared__ double sh[12 * 4];
-    const int nb = sg.gx * sg.gi;
-    const int lb = xcd_block(blockIdx.x, nb);
-    const int bi = lb / sg.gx;
-    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
-    double acc[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
-    if (t < d.M * d.nz) {
-        const int jj = t / d.nz;
-        const int k = t - jj * d.nz;
-        const int j = jj + 1;
-        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
-        const int km = (k == 0) ? d.nz - 1 : k - 1;
-        const int i1 = min(d.nx, (bi + 1) * sg.ci);
-#pragma unroll 2
-        for (int i = bi * sg.ci; i < i1; ++i) {
-            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
-            const int im = (i == 0) ? d.nx - 1 : i - 1;
-            const int rb = node(d, i, j, 0), xpb = node(d, ip, j, 0), xmb = node(d, im, j, 0);
-            const int c0 = rb + k;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double* wc = w.p[c];
-                const double* pc = psi.p[c];
-                const double wv = wc[c0];
-                {
-                    const double ylo = wc[c0 - d.nz], yhi = wc[c0 + d.nz];
-                    const double b = src.p[c][c0];
-                    const double wall = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
-                    const double lap = (wc[xpb + k] + wc[xmb + k] + ylo + yhi + wc[rb + kp] +
-                                        wc[rb + km] - 6.0 * wv) * d.inv_h2;
-                    const double r = b - lap, bt = b - wall * d.inv_h2;
-                    acc[c] += r * r;
-                    acc[3 + c] += bt * bt;
-                }
-                {
-                    const double ylo = pc[c0 - d.nz], yhi = pc[c0 + d.nz];
-                    const double b = -wv;
-                    const double wall = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
-                    const double lap = (pc[xpb + k] + pc[xmb + k] + ylo + yhi + pc[rb + kp] +
-                                        pc[rb + km] - 6.0 * pc[c0]) * d.inv_h2;
-                    const double r = b - lap, bt = b - wall * d.inv_h2;
-                    acc[6 + c] += r * r;
-                    acc[9 + c] += bt * bt;
-                }
-            }
-        }
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        const double sum = wave_sum(acc[q]);
-        if (lane == 0) sh[q * 4 + wv] = sum;
-    }
-    __syncthreads();
-    if (threadIdx.x < 12) {
-        const double sum = sh[threadIdx.x * 4 + 0] + sh[threadIdx.x * 4 + 1] +
-                           sh[threadIdx.x * 4 + 2] + sh[threadIdx.x * 4 + 3];
-        partials[threadIdx.x * kMaxPartialBlocks + blockIdx.x] = sum;
-    }
-}
-
 // check: relative residual sqrt(sum_c r^2 / sum_c b~^2) in a fixed summation order; sets the
 // convergence flag that gates the following cycles, counts the cycle and raises ST_NOCONV
 // on the last allowed cycle, ST_NONFINITE on NaN/Inf.
@@ -1442,13 +1374,6 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
 int resid_blocks(const Dims& d) {
     const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
     return g.gx * g.gi;
-}
-
-void launch_resid_pair(hipStream_t s, const Dims& d, double* const src[3], double* const w[3],
-                       double* const psi[3], double* partials) {
-    CPtr3 a{{src[0], src[1], src[2]}}, b{{w[0], w[1], w[2]}}, c{{psi[0], psi[1], psi[2]}};
-    const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
-    launch_kernel(k_resid_pair, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, a, b, c, g, partials);
 }
 
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,

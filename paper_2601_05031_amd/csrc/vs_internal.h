@@ -198,8 +198,6 @@ void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate);
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
                   int last_cycle, double* scal, int* istat, const int* gate, int slot0 = 0);
-// Both residuals of a step in one pass: partial slots 0-5 (vorticity), 6-11 (stream vector).
-void launch_resid_pair(hipStream_t s, const Dims& d, double* const src[3], double* const w[3],
-                       double* const psi[3], double* partials);
+
 
 }  // namespace vs
