@@ -40,6 +40,65 @@ __global__ __launch_bounds__(kBlock) void k_advance(
     out[n.c] = phi[n.c] + dt * (mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
 }
 
+// k_advance marching along x: each lane owns one (j, k) and walks kAdvSlab consecutive
+// x-planes, keeping phi, mu, psi_y and psi_z of the planes i-1, i, i+1 in registers, so the
+// x-neighbours are not re-read; the y and z neighbours come through the cache. Same
+// arithmetic, in the same order, as the plain kernel.
+constexpr int kAdvSlab = 4;
+
+__global__ __launch_bounds__(kBlock) void k_advance_x(
+    const double* __restrict__ phi, const double* __restrict__ mu,
+    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
+    double* __restrict__ out, Dims d, SlabGrid sg, const double* __restrict__ scal, double dt,
+    double mob, double vz_lo, double vz_hi) {
+    const int nb = sg.gx * sg.gi;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int bi = lb / sg.gx;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
+    if (t >= d.ny * d.nz) return;
+    const int j = t / d.nz, k = t - (t / d.nz) * d.nz;
+    const int i0 = bi * sg.ci, i1 = min(d.nx, i0 + sg.ci);
+    const int plane = d.ny * d.nz;
+    const int jp = (j + 1 == d.ny) ? d.ny - 2 : j + 1;   // mirror ghosts (phi, mu)
+    const int jm = (j == 0) ? 1 : j - 1;
+    const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+    const int km = (k == 0) ? d.nz - 1 : k - 1;
+    const bool wall = (j == 0 || j == d.ny - 1);
+    const int o = j * d.nz + k;                          // offset inside a plane
+    const int oyp = jp * d.nz + k, oym = jm * d.nz + k, ozp = j * d.nz + kp, ozm = j * d.nz + km;
+    const double lam = scal[SC_LAMV];
+    auto pl = [&](int i) { return (size_t)((i + d.nx) % d.nx) * plane; };
+    size_t b = pl(i0 - 1);
+    double phm = phi[b + o], mum = mu[b + o], pym = wall ? 0.0 : py[b + o], pzm = wall ? 0.0 : pz[b + o];
+    b = pl(i0);
+    double ph0 = phi[b + o], mu0 = mu[b + o], py0 = wall ? 0.0 : py[b + o], pz0 = wall ? 0.0 : pz[b + o];
+    for (int i = i0; i < i1; ++i) {
+        const size_t bc = (size_t)i * plane, bn = pl(i + 1);
+        const double php = phi[bn + o], mup = mu[bn + o];
+        const double pyp = wall ? 0.0 : py[bn + o], pzp = wall ? 0.0 : pz[bn + o];
+        const double lmu = (mup + mum + mu[bc + oyp] + mu[bc + oym] + mu[bc + ozp] + mu[bc + ozm] -
+                            6.0 * mu0) * d.inv_h2;
+        const double dx = (php - phm) * d.inv_2h;
+        const double dy = (phi[bc + oyp] - phi[bc + oym]) * d.inv_2h;
+        const double dz = (phi[bc + ozp] - phi[bc + ozm]) * d.inv_2h;
+        double vx = 0.0, vy = 0.0, vz;
+        if (j == 0) {
+            vz = vz_lo;
+        } else if (j == d.ny - 1) {
+            vz = vz_hi;
+        } else {
+            vx = ((pz[bc + oyp] - pz[bc + oym]) - (py[bc + ozp] - py[bc + ozm])) * d.inv_2h;
+            vy = ((px[bc + ozp] - px[bc + ozm]) - (pzp - pzm)) * d.inv_2h;
+            vz = ((pyp - pym) - (px[bc + oyp] - px[bc + oym])) * d.inv_2h;
+        }
+        out[bc + o] = ph0 + dt * (mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
+        phm = ph0; ph0 = php;
+        mum = mu0; mu0 = mup;
+        pym = py0; py0 = pyp;
+        pzm = pz0; pz0 = pzp;
+    }
+}
+
 // mu from phi. Bending (SM eq. (35)): g = phi^3 - phi - eps^2 L_h phi,
 // mu = C_b [(3 phi^2 - 1) g - eps^2 L_h g] - gamma_A L_h phi. Cahn-Hilliard:
 // mu = phi^3 - phi - sigma L_h phi. g never reaches HBM.
@@ -274,8 +333,12 @@ __global__ void k_reset_stats(double* scal, int* istat) {
 void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
                     const double* const psi[3], double* phi_out, const double* scal, double dt,
                     double mobility, double vz_lo, double vz_hi) {
-    launch_kernel(k_advance, plane_grid(d), dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
-                       psi[2], phi_out, d, scal, dt, mobility, vz_lo, vz_hi);
+    SlabGrid g;
+    g.gx = (d.ny * d.nz + kBlock - 1) / kBlock;
+    g.ci = kAdvSlab;
+    g.gi = (d.nx + kAdvSlab - 1) / kAdvSlab;
+    launch_kernel(k_advance_x, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
+                  psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi);
 }
 
 int va_partial_blocks(const Dims& d) {
