@@ -219,8 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
 
 // Block partials of sum_w phi and sum_w [(eps/2)|D phi|^2 + (phi^2-1)^2/(4 eps)]
 // (trapezoid weights w = 1/2 on the wall rows). Each thread owns one (j, k) and walks ci
-// consecutive x-planes (the i-1 plane it reads was the previous iteration's centre, still in
-// cache); the partial of block b is written to slot b: fixed order, deterministic.
+// consecutive x-planes, keeping phi of the planes i-1, i, i+1 in registers; the partial of
+// block b is written to slot b: fixed order, deterministic.
 __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict__ phi, Dims d,
                                                        double eps, SlabGrid sg,
                                                        double* __restrict__ partials) {
@@ -235,16 +235,28 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
         const int k = t - j * d.nz;
         const double w = (j == 0 || j == d.ny - 1) ? 0.5 : 1.0;
         const double inv4e = 0.25 / eps;
-        const int i1 = min(d.nx, (bi + 1) * sg.ci);
-        for (int i = bi * sg.ci; i < i1; ++i) {
-            const Nbr n = neighbours_mirror(d, i, j, k);
-            const double p = phi[n.c];
-            const double dx = (phi[n.xp] - phi[n.xm]) * d.inv_2h;
-            const double dy = (phi[n.yp] - phi[n.ym]) * d.inv_2h;
-            const double dz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
+        const int i0 = bi * sg.ci, i1 = min(d.nx, (bi + 1) * sg.ci);
+        // phi of the planes i-1, i, i+1 at (j, k) in registers; y, z neighbours via the cache
+        const int plane = d.ny * d.nz;
+        const int o = j * d.nz + k;
+        const int oyp = ((j + 1 == d.ny) ? d.ny - 2 : j + 1) * d.nz + k;
+        const int oym = ((j == 0) ? 1 : j - 1) * d.nz + k;
+        const int ozp = j * d.nz + ((k + 1 == d.nz) ? 0 : k + 1);
+        const int ozm = j * d.nz + ((k == 0) ? d.nz - 1 : k - 1);
+        double pm = phi[(size_t)((i0 + d.nx - 1) % d.nx) * plane + o];
+        double p0 = phi[(size_t)i0 * plane + o];
+        for (int i = i0; i < i1; ++i) {
+            const size_t bc = (size_t)i * plane;
+            const double pp = phi[(size_t)((i + 1) % d.nx) * plane + o];
+            const double p = p0;
+            const double dx = (pp - pm) * d.inv_2h;
+            const double dy = (phi[bc + oyp] - phi[bc + oym]) * d.inv_2h;
+            const double dz = (phi[bc + ozp] - phi[bc + ozm]) * d.inv_2h;
             const double q = p * p - 1.0;
             acc[0] += w * p;
             acc[1] += w * (0.5 * eps * (dx * dx + dy * dy + dz * dz) + q * q * inv4e);
+            pm = p0;
+            p0 = pp;
         }
     }
     block_sum<2>(acc, sh);
