@@ -353,14 +353,16 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
                   psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi);
 }
 
+constexpr int kVaMaxBlocks = 1024;   // longer x-slabs per lane, a shorter final sum
+
 int va_partial_blocks(const Dims& d) {
-    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kMaxPartialBlocks);
+    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kVaMaxBlocks);
     return g.gx * g.gi;
 }
 
 void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
                         double* partials) {
-    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kMaxPartialBlocks);
+    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kVaMaxBlocks);
     launch_kernel(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
                        partials);
 }
