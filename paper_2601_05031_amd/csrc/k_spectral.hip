@@ -932,16 +932,6 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
             if (o.x >= 0) st(sc + o.x + p, ha);
             if (o.y >= 0) st(sc + o.y + p, hb);
         };
-        if (rhs.fold_walls) {
-            // f alone: one unconditional load per element
-            auto loadf = [&](const RowPair& rp, int k1, int k2) -> double2 {
-                const int k = k1 + A * k2;
-                return make_double2(rp.a >= 0 ? sg * fc[rp.a + k] : 0.0,
-                                    rp.b >= 0 ? sg * fc[rp.b + k] : 0.0);
-            };
-            two_pass_hartley<B, A, false>(Y, tw, prep, loadf, store);
-            return;
-        }
         two_pass_hartley<B, A, false>(Y, tw, prepw, load, storew);
         return;
     }
@@ -1360,6 +1350,16 @@ void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, void* 
         tridiag_pair_t<float>(s, d, tri, spec, spec2, olo, ohi, lo, hi);
     else
         tridiag_pair_t<double>(s, d, tri, spec, spec2, olo, ohi, lo, hi);
+}
+
+void launch_dht_z_fwd(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                      const double* const f[3], void* const spec[3], int ncomp) {
+    // the z pass of the inverse computes the same Hartley sums (H is its own inverse up to
+    // the scale, which the tridiagonal solve applies), from FP64 input to FP64 output
+    void* const in[3] = {(void*)f[0], ncomp > 1 ? (void*)f[1] : nullptr, ncomp > 2 ? (void*)f[2] : nullptr};
+    double* const out[3] = {(double*)spec[0], ncomp > 1 ? (double*)spec[1] : nullptr,
+                            ncomp > 2 ? (double*)spec[2] : nullptr};
+    dht_z_out_t<double>(s, d, pz, twz, in, out, ncomp, 0, nullptr);
 }
 
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,

@@ -317,11 +317,11 @@ void enqueue_flow(vs_state* S, const double* phi) {
         enqueue_solve(S, rp, S->ps, 3, rtol, mc, TAG_PSI, 1);
         return;
     }
-    const double* const cu[3] = {S->om[0], S->om[1], S->om[2]};
-    RhsArgs rvf = rv;
-    rvf.fold_walls = 1;   // the omega wall terms go into mode (0, 0) of the tridiagonal solve
+    // The direct transform reads S alone: the omega wall terms go into mode (0, 0) of the
+    // tridiagonal solve.
     timed(S, K_RHS_Z_OMEGA, [&] {
-        launch_rhs_dht_z(S->stream, d, S->pz, S->twz, rvf, cu, 3, 0, S->spec, false, nullptr);
+        const double* const sv[3] = {S->src[0], S->src[1], S->src[2]};
+        launch_dht_z_fwd(S->stream, d, S->pz, S->twz, sv, S->spec, 3);
     });
     timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
     timed(S, K_TRIDIAG_PAIR, [&] {

@@ -91,9 +91,6 @@ enum RhsMode {
 struct RhsArgs {
     int mode;
     const double* f[3];      // RHS_FIELD arrays, or omega for RHS_NEGW
-    // 1: the direct transform reads f alone; the wall terms (wall values constant over each
-    // wall plane) are added in mode (0, 0) by the tridiagonal solve instead
-    int fold_walls;
 };
 
 // Plan of a length-n transform: radices applied in order (Stockham passes).
@@ -147,6 +144,10 @@ void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
                       void* const spec[3], bool f32, const int* gate);
 void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
                   void* const spec[3], int ncomp, bool f32, const int* gate);
+// Hartley along z of FP64 fields on the interior rows into FP64 spectral storage (the direct
+// vorticity transform of the source S, whose wall terms are folded into mode (0, 0)).
+void launch_dht_z_fwd(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
+                      const double* const f[3], void* const spec[3], int ncomp);
 void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
                       int ncomp, bool f32, const int* gate);
 // Vorticity modes solved in place in spec (as launch_tridiag_y), then the stream-vector modes
