@@ -93,6 +93,14 @@ def test_null_state_calls():
     assert L.vs_grad_step(None, 1e-3, None, None, None) == V.VS_E_STATE
     off = ctypes.c_size_t(0)
     assert L.vs_field_offset(None, 0, ctypes.byref(off)) == V.VS_E_STATE
+    w = V.VsWalls(V.VS_POISEUILLE, 0.05, 0.0)
+    assert L.vs_set_walls(None, ctypes.byref(w)) == V.VS_E_STATE
+    out = (ctypes.c_double * 4)()
+    assert L.vs_diagnostics(None, None, out) == V.VS_E_STATE
+    assert L.vs_batch_step(None, None, 2) == V.VS_E_STATE
+    b = ctypes.c_void_p(0)
+    assert L.vs_batch_create(None, 0, None, 1, ctypes.byref(b)) == V.VS_E_ARG
+    L.vs_batch_destroy(None)
     L.vs_destroy(None)
     assert L.vs_profile_count() >= 10
     assert L.vs_profile_name(0) == b"advance"
