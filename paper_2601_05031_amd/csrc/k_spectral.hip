@@ -1053,7 +1053,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // thread owns one interior (j, k) and walks ci consecutive x-planes; blocks ordered per XCD.
 __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr3 u, int ncomp,
                                                       SlabGrid sg, double* __restrict__ partials,
-                                                      const int* gate) {
+                                                      const int* gate, int slot0) {
     if (gate && *gate) return;
     __shared__ double sh[6 * 4];
     const int nb = sg.gx * sg.gi;
@@ -1098,7 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
     if (threadIdx.x < 6) {
         const double s = sh[threadIdx.x * 4 + 0] + sh[threadIdx.x * 4 + 1] +
                          sh[threadIdx.x * 4 + 2] + sh[threadIdx.x * 4 + 3];
-        partials[threadIdx.x * kMaxPartialBlocks + blockIdx.x] = s;
+        partials[(slot0 + threadIdx.x) * kMaxPartialBlocks + blockIdx.x] = s;
     }
 }
 
@@ -1148,6 +1148,53 @@ __global__ __launch_bounds__(1024) void k_check(const double* __restrict__ parti
     }
     if (!conv && last_cycle) istat[IS_FLAGS] |= ST_NOCONV;
     if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
+}
+
+// Convergence checks of the two flow solves of a step, each of a single cycle, in one launch:
+// partial slots 0-5 hold the vorticity residual, 6-11 the stream-vector one; the two checks
+// run in a row (vorticity, then stream vector) as two last-cycle checks would.
+__global__ __launch_bounds__(1024) void k_check_flow(const double* __restrict__ partials,
+                                                    int nblocks, double rtol, double* scal,
+                                                    int* istat) {
+    __shared__ double sh[4 * 16];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const double* pb = partials + (size_t)(3 * g) * kMaxPartialBlocks + b;
+            a[g] += pb[0] + pb[kMaxPartialBlocks] + pb[2 * kMaxPartialBlocks];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) a[g] = wave_sum(a[g]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) sh[g * 16 + wv] = a[g];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int g = 0; g < 4; ++g) {
+        a[g] = 0.0;
+        for (int q = 0; q < nw; ++q) a[g] += sh[g * 16 + q];
+    }
+    for (int sidx = 0; sidx < 2; ++sidx) {
+        const double rr = a[2 * sidx], bb = a[2 * sidx + 1];
+        double rel;
+        if (bb > 0.0)
+            rel = sqrt(rr / bb);
+        else
+            rel = (rr > 0.0) ? INFINITY : 0.0;
+        if (rr != rr || bb != bb) rel = NAN;
+        const int conv = (rel <= rtol) ? 1 : 0;
+        istat[IS_CONV] = conv;
+        istat[IS_CYCLES] += 1;
+        scal[SC_RELRES_LAST] = rel;
+        const double prev = scal[SC_RELRES_MAX];
+        scal[SC_RELRES_MAX] = (rel != rel || rel > prev) ? rel : prev;
+        if (!conv) istat[IS_FLAGS] |= ST_NOCONV;
+        if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
+    }
 }
 
 // Rows per block of the z kernels: 2 * (kTileElems / nz), i.e. kTileElems / nz complex lines.
@@ -1377,11 +1424,18 @@ int resid_blocks(const Dims& d) {
 }
 
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
-                       const double* const u[3], int ncomp, double* partials, const int* gate) {
+                       const double* const u[3], int ncomp, double* partials, const int* gate,
+                       int slot0) {
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
     const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
     launch_kernel(k_resid_norm, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, rhs, uu, ncomp, g,
-                       partials, gate);
+                  partials, gate, slot0);
+}
+
+void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,
+                       double* scal, int* istat) {
+    launch_kernel(k_check_flow, dim3(1), dim3(1024), 0, s, partials, resid_blocks(d), rtol, scal,
+                  istat);
 }
 
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,

@@ -336,6 +336,15 @@ void enqueue_flow(vs_state* S, const double* phi) {
     timed(S, K_DHT_Z_OUT, [&] {
         launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec2, S->ps, 3, 0, false, nullptr);
     });
+    if (mc == 1) {
+        // one cycle each: both residual passes, then both checks in one launch
+        const double* const co[3] = {S->om[0], S->om[1], S->om[2]};
+        const double* const cp[3] = {S->ps[0], S->ps[1], S->ps[2]};
+        timed(S, K_RESID_OMEGA, [&] { launch_resid_norm(S->stream, d, rv, co, 3, S->part, nullptr, 0); });
+        timed(S, K_RESID_PSI, [&] { launch_resid_norm(S->stream, d, rp, cp, 3, S->part, nullptr, 6); });
+        timed(S, K_CHECK, [&] { launch_check_flow(S->stream, d, S->part, rtol, S->scal, S->istat); });
+        return;
+    }
     enqueue_verify(S, rv, S->om, 3, rtol, 0, mc == 1, TAG_OMEGA, nullptr);
     for (int cyc = 1; cyc < mc; ++cyc) {
         const int* gate = S->istat + IS_CONV;

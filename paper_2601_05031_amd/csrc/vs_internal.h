@@ -195,8 +195,14 @@ void launch_adj_mu2(hipStream_t s, const Dims& d, const double* phi, const doubl
                     const double* gbar, const double* scal, int model, double C_b, double eps,
                     double sigma, double dt, double mobility, double rate_V, double k_A,
                     double* phibar);
+// Residual-norm partials of a solve into slots slot0 .. slot0+5.
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
-                       const double* const u[3], int ncomp, double* partials, const int* gate);
+                       const double* const u[3], int ncomp, double* partials, const int* gate,
+                       int slot0 = 0);
+// The two single-cycle flow checks of a step in one launch (vorticity partials in slots 0-5,
+// stream vector in 6-11).
+void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,
+                       double* scal, int* istat);
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
                   int last_cycle, double* scal, int* istat, const int* gate, int slot0 = 0);
 
