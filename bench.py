@@ -193,6 +193,27 @@ def batched_run(P, torch, steps: int, nstreams: int) -> dict:
     return out
 
 
+def copy_ceiling(torch) -> float:
+    """Device-to-device copy of a 1 GiB FP64 buffer (read + write bytes per second, GB/s): the
+    practical streaming ceiling next to the nominal 8 TB/s."""
+    a = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / t / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,9 +300,11 @@ def main():
     dom_mean_s = kern[dom]["mean_us"] * 1e-6
     achieved = dom_bytes / dom_mean_s / 1e9
     traffic = stored_traffic(dom, base.name)
+    ceiling = copy_ceiling(torch)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": dom_bytes, "mean_launch_us": round(kern[dom]["mean_us"], 2)}
+                "algorithmic_bytes_per_launch": dom_bytes, "mean_launch_us": round(kern[dom]["mean_us"], 2),
+                "copy_ceiling": round(ceiling, 1), "frac_of_copy_ceiling": round(achieved / ceiling, 4)}
     step_bytes = sum(kernel_bytes(k, nx, ny, nz) * v["launches"] for k, v in kern.items()
                      if kernel_bytes(k, nx, ny, nz)) / args.profile_steps
     step_kernel_ms = sum(v["total_ms"] for v in kern.values()) / args.profile_steps

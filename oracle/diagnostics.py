@@ -11,6 +11,9 @@ TEST INFRASTRUCTURE ONLY: imported by the tests, never by the HIP product path.
     of omega and psi about the no-body fields omega_0, psi_0), trapezoid rule in y (R4);
   * the free energy: bending, SM eq. (30) without the area term (``vsref.bending_energy``), or
     Cahn-Hilliard, eq. F_CH: int 1/4 (phi^2 - 1)^2 + (sigma/2) |grad phi|^2;
+  * two checks of a run's health: the gauge defect int (div psi)^2 over the interior rows
+    (the Coulomb gauge div psi = 0 is assumed, not imposed: main text after eq. (7), reading
+    R14), with central differences, and the largest speed |v| over the nodes;
   * time-dependent walls (SM "Time-dependency and inertial flow": only the boundary data
     change): ``set_walls`` replaces the wall speeds and re-solves omega and psi from the
     current phi and mu with the new walls.
@@ -64,6 +67,23 @@ def observables(omega: np.ndarray, psi: np.ndarray, grid: Grid, walls: Walls):
     oo = h3 * float(np.sum(w * np.sum((omega - om0) ** 2, axis=0)))
     op = h3 * float(np.sum(w * np.sum((psi - ps0) ** 2, axis=0)))
     return oo, op
+
+
+def gauge_defect(psi: np.ndarray, grid: Grid) -> float:
+    """h^3 sum over the interior rows of (D_x psi_x + D_y psi_y + D_z psi_z)^2."""
+    h = grid.h
+    px, py, pz = psi
+    dx = (np.roll(px, -1, 0) - np.roll(px, 1, 0))[:, 1:-1, :] / (2.0 * h)
+    dy = (py[:, 2:, :] - py[:, :-2, :]) / (2.0 * h)
+    dz = (np.roll(pz, -1, 2) - np.roll(pz, 1, 2))[:, 1:-1, :] / (2.0 * h)
+    div = dx + dy + dz
+    return grid.h**3 * float(np.sum(div * div))
+
+
+def max_speed(psi: np.ndarray, grid: Grid, walls: Walls) -> float:
+    """max |v| over the nodes, v as the step uses it."""
+    v = velocity(psi, grid, walls)
+    return float(np.sqrt(np.max(np.sum(v * v, axis=0))))
 
 
 def ch_energy(phi: np.ndarray, grid: Grid, sigma: float) -> float:

@@ -95,3 +95,28 @@ def test_set_walls_re_solves_the_flow_and_shifts_by_the_no_body_difference():
     # exactly, so the change is the difference of the no-body fields
     assert np.allclose(s2.omega - s1.omega, om2 - om1, atol=1e-13)
     assert np.allclose(s2.psi - s1.psi, ps2 - ps1, atol=1e-13)
+
+
+def test_gauge_defect_closed_forms():
+    g = O.Grid(12, 9, 10, h=0.7)
+    walls = O.Walls(O.POISEUILLE, 0.05)
+    _, ps0 = O.no_body_fields(g, walls)
+    assert D.gauge_defect(ps0, g) == 0.0
+    psi = np.zeros((3,) + g.shape)
+    i = np.arange(g.nx)
+    psi[0] = np.sin(2.0 * math.pi * i / g.nx)[:, None, None]
+    M = g.ny - 2
+    exact = g.h * g.nz * M * (g.nx / 2.0) * math.sin(2.0 * math.pi / g.nx) ** 2
+    assert D.gauge_defect(psi, g) == pytest.approx(exact, rel=1e-12)
+
+
+def test_max_speed_of_channel_flows():
+    g = O.Grid(6, 21, 8, h=0.5)          # ny odd: a node on the centreline
+    U = 0.07
+    walls = O.Walls(O.POISEUILLE, U)
+    _, psi = O.no_body_fields(g, walls)
+    # the central difference of the cubic psi_x offsets v_z by -4 U h^2 / (3 H^2)
+    assert D.max_speed(psi, g, walls) == pytest.approx(U * (1.0 - 4.0 * g.h**2 / (3.0 * g.H**2)), rel=1e-12)
+    walls = O.Walls(O.COUETTE, -0.03, 0.05)
+    _, psi = O.no_body_fields(g, walls)
+    assert D.max_speed(psi, g, walls) == pytest.approx(0.05, rel=1e-12)
