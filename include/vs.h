@@ -197,12 +197,15 @@ vs_status vs_set_walls(vs_state* state, const vs_walls* walls);
  *   out[2] = free energy: bending, SM eq. (30) without the area term,
  *            3 sqrt(2) kappa/(8 eps^3) int g^2; Cahn-Hilliard, eq. F_CH,
  *            int 1/4 (phi^2 - 1)^2 + (sigma/2) |grad phi|^2;
- *   out[3] = max sigma_t.
+ *   out[3] = max sigma_t;
+ *   out[4] = gauge defect int (div psi)^2 over the interior rows, central differences (the
+ *            Coulomb gauge div psi = 0 is assumed, not imposed: main text after eq. (7));
+ *   out[5] = max |v| over the nodes (curl psi inside, the wall speed on the walls).
  * sigma_t: device, nx*ny*nz doubles, or NULL: the in-plane shear-stress intensity of the
  * section "In plane shear", sqrt(s_xy^2 + s_yz^2 + s_xz^2) with s_ij = eta (d_j v_i + d_i v_j)
  * by central differences of v (curl psi inside, the wall speed on the walls), on the interior
  * rows; 0 on the wall rows. */
-vs_status vs_diagnostics(vs_state* state, double* sigma_t, double out[4]);
+vs_status vs_diagnostics(vs_state* state, double* sigma_t, double out[6]);
 
 /* Byte offset, inside the workspace, of field `field` (VS_PHI ... VS_PSI_Z) as it stands
  * now (phi moves between two buffers from step to step: query after each vs_step). */

@@ -6,6 +6,8 @@
 //     int |psi - psi_0|^2 about the no-body channel fields, trapezoid weights in y;
 //   * the free-energy density: g^2 (bending, SM eq. (30) without the area term) or
 //     1/4 (phi^2 - 1)^2 + (sigma/2) |D phi|^2 (Cahn-Hilliard, eq. F_CH);
+//   * the gauge defect (D . psi)^2 on the interior rows (the Coulomb gauge is assumed, not
+//     imposed) and the largest speed |v|;
 //   * time-dependent walls (SM "Time-dependency and inertial flow"): the Poisson problems
 //     are linear in the wall data and the no-body fields (polynomials of degree <= 3 in y)
 //     solve them exactly, so a change of wall speeds adds the difference of the no-body fields
@@ -24,10 +26,10 @@ __global__ __launch_bounds__(kBlock) void k_diag(const double* __restrict__ phi,
                                                 int model, double eps, double sigma, SlabGrid sg,
                                                 double* __restrict__ sigma_t,
                                                 double* __restrict__ partials) {
-    __shared__ double sh[3 * 16];
-    __shared__ double shm[16];
-    double acc[3] = {0.0, 0.0, 0.0};
-    double smax = 0.0;
+    __shared__ double sh[4 * 16];
+    __shared__ double shm[2 * 16];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double smax = 0.0, vmax = 0.0;
     const SlabIter it = slab_iter(d, sg);
     if (it.ok) {
         const int j = it.j, k = it.k;
@@ -53,8 +55,16 @@ __global__ __launch_bounds__(kBlock) void k_diag(const double* __restrict__ phi,
                 acc[2] += w * g * g;
             }
             double st = 0.0;
+            {
+                const double vx = vx_at(vel, d, i, j, k), vy = vy_at(vel, d, i, j, k), vz = vz_at(vel, d, i, j, k);
+                vmax = fmax(vmax, sqrt(vx * vx + vy * vy + vz * vz));
+            }
             if (interior(d, j)) {
                 const int ip = wrap(i + 1, d.nx), im = wrap(i - 1, d.nx);
+                const double dv = (vel.px[node(d, ip, j, k)] - vel.px[node(d, im, j, k)]) * d.inv_2h +
+                                  (vel.py[node(d, i, j + 1, k)] - vel.py[node(d, i, j - 1, k)]) * d.inv_2h +
+                                  (vel.pz[node(d, i, j, kp)] - vel.pz[node(d, i, j, km)]) * d.inv_2h;
+                acc[3] += dv * dv;
                 const double sxy = (vx_at(vel, d, i, j + 1, k) - vx_at(vel, d, i, j - 1, k)) +
                                    (vy_at(vel, d, ip, j, k) - vy_at(vel, d, im, j, k));
                 const double syz = (vy_at(vel, d, i, j, kp) - vy_at(vel, d, i, j, km)) +
@@ -67,46 +77,68 @@ __global__ __launch_bounds__(kBlock) void k_diag(const double* __restrict__ phi,
             smax = fmax(smax, st);
         }
     }
-    block_sum<3>(acc, sh);
-    // block maximum, fixed order
+    block_sum<4>(acc, sh);
+    // block maxima, fixed order
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off, 64));
-    if (lane == 0) shm[wv] = smax;
+    for (int off = 32; off > 0; off >>= 1) {
+        smax = fmax(smax, __shfl_down(smax, off, 64));
+        vmax = fmax(vmax, __shfl_down(vmax, off, 64));
+    }
+    if (lane == 0) {
+        shm[wv] = smax;
+        shm[16 + wv] = vmax;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) m = fmax(m, shm[q]);
+        double m = 0.0, mv = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            m = fmax(m, shm[q]);
+            mv = fmax(mv, shm[16 + q]);
+        }
 #pragma unroll
-        for (int q = 0; q < 3; ++q) partials[q * kMaxPartialBlocks + blockIdx.x] = acc[q];
-        partials[3 * kMaxPartialBlocks + blockIdx.x] = m;
+        for (int q = 0; q < 4; ++q) partials[q * kMaxPartialBlocks + blockIdx.x] = acc[q];
+        partials[4 * kMaxPartialBlocks + blockIdx.x] = m;
+        partials[5 * kMaxPartialBlocks + blockIdx.x] = mv;
     }
 }
 
 __global__ __launch_bounds__(1024) void k_diag_finalize(const double* __restrict__ partials,
                                                        int nblocks, double* scal) {
-    __shared__ double sh[3 * 16];
-    __shared__ double shm[16];
-    double acc[3] = {0.0, 0.0, 0.0};
-    double m = 0.0;
+    __shared__ double sh[4 * 16];
+    __shared__ double shm[2 * 16];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double m = 0.0, mv = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc[q] += partials[q * kMaxPartialBlocks + b];
-        m = fmax(m, partials[3 * kMaxPartialBlocks + b]);
+        for (int q = 0; q < 4; ++q) acc[q] += partials[q * kMaxPartialBlocks + b];
+        m = fmax(m, partials[4 * kMaxPartialBlocks + b]);
+        mv = fmax(mv, partials[5 * kMaxPartialBlocks + b]);
     }
-    block_sum<3>(acc, sh);
+    block_sum<4>(acc, sh);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
-    if (lane == 0) shm[wv] = m;
+    for (int off = 32; off > 0; off >>= 1) {
+        m = fmax(m, __shfl_down(m, off, 64));
+        mv = fmax(mv, __shfl_down(mv, off, 64));
+    }
+    if (lane == 0) {
+        shm[wv] = m;
+        shm[16 + wv] = mv;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double mm = 0.0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) mm = fmax(mm, shm[q]);
+        double mm = 0.0, mmv = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            mm = fmax(mm, shm[q]);
+            mmv = fmax(mmv, shm[16 + q]);
+        }
         scal[SC_DG_OMEGA] = acc[0];
         scal[SC_DG_PSI] = acc[1];
         scal[SC_DG_ENERGY] = acc[2];
+        scal[SC_DG_GAUGE] = acc[3];
         scal[SC_DG_SMAX] = mm;
+        scal[SC_DG_VMAX] = mmv;
     }
 }
 

@@ -699,7 +699,7 @@ vs_status vs_set_walls(vs_state* S, const vs_walls* walls) {
     return VS_OK;
 }
 
-vs_status vs_diagnostics(vs_state* S, double* sigma_t, double out[4]) {
+vs_status vs_diagnostics(vs_state* S, double* sigma_t, double out[6]) {
     if (!S) return fail(VS_E_STATE, "state is NULL");
     if (!out) return fail(VS_E_ARG, "out is NULL");
     const Dims& d = S->d;
@@ -715,6 +715,8 @@ vs_status vs_diagnostics(vs_state* S, double* sigma_t, double out[4]) {
     out[1] = h3 * sc[SC_DG_PSI];
     out[2] = (S->p.model == VS_BENDING ? cF : 1.0) * h3 * sc[SC_DG_ENERGY];
     out[3] = sc[SC_DG_SMAX];
+    out[4] = h3 * sc[SC_DG_GAUGE];
+    out[5] = sc[SC_DG_VMAX];
     return VS_OK;
 }
 

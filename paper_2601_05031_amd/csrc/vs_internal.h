@@ -71,6 +71,8 @@ enum {
     SC_DG_PSI = 17,           // sum_w |psi - psi_0|^2
     SC_DG_ENERGY = 18,        // sum_w of the free-energy density (g^2 for bending)
     SC_DG_SMAX = 19,          // max sigma_t
+    SC_DG_GAUGE = 20,         // sum over the interior of (D . psi)^2
+    SC_DG_VMAX = 21,          // max |v|
     SC_NSCAL = 24
 };
 // Slots of the device status array (ints).

@@ -216,10 +216,11 @@ class Solver:
         if sigma_t is not None and (sigma_t.dtype != self.torch.float64 or not sigma_t.is_contiguous()
                                     or tuple(sigma_t.shape) != self.shape):
             raise ValueError("sigma_t must be a contiguous float64 tensor of the grid shape")
-        out = (ctypes.c_double * 4)()
+        out = (ctypes.c_double * 6)()
         ptr = ctypes.c_void_p(sigma_t.data_ptr()) if sigma_t is not None else None
         _check(lib().vs_diagnostics(self._st, ptr, out), "vs_diagnostics")
-        return {"obs_omega": out[0], "obs_psi": out[1], "energy": out[2], "sigma_t_max": out[3]}
+        return {"obs_omega": out[0], "obs_psi": out[1], "energy": out[2], "sigma_t_max": out[3],
+                "gauge_defect": out[4], "speed_max": out[5]}
 
     def save(self) -> bytes:
         n = ctypes.c_size_t(0)

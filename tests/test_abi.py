@@ -95,7 +95,7 @@ def test_null_state_calls():
     assert L.vs_field_offset(None, 0, ctypes.byref(off)) == V.VS_E_STATE
     w = V.VsWalls(V.VS_POISEUILLE, 0.05, 0.0)
     assert L.vs_set_walls(None, ctypes.byref(w)) == V.VS_E_STATE
-    out = (ctypes.c_double * 4)()
+    out = (ctypes.c_double * 6)()
     assert L.vs_diagnostics(None, None, out) == V.VS_E_STATE
     assert L.vs_batch_step(None, None, 2) == V.VS_E_STATE
     b = ctypes.c_void_p(0)

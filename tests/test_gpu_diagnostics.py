@@ -71,6 +71,8 @@ def test_diagnostics_match_oracle(name):
     sref = D.shear_stress(ref.psi, g, walls, p.eta)
     oo, op = D.observables(ref.omega, ref.psi, g, walls)
     F = D.free_energy(ref.phi, g, p)
+    G = D.gauge_defect(ref.psi, g)
+    vmax = D.max_speed(ref.psi, g, walls)
     e = rel_l2(st.cpu().numpy(), sref)
     say(f"  sigma_t relL2={e:.2e} max {dg['sigma_t_max']:.10e} vs {sref.max():.10e}; "
         f"obs {dg['obs_omega']:.10e}/{oo:.10e} {dg['obs_psi']:.10e}/{op:.10e}; F {dg['energy']:.10e}/{F:.10e}")
@@ -79,6 +81,9 @@ def test_diagnostics_match_oracle(name):
     assert dg["obs_omega"] == pytest.approx(oo, rel=TOL)
     assert dg["obs_psi"] == pytest.approx(op, rel=TOL)
     assert dg["energy"] == pytest.approx(F, rel=TOL)
+    say(f"  gauge {dg['gauge_defect']:.10e}/{G:.10e} vmax {dg['speed_max']:.10e}/{vmax:.10e}")
+    assert dg["gauge_defect"] == pytest.approx(G, rel=TOL)
+    assert dg["speed_max"] == pytest.approx(vmax, rel=TOL)
 
 
 @pytest.mark.parametrize("kind", ["poiseuille", "couette"])
