@@ -291,8 +291,8 @@ void enqueue_va_mu(vs_state* S, const double* phi, int init) {
 }
 
 // The flow part of a step (main text eq. (5b), then (5c)). Cycle 0 of the two vector solves
-// shares one spectral pass: the vorticity modes after the Thomas solve are, up to -h^2, the
-// transformed right-hand side of the stream-vector problem, so psi needs no forward
+// shares one spectral pass: the vorticity modes after the tridiagonal solve are, up to -h^2,
+// the transformed right-hand side of the stream-vector problem, so psi needs no forward
 // transform. Both fields are then verified against their own spatial residual; correction
 // cycles (normally never run in FP64) use the generic path.
 void enqueue_flow(vs_state* S, const double* phi) {
@@ -345,13 +345,13 @@ void enqueue_flow(vs_state* S, const double* phi) {
         timed(S, K_CHECK, [&] { launch_check_flow(S->stream, d, S->part, rtol, S->scal, S->istat); });
         return;
     }
-    enqueue_verify(S, rv, S->om, 3, rtol, 0, mc == 1, TAG_OMEGA, nullptr);
+    enqueue_verify(S, rv, S->om, 3, rtol, 0, 0, TAG_OMEGA, nullptr);
     for (int cyc = 1; cyc < mc; ++cyc) {
         const int* gate = S->istat + IS_CONV;
         enqueue_cycle(S, rv, S->om, 3, 1, TAG_OMEGA, gate);
         enqueue_verify(S, rv, S->om, 3, rtol, cyc, cyc == mc - 1, TAG_OMEGA, gate);
     }
-    enqueue_verify(S, rp, S->ps, 3, rtol, 0, mc == 1, TAG_PSI, nullptr);
+    enqueue_verify(S, rp, S->ps, 3, rtol, 0, 0, TAG_PSI, nullptr);
     for (int cyc = 1; cyc < mc; ++cyc) {
         const int* gate = S->istat + IS_CONV;
         enqueue_cycle(S, rp, S->ps, 3, 1, TAG_PSI, gate);
