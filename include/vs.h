@@ -80,7 +80,8 @@ enum {
 
 /* Grid ("Numerical implementation"). ny counts both wall rows; ny >= 3.
  * nx, nz >= 4, even, of the form 2^a 3^b, at most 512 (the periodic directions are
- * diagonalised by fast transforms of these lengths). */
+ * diagonalised by fast transforms of these lengths); ny * nz <= 2^20 (one x-plane) and
+ * nx * ny * nz <= 2^30. Larger grids fail with VS_E_ARG / VS_E_UNSUPPORTED. */
 typedef struct {
     int32_t nx, ny, nz;
     double h;

@@ -1049,56 +1049,76 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// resid_norm: block partials of sum (b - L_h u)_c^2 and sum b~_c^2 over the interior. Each
-// thread owns one interior (j, k) and walks ci consecutive x-planes; blocks ordered per XCD.
+// resid_norm: block partials of sum (b - L_h u)_c^2 and sum b~_c^2 over the interior. A block
+// owns one component c and a slab of ci consecutive x-planes; each thread owns one interior
+// (j, k) and walks the slab with u_c at x-1 and x kept in registers, so one new centre value
+// is read per plane. Blocks are ordered per XCD. Streaming a single component (u_c and b_c)
+// per block keeps two arrays in flight per wave instead of six, which runs close to the copy
+// rate where reading every component at each node does not.
 __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr3 u, int ncomp,
                                                       SlabGrid sg, double* __restrict__ partials,
                                                       const int* gate, int slot0) {
     if (gate && *gate) return;
-    __shared__ double sh[6 * 4];
+    __shared__ double sh[2 * 4];
     const int nb = sg.gx * sg.gi;
-    const int lb = xcd_block(blockIdx.x, nb);
+    const int lb0 = xcd_block(blockIdx.x, ncomp * nb);
+    const int c = lb0 / nb;
+    const int lb = lb0 - c * nb;
     const int bi = lb / sg.gx;
     const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    // block-uniform selects keep the pointer choice in scalar registers
+    const double* uc = c == 0 ? u.p[0] : c == 1 ? u.p[1] : u.p[2];
+    const double* fc = c == 0 ? rhs.f[0] : c == 1 ? rhs.f[1] : rhs.f[2];
+    const double sgn = (rhs.mode == RHS_NEGW) ? -1.0 : 1.0;
+    double rr = 0.0, bb = 0.0;
     if (t < d.M * d.nz) {
         const int jj = t / d.nz;
         const int k = t - jj * d.nz;
         const int j = jj + 1;
-        const int i1 = min(d.nx, (bi + 1) * sg.ci);
+        const int plane = d.ny * d.nz;
+        const int off = j * d.nz + k;
+        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+        const int km = (k == 0) ? d.nz - 1 : k - 1;
+        const int i0 = bi * sg.ci;
+        const int i1 = min(d.nx, i0 + sg.ci);
+        const int im0 = (i0 == 0) ? d.nx - 1 : i0 - 1;
+        double um = uc[im0 * plane + off];
+        double ux = uc[i0 * plane + off];
 #pragma unroll 2
-        for (int i = bi * sg.ci; i < i1; ++i) {
+        for (int i = i0; i < i1; ++i) {
             const int ip = (i + 1 == d.nx) ? 0 : i + 1;
-            const int im = (i == 0) ? d.nx - 1 : i - 1;
-            const int rb = node(d, i, j, 0), xpb = node(d, ip, j, 0), xmb = node(d, im, j, 0);
+            const int rb = i * plane + j * d.nz;
             const int c0 = rb + k;
-            const int kp = (k + 1 == d.nz) ? 0 : k + 1;
-            const int km = (k == 0) ? d.nz - 1 : k - 1;
-            for (int c = 0; c < ncomp; ++c) {
-                const double* uc = u.p[c];
-                const double b = rhs_val(rhs, c, c0);
-                const double ylo = uc[c0 - d.nz], yhi = uc[c0 + d.nz];
-                const double w = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
-                const double lap = (uc[xpb + k] + uc[xmb + k] + ylo + yhi + uc[rb + kp] +
-                                    uc[rb + km] - 6.0 * uc[c0]) * d.inv_h2;
-                const double r = b - lap;
-                const double bt = b - w * d.inv_h2;
-                acc[c] += r * r;
-                acc[3 + c] += bt * bt;
-            }
+            const double up = uc[ip * plane + off];
+            const double b = sgn * fc[c0];
+            const double ylo = uc[c0 - d.nz], yhi = uc[c0 + d.nz];
+            const double w = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
+            const double lap = (up + um + ylo + yhi + uc[rb + kp] + uc[rb + km] - 6.0 * ux) *
+                               d.inv_h2;
+            const double r = b - lap;
+            const double bt = b - w * d.inv_h2;
+            rr += r * r;
+            bb += bt * bt;
+            um = ux;
+            ux = up;
         }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const double s = wave_sum(acc[q]);
-        if (lane == 0) sh[q * 4 + w] = s;
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (lane == 0) {
+        sh[w] = rr;
+        sh[4 + w] = bb;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
-        const double s = sh[threadIdx.x * 4 + 0] + sh[threadIdx.x * 4 + 1] +
-                         sh[threadIdx.x * 4 + 2] + sh[threadIdx.x * 4 + 3];
-        partials[(slot0 + threadIdx.x) * kMaxPartialBlocks + blockIdx.x] = s;
+    if (threadIdx.x < 2) {
+        const int q = threadIdx.x;
+        partials[(slot0 + 3 * q + c) * kMaxPartialBlocks + lb] =
+            sh[4 * q + 0] + sh[4 * q + 1] + sh[4 * q + 2] + sh[4 * q + 3];
+    } else if (c == 0 && threadIdx.x < 8) {
+        // the check sums three components: the blocks of component 0 clear the absent ones
+        const int q = (threadIdx.x - 2) / 3, cc = (threadIdx.x - 2) - 3 * q;
+        if (cc >= ncomp) partials[(slot0 + 3 * q + cc) * kMaxPartialBlocks + lb] = 0.0;
     }
 }
 
@@ -1418,8 +1438,12 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
         dht_z_out_t<double>(s, d, pz, twz, spec, u, ncomp, add, gate);
 }
 
+// Residual blocks per component: slabs of x-planes chosen so that about a thousand blocks
+// cover one component (each component adds as many again).
+static SlabGrid resid_grid(const Dims& d) { return slab_grid(d.M * d.nz, d.nx, 1024); }
+
 int resid_blocks(const Dims& d) {
-    const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
+    const SlabGrid g = resid_grid(d);
     return g.gx * g.gi;
 }
 
@@ -1427,9 +1451,9 @@ void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate,
                        int slot0) {
     CPtr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
-    const SlabGrid g = slab_grid(d.M * d.nz, d.nx, kMaxPartialBlocks);
-    launch_kernel(k_resid_norm, dim3(g.gx * g.gi), dim3(kBlock), 0, s, d, rhs, uu, ncomp, g,
-                  partials, gate, slot0);
+    const SlabGrid g = resid_grid(d);
+    launch_kernel(k_resid_norm, dim3(ncomp * g.gx * g.gi), dim3(kBlock), 0, s, d, rhs, uu, ncomp,
+                  g, partials, gate, slot0);
 }
 
 void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,

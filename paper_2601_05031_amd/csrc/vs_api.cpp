@@ -104,6 +104,10 @@ vs_status check_grid(const vs_grid* g) {
         return fail(VS_E_UNSUPPORTED, "nz = %d: need even 4 <= nz <= 512 of the form 2^a 3^b", g->nz);
     if ((long long)g->nx * g->ny * g->nz > (1ll << 30))
         return fail(VS_E_ARG, "grid too large");
+    // reductions keep one partial per block of 256 plane nodes: at most kMaxPartialBlocks
+    if ((long long)g->ny * g->nz > 256ll * kMaxPartialBlocks)
+        return fail(VS_E_ARG, "ny * nz = %lld: at most %d nodes per x-plane",
+                    (long long)g->ny * g->nz, 256 * kMaxPartialBlocks);
     return VS_OK;
 }
 

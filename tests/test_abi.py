@@ -45,6 +45,8 @@ def test_workspace_bytes_and_layout():
     ((128, 16, 1024, 1.0), V.VS_E_UNSUPPORTED),
     ((128, 16, 128, 0.0), V.VS_E_ARG),
     ((33, 16, 32, 1.0), V.VS_E_UNSUPPORTED),
+    ((4, 2049, 512, 1.0), V.VS_E_ARG),          # one x-plane above 2^20 nodes
+    ((512, 4097, 512, 1.0), V.VS_E_ARG),        # above 2^30 nodes
 ])
 def test_grid_validation(grid, code):
     with pytest.raises(V.VsError) as e:
