@@ -48,6 +48,7 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
         "dht_z_out": 48 * Ni,         # 3 spectral fields in; 3 solution fields out
         "resid_norm_omega": 48 * Ni,  # S(3), omega(3) in
         "resid_norm_psi": 48 * Ni,    # omega(3), psi(3) in
+        "resid_norm_flow": 72 * Ni,   # omega(3), S(3), psi(3) in: both flow residuals
     }
     return table.get(name)
 

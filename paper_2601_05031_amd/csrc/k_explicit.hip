@@ -105,8 +105,8 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
 //
 // mu by x-marching tiles. A block owns a kMuTY x kMuTZ tile of (j, k) and walks kMuNI
 // consecutive x-planes: a 4-plane ring of phi (halo 2 in y and z) and a 3-plane ring of g
-// (halo 1) live in LDS, the next phi plane is prefetched into registers while the current
-// one is computed, and every x-neighbour comes from the rings instead of L2. Rows beyond the
+// (halo 1) live in LDS, the phi planes are prefetched into registers kMuD planes ahead of
+// their use, and every x-neighbour comes from the rings instead of L2. Rows beyond the
 // walls are filled with the mirror image (j -> -j, ny-1+m -> ny-1-m), so g computed there is
 // the mirror ghost of g. Sums run in the order of lap7, so the result equals the plain
 // stencil's bit for bit.
@@ -114,6 +114,22 @@ constexpr int kMuTY = 4, kMuTZ = 64, kMuNI = 8;
 constexpr int kPY = kMuTY + 4, kPZ = kMuTZ + 4, kPN = kPY * kPZ;
 constexpr int kGY = kMuTY + 2, kGZ = kMuTZ + 2, kGN = kGY * kGZ;
 constexpr int kPre = (kPN + kBlock - 1) / kBlock;
+constexpr int kPS = kPre * kBlock;               // phi slot, padded: every lane loads and stores
+constexpr int kGI = (kGN + kBlock - 1) / kBlock;
+constexpr int kGS = kGI * kBlock;                // g slot, padded likewise
+constexpr int kMuD = 2;                          // phi planes in flight ahead of their use
+static_assert(((kGS - 1) / kGZ + 2) * kPZ + kGZ < kPS, "padded g nodes read inside the phi slot");
+
+// Store through a buffer resource over one x-plane: a lane outside the grid passes an
+// offset past the plane's extent and the hardware drops its store, so the store needs no
+// branch (a branch around it would make the compiler wait for every load in flight).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void plane_store(double* plane_base, unsigned plane_bytes,
+                                            unsigned byte_off, double v) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(plane_base, 0, (int)plane_bytes, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, 0);
+}
 
 __device__ __forceinline__ int mirror_row(int j, int ny) {
     j = j < 0 ? -j : (j > ny - 1 ? 2 * (ny - 1) - j : j);
@@ -124,13 +140,18 @@ __device__ __forceinline__ int wrap_mod(int k, int n) {
     return k < 0 ? k + n : k;
 }
 
+// The plane loop is straight-line code: a fixed kMuNI steps, fully unrolled, no branch
+// around a load or a store (planes past the slab end are computed on wrapped planes and
+// their stores dropped; padding lanes load and store inside padded LDS slots). That keeps
+// the compiler's memory-counter waits exact, so the kMuD planes in flight are really in
+// flight while the block computes.
 template <bool BEND>
 __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ phi,
                                                    double* __restrict__ mu, Dims d,
                                                    const double* __restrict__ scal, double C_b,
                                                    double eps, double sigma) {
-    __shared__ double P[4][kPN];
-    __shared__ double G[BEND ? 3 : 1][BEND ? kGN : 1];
+    __shared__ double P[4][kPS];
+    __shared__ double G[BEND ? 3 : 1][BEND ? kGS : 1];
     const int tz_n = (d.nz + kMuTZ - 1) / kMuTZ;
     const int ty_n = (d.ny + kMuTY - 1) / kMuTY;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -139,7 +160,8 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
     const int j0 = (rem / tz_n) * kMuTY, k0 = (rem - (rem / tz_n) * tz_n) * kMuTZ;
     const int i0 = ic * kMuNI, i1 = min(d.nx, i0 + kMuNI);
     const int plane = d.ny * d.nz;
-    // region element e -> node offset inside a plane (mirror rows, periodic z)
+    // region element e -> node offset inside a plane (mirror rows, periodic z); padding
+    // elements load node 0
     int roff[kPre];
 #pragma unroll
     for (int q = 0; q < kPre; ++q) {
@@ -150,22 +172,24 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
     auto fetch = [&](int i, double (&v)[kPre]) {
         const double* src = phi + (size_t)wrap_mod(i, d.nx) * plane;
 #pragma unroll
-        for (int q = 0; q < kPre; ++q)
-            if (threadIdx.x + q * kBlock < kPN) v[q] = src[roff[q]];
+        for (int q = 0; q < kPre; ++q) v[q] = src[roff[q]];
     };
     auto put = [&](double* dst, const double (&v)[kPre]) {
 #pragma unroll
-        for (int q = 0; q < kPre; ++q)
-            if (threadIdx.x + q * kBlock < kPN) dst[threadIdx.x + q * kBlock] = v[q];
+        for (int q = 0; q < kPre; ++q) dst[threadIdx.x + q * kBlock] = v[q];
     };
     auto slot = [](int m) { return m & 3; };   // m >= -2 + 4 below
     const double eps2 = eps * eps;
+    // g on the (kMuTY + 2) x (kMuTZ + 2) halo tile of plane m; the padding elements compute
+    // on phi rows inside the padded slot and land in the g slot's padding
     auto make_g = [&](int m) {
         const double* pc = P[slot(m + 4)];
         const double* pm = P[slot(m + 3)];
         const double* pp = P[slot(m + 5)];
         double* g = G[BEND ? (m + 3) % 3 : 0];
-        for (int e = threadIdx.x; e < kGN; e += kBlock) {
+#pragma unroll
+        for (int q = 0; q < kGI; ++q) {
+            const int e = threadIdx.x + q * kBlock;
             const int r = e / kGZ, c = e - (e / kGZ) * kGZ;
             const int x = (r + 1) * kPZ + (c + 1);
             const double p = pc[x];
@@ -173,47 +197,62 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
             g[e] = p * p * p - p - eps2 * l;
         }
     };
-    double v[kPre];
-    // prologue: phi planes i0-2 .. i0+1, g planes i0-1 and i0
-    for (int m = -2; m <= 1; ++m) {
-        fetch(i0 + m, v);
-        put(P[slot(i0 + m + 4)], v);
+    // prologue: phi planes i0-2 .. i0+1 (loads all in flight together), g planes i0-1, i0
+    {
+        double w0[kPre], w1[kPre], w2[kPre], w3[kPre];
+        fetch(i0 - 2, w0);
+        fetch(i0 - 1, w1);
+        fetch(i0, w2);
+        fetch(i0 + 1, w3);
+        put(P[slot(i0 + 2)], w0);
+        put(P[slot(i0 + 3)], w1);
+        put(P[slot(i0 + 4)], w2);
+        put(P[slot(i0 + 5)], w3);
     }
     __syncthreads();
     if (BEND) {
         make_g(i0 - 1);
         make_g(i0);
     }
-    fetch(i0 + 2, v);
+    // phi(i0 + s + 2) is put at step s from register set s % kMuD, fetched kMuD steps earlier
+    double v[kMuD][kPre];
+#pragma unroll
+    for (int s = 0; s < kMuD; ++s) fetch(i0 + 2 + s, v[s]);
     const int tj = threadIdx.x / kMuTZ, tk = threadIdx.x - (threadIdx.x / kMuTZ) * kMuTZ;
     const int j = j0 + tj, k = k0 + tk;
     const bool out = j < d.ny && k < d.nz;
+    const unsigned pbytes = (unsigned)plane * 8u;
+    const unsigned oofs = (unsigned)(j * d.nz + k) * 8u;
     const double gamma = scal[SC_GAMMA];
-    for (int i = i0; i < i1; ++i) {
+#pragma unroll
+    for (int s = 0; s < kMuNI; ++s) {
+        const int i = i0 + s;
         __syncthreads();                         // the slot of phi(i-2) and g(i-2) are free
-        put(P[slot(i + 6)], v);                  // phi(i+2)
+        put(P[slot(i + 6)], v[s % kMuD]);        // phi(i+2)
         __syncthreads();
-        if (i + 1 < i1) fetch(i + 3, v);         // in flight during the computation below
+        fetch(i + 2 + kMuD, v[s % kMuD]);        // in flight during the next kMuD steps
         if (BEND) make_g(i + 1);
         __syncthreads();
-        if (!out) continue;
         const double* pc = P[slot(i + 4)];
         const int x = (tj + 2) * kPZ + (tk + 2);
         const double p = pc[x];
         const double lphi = (P[slot(i + 5)][x] + P[slot(i + 3)][x] + pc[x + kPZ] + pc[x - kPZ] +
                              pc[x + 1] + pc[x - 1] - 6.0 * p) * d.inv_h2;
-        const size_t o = (size_t)i * plane + (size_t)j * d.nz + k;
+        double m;
         if (!BEND) {
-            mu[o] = p * p * p - p - sigma * lphi;
-            continue;
+            m = p * p * p - p - sigma * lphi;
+        } else {
+            const double* gc = G[(i + 3) % 3];
+            const int y = (tj + 1) * kGZ + (tk + 1);
+            const double g0 = gc[y];
+            const double gs = G[(i + 4) % 3][y] + G[(i + 2) % 3][y] + gc[y + kGZ] + gc[y - kGZ] +
+                              gc[y + 1] + gc[y - 1];
+            const double lg = (gs - 6.0 * g0) * d.inv_h2;
+            m = C_b * ((3.0 * p * p - 1.0) * g0 - eps2 * lg) - gamma * lphi;
         }
-        const double* gc = G[(i + 3) % 3];
-        const int y = (tj + 1) * kGZ + (tk + 1);
-        const double g0 = gc[y];
-        const double gs = G[(i + 4) % 3][y] + G[(i + 2) % 3][y] + gc[y + kGZ] + gc[y - kGZ] +
-                          gc[y + 1] + gc[y - 1];
-        const double lg = (gs - 6.0 * g0) * d.inv_h2;
-        mu[o] = C_b * ((3.0 * p * p - 1.0) * g0 - eps2 * lg) - gamma * lphi;
+        // lanes outside the grid, and planes past the slab end, have their stores dropped
+        const bool keep = out && i < i1;
+        plane_store(mu + (size_t)(keep ? i : 0) * plane, pbytes, keep ? oofs : pbytes, m);
     }
 }
 
@@ -245,6 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
         const int ozm = j * d.nz + ((k == 0) ? d.nz - 1 : k - 1);
         double pm = phi[(size_t)((i0 + d.nx - 1) % d.nx) * plane + o];
         double p0 = phi[(size_t)i0 * plane + o];
+#pragma unroll 4
         for (int i = i0; i < i1; ++i) {
             const size_t bc = (size_t)i * plane;
             const double pp = phi[(size_t)((i + 1) % d.nx) * plane + o];

@@ -1122,6 +1122,87 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
     }
 }
 
+// resid_flow: both residual norms of the flow solve in one pass, in the layout of resid_norm
+// (vorticity in slots 0-5, stream vector in slots 6-11). A block owns one component c and
+// streams omega_c, S_c and psi_c: omega_c is read once for both problems (its stencil for
+// eq. (5b), its centre as the right-hand side -omega_c of eq. (5c)). Sums are those of
+// resid_norm, term for term.
+__global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 src, CPtr3 ps,
+                                                      SlabGrid sg,
+                                                      double* __restrict__ partials) {
+    __shared__ double sh[4 * 4];
+    const int nb = sg.gx * sg.gi;
+    const int lb0 = xcd_block(blockIdx.x, 3 * nb);
+    const int c = lb0 / nb;
+    const int lb = lb0 - c * nb;
+    const int bi = lb / sg.gx;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
+    const double* wc = c == 0 ? om.p[0] : c == 1 ? om.p[1] : om.p[2];
+    const double* sc = c == 0 ? src.p[0] : c == 1 ? src.p[1] : src.p[2];
+    const double* pc = c == 0 ? ps.p[0] : c == 1 ? ps.p[1] : ps.p[2];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (t < d.M * d.nz) {
+        const int jj = t / d.nz;
+        const int k = t - jj * d.nz;
+        const int j = jj + 1;
+        const int plane = d.ny * d.nz;
+        const int off = j * d.nz + k;
+        const int kp = (k + 1 == d.nz) ? 0 : k + 1;
+        const int km = (k == 0) ? d.nz - 1 : k - 1;
+        const int i0 = bi * sg.ci;
+        const int i1 = min(d.nx, i0 + sg.ci);
+        const int im0 = (i0 == 0) ? d.nx - 1 : i0 - 1;
+        double wm = wc[im0 * plane + off], wx = wc[i0 * plane + off];
+        double pm = pc[im0 * plane + off], px = pc[i0 * plane + off];
+#pragma unroll 2
+        for (int i = i0; i < i1; ++i) {
+            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+            const int rb = i * plane + j * d.nz;
+            const int c0 = rb + k;
+            const double wp = wc[ip * plane + off];
+            const double pp = pc[ip * plane + off];
+            {
+                const double b = sc[c0];
+                const double ylo = wc[c0 - d.nz], yhi = wc[c0 + d.nz];
+                const double w = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
+                const double lap = (wp + wm + ylo + yhi + wc[rb + kp] + wc[rb + km] - 6.0 * wx) *
+                                   d.inv_h2;
+                const double r = b - lap;
+                const double bt = b - w * d.inv_h2;
+                a[0] += r * r;
+                a[1] += bt * bt;
+            }
+            {
+                const double b = -wx;
+                const double ylo = pc[c0 - d.nz], yhi = pc[c0 + d.nz];
+                const double w = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
+                const double lap = (pp + pm + ylo + yhi + pc[rb + kp] + pc[rb + km] - 6.0 * px) *
+                                   d.inv_h2;
+                const double r = b - lap;
+                const double bt = b - w * d.inv_h2;
+                a[2] += r * r;
+                a[3] += bt * bt;
+            }
+            wm = wx;
+            wx = wp;
+            pm = px;
+            px = pp;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double v = wave_sum(a[q]);
+        if (lane == 0) sh[4 * q + w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;   // 0: omega r, 1: omega b~, 2: psi r, 3: psi b~
+        partials[(3 * q + c) * kMaxPartialBlocks + lb] =
+            sh[4 * q + 0] + sh[4 * q + 1] + sh[4 * q + 2] + sh[4 * q + 3];
+    }
+}
+
 // check: relative residual sqrt(sum_c r^2 / sum_c b~^2) in a fixed summation order; sets the
 // convergence flag that gates the following cycles, counts the cycle and raises ST_NOCONV
 // on the last allowed cycle, ST_NONFINITE on NaN/Inf.
@@ -1454,6 +1535,14 @@ void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
     const SlabGrid g = resid_grid(d);
     launch_kernel(k_resid_norm, dim3(ncomp * g.gx * g.gi), dim3(kBlock), 0, s, d, rhs, uu, ncomp,
                   g, partials, gate, slot0);
+}
+
+void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
+                       const double* const src[3], const double* const ps[3], double* partials) {
+    const CPtr3 o{{om[0], om[1], om[2]}}, f{{src[0], src[1], src[2]}}, p{{ps[0], ps[1], ps[2]}};
+    const SlabGrid g = resid_grid(d);
+    launch_kernel(k_resid_flow, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
+                  partials);
 }
 
 void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,

@@ -41,12 +41,13 @@ vs_status fail(vs_status code, const char* fmt, ...) {
 enum KClass {
     K_ADVANCE, K_VA_PARTIALS, K_FINALIZE_VA, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
-    K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_NCLASS
+    K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "finalize_va", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
     "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
-    "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats"};
+    "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
+    "resid_norm_flow"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -341,11 +342,11 @@ void enqueue_flow(vs_state* S, const double* phi) {
         launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec2, S->ps, 3, 0, false, nullptr);
     });
     if (mc == 1) {
-        // one cycle each: both residual passes, then both checks in one launch
+        // one cycle each: both residuals in one pass, then both checks in one launch
         const double* const co[3] = {S->om[0], S->om[1], S->om[2]};
+        const double* const cs[3] = {S->src[0], S->src[1], S->src[2]};
         const double* const cp[3] = {S->ps[0], S->ps[1], S->ps[2]};
-        timed(S, K_RESID_OMEGA, [&] { launch_resid_norm(S->stream, d, rv, co, 3, S->part, nullptr, 0); });
-        timed(S, K_RESID_PSI, [&] { launch_resid_norm(S->stream, d, rp, cp, 3, S->part, nullptr, 6); });
+        timed(S, K_RESID_FLOW, [&] { launch_resid_flow(S->stream, d, co, cs, cp, S->part); });
         timed(S, K_CHECK, [&] { launch_check_flow(S->stream, d, S->part, rtol, S->scal, S->istat); });
         return;
     }

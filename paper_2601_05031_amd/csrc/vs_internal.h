@@ -164,6 +164,10 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
                       void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
                       const int* gate);
 int resid_blocks(const Dims& d);
+// Both flow residuals (vorticity, eq. (5b): b = S; stream vector, eq. (5c): b = -omega) in
+// one pass, into partial slots 0-5 and 6-11 as two resid_norm launches would write them.
+void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
+                       const double* const src[3], const double* const ps[3], double* partials);
 
 // ---------------------------------------------------------------- reverse step (k_adjoint.hip)
 // a = dL/dphi^{n+1}; writes phibar (dL/dphi^n, partial), mubar and psibar(3); gathers
