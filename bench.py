@@ -227,6 +227,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-steps", type=int, default=500,
                     help="steps of the FP64 vs FP32-refined comparison on droplet256 (0 = skip)")
+    ap.add_argument("--graph-steps", type=int, default=-1,
+                    help="steps of the headline instances replayed as one graph (-1: --steps, 0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="steps of the 64-instance batch (0 = skip)")
     ap.add_argument("--batch-streams", type=int, default=8)
@@ -314,11 +316,12 @@ def main():
     # small reduction kernels and launch gaps of one instance overlap the others' work; an
     # extra figure, `value` stays the plain sequential vs_step path above
     headline_graph = None
-    if args.steps >= 2:
+    gsteps = args.steps if args.graph_steps < 0 else args.graph_steps
+    if gsteps >= 2:
         b = P.Batch(solvers, nstreams=len(solvers))
         b.step(base.dt, 2)                      # capture + first replay, untimed
         torch.cuda.synchronize()
-        kb = args.steps - (args.steps & 1)
+        kb = gsteps - (gsteps & 1)
         t0 = time.perf_counter()
         b.step(base.dt, kb)
         torch.cuda.synchronize()

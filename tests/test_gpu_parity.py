@@ -153,6 +153,28 @@ def test_step_parity_one_cycle(seed):
     assert sc["relres"] <= w.rtol
 
 
+def test_combined_flow_residual_matches_separate_passes():
+    """With one cycle per solve the two flow residuals run as one combined pass; with two
+    cycles each solve is verified by its own residual pass. The direct solve converges in
+    cycle 0 either way, so the fields agree bit for bit and the largest relative residual
+    of the two verifications agrees to rounding."""
+    w = workload("vesicle32", seed=3)
+    say("case combined vs separate flow residuals vesicle32 seed=3")
+    one = P.solver_for(w, max_cycles=1)
+    two = P.solver_for(w, max_cycles=2)
+    one.step(w.dt, 3)
+    two.step(w.dt, 3)
+    f1, f2 = one.fields(), two.fields()
+    r1, r2 = one.scalars()["relres"], two.scalars()["relres"]
+    one.close()
+    two.close()
+    for k in FIELD_NAMES:
+        assert np.array_equal(f1[k], f2[k]), k
+    say(f"  relres combined={r1:.6e} separate={r2:.6e}")
+    assert 0.0 < r1 <= w.rtol
+    assert r1 == pytest.approx(r2, rel=1e-12)
+
+
 def test_step_parity_cahn_hilliard_couette():
     """Cahn-Hilliard droplet in plane Couette flow (walls at -/+0.05)."""
     w = workload("droplet256", grid=GridSpec(48, 32, 96), R0=9.0, nsteps=5)
