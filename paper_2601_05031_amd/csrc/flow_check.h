@@ -1,0 +1,64 @@
+// Convergence check of the two flow solves of a step, each of a single cycle (main text
+// eq. (5b), (5c); the solves are verified against a relative-residual tolerance). Partial
+// slots 0-5 hold the vorticity residual sums, 6-11 the stream-vector ones (per component,
+// value-major: r^2 in slots 0-2, b~^2 in 3-5); the two checks run in a row (vorticity, then
+// stream vector) as two last-cycle checks would. Shared by the standalone check kernel and by
+// the first block of the next step's advance, which takes the check of the previous step.
+#pragma once
+#include "vs_internal.h"
+
+namespace vs {
+
+__device__ __forceinline__ double fc_wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Call from every thread of one block (a multiple of 64 threads, at most 1024); sh holds
+// 4 * 16 doubles.
+__device__ inline void flow_check_block(const double* __restrict__ partials, int nblocks,
+                                        double rtol, double* scal, int* istat, double* sh) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const double* pb = partials + (size_t)(3 * g) * kMaxPartialBlocks + b;
+            a[g] += pb[0] + pb[kMaxPartialBlocks] + pb[2 * kMaxPartialBlocks];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) a[g] = fc_wave_sum(a[g]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) sh[g * 16 + wv] = a[g];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int g = 0; g < 4; ++g) {
+            a[g] = 0.0;
+            for (int q = 0; q < nw; ++q) a[g] += sh[g * 16 + q];
+        }
+        for (int sidx = 0; sidx < 2; ++sidx) {
+            const double rr = a[2 * sidx], bb = a[2 * sidx + 1];
+            double rel;
+            if (bb > 0.0)
+                rel = sqrt(rr / bb);
+            else
+                rel = (rr > 0.0) ? INFINITY : 0.0;
+            if (rr != rr || bb != bb) rel = NAN;
+            const int conv = (rel <= rtol) ? 1 : 0;
+            istat[IS_CONV] = conv;
+            istat[IS_CYCLES] += 1;
+            scal[SC_RELRES_LAST] = rel;
+            const double prev = scal[SC_RELRES_MAX];
+            scal[SC_RELRES_MAX] = (rel != rel || rel > prev) ? rel : prev;
+            if (!conv) istat[IS_FLAGS] |= ST_NOCONV;
+            if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace vs

@@ -3,6 +3,7 @@
 //   fused in registers; the chemical potential (SM eq. (35) bending, eq. F_CH / SM (31)
 //   Cahn-Hilliard); the volume and area integrals (SM eq. (37), (32)) with the penalty
 //   multipliers (SM "Lagrange multipliers"). Launch shape and wall handling: stencil.h.
+#include "flow_check.h"
 #include "stencil.h"
 
 namespace vs {
@@ -49,8 +50,13 @@ constexpr int kAdvSlab = 4;
 __global__ __launch_bounds__(kBlock) void k_advance_x(
     const double* __restrict__ phi, const double* __restrict__ mu,
     const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
-    double* __restrict__ out, Dims d, SlabGrid sg, const double* __restrict__ scal, double dt,
-    double mob, double vz_lo, double vz_hi) {
+    double* __restrict__ out, Dims d, SlabGrid sg, double* scal, double dt, double mob,
+    double vz_lo, double vz_hi, PrevCheck ck) {
+    if (ck.partials && blockIdx.x == 0) {
+        // the previous step's flow check, off the critical path of this kernel's other blocks
+        __shared__ double shc[4 * 16];
+        flow_check_block(ck.partials, ck.nblocks, ck.rtol, scal, ck.istat, shc);
+    }
     const int nb = sg.gx * sg.gi;
     const int lb = xcd_block(blockIdx.x, nb);
     const int bi = lb / sg.gx;
@@ -97,6 +103,78 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
         pym = py0; py0 = pyp;
         pzm = pz0; pz0 = pzp;
     }
+}
+
+// V = (|Omega| + h^3 sum_w phi)/2, A = 3/(2 sqrt 2) h^3 sum_w(...); then
+// lambda_V = 2 rate_V (V0 - V)/(M |Omega|) and gamma_A = gamma0 + k_A (A - A0)/A0
+// (off when k_A = 0 or A0 = 0); init also sets V0 = V, A0 = A. Every block of the calling
+// kernel sums the block partials in the same fixed order and gets the same gamma_A; block 0
+// writes the scalars. In three parts, so that the loads overlap other loads and the block
+// sum rides on a barrier the caller has anyway:
+//   va_load    each thread loads its kVaPer partials per slot (b = thread + u * blockDim);
+//   va_reduce  per-thread sums in that order, wave sums into sh (before a barrier);
+//   va_final   after the barrier: every thread adds the wave sums in order and finishes.
+// More than kVaPer * blockDim partials (x-planes above 2^18 nodes) take a plain loop.
+constexpr int kVaPer = 4;
+struct VaLoads {
+    double v[2][kVaPer];
+};
+__device__ __forceinline__ void va_load(const VaFinal& va, VaLoads& L) {
+#pragma unroll
+    for (int u = 0; u < kVaPer; ++u) {
+        const int b = threadIdx.x + u * blockDim.x;
+        const int bc = b < va.nblocks ? b : 0;
+        L.v[0][u] = va.partials[0 * kMaxPartialBlocks + bc];
+        L.v[1][u] = va.partials[1 * kMaxPartialBlocks + bc];
+    }
+}
+__device__ __forceinline__ void va_reduce(const VaFinal& va, const VaLoads& L, double* sh) {
+    double acc[2] = {0.0, 0.0};
+    if (va.nblocks <= kVaPer * (int)blockDim.x) {
+#pragma unroll
+        for (int u = 0; u < kVaPer; ++u) {
+            const bool ok = (int)(threadIdx.x + u * blockDim.x) < va.nblocks;
+            acc[0] += ok ? L.v[0][u] : 0.0;
+            acc[1] += ok ? L.v[1][u] : 0.0;
+        }
+    } else {
+        for (int b = threadIdx.x; b < va.nblocks; b += blockDim.x) {
+            acc[0] += va.partials[0 * kMaxPartialBlocks + b];
+            acc[1] += va.partials[1 * kMaxPartialBlocks + b];
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) sh[q * 16 + w] = s;
+    }
+}
+__device__ __forceinline__ double va_final(const VaFinal& va, const Dims& d, const double* sh) {
+    const int nw = blockDim.x >> 6;
+    double acc[2] = {0.0, 0.0};
+    for (int q = 0; q < 2; ++q)
+        for (int i = 0; i < nw; ++i) acc[q] += sh[q * 16 + i];
+    const double h3 = d.h * d.h * d.h;
+    const double vol = (double)d.nx * d.nz * (d.ny - 1) * h3;
+    const double V = 0.5 * (vol + h3 * acc[0]);
+    const double A = 3.0 / (2.0 * 1.4142135623730951) * h3 * acc[1];
+    const double V0 = va.init ? V : va.scal[SC_V0];
+    const double A0 = va.init ? A : va.scal[SC_A0];
+    double gamma = va.gamma0;
+    if (va.k_A != 0.0 && A0 > 0.0) gamma += va.k_A * (A - A0) / A0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (va.init) {
+            va.scal[SC_V0] = V;
+            va.scal[SC_A0] = A;
+        }
+        va.scal[SC_V] = V;
+        va.scal[SC_A] = A;
+        va.scal[SC_LAMV] = 2.0 * va.rate_V * (V0 - V) / (va.mobility * vol);
+        va.scal[SC_GAMMA] = gamma;
+        if (!isfinite(V) || !isfinite(A)) va.istat[IS_FLAGS] |= ST_NONFINITE;
+    }
+    return gamma;
 }
 
 // mu from phi. Bending (SM eq. (35)): g = phi^3 - phi - eps^2 L_h phi,
@@ -147,11 +225,11 @@ __device__ __forceinline__ int wrap_mod(int k, int n) {
 // flight while the block computes.
 template <bool BEND>
 __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ phi,
-                                                   double* __restrict__ mu, Dims d,
-                                                   const double* __restrict__ scal, double C_b,
-                                                   double eps, double sigma) {
+                                                   double* __restrict__ mu, Dims d, VaFinal va,
+                                                   double C_b, double eps, double sigma) {
     __shared__ double P[4][kPS];
     __shared__ double G[BEND ? 3 : 1][BEND ? kGS : 1];
+    __shared__ double shv[2 * 16];
     const int tz_n = (d.nz + kMuTZ - 1) / kMuTZ;
     const int ty_n = (d.ny + kMuTY - 1) / kMuTY;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -197,19 +275,24 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
             g[e] = p * p * p - p - eps2 * l;
         }
     };
-    // prologue: phi planes i0-2 .. i0+1 (loads all in flight together), g planes i0-1, i0
+    // prologue: phi planes i0-2 .. i0+1 (loads all in flight together), gamma_A from the
+    // volume/area partials, g planes i0-1, i0
     {
+        VaLoads vl;
+        va_load(va, vl);                   // first, so their sums need not wait for phi
         double w0[kPre], w1[kPre], w2[kPre], w3[kPre];
         fetch(i0 - 2, w0);
         fetch(i0 - 1, w1);
         fetch(i0, w2);
         fetch(i0 + 1, w3);
+        va_reduce(va, vl, shv);
         put(P[slot(i0 + 2)], w0);
         put(P[slot(i0 + 3)], w1);
         put(P[slot(i0 + 4)], w2);
         put(P[slot(i0 + 5)], w3);
     }
     __syncthreads();
+    const double gamma = va_final(va, d, shv);
     if (BEND) {
         make_g(i0 - 1);
         make_g(i0);
@@ -223,7 +306,6 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
     const bool out = j < d.ny && k < d.nz;
     const unsigned pbytes = (unsigned)plane * 8u;
     const unsigned oofs = (unsigned)(j * d.nz + k) * 8u;
-    const double gamma = scal[SC_GAMMA];
 #pragma unroll
     for (int s = 0; s < kMuNI; ++s) {
         const int i = i0 + s;
@@ -306,39 +388,6 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
     }
 }
 
-// V = (|Omega| + h^3 sum_w phi)/2, A = 3/(2 sqrt 2) h^3 sum_w(...); then
-// lambda_V = 2 rate_V (V0 - V)/(M |Omega|) and gamma_A = gamma0 + k_A (A - A0)/A0
-// (off when k_A = 0 or A0 = 0). init != 0 also sets V0 = V, A0 = A.
-__global__ __launch_bounds__(1024) void k_finalize_va(const double* __restrict__ partials,
-                                                       int nblocks, Dims d, double* scal,
-                                                       int* istat, int init, double rate_V,
-                                                       double k_A, double gamma0, double mob) {
-    __shared__ double sh[2 * 16];
-    double acc[2] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        acc[0] += partials[0 * kMaxPartialBlocks + b];
-        acc[1] += partials[1 * kMaxPartialBlocks + b];
-    }
-    block_sum<2>(acc, sh);
-    if (threadIdx.x != 0) return;
-    const double h3 = d.h * d.h * d.h;
-    const double vol = (double)d.nx * d.nz * (d.ny - 1) * h3;
-    const double V = 0.5 * (vol + h3 * acc[0]);
-    const double A = 3.0 / (2.0 * 1.4142135623730951) * h3 * acc[1];
-    if (init) {
-        scal[SC_V0] = V;
-        scal[SC_A0] = A;
-    }
-    const double V0 = scal[SC_V0], A0 = scal[SC_A0];
-    scal[SC_V] = V;
-    scal[SC_A] = A;
-    scal[SC_LAMV] = 2.0 * rate_V * (V0 - V) / (mob * vol);
-    double gamma = gamma0;
-    if (k_A != 0.0 && A0 > 0.0) gamma += k_A * (A - A0) / A0;
-    scal[SC_GAMMA] = gamma;
-    if (!isfinite(V) || !isfinite(A)) istat[IS_FLAGS] |= ST_NONFINITE;
-}
-
 // Vorticity source S = (1/eta) D phi x D mu (main text eq. (5b)) at the interior rows, stored
 // so that the transform and the residual of the vorticity solve read it as a plain field.
 __global__ __launch_bounds__(kBlock) void k_source(const double* __restrict__ phi,
@@ -383,14 +432,14 @@ __global__ void k_reset_stats(double* scal, int* istat) {
 }  // namespace
 
 void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                    const double* const psi[3], double* phi_out, const double* scal, double dt,
-                    double mobility, double vz_lo, double vz_hi) {
+                    const double* const psi[3], double* phi_out, double* scal, double dt,
+                    double mobility, double vz_lo, double vz_hi, const PrevCheck& ck) {
     SlabGrid g;
     g.gx = (d.ny * d.nz + kBlock - 1) / kBlock;
     g.ci = kAdvSlab;
     g.gi = (d.nx + kAdvSlab - 1) / kAdvSlab;
     launch_kernel(k_advance_x, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
-                  psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi);
+                  psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
 }
 
 constexpr int kVaMaxBlocks = 1024;   // longer x-slabs per lane, a shorter final sum
@@ -407,21 +456,14 @@ void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double 
                        partials);
 }
 
-void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
-                        double* scal, int* istat, int init, double rate_V, double k_A,
-                        double gamma0, double mobility) {
-    launch_kernel(k_finalize_va, dim3(1), dim3(1024), 0, s, partials, nblocks, d, scal,
-                       istat, init, rate_V, k_A, gamma0, mobility);
-}
-
-void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const double* scal,
+void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const VaFinal& va,
                int model, double C_b, double eps, double sigma) {
     const int nb = ((d.ny + kMuTY - 1) / kMuTY) * ((d.nz + kMuTZ - 1) / kMuTZ) *
                    ((d.nx + kMuNI - 1) / kMuNI);
     if (model == VS_CAHN_HILLIARD)
-        launch_kernel(k_mu_tile<false>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, scal, C_b, eps, sigma);
+        launch_kernel(k_mu_tile<false>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, va, C_b, eps, sigma);
     else
-        launch_kernel(k_mu_tile<true>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, scal, C_b, eps, sigma);
+        launch_kernel(k_mu_tile<true>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, va, C_b, eps, sigma);
 }
 
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof) {

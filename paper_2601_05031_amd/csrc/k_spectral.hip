@@ -19,6 +19,7 @@
 // and likewise for b. The FFT is a Stockham autosort transform in LDS with radix-4/2/3
 // passes (line lengths 2^a 3^b), twiddles from a table exp(-2 pi i m/n).
 #include "fft_reg.h"
+#include "flow_check.h"
 #include "vs_internal.h"
 
 namespace vs {
@@ -1251,51 +1252,12 @@ __global__ __launch_bounds__(1024) void k_check(const double* __restrict__ parti
     if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
 }
 
-// Convergence checks of the two flow solves of a step, each of a single cycle, in one launch:
-// partial slots 0-5 hold the vorticity residual, 6-11 the stream-vector one; the two checks
-// run in a row (vorticity, then stream vector) as two last-cycle checks would.
+// Convergence checks of the two flow solves of a step in one launch (flow_check.h).
 __global__ __launch_bounds__(1024) void k_check_flow(const double* __restrict__ partials,
                                                     int nblocks, double rtol, double* scal,
                                                     int* istat) {
     __shared__ double sh[4 * 16];
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const double* pb = partials + (size_t)(3 * g) * kMaxPartialBlocks + b;
-            a[g] += pb[0] + pb[kMaxPartialBlocks] + pb[2 * kMaxPartialBlocks];
-        }
-    }
-#pragma unroll
-    for (int g = 0; g < 4; ++g) a[g] = wave_sum(a[g]);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int g = 0; g < 4; ++g) sh[g * 16 + wv] = a[g];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int g = 0; g < 4; ++g) {
-        a[g] = 0.0;
-        for (int q = 0; q < nw; ++q) a[g] += sh[g * 16 + q];
-    }
-    for (int sidx = 0; sidx < 2; ++sidx) {
-        const double rr = a[2 * sidx], bb = a[2 * sidx + 1];
-        double rel;
-        if (bb > 0.0)
-            rel = sqrt(rr / bb);
-        else
-            rel = (rr > 0.0) ? INFINITY : 0.0;
-        if (rr != rr || bb != bb) rel = NAN;
-        const int conv = (rel <= rtol) ? 1 : 0;
-        istat[IS_CONV] = conv;
-        istat[IS_CYCLES] += 1;
-        scal[SC_RELRES_LAST] = rel;
-        const double prev = scal[SC_RELRES_MAX];
-        scal[SC_RELRES_MAX] = (rel != rel || rel > prev) ? rel : prev;
-        if (!conv) istat[IS_FLAGS] |= ST_NOCONV;
-        if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
-    }
+    flow_check_block(partials, nblocks, rtol, scal, istat, sh);
 }
 
 // Rows per block of the z kernels: 2 * (kTileElems / nz), i.e. kTileElems / nz complex lines.

@@ -157,6 +157,10 @@ struct vs_state {
     double* phi[2] = {nullptr, nullptr};
     int cur = 0;
     double* mu = nullptr;
+    // the flow check of the last enqueued step is left to the next step's advance kernel
+    // (set only between two steps of one vs_step call or one captured batch; never across
+    // API calls)
+    bool check_pending = false;
     double* om[3] = {};
     double* ps[3] = {};
     void* spec[3] = {};
@@ -286,12 +290,10 @@ void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncom
 void enqueue_va_mu(vs_state* S, const double* phi, int init) {
     const int nb = va_partial_blocks(S->d);
     timed(S, K_VA_PARTIALS, [&] { launch_va_partials(S->stream, S->d, phi, S->p.eps, S->part); });
-    timed(S, K_FINALIZE_VA, [&] {
-        launch_finalize_va(S->stream, S->d, S->part, nb, S->scal, S->istat, init, S->p.rate_V,
-                           S->p.k_A, S->p.gamma0, S->p.mobility);
-    });
+    const VaFinal va{S->part, nb, init, S->p.rate_V, S->p.k_A, S->p.gamma0, S->p.mobility,
+                     S->scal, S->istat};
     timed(S, K_MU, [&] {
-        launch_mu(S->stream, S->d, phi, S->mu, S->scal, S->p.model, S->C_b(), S->p.eps, S->p.sigma);
+        launch_mu(S->stream, S->d, phi, S->mu, va, S->p.model, S->C_b(), S->p.eps, S->p.sigma);
     });
 }
 
@@ -300,7 +302,7 @@ void enqueue_va_mu(vs_state* S, const double* phi, int init) {
 // the transformed right-hand side of the stream-vector problem, so psi needs no forward
 // transform. Both fields are then verified against their own spatial residual; correction
 // cycles (normally never run in FP64) use the generic path.
-void enqueue_flow(vs_state* S, const double* phi) {
+void enqueue_flow(vs_state* S, const double* phi, bool defer_check) {
     const Dims& d = S->d;
     const double rtol = S->p.poisson_rtol;
     const int mc = S->p.poisson_max_cycles;
@@ -342,12 +344,17 @@ void enqueue_flow(vs_state* S, const double* phi) {
         launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec2, S->ps, 3, 0, false, nullptr);
     });
     if (mc == 1) {
-        // one cycle each: both residuals in one pass, then both checks in one launch
+        // one cycle each: both residuals in one pass, then both checks in one launch, or, when
+        // another step follows in the same call, in the first block of its advance kernel
+        // (no correction cycle waits on the result)
         const double* const co[3] = {S->om[0], S->om[1], S->om[2]};
         const double* const cs[3] = {S->src[0], S->src[1], S->src[2]};
         const double* const cp[3] = {S->ps[0], S->ps[1], S->ps[2]};
         timed(S, K_RESID_FLOW, [&] { launch_resid_flow(S->stream, d, co, cs, cp, S->part); });
-        timed(S, K_CHECK, [&] { launch_check_flow(S->stream, d, S->part, rtol, S->scal, S->istat); });
+        if (defer_check)
+            S->check_pending = true;
+        else
+            timed(S, K_CHECK, [&] { launch_check_flow(S->stream, d, S->part, rtol, S->scal, S->istat); });
         return;
     }
     enqueue_verify(S, rv, S->om, 3, rtol, 0, 0, TAG_OMEGA, nullptr);
@@ -364,17 +371,24 @@ void enqueue_flow(vs_state* S, const double* phi) {
     }
 }
 
-void enqueue_step(vs_state* S, double dt) {
+// One time step. more_follow: another step of the same call comes after this one, so its
+// advance kernel can take this step's flow check.
+void enqueue_step(vs_state* S, double dt, bool more_follow) {
     const double* phi = S->phi[S->cur];
     double* out = S->phi[1 - S->cur];
     const double* const psc[3] = {S->ps[0], S->ps[1], S->ps[2]};
+    PrevCheck ck{nullptr, 0, 0.0, nullptr};
+    if (S->check_pending) {
+        ck = PrevCheck{S->part, resid_blocks(S->d), S->p.poisson_rtol, S->istat};
+        S->check_pending = false;
+    }
     timed(S, K_ADVANCE, [&] {
         launch_advance(S->stream, S->d, phi, S->mu, psc, out, S->scal, dt, S->p.mobility,
-                       S->vz_lo, S->vz_hi);
+                       S->vz_lo, S->vz_hi, ck);
     });
     S->cur = 1 - S->cur;
     enqueue_va_mu(S, out, 0);
-    enqueue_flow(S, out);
+    enqueue_flow(S, out, more_follow);
 }
 
 // No-body channel tables on the node rows (the wall data of "Boundary conditions", reading
@@ -571,7 +585,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     }
     INIT_TRY(hipGetLastError());
     enqueue_va_mu(S, S->phi[0], 1);
-    enqueue_flow(S, S->phi[0]);
+    enqueue_flow(S, S->phi[0], false);
     INIT_TRY(hipGetLastError());
     st = collect(S, "vs_init");
     if (st != VS_OK) return bail(st);
@@ -617,7 +631,7 @@ vs_status vs_step(vs_state* S, double dt, int32_t nsteps) {
             return fail(VS_E_UNSTABLE, "dt = %.4g exceeds the forward-Euler bound %.4g", dt, 2.0 / rate);
     }
     timed(S, K_RESET, [&] { launch_reset_stats(S->stream, S->scal, S->istat); });
-    for (int s = 0; s < nsteps; ++s) enqueue_step(S, dt);
+    for (int s = 0; s < nsteps; ++s) enqueue_step(S, dt, s + 1 < nsteps);
     HIP_TRY(hipGetLastError());
     S->step += nsteps;
     return collect(S, "vs_step");
@@ -897,8 +911,8 @@ vs_status batch_capture(vs_batch* B, const double* dt) {
             if ((e = hipStreamWaitEvent(B->streams[k], B->ev[0], 0)) != hipSuccess) return e;
         for (size_t i = 0; i < B->st.size(); ++i) {
             vs_state* S = B->st[i];
-            enqueue_step(S, dt[i]);
-            enqueue_step(S, dt[i]);
+            enqueue_step(S, dt[i], true);
+            enqueue_step(S, dt[i], false);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (int k = 0; k < ns; ++k) {

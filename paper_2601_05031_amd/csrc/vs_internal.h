@@ -120,16 +120,32 @@ static inline SlabGrid slab_grid(int plane, int nx, int maxb) {
 constexpr int kPartialSlots = 12;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
 
 // ---------------------------------------------------------------- explicit stencils
+// The flow check of the previous step (flow_check.h), taken by the first block of the
+// advance kernel when partials is not null.
+struct PrevCheck {
+    const double* partials;
+    int nblocks;
+    double rtol;
+    int* istat;
+};
 void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                    const double* const psi[3], double* phi_out, const double* scal,
-                    double dt, double mobility, double vz_lo, double vz_hi);
+                    const double* const psi[3], double* phi_out, double* scal,
+                    double dt, double mobility, double vz_lo, double vz_hi, const PrevCheck& ck);
 void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
                         double* partials);
 int va_partial_blocks(const Dims& d);
-void launch_finalize_va(hipStream_t s, const Dims& d, const double* partials, int nblocks,
-                        double* scal, int* istat, int init, double rate_V, double k_A,
-                        double gamma0, double mobility);
-void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const double* scal,
+// V, A and the penalty multipliers lambda_V, gamma_A (SM (32), (37), "Lagrange multipliers")
+// from the volume/area block partials, then mu from phi with that gamma_A: every mu block
+// reduces the partials itself (same fixed order in every block) and block 0 writes V, A,
+// lambda_V, gamma_A (and V0, A0 when init) to scal.
+struct VaFinal {
+    const double* partials;
+    int nblocks, init;
+    double rate_V, k_A, gamma0, mobility;
+    double* scal;
+    int* istat;
+};
+void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const VaFinal& va,
                int model, double C_b, double eps, double sigma);
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof);
 // S = (1/eta) D phi x D mu on the interior rows (main text eq. (5b)), into src[0..2].
