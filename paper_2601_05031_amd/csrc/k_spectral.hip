@@ -537,41 +537,47 @@ __device__ __forceinline__ void seg_solve(double (&x)[LMAX], const SegCoef<LMAX>
 #pragma unroll
     for (int u = LMAX - 1; u >= 0; --u)
         if (u < Lm) p = x[u] - c[u] * p;
-    // reduced system: forward sweep in every lane, keeping this lane's coefficients
-    double a = 0.0, b = 0.0, mph = 0.0, mch = 0.0, mal = 0.0, mbe = 0.0;
+    // reduced system. Every segment's p and q are gathered first (independent shuffles, in
+    // flight together); every lane then runs the forward sweep and the back substitution of
+    // the whole reduced system itself, keeping phi and chi of every segment, so no value has
+    // to travel between lanes after the gather.
+    double P[S], Q[S];
 #pragma unroll
     for (int kk = 0; kk < S; ++kk) {
-        const double pk = __shfl(p, kk, S);
-        const double qk = __shfl(q, kk, S);
+        P[kk] = __shfl(p, kk, S);
+        Q[kk] = __shfl(q, kk, S);
+    }
+    double a = 0.0, b = 0.0, alp = 0.0, bep = 0.0;
+    double PH[S], CH[S];
+#pragma unroll
+    for (int kk = 0; kk < S; ++kk) {
         const bool lng = nlong == 0 || kk < nlong;   // nlong = 0: all segments have Lm rows
         const double g11 = lng ? cf.g11l : cf.g11s;
         const double g1l = lng ? cf.g1ll : cf.g1ls;
         const double rden = 1.0 / (1.0 - g11 * b);
-        const double ph = (pk - g11 * a) * rden;
+        const double ph = (P[kk] - g11 * a) * rden;
         const double ch = g1l * rden;
-        const double an = qk - g1l * a + g1l * b * ph;
+        const double an = Q[kk] - g1l * a + g1l * b * ph;
         const double bn = g11 + g1l * b * ch;
-        if (kk == k) {
-            mph = ph;
-            mch = ch;
-            mal = an;
-            mbe = bn;
+        PH[kk] = ph;
+        CH[kk] = ch;
+        if (kk == k - 1) {   // alpha, beta of the segment before this lane's
+            alp = an;
+            bep = bn;
         }
         a = an;
         b = bn;
     }
-    // back sweep down the lanes: F_k = phi_k - chi_k F_{k+1}
-    double Fk = mph;
+    // back substitution F_kk = phi_kk - chi_kk F_{kk+1} (F_S = 0); this lane keeps F_k, F_{k+1}
+    double F = 0.0, Fk = 0.0, Fnext = 0.0;
 #pragma unroll
-    for (int it = 1; it < S; ++it) {
-        const double up = __shfl(Fk, k + 1 < S ? k + 1 : k, S);
-        Fk = mph - mch * (k + 1 < S ? up : 0.0);
+    for (int kk = S - 1; kk >= 0; --kk) {
+        if (kk == k) Fnext = F;
+        F = PH[kk] - CH[kk] * F;
+        if (kk == k) Fk = F;
     }
-    const double fup = __shfl(Fk, k + 1 < S ? k + 1 : k, S);
-    const double Fnext = k + 1 < S ? fup : 0.0;
-    const double Ek = mal - mbe * Fnext;
-    const double eup = __shfl(Ek, k > 0 ? k - 1 : k, S);
-    const double Eprev = k > 0 ? eup : 0.0;
+    // E_{k-1} = alpha_{k-1} - beta_{k-1} F_k
+    const double Eprev = k > 0 ? alp - bep * Fk : 0.0;
     // finish the segment bottom up
     double xn = 0.0, pc = 0.0;
 #pragma unroll
