@@ -603,6 +603,7 @@ __device__ __forceinline__ void seg_solve(double (&x)[LMAX], const SegCoef<LMAX>
 template <int S>
 struct SegLane {
     int p, q, k, Lm, nlong;
+    int a;          // first interior row (0-based) of the lane's segment
     bool act, shortl;
     unsigned cls, ncls;
     unsigned off;   // offset of (p, first row of the segment, q); grids stay below 2^31 nodes
@@ -623,6 +624,7 @@ __device__ __forceinline__ SegLane<S> seg_lane(const Dims& d) {
     sl.Lm = base + (sl.nlong > 0);
     sl.shortl = sl.nlong > 0 && sl.k >= sl.nlong;
     const int a = sl.k * base + min(sl.k, sl.nlong);
+    sl.a = a;
     const int pc = min(sl.p, d.nx - sl.p);
     const int qc = min(sl.q, d.nz - sl.q);
     sl.ncls = (unsigned)((d.nx / 2 + 1) * (d.nz / 2 + 1));
@@ -683,6 +685,38 @@ __global__ __launch_bounds__(256) void k_tridiag_seg(Dims d, const double* __res
     seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
 }
 
+// Store of a block's solved columns through LDS: the lanes put their segment rows into a
+// (row, mode) tile, then the block writes it row by row, so a wave stores whole runs of
+// consecutive modes (full cache lines) instead of 64-byte pieces of eight rows. A short
+// segment's phantom row is not put (it would land on the next segment's first row). The
+// tile holds rows x modes = M x (256 / S) values; every thread of the block calls this.
+template <int S, int LMAX>
+constexpr bool seg_tiled() {
+    return LMAX * (256 + S) * (int)sizeof(double) <= 48 * 1024;
+}
+template <int S, int LMAX, class ST>
+__device__ __forceinline__ void seg_store_tile(const double (&x)[LMAX], ST* base, double* tile,
+                                               const SegLane<S>& sl, const Dims& d) {
+    constexpr int NM = 256 / S;   // modes per block
+    constexpr int TS = NM + 1;    // padded tile row
+    const int m = (int)threadIdx.x / S;
+#pragma unroll
+    for (int u = 0; u < LMAX; ++u)
+        if (u < sl.Lm && (u < sl.Lm - 1 || !sl.shortl)) tile[(sl.a + u) * TS + m] = x[u];
+    __syncthreads();
+    const int nmodes = d.nx * d.nz;
+    const int mode0 = (int)blockIdx.x * NM;
+    for (int e = threadIdx.x; e < d.M * NM; e += 256) {
+        const int row = e / NM, mm = e - (e / NM) * NM;
+        const int mode = mode0 + mm;
+        if (mode < nmodes) {
+            const int pp = mode / d.nz, qq = mode - (mode / d.nz) * d.nz;
+            st(base + ((size_t)(pp * d.ny + 1 + row) * d.nz + qq), tile[row * TS + mm]);
+        }
+    }
+    __syncthreads();   // the tile is free again
+}
+
 // Segmented vorticity + stream-vector pair: the vorticity modes U_w (f = scale * B) are solved
 // and stored in spec, then the stream-vector problem lap psi = -w is solved from them in
 // registers, f_j = -h^2 U_w(j) - [p = q = 0]([j = 1] psi_lo + [j = M] psi_hi), into spec2.
@@ -698,6 +732,8 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
         sl.shortl = NLF > 0 && sl.k >= NLF;
     }
     const int c3 = blockIdx.y;
+    constexpr bool kTile = seg_tiled<S, LMAX>();
+    __shared__ double tile[kTile ? LMAX * (256 + S) : 1];
     SegCoef<LMAX> cf;
     seg_coef<LMAX>(cf, tri, sl.cls, sl.ncls, d.M, sl.Lm);
     ST* col = spec.p[c3];
@@ -718,7 +754,10 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
         }
     }
     seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
-    seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
+    if (kTile)
+        seg_store_tile<S, LMAX, ST>(x, col, tile, sl, d);
+    else
+        seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
     const double h2 = d.h * d.h;
     const double wlo = c3 == 0 ? plo.x : (c3 == 1 ? plo.y : plo.z);
     const double whi = c3 == 0 ? phi_.x : (c3 == 1 ? phi_.y : phi_.z);
@@ -730,7 +769,10 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
         x[u] = f;
     }
     seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
-    seg_store<S, LMAX, ST>(x, spec2.p[c3], N, d.nz, sl);
+    if (kTile)
+        seg_store_tile<S, LMAX, ST>(x, spec2.p[c3], tile, sl, d);
+    else
+        seg_store<S, LMAX, ST>(x, spec2.p[c3], N, d.nz, sl);
 }
 
 // dht_z_out: Hartley along z of the solved modes, then u = result (add = 0) or u += result.
