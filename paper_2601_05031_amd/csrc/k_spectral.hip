@@ -1176,6 +1176,10 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
 // streams omega_c, S_c and psi_c: omega_c is read once for both problems (its stencil for
 // eq. (5b), its centre as the right-hand side -omega_c of eq. (5c)). Sums are those of
 // resid_norm, term for term.
+// ZS (n_z a multiple of 64, so a wave covers 64 consecutive z of one row): the z neighbours
+// come from the neighbouring lanes' centre values by shuffles, and the two row-edge values
+// from one wave-uniform load each, instead of two full loads per field and plane.
+template <bool ZS>
 __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 src, CPtr3 ps,
                                                       SlabGrid sg,
                                                       double* __restrict__ partials) {
@@ -1198,6 +1202,22 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
         const int off = j * d.nz + k;
         const int kp = (k + 1 == d.nz) ? 0 : k + 1;
         const int km = (k == 0) ? d.nz - 1 : k - 1;
+        const int ln = threadIdx.x & 63;
+        const int k0 = k - ln;                               // first z of the wave (ZS)
+        const int kpe = (k0 + 64 == d.nz) ? 0 : k0 + 64;     // z after the wave's last
+        const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;       // z before the wave's first
+        // z neighbours of u at plane row rb, c its centre value
+        auto zpair = [&](const double* u, int rb, double cval, double& zp, double& zm) {
+            if (ZS) {
+                const double up = __shfl_down(cval, 1, 64), dn = __shfl_up(cval, 1, 64);
+                const double ep = u[rb + kpe], em = u[rb + kme];   // one line each
+                zp = ln == 63 ? ep : up;
+                zm = ln == 0 ? em : dn;
+            } else {
+                zp = u[rb + kp];
+                zm = u[rb + km];
+            }
+        };
         const int i0 = bi * sg.ci;
         const int i1 = min(d.nx, i0 + sg.ci);
         const int im0 = (i0 == 0) ? d.nx - 1 : i0 - 1;
@@ -1214,8 +1234,9 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
                 const double b = sc[c0];
                 const double ylo = wc[c0 - d.nz], yhi = wc[c0 + d.nz];
                 const double w = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
-                const double lap = (wp + wm + ylo + yhi + wc[rb + kp] + wc[rb + km] - 6.0 * wx) *
-                                   d.inv_h2;
+                double zp, zm;
+                zpair(wc, rb, wx, zp, zm);
+                const double lap = (wp + wm + ylo + yhi + zp + zm - 6.0 * wx) * d.inv_h2;
                 const double r = b - lap;
                 const double bt = b - w * d.inv_h2;
                 a[0] += r * r;
@@ -1225,8 +1246,9 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
                 const double b = -wx;
                 const double ylo = pc[c0 - d.nz], yhi = pc[c0 + d.nz];
                 const double w = (j == 1 ? ylo : 0.0) + (j == d.M ? yhi : 0.0);
-                const double lap = (pp + pm + ylo + yhi + pc[rb + kp] + pc[rb + km] - 6.0 * px) *
-                                   d.inv_h2;
+                double zp, zm;
+                zpair(pc, rb, px, zp, zm);
+                const double lap = (pp + pm + ylo + yhi + zp + zm - 6.0 * px) * d.inv_h2;
                 const double r = b - lap;
                 const double bt = b - w * d.inv_h2;
                 a[2] += r * r;
@@ -1551,8 +1573,13 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
                        const double* const src[3], const double* const ps[3], double* partials) {
     const CPtr3 o{{om[0], om[1], om[2]}}, f{{src[0], src[1], src[2]}}, p{{ps[0], ps[1], ps[2]}};
     const SlabGrid g = resid_grid(d);
-    launch_kernel(k_resid_flow, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
-                  partials);
+    // a whole number of waves per row lets the z neighbours come from shuffles
+    if (d.nz % 64 == 0)
+        launch_kernel(k_resid_flow<true>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p,
+                      g, partials);
+    else
+        launch_kernel(k_resid_flow<false>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p,
+                      g, partials);
 }
 
 void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,
