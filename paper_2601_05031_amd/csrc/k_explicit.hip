@@ -10,41 +10,12 @@ namespace vs {
 
 namespace {
 
-// phi_out = phi + dt [ M (L_h mu + lambda_V) - v . D phi ], v = curl psi inside, wall speed on
-// the walls. Reads phi, mu, psi_x, psi_y, psi_z once (neighbours via cache), writes phi_out.
-__global__ __launch_bounds__(kBlock) void k_advance(
-    const double* __restrict__ phi, const double* __restrict__ mu,
-    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
-    double* __restrict__ out, Dims d, const double* __restrict__ scal, double dt, double mob,
-    double vz_lo, double vz_hi) {
-    int i, j, k;
-    bool ok;
-    plane_index(d, i, j, k, ok);
-    if (!ok) return;
-    const Nbr n = neighbours_mirror(d, i, j, k);
-    const double lam = scal[SC_LAMV];
-    const double lmu = lap7(mu, n, d.inv_h2);
-    const double dx = (phi[n.xp] - phi[n.xm]) * d.inv_2h;
-    const double dy = (phi[n.yp] - phi[n.ym]) * d.inv_2h;
-    const double dz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
-    double vx = 0.0, vy = 0.0, vz;
-    if (j == 0) {
-        vz = vz_lo;
-    } else if (j == d.ny - 1) {
-        vz = vz_hi;
-    } else {
-        // interior rows: the y neighbours are true rows (the mirror never applies here)
-        vx = ((pz[n.yp] - pz[n.ym]) - (py[n.zp] - py[n.zm])) * d.inv_2h;
-        vy = ((px[n.zp] - px[n.zm]) - (pz[n.xp] - pz[n.xm])) * d.inv_2h;
-        vz = ((py[n.xp] - py[n.xm]) - (px[n.yp] - px[n.ym])) * d.inv_2h;
-    }
-    out[n.c] = phi[n.c] + dt * (mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
-}
-
-// k_advance marching along x: each lane owns one (j, k) and walks kAdvSlab consecutive
-// x-planes, keeping phi, mu, psi_y and psi_z of the planes i-1, i, i+1 in registers, so the
-// x-neighbours are not re-read; the y and z neighbours come through the cache. Same
-// arithmetic, in the same order, as the plain kernel.
+// phi_out = phi + dt [ M (L_h mu + lambda_V) - v . D phi ], v = curl psi (eq. (3)) on the
+// interior rows and the wall speed on the walls; D is the central difference, L_h the
+// 7-point Laplacian with mirror ghosts in y (phi[-1] = phi[1], phi[ny] = phi[ny-2]).
+// Marching along x: each lane owns one (j, k) and walks kAdvSlab consecutive x-planes,
+// keeping phi, mu, psi_y and psi_z of the planes i-1, i, i+1 in registers, so the
+// x-neighbours are not re-read; the y and z neighbours come through the cache.
 constexpr int kAdvSlab = 4;
 
 __global__ __launch_bounds__(kBlock) void k_advance_x(

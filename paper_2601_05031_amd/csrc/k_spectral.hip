@@ -4,20 +4,25 @@
 // The periodic second differences in x and z are diagonalised by the discrete Hartley
 // transform H (H_pk = cos(2 pi p k/n) + sin(2 pi p k/n)): each column of H is an eigenvector
 // with eigenvalue (2 cos(2 pi p/n) - 2)/h^2, and H H = n I. So L_h u = b becomes, for every
-// Hartley mode (p, q), one symmetric tridiagonal system in y, solved by the Thomas
-// algorithm with precomputed pivots. Everything stays real: no complex spectrum is stored.
+// Hartley mode (p, q), one symmetric tridiagonal system in y with precomputed pivots, solved
+// in register segments (or by a two-ended elimination for very short or tall columns).
+// Everything stays real: no complex spectrum is stored.
 //
-// Pass structure for one vector solve (three components, each pass one launch):
-//   rhs_dht_z : b~ (or the residual b - L_h u) on the interior rows, Hartley along z
-//   dht_x     : Hartley along x, in place
-//   tridiag_y : Thomas along y per mode, scaled by h^2/(nx nz), in place
-//   dht_x     : Hartley along x, in place
-//   dht_z_out : Hartley along z, write (or add to) u
-//   resid_norm, check : ||b - L_h u||^2, ||b~||^2, relative residual, convergence flag
+// Pass structure of the two flow solves of a step (each pass one launch):
+//   z transform of S : Hartley along z of the vorticity source (the dht_z_out kernel)
+//   dht_x            : Hartley along x, in place
+//   tridiag_pair     : vorticity modes (walls in mode (0, 0)), then the stream-vector modes
+//                      from them, scaled by h^2/(nx nz), into two spectral buffers
+//   dht_x, dht_z_out : Hartley along x, then z, for each of the two fields
+//   resid_flow, check: ||b - L_h u||^2 and ||b~||^2 of both problems, relative residuals
+// The general form of one vector solve (vs_poisson_solve, refinement cycles) starts with
+// rhs_dht_z (b~, or the residual b - L_h u, on the interior rows, Hartley along z) and runs
+// dht_x, tridiag_y, dht_x, dht_z_out, resid_norm and check for each cycle.
 // A Hartley transform of a real line is computed by a complex FFT of two lines packed as
 // (line a) + i (line b), then H_a(p) = Re A_p - Im A_p with A_p = (Z_p + conj Z_{n-p})/2,
-// and likewise for b. The FFT is a Stockham autosort transform in LDS with radix-4/2/3
-// passes (line lengths 2^a 3^b), twiddles from a table exp(-2 pi i m/n).
+// and likewise for b. Line lengths n = B A (B in {8, 16}, A in {3, 4, 6, 8, 12, 16}) use a
+// two-pass register FFT; other 2^a 3^b lengths a Stockham transform in LDS with radix-4/2/3
+// passes. Twiddles come from a table exp(-2 pi i m/n).
 #include "fft_reg.h"
 #include "flow_check.h"
 #include "vs_internal.h"
