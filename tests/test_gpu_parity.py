@@ -305,6 +305,38 @@ def test_nan_injection_reports_nonfinite():
     s.close()
 
 
+def test_nan_injection_reports_nonfinite_over_several_steps():
+    """Several steps in one call: the flow checks of all but the last step run inside the
+    next step's advance kernel; a NaN still surfaces as NONFINITE at the end of the call."""
+    w = workload("vesicle32")
+    say("case nan injection, 3 steps in one call")
+    s = P.solver_for(w, max_cycles=1)
+    blob = bytearray(s.save())
+    hdr = len(blob) - 8 * 8 * w.grid.N
+    arr = np.frombuffer(blob, dtype=np.float64, count=w.grid.N, offset=hdr).copy()
+    arr[777] = np.nan
+    blob[hdr:hdr + 8 * w.grid.N] = arr.tobytes()
+    s.load(bytes(blob))
+    with pytest.raises(V.VsError) as e:
+        s.step(w.dt, 3)
+    assert e.value.code == V.VS_E_NONFINITE
+    s.close()
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 5])
+def test_every_flow_check_runs_once_per_step(nsteps):
+    """With one cycle per solve each step runs two checks (vorticity, stream vector), whether
+    in the standalone check kernel or in the next step's advance kernel."""
+    w = workload("vesicle32", seed=5)
+    say(f"case check count nsteps={nsteps}")
+    s = P.solver_for(w, max_cycles=1)
+    s.step(w.dt, nsteps)
+    sc = s.scalars()
+    s.close()
+    assert sc["cycles"] == 2 * nsteps
+    assert 0.0 < sc["relres"] <= w.rtol
+
+
 def test_phi_sphere_helper_shapes():
     g = GridSpec(8, 8, 8)
     assert phi_sphere(g, 2.0, 1.0).shape == (8, 8, 8)
