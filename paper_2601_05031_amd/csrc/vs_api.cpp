@@ -39,12 +39,12 @@ vs_status fail(vs_status code, const char* fmt, ...) {
 
 // Kernel classes for the event timer.
 enum KClass {
-    K_ADVANCE, K_VA_PARTIALS, K_FINALIZE_VA, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
+    K_ADVANCE, K_VA_PARTIALS, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
     K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
-    "advance", "va_partials", "finalize_va", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
+    "advance", "va_partials", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
     "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
     "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
     "resid_norm_flow"};
