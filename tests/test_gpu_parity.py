@@ -191,13 +191,16 @@ def test_step_parity_tall_channels(ny):
     compare(got, ref_fields(ref), label=f"ny={ny}")
 
 
-def test_step_parity_vesicle128_full_size():
-    """The 128^3 prolate vesicle at full size, kappa = 1, first 3 steps, in the launch
-    configuration the benchmark times (one verified cycle per Poisson solve, the combined
-    residual pass). The oracle takes about two seconds per step."""
-    w = workload("vesicle128", nsteps=3, max_cycles=1)
-    got, sc, ref = run_both(w, 3)
-    compare(got, ref_fields(ref), label="128^3 3 steps")
+@pytest.mark.parametrize("kappa,nsteps", [(1.0, 10), (0.5, 3), (2.0, 3)])
+def test_step_parity_vesicle128_full_size(kappa, nsteps):
+    """The 128^3 prolate vesicle at full size, first steps of each kappa of the benchmark,
+    in the launch configuration the benchmark times (one verified cycle per Poisson solve,
+    the combined residual pass, the checks of all but the last step inside the next advance,
+    all steps in one call). The oracle takes about two seconds per step."""
+    w = workload("vesicle128", nsteps=nsteps, max_cycles=1, kappa=kappa)
+    got, sc, ref = run_both(w, nsteps)
+    compare(got, ref_fields(ref), label=f"128^3 kappa={kappa} {nsteps} steps")
+    assert sc["cycles"] == 2 * nsteps and sc["relres"] <= w.rtol
 
 
 def test_no_body_channel_is_exact():
