@@ -194,6 +194,75 @@ def batched_run(P, torch, steps: int, nstreams: int) -> dict:
     return out
 
 
+def adjoint_run(P, torch, nsteps: int, checkpoint_every: int = 10) -> dict:
+    """The 96^3 differentiation workload: a rollout gradient (forward with vs_save_state
+    checkpoints, then in reverse: reload, recompute to the level, vs_grad_step) of
+    L = ||phi^n - target||^2, target from kappa = 1.5 and 1.2 times the wall speed; and
+    the reverse step alone, timed on a fixed state."""
+    from workloads import workload
+
+    w = workload("adjoint96")
+    N = w.grid.N
+    st = P.solver_for(w.with_(kappa=1.5, u0=1.2 * w.u0))
+    st.step(w.dt, nsteps)
+    target = st.field("phi").clone()
+    st.close()
+    s = P.solver_for(w)
+    P.rollout_gradient(s, w.dt, 2, target, checkpoint_every)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(w.dt, nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s2 = P.solver_for(w)
+    t0 = time.perf_counter()
+    L, kb, sb, _ = P.rollout_gradient(s2, w.dt, nsteps, target, checkpoint_every)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    a = torch.randn(w.grid.shape, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    s2.grad_step(w.dt, a, b)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s2.grad_step(w.dt, a, b)
+    torch.cuda.synchronize()
+    t_rev = (time.perf_counter() - t0) / reps
+    s.close()
+    s2.close()
+    ce = max(1, checkpoint_every)
+    recompute = sum(n - (n // ce) * ce for n in range(nsteps))
+    out = {"workload": "adjoint96", "grid": list(w.grid.shape), "steps": nsteps,
+           "checkpoint_every": ce, "forward_ms_per_step": 1e3 * t_fwd / nsteps,
+           "reverse_ms_per_step": 1e3 * t_rev,
+           "reverse_cell_updates_per_s": N / t_rev,
+           "rollout_gradient_s": t_grad,
+           "rollout_forward_steps": nsteps + recompute, "rollout_reverse_steps": nsteps,
+           "loss": L, "dL_dkappa": kb, "dL_dscale": sb}
+    print(f"bench: adjoint96 forward {1e3 * t_fwd / nsteps:.3f} ms/step, reverse "
+          f"{1e3 * t_rev:.3f} ms/step, rollout gradient of {nsteps} steps {t_grad:.2f} s",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def diagnostics_run(P, torch, base) -> dict:
+    """vs_diagnostics on the 128^3 vesicle after 20 steps: the shear-stress field and the
+    reductions, timed over 10 calls."""
+    s = P.solver_for(base)
+    s.step(base.dt, 20)
+    sig = torch.empty(base.grid.shape, dtype=torch.float64, device="cuda")
+    d = s.diagnostics(sig)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.diagnostics(sig)
+    t = (time.perf_counter() - t0) / reps
+    s.close()
+    return {"workload": base.name, "ms_per_call": 1e3 * t, "values_after_20_steps": d}
+
+
 def copy_ceiling(torch) -> float:
     """Device-to-device copy of a 1 GiB FP64 buffer (read + write bytes per second, GB/s): the
     practical streaming ceiling next to the nominal 8 TB/s."""
@@ -232,6 +301,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="steps of the 64-instance batch (0 = skip)")
     ap.add_argument("--batch-streams", type=int, default=8)
+    ap.add_argument("--adjoint-steps", type=int, default=50,
+                    help="steps of the 96^3 rollout gradient (0 = skip)")
+    ap.add_argument("--no-diagnostics", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -346,6 +418,14 @@ def main():
     if args.batch_steps > 0:
         batched = batched_run(P, torch, args.batch_steps + (args.batch_steps & 1), args.batch_streams)
 
+    adjoint = None
+    if args.adjoint_steps > 0:
+        adjoint = adjoint_run(P, torch, args.adjoint_steps)
+
+    diagnostics = None
+    if not args.no_diagnostics:
+        diagnostics = diagnostics_run(P, torch, base)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
@@ -381,6 +461,8 @@ def main():
         "instances_as_one_graph": headline_graph,
         "fp64_vs_fp32_refined": precision,
         "batched": batched,
+        "adjoint": adjoint,
+        "diagnostics": diagnostics,
     }
     print(json.dumps(out), flush=True)
 
