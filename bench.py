@@ -198,10 +198,11 @@ def adjoint_run(P, torch, nsteps: int, checkpoint_every: int = 10) -> dict:
     """The 96^3 differentiation workload: a rollout gradient (forward with vs_save_state
     checkpoints, then in reverse: reload, recompute to the level, vs_grad_step) of
     L = ||phi^n - target||^2, target from kappa = 1.5 and 1.2 times the wall speed; and
-    the reverse step alone, timed on a fixed state."""
+    the reverse step alone, timed on a fixed state. One verified cycle per Poisson solve, the
+    launch configuration of the headline."""
     from workloads import workload
 
-    w = workload("adjoint96")
+    w = workload("adjoint96", max_cycles=1)   # one verified cycle per solve, as the headline
     N = w.grid.N
     st = P.solver_for(w.with_(kappa=1.5, u0=1.2 * w.u0))
     st.step(w.dt, nsteps)
@@ -234,6 +235,7 @@ def adjoint_run(P, torch, nsteps: int, checkpoint_every: int = 10) -> dict:
     ce = max(1, checkpoint_every)
     recompute = sum(n - (n // ce) * ce for n in range(nsteps))
     out = {"workload": "adjoint96", "grid": list(w.grid.shape), "steps": nsteps,
+           "poisson_max_cycles": w.max_cycles,
            "checkpoint_every": ce, "forward_ms_per_step": 1e3 * t_fwd / nsteps,
            "reverse_ms_per_step": 1e3 * t_rev,
            "reverse_cell_updates_per_s": N / t_rev,

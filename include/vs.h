@@ -215,10 +215,13 @@ vs_status vs_field_offset(const vs_state* state, int32_t field, size_t* byte_off
 /* Copy the VS_NSCALARS global scalars (slots VS_S_*) to host memory `out`. Synchronises. */
 vs_status vs_get_scalars(vs_state* state, double out[VS_NSCALARS]);
 
-/* Checkpoint: write phi, mu, omega, psi, the scalars and the step count into host memory.
- * With blob == NULL only *bytes is set to the size needed. Synchronises. */
+/* Checkpoint: write phi, mu, omega, psi, the scalars, the wall speeds and the step count into
+ * blob, which may be host memory or device memory (device allocations are detected; then the
+ * fields are copied device to device, so a rollout can keep its checkpoints in HBM). With
+ * blob == NULL only *bytes is set to the size needed. Synchronises. */
 vs_status vs_save_state(vs_state* state, void* blob, size_t* bytes);
-/* Restore a checkpoint written by vs_save_state for the same grid. Synchronises. */
+/* Restore a checkpoint written by vs_save_state for the same grid and wall kind, from host or
+ * device memory. Synchronises. */
 vs_status vs_load_state(vs_state* state, const void* blob, size_t bytes);
 
 /* Per-kernel timing with HIP events on the state's stream, for measurement tools:

@@ -780,6 +780,17 @@ struct BlobHeader {
     double u0, u1;            // wall speeds
     double scal[SC_NSCAL];
 };
+
+// Whether p points into device memory (a checkpoint may live on the device: then every copy
+// stays on the device). Host memory the runtime does not know reports an error: cleared.
+bool device_blob(const void* p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
 }  // namespace
 
 vs_status vs_save_state(vs_state* S, void* blob, size_t* bytes) {
@@ -793,6 +804,7 @@ vs_status vs_save_state(vs_state* S, void* blob, size_t* bytes) {
     }
     if (*bytes < need) return fail(VS_E_ARG, "blob has %zu bytes, needs %zu", *bytes, need);
     HIP_TRY(hipStreamSynchronize(S->stream));
+    const bool dev = device_blob(blob);
     BlobHeader hd{};
     std::memcpy(hd.magic, "VSSTATE2", 8);
     hd.nx = S->g.nx;
@@ -803,10 +815,16 @@ vs_status vs_save_state(vs_state* S, void* blob, size_t* bytes) {
     hd.u0 = S->w.u0;
     hd.u1 = S->w.u1;
     HIP_TRY(hipMemcpy(hd.scal, S->scal, sizeof hd.scal, hipMemcpyDeviceToHost));
-    std::memcpy(blob, &hd, sizeof hd);
+    if (dev)
+        HIP_TRY(hipMemcpy(blob, &hd, sizeof hd, hipMemcpyHostToDevice));
+    else
+        std::memcpy(blob, &hd, sizeof hd);
     double* dst = (double*)((char*)blob + sizeof hd);
     const double* src[8] = {S->phi[S->cur], S->mu, S->om[0], S->om[1], S->om[2], S->ps[0], S->ps[1], S->ps[2]};
-    for (int q = 0; q < 8; ++q) HIP_TRY(hipMemcpy(dst + q * N, src[q], N * sizeof(double), hipMemcpyDeviceToHost));
+    for (int q = 0; q < 8; ++q)
+        HIP_TRY(hipMemcpyAsync(dst + q * N, src[q], N * sizeof(double),
+                               dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
     *bytes = need;
     return VS_OK;
 }
@@ -817,15 +835,22 @@ vs_status vs_load_state(vs_state* S, const void* blob, size_t bytes) {
     const size_t N = (size_t)S->g.nx * S->g.ny * S->g.nz;
     const size_t need = sizeof(BlobHeader) + 8 * N * sizeof(double);
     if (bytes < need) return fail(VS_E_ARG, "blob has %zu bytes, needs %zu", bytes, need);
+    const bool dev = device_blob(blob);
     BlobHeader hd;
-    std::memcpy(&hd, blob, sizeof hd);
+    if (dev)
+        HIP_TRY(hipMemcpy(&hd, blob, sizeof hd, hipMemcpyDeviceToHost));
+    else
+        std::memcpy(&hd, blob, sizeof hd);
     if (std::memcmp(hd.magic, "VSSTATE2", 8) != 0) return fail(VS_E_ARG, "not a vs_save_state blob");
     if (hd.nx != S->g.nx || hd.ny != S->g.ny || hd.nz != S->g.nz) return fail(VS_E_ARG, "grid mismatch");
     if (hd.kind != S->w.kind) return fail(VS_E_ARG, "wall kind mismatch");
     HIP_TRY(hipStreamSynchronize(S->stream));
     const double* src = (const double*)((const char*)blob + sizeof hd);
     double* dst[8] = {S->phi[S->cur], S->mu, S->om[0], S->om[1], S->om[2], S->ps[0], S->ps[1], S->ps[2]};
-    for (int q = 0; q < 8; ++q) HIP_TRY(hipMemcpy(dst[q], src + q * N, N * sizeof(double), hipMemcpyHostToDevice));
+    for (int q = 0; q < 8; ++q)
+        HIP_TRY(hipMemcpyAsync(dst[q], src + q * N, N * sizeof(double),
+                               dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
     HIP_TRY(hipMemcpy(S->scal, hd.scal, sizeof hd.scal, hipMemcpyHostToDevice));
     S->step = hd.step;
     S->gamma_host = hd.scal[SC_GAMMA];

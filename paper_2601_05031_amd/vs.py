@@ -222,15 +222,28 @@ class Solver:
         return {"obs_omega": out[0], "obs_psi": out[1], "energy": out[2], "sigma_t_max": out[3],
                 "gauge_defect": out[4], "speed_max": out[5]}
 
-    def save(self) -> bytes:
+    def save(self, device: bool = False):
+        """Checkpoint as bytes (host), or as a uint8 tensor on the solver's device."""
         n = ctypes.c_size_t(0)
         _check(lib().vs_save_state(self._st, None, ctypes.byref(n)), "vs_save_state")
+        if device:
+            blob = self.torch.empty(n.value, dtype=self.torch.uint8, device=self._ws.device)
+            _check(lib().vs_save_state(self._st, ctypes.c_void_p(blob.data_ptr()), ctypes.byref(n)),
+                   "vs_save_state")
+            return blob
         buf = ctypes.create_string_buffer(n.value)
         _check(lib().vs_save_state(self._st, buf, ctypes.byref(n)), "vs_save_state")
         return buf.raw
 
-    def load(self, blob: bytes):
-        _check(lib().vs_load_state(self._st, blob, len(blob)), "vs_load_state")
+    def load(self, blob):
+        """Restore a checkpoint from save(): bytes, or a device uint8 tensor."""
+        if isinstance(blob, (bytes, bytearray)):
+            _check(lib().vs_load_state(self._st, bytes(blob), len(blob)), "vs_load_state")
+            return
+        if blob.dtype != self.torch.uint8 or not blob.is_contiguous():
+            raise ValueError("a device checkpoint is a contiguous uint8 tensor from save(device=True)")
+        _check(lib().vs_load_state(self._st, ctypes.c_void_p(blob.data_ptr()), blob.numel()),
+               "vs_load_state")
 
     # ---------------------------------------------------------------- measurement
     def profile(self, on: bool):
@@ -300,11 +313,11 @@ def rollout_gradient(solver: "Solver", dt: float, nsteps: int, target, checkpoin
     its vs_grad_step. The solver is left at the initial state."""
     torch = solver.torch
     ce = max(1, int(checkpoint_every))
-    ckpt = {0: solver.save()}
+    ckpt = {0: solver.save(device=True)}   # checkpoints stay in HBM
     for n in range(nsteps):
         solver.step(dt, 1)
         if (n + 1) % ce == 0:
-            ckpt[n + 1] = solver.save()
+            ckpt[n + 1] = solver.save(device=True)
     r = solver.field("phi") - target
     loss = float((r * r).sum())
     a = (2.0 * r).contiguous()

@@ -265,6 +265,33 @@ def test_repeat_runs_bitwise_equal_and_checkpoint_resume():
         s.close()
 
 
+def test_device_checkpoint_equals_host_checkpoint():
+    """A checkpoint kept in device memory restores the same state as one in host memory,
+    into the same or another solver, and the two blobs hold the same bytes."""
+    w = workload("vesicle32", seed=4)
+    say("case device checkpoint vesicle32")
+    a = P.solver_for(w, max_cycles=1)
+    a.step(w.dt, 2)
+    hb = a.save()
+    db = a.save(device=True)
+    assert db.is_cuda and db.numel() == len(hb)
+    assert bytes(db.cpu().numpy().tobytes()) == hb
+    a.step(w.dt, 2)
+    ref = a.fields()
+    b = P.solver_for(w.with_(seed=6), max_cycles=1)
+    b.load(db)
+    b.step(w.dt, 2)
+    a.load(hb)
+    a.step(w.dt, 2)
+    fa, fb = a.fields(), b.fields()
+    for k in FIELD_NAMES:
+        assert np.array_equal(fa[k], ref[k]), k
+        assert np.array_equal(fb[k], ref[k]), k
+    assert b.scalars()["step"] == 4
+    a.close()
+    b.close()
+
+
 # ------------------------------------------------------------------------- error paths
 def test_unstable_dt_rejected_before_enqueue():
     w = workload("vesicle32")
