@@ -389,6 +389,21 @@ __global__ __launch_bounds__(kBlock) void k_fill_profile(double* __restrict__ ds
     dst[node(d, i, j, k)] = prof ? prof[j] : 0.0;
 }
 
+// Zero the two wall rows (j = 0 and j = ny-1) of up to six fields: homogeneous Dirichlet
+// data for a solve whose interior the solve itself writes.
+struct Fields6 {
+    double* p[6];
+};
+__global__ __launch_bounds__(kBlock) void k_zero_walls(Fields6 f, Dims d) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    const int plane = d.nx * d.nz;
+    if (e >= 2 * plane) return;
+    const int wall = e / plane, r = e - wall * plane;
+    const int i = r / d.nz, k = r - (r / d.nz) * d.nz;
+    const int j = wall ? d.ny - 1 : 0;
+    f.p[blockIdx.y][node(d, i, j, k)] = 0.0;
+}
+
 __global__ void k_reset_stats(double* scal, int* istat) {
     if (threadIdx.x == 0) {
         scal[SC_RELRES_MAX] = 0.0;
@@ -435,6 +450,14 @@ void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, cons
         launch_kernel(k_mu_tile<false>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, va, C_b, eps, sigma);
     else
         launch_kernel(k_mu_tile<true>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, va, C_b, eps, sigma);
+}
+
+void launch_zero_walls(hipStream_t s, const Dims& d, double* const f[], int nf) {
+    if (nf < 1 || nf > 6) return;
+    Fields6 ff{};
+    for (int q = 0; q < nf; ++q) ff.p[q] = f[q];
+    const int n = 2 * d.nx * d.nz;
+    launch_kernel(k_zero_walls, dim3((n + kBlock - 1) / kBlock, nf), dim3(kBlock), 0, s, ff, d);
 }
 
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof) {

@@ -657,15 +657,16 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
     // advection, L_h mu and lambda_V terms; q = psi_bar
     launch_adj_advect(st, d, adj_next, phi, cps, dt, S->p.mobility, S->vz_lo, S->vz_hi, adj_prev,
                       mubar, q, S->part, S->scal);
-    // psi_int = P(-omega_int; psi walls): first adjoint solve, homogeneous walls
-    for (int c = 0; c < 3; ++c) launch_fill_profile(st, d, u1[c], nullptr);
+    // psi_int = P(-omega_int; psi walls): first adjoint solve, homogeneous walls (the solve
+    // writes the interior; only the wall rows need zeros)
+    launch_zero_walls(st, d, u1, 3);
     RhsArgs r1{};
     r1.mode = RHS_FIELD;
     for (int c = 0; c < 3; ++c) r1.f[c] = q[c];
     enqueue_solve(S, r1, u1, 3, rtol, mc, TAG_FIELD);
     launch_adj_wall_couple(st, d, u1, S->ps, S->part, S->scal, SC_ADJ_PSIC);
     // omega_int = P(S; omega walls): second adjoint solve of -u1, into q = S_bar
-    for (int c = 0; c < 3; ++c) launch_fill_profile(st, d, q[c], nullptr);
+    launch_zero_walls(st, d, q, 3);
     RhsArgs r2{};
     r2.mode = RHS_NEGW;
     for (int c = 0; c < 3; ++c) r2.f[c] = u1[c];

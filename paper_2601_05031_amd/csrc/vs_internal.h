@@ -148,6 +148,8 @@ struct VaFinal {
 void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const VaFinal& va,
                int model, double C_b, double eps, double sigma);
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof);
+// Zero the wall rows j = 0, ny-1 of nf <= 6 fields in one launch.
+void launch_zero_walls(hipStream_t s, const Dims& d, double* const f[], int nf);
 // S = (1/eta) D phi x D mu on the interior rows (main text eq. (5b)), into src[0..2].
 void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
                    double inv_eta, double* const src[3]);
