@@ -41,6 +41,12 @@ or inconsistent are listed here and in the design notes:
   R12 each Poisson problem is the exact solution of the discrete 7-point system on the
       interior nodes with Dirichlet wall values (here by the eigen-decomposition of L_h:
       DFT in x and z, sine transform in y).
+  R23 inertial variant (SM "Time-dependency and inertial flow", eq. (36)): with density
+      rho > 0 the vorticity obeys (rho/eta) d(omega)/dt - lap omega = -(1/eta) grad phi x
+      grad mu. The time derivative is taken backward (implicit) in the same segregated
+      step: (L_h - a) omega^{n+1} = S^{n+1} - a omega^n, a = rho / (eta dt), with the same
+      Dirichlet wall values; psi then from eq. (5c) as before. rho = 0 is eq. (5b).
+  R24 the initial omega^0 of an inertial run is the quasi-steady one of eq. (5b).
 """
 from __future__ import annotations
 
@@ -104,6 +110,7 @@ class Params:
     rate_V: float = 0.0
     k_A: float = 0.0
     bend_scale: float = 1.0
+    rho: float = 0.0      # fluid density of the inertial variant (R23); 0 = eq. (5b)
 
     @property
     def C_b(self) -> float:
@@ -278,14 +285,17 @@ def vorticity_source(phi, mu, grid: Grid, eta: float) -> np.ndarray:
     return np.stack([fy * mz - fz * my, fz * mx - fx * mz, fx * my - fy * mx]) / eta
 
 
-def poisson_solve(b_int: np.ndarray, u_lo: np.ndarray, u_hi: np.ndarray, grid: Grid) -> np.ndarray:
-    """Exact solution of L_h u = b on the interior rows with Dirichlet walls (R12).
+def poisson_solve(b_int: np.ndarray, u_lo: np.ndarray, u_hi: np.ndarray, grid: Grid,
+                  shift: float = 0.0) -> np.ndarray:
+    """Exact solution of (L_h - shift) u = b on the interior rows with Dirichlet walls (R12;
+    shift > 0 is the implicit inertial vorticity problem of R23).
 
     b_int: (nx, ny-2, nz) right-hand side on j = 1..ny-2. u_lo, u_hi: (nx, nz) wall values
     at j = 0 and j = ny-1. The wall values are moved to the right-hand side, then L_h with
     homogeneous Dirichlet walls is inverted through its eigenvectors: discrete Fourier modes
     in x and z (eigenvalue (2 cos(2 pi p/n) - 2)/h^2) and sine modes sin(pi m j/(ny-1)) in y
-    (eigenvalue (2 cos(pi m/(ny-1)) - 2)/h^2, m = 1..ny-2).
+    (eigenvalue (2 cos(pi m/(ny-1)) - 2)/h^2, m = 1..ny-2); the shift moves every eigenvalue
+    by -shift.
     """
     nx, ny, nz, h = grid.nx, grid.ny, grid.nz, grid.h
     M = ny - 2
@@ -298,18 +308,26 @@ def poisson_solve(b_int: np.ndarray, u_lo: np.ndarray, u_hi: np.ndarray, grid: G
     bh = scipy.fft.dst(bt, type=1, axis=1)
     bh = scipy.fft.rfft(bh, axis=2)
     bh = scipy.fft.fft(bh, axis=0)
-    uh = bh / (lx[:, None, None] + ly[None, :, None] + lz[None, None, :])
+    uh = bh / (lx[:, None, None] + ly[None, :, None] + lz[None, None, :] - shift)
     u = scipy.fft.ifft(uh, axis=0)
     u = scipy.fft.irfft(u, n=nz, axis=2)
     return scipy.fft.idst(u, type=1, axis=1)
 
 
-def solve_flow(phi, mu, grid: Grid, walls: Walls, params: Params):
-    """omega from eq. (5b), then psi from eq. (5c) (segregated order), walls from R11."""
+def solve_flow(phi, mu, grid: Grid, walls: Walls, params: Params, omega_prev=None,
+               dt: float | None = None):
+    """omega from eq. (5b), then psi from eq. (5c) (segregated order), walls from R11. With
+    params.rho > 0 and the previous vorticity and dt given, omega from the implicit inertial
+    problem of R23 instead."""
     omega, psi = no_body_fields(grid, walls)
     S = vorticity_source(phi, mu, grid, params.eta)
+    shift = 0.0
+    if params.rho > 0.0 and omega_prev is not None:
+        shift = params.rho / (params.eta * dt)
+        S = S - shift * omega_prev[:, :, 1:-1, :]
     for c in range(3):
-        omega[c, :, 1:-1, :] = poisson_solve(S[c], omega[c, :, 0, :], omega[c, :, -1, :], grid)
+        omega[c, :, 1:-1, :] = poisson_solve(S[c], omega[c, :, 0, :], omega[c, :, -1, :], grid,
+                                             shift)
     for c in range(3):
         psi[c, :, 1:-1, :] = poisson_solve(-omega[c, :, 1:-1, :], psi[c, :, 0, :], psi[c, :, -1, :], grid)
     return omega, psi
@@ -340,7 +358,7 @@ def step(s: State, dt: float, grid: Grid, walls: Walls, params: Params, flow: bo
     lam_V, gamma_A = multipliers(V, A, s.V0, s.A0, grid, params)
     mu = chemical_potential(phi, grid, params, gamma_A)
     if flow:
-        omega, psi = solve_flow(phi, mu, grid, walls, params)
+        omega, psi = solve_flow(phi, mu, grid, walls, params, s.omega, dt)
     else:
         omega, psi = s.omega, s.psi
     return replace(s, phi=phi, mu=mu, omega=omega, psi=psi, V=V, A=A, lam_V=lam_V,

@@ -42,10 +42,11 @@ def grad_m(u, h):
     return d
 
 
-def poisson_dense(b, ulo, uhi, h):
-    """Solve L_h u = b on j = 1..ny-2 with u = ulo at j = 0, uhi at j = ny-1, by assembling
-    the matrix entry by entry and calling a dense solver. b has the full (nx, ny, nz) shape;
-    its wall rows are ignored. Returns the full field including the walls."""
+def poisson_dense(b, ulo, uhi, h, shift=0.0):
+    """Solve (L_h - shift) u = b on j = 1..ny-2 with u = ulo at j = 0, uhi at j = ny-1, by
+    assembling the matrix entry by entry and calling a dense solver. b has the full
+    (nx, ny, nz) shape; its wall rows are ignored. Returns the full field including the
+    walls."""
     nx, ny, nz = b.shape
     M = ny - 2
     n = nx * M * nz
@@ -59,7 +60,7 @@ def poisson_dense(b, ulo, uhi, h):
         for j in range(1, ny - 1):
             for k in range(nz):
                 r = idx(i, j, k)
-                A[r, r] += -6.0 / h**2
+                A[r, r] += -6.0 / h**2 - shift
                 rhs[r] = b[i, j, k]
                 for (ii, jj, kk) in ((i + 1, j, k), (i - 1, j, k), (i, j, k + 1), (i, j, k - 1),
                                      (i, j + 1, k), (i, j - 1, k)):
