@@ -113,7 +113,13 @@ typedef struct {
  *  poisson_rtol, poisson_max_cycles: each Poisson solve of vs_step runs up to max_cycles
  *            refinement cycles until ||b - L_h u||_2 <= rtol ||b||_2 over the three
  *            components (b includes the wall terms); max_cycles in [1, 16].
- *  flags     VS_ALLOW_UNSTABLE skips the forward-Euler stability check of vs_step. */
+ *  flags     VS_ALLOW_UNSTABLE skips the forward-Euler stability check of vs_step.
+ *  rho       fluid density of the inertial variant (SM "Time-dependency and inertial flow",
+ *            eq. (36)): (rho/eta) d(omega)/dt - lap omega = -(1/eta) grad phi x grad mu,
+ *            taken implicitly in each step, (L_h - a) omega^{n+1} = S - a omega^n with
+ *            a = rho/(eta dt); omega^0 is the quasi-steady field of eq. (5b). 0 = eq. (5b).
+ *            rho > 0 needs precision VS_FP64 and poisson_max_cycles = 1 (VS_E_UNSUPPORTED
+ *            otherwise); vs_grad_step and vs_set_walls return VS_E_UNSUPPORTED for it. */
 typedef struct {
     int32_t model;
     int32_t precision;
@@ -124,6 +130,7 @@ typedef struct {
     double poisson_rtol;
     int32_t poisson_max_cycles;
     int32_t flags;
+    double rho;
 } vs_params;
 
 typedef struct vs_state vs_state;
@@ -160,7 +167,9 @@ vs_status vs_poisson_solve(vs_state* state, const double* f, double* u, double r
  * 2 / (M (12/h^2) [C_b (2 + 12 eps^2/h^2)^2 + 12 |gamma_A|/h^2]) (bending) or
  * 2 / (M (12/h^2)(2 + 12 sigma/h^2)) (Cahn–Hilliard), unless VS_ALLOW_UNSTABLE is set.
  * Device-side failures (VS_E_NOCONV, VS_E_NONFINITE) are reported at the end of the call,
- * after all nsteps have run. Synchronises the stream once, at the end. */
+ * after all nsteps have run. Synchronises the stream once, at the end. With rho > 0 the
+ * first call with a new dt also synchronises before it enqueues anything, to upload that
+ * dt's vorticity pivots (so it cannot run under stream capture). */
 vs_status vs_step(vs_state* state, double dt, int32_t nsteps);
 
 /* Reverse step of one time step (the discrete adjoint of vs_step's update, FP64 mode only;

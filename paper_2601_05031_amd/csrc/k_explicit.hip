@@ -359,12 +359,19 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
     }
 }
 
+struct Om3 {
+    const double* p[3];
+};
+
 // Vorticity source S = (1/eta) D phi x D mu (main text eq. (5b)) at the interior rows, stored
 // so that the transform and the residual of the vorticity solve read it as a plain field.
+// The inertial variant (SM eq. (36), implicit in time) stores S - a omega^n instead, the
+// right-hand side of (L_h - a) omega^{n+1}, a = rho / (eta dt).
 __global__ __launch_bounds__(kBlock) void k_source(const double* __restrict__ phi,
                                                   const double* __restrict__ mu, Dims d,
                                                   double inv_eta, double* __restrict__ sx,
-                                                  double* __restrict__ sy, double* __restrict__ sz) {
+                                                  double* __restrict__ sy, double* __restrict__ sz,
+                                                  double a, Om3 om) {
     int i, j, k;
     bool ok;
     plane_index(d, i, j, k, ok);
@@ -374,9 +381,17 @@ __global__ __launch_bounds__(kBlock) void k_source(const double* __restrict__ ph
                  fz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
     const double mx = (mu[n.xp] - mu[n.xm]) * d.inv_2h, my = (mu[n.yp] - mu[n.ym]) * d.inv_2h,
                  mz = (mu[n.zp] - mu[n.zm]) * d.inv_2h;
-    sx[n.c] = (fy * mz - fz * my) * inv_eta;
-    sy[n.c] = (fz * mx - fx * mz) * inv_eta;
-    sz[n.c] = (fx * my - fy * mx) * inv_eta;
+    double s0 = (fy * mz - fz * my) * inv_eta;
+    double s1 = (fz * mx - fx * mz) * inv_eta;
+    double s2 = (fx * my - fy * mx) * inv_eta;
+    if (a != 0.0) {
+        s0 -= a * om.p[0][n.c];
+        s1 -= a * om.p[1][n.c];
+        s2 -= a * om.p[2][n.c];
+    }
+    sx[n.c] = s0;
+    sy[n.c] = s1;
+    sz[n.c] = s2;
 }
 
 // dst[(i, j, k)] = prof[j]: the no-body channel fields as initial guesses and wall rows.
@@ -465,9 +480,12 @@ void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double
 }
 
 void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                   double inv_eta, double* const src[3]) {
+                   double inv_eta, double* const src[3], double a,
+                   const double* const omega[3]) {
+    Om3 om{{nullptr, nullptr, nullptr}};
+    if (a != 0.0) om = Om3{{omega[0], omega[1], omega[2]}};
     launch_kernel(k_source, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0],
-                       src[1], src[2]);
+                  src[1], src[2], a, om);
 }
 
 void launch_reset_stats(hipStream_t s, double* scal, int* istat) {

@@ -725,8 +725,11 @@ __device__ __forceinline__ void seg_store_tile(const double (&x)[LMAX], ST* base
 // Segmented vorticity + stream-vector pair: the vorticity modes U_w (f = scale * B) are solved
 // and stored in spec, then the stream-vector problem lap psi = -w is solved from them in
 // registers, f_j = -h^2 U_w(j) - [p = q = 0]([j = 1] psi_lo + [j = M] psi_hi), into spec2.
+// triw holds the vorticity's pivots: tri itself, or those of the shifted operator L_h - a of
+// the inertial variant (SM eq. (36)).
 template <int S, int LMAX, class ST, int LMF, int NLF>
 __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* __restrict__ tri,
+                                                         const double* __restrict__ triw,
                                                          SPtr3<ST> spec, SPtr3<ST> spec2,
                                                          double3 olo, double3 ohi, double3 plo,
                                                          double3 phi_, double scale) {
@@ -740,7 +743,7 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
     constexpr bool kTile = seg_tiled<S, LMAX>();
     __shared__ double tile[kTile ? LMAX * (256 + S) : 1];
     SegCoef<LMAX> cf;
-    seg_coef<LMAX>(cf, tri, sl.cls, sl.ncls, d.M, sl.Lm);
+    seg_coef<LMAX>(cf, triw, sl.cls, sl.ncls, d.M, sl.Lm);
     ST* col = spec.p[c3];
     const unsigned N = (unsigned)(d.nx * d.ny * d.nz);
     double x[LMAX];
@@ -763,6 +766,8 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
         seg_store_tile<S, LMAX, ST>(x, col, tile, sl, d);
     else
         seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
+    // the stream-vector problem has no shift: its own pivots when the vorticity's differ
+    if (triw != tri) seg_coef<LMAX>(cf, tri, sl.cls, sl.ncls, d.M, sl.Lm);
     const double h2 = d.h * d.h;
     const double wlo = c3 == 0 ? plo.x : (c3 == 1 ? plo.y : plo.z);
     const double whi = c3 == 0 ? phi_.x : (c3 == 1 ? phi_.y : phi_.z);
@@ -1186,7 +1191,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
 // from one wave-uniform load each, instead of two full loads per field and plane.
 template <bool ZS>
 __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 src, CPtr3 ps,
-                                                      SlabGrid sg,
+                                                      SlabGrid sg, double ashift,
                                                       double* __restrict__ partials) {
     __shared__ double sh[4 * 4];
     const int nb = sg.gx * sg.gi;
@@ -1242,7 +1247,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
                 double zp, zm;
                 zpair(wc, rb, wx, zp, zm);
                 const double lap = (wp + wm + ylo + yhi + zp + zm - 6.0 * wx) * d.inv_h2;
-                const double r = b - lap;
+                // the inertial variant solves (L_h - a) omega = b
+                const double r = b - (ashift != 0.0 ? lap - ashift * wx : lap);
                 const double bt = b - w * d.inv_h2;
                 a[0] += r * r;
                 a[1] += bt * bt;
@@ -1454,26 +1460,26 @@ int seg_shape(int M) {
 // stream-vector kernel. Grids with ny = n in {32, 48, 64, 96, 128, 256} (M = n - 2) get
 // their segment lengths as compile-time constants.
 template <bool PAIR, int S, int LMAX, class ST, int LMF, int NLF>
-void seg_launch(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                void* const spec2[3], int ncomp, const int* gate, double3 olo, double3 ohi,
-                double3 lo, double3 hi, double scale) {
+void seg_launch(hipStream_t s, const Dims& d, const double* tri, const double* triw,
+                void* const spec[3], void* const spec2[3], int ncomp, const int* gate,
+                double3 olo, double3 ohi, double3 lo, double3 hi, double scale) {
     const dim3 grid((unsigned)(((long)d.nx * d.nz * S + 255) / 256), ncomp);
     if (PAIR)
         launch_kernel((k_tridiag_pair_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d,
-                           tri, sptr<ST>(spec, 3), sptr<ST>(spec2, 3), olo, ohi, lo, hi, scale);
+                      tri, triw, sptr<ST>(spec, 3), sptr<ST>(spec2, 3), olo, ohi, lo, hi, scale);
     else
         launch_kernel((k_tridiag_seg<S, LMAX, ST, LMF, NLF>), grid, dim3(256), 0, s, d, tri,
                            sptr<ST>(spec, ncomp), gate, scale);
 }
 
 template <bool PAIR, class ST>
-bool seg_dispatch(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                  void* const spec2[3], int ncomp, const int* gate, double3 olo, double3 ohi,
-                  double3 lo, double3 hi) {
+bool seg_dispatch(hipStream_t s, const Dims& d, const double* tri, const double* triw,
+                  void* const spec[3], void* const spec2[3], int ncomp, const int* gate,
+                  double3 olo, double3 ohi, double3 lo, double3 hi) {
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
 #define VS_SEG(S_, LMAX_, LMF_, NLF_) \
-    seg_launch<PAIR, S_, LMAX_, ST, LMF_, NLF_>(s, d, tri, spec, spec2, ncomp, gate, olo, ohi, lo, \
-                                                hi, scale)
+    seg_launch<PAIR, S_, LMAX_, ST, LMF_, NLF_>(s, d, tri, triw, spec, spec2, ncomp, gate, olo, \
+                                                ohi, lo, hi, scale)
     switch (d.M) {
     case 30: VS_SEG(4, 8, 8, 2); return true;
     case 46: VS_SEG(4, 16, 12, 2); return true;
@@ -1497,7 +1503,7 @@ template <class ST>
 void tridiag_y_t(hipStream_t s, const Dims& d, const double* tri, void* const spec[3], int ncomp,
                  const int* gate) {
     const double3 z = make_double3(0.0, 0.0, 0.0);
-    if (seg_dispatch<false, ST>(s, d, tri, spec, nullptr, ncomp, gate, z, z, z, z)) return;
+    if (seg_dispatch<false, ST>(s, d, tri, tri, spec, nullptr, ncomp, gate, z, z, z, z)) return;
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
     const dim3 grid((2 * d.nx * d.nz + 63) / 64, ncomp);
     launch_kernel(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, ncomp), gate,
@@ -1505,12 +1511,13 @@ void tridiag_y_t(hipStream_t s, const Dims& d, const double* tri, void* const sp
 }
 
 template <class ST>
-void tridiag_pair_t(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                    void* const spec2[3], double3 olo, double3 ohi, double3 lo, double3 hi) {
-    if (seg_dispatch<true, ST>(s, d, tri, spec, spec2, 3, nullptr, olo, ohi, lo, hi)) return;
+void tridiag_pair_t(hipStream_t s, const Dims& d, const double* tri, const double* triw,
+                    void* const spec[3], void* const spec2[3], double3 olo, double3 ohi,
+                    double3 lo, double3 hi) {
+    if (seg_dispatch<true, ST>(s, d, tri, triw, spec, spec2, 3, nullptr, olo, ohi, lo, hi)) return;
     const double scale = d.h * d.h / ((double)d.nx * d.nz);
     const dim3 grid((2 * d.nx * d.nz + 63) / 64, 3);
-    launch_kernel(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
+    launch_kernel(k_tridiag_y<ST>, grid, dim3(64), 0, s, d, triw, sptr<ST>(spec, 3),
                   (const int*)nullptr, scale, olo, ohi);
     launch_kernel(k_tridiag_psi<ST>, grid, dim3(64), 0, s, d, tri, sptr<ST>(spec, 3),
                        sptr<ST>(spec2, 3), lo, hi);
@@ -1524,17 +1531,19 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* con
         tridiag_y_t<double>(s, d, tri, spec, ncomp, gate);
 }
 
-void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                         void* const spec2[3], const double om_lo[3], const double om_hi[3],
-                         const double psi_lo[3], const double psi_hi[3], bool f32) {
+void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, const double* triw,
+                         void* const spec[3], void* const spec2[3], const double om_lo[3],
+                         const double om_hi[3], const double psi_lo[3], const double psi_hi[3],
+                         bool f32) {
     const double3 olo = make_double3(om_lo[0], om_lo[1], om_lo[2]);
     const double3 ohi = make_double3(om_hi[0], om_hi[1], om_hi[2]);
     const double3 lo = make_double3(psi_lo[0], psi_lo[1], psi_lo[2]);
     const double3 hi = make_double3(psi_hi[0], psi_hi[1], psi_hi[2]);
+    if (!triw) triw = tri;
     if (f32)
-        tridiag_pair_t<float>(s, d, tri, spec, spec2, olo, ohi, lo, hi);
+        tridiag_pair_t<float>(s, d, tri, triw, spec, spec2, olo, ohi, lo, hi);
     else
-        tridiag_pair_t<double>(s, d, tri, spec, spec2, olo, ohi, lo, hi);
+        tridiag_pair_t<double>(s, d, tri, triw, spec, spec2, olo, ohi, lo, hi);
 }
 
 void launch_dht_z_fwd(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
@@ -1575,16 +1584,17 @@ void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
 }
 
 void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
-                       const double* const src[3], const double* const ps[3], double* partials) {
+                       const double* const src[3], const double* const ps[3], double ashift,
+                       double* partials) {
     const CPtr3 o{{om[0], om[1], om[2]}}, f{{src[0], src[1], src[2]}}, p{{ps[0], ps[1], ps[2]}};
     const SlabGrid g = resid_grid(d);
     // a whole number of waves per row lets the z neighbours come from shuffles
     if (d.nz % 64 == 0)
         launch_kernel(k_resid_flow<true>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p,
-                      g, partials);
+                      g, ashift, partials);
     else
         launch_kernel(k_resid_flow<false>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p,
-                      g, partials);
+                      g, ashift, partials);
 }
 
 void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,

@@ -70,10 +70,11 @@ struct Layout {
     size_t off_src;         // 3 fields: the vorticity source S of the current step
     size_t off_spec2;       // 3 spectral fields: the stream-vector modes
     size_t off_twx, off_twz, off_tri, off_part, off_prof, off_scal, off_istat;
+    size_t off_tri2;        // the shifted vorticity pivots of the inertial variant (or 0)
     size_t total;
 };
 
-Layout make_layout(const vs_grid& g) {
+Layout make_layout(const vs_grid& g, bool inertial) {
     const size_t N = (size_t)g.nx * g.ny * g.nz;
     const size_t fb = align_up(N * sizeof(double));
     const size_t M = (size_t)g.ny - 2;
@@ -90,8 +91,36 @@ Layout make_layout(const vs_grid& g) {
     L.off_prof = o;   o += align_up(4 * (size_t)g.ny * sizeof(double));   // tables + a change
     L.off_scal = o;   o += align_up(SC_NSCAL * sizeof(double));
     L.off_istat = o;  o += align_up(IS_NSTAT * sizeof(int));
+    L.off_tri2 = 0;
+    if (inertial) {
+        L.off_tri2 = o;
+        o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * (M + 1) * sizeof(double));
+    }
     L.total = o;
     return L;
+}
+
+// Pivots c'_j = 1/(beta - c'_{j-1}) of tridiag(1, beta, 1) per Hartley mode class (p, q) up
+// to the conjugate pair, beta = 2 cos(2 pi p/nx) + 2 cos(2 pi q/nz) - 6 - shift_h2, and beta
+// itself as row M. shift_h2 = a h^2 for the operator L_h - a (0: L_h).
+std::vector<double> pivot_table(const vs_grid& g, double shift_h2) {
+    const int M = g.ny - 2, hx = g.nx / 2 + 1, hz = g.nz / 2 + 1;
+    std::vector<double> tri((size_t)hx * hz * (M + 1));
+    for (int pc = 0; pc < hx; ++pc)
+        for (int qc = 0; qc < hz; ++qc) {
+            const long double PI = 3.14159265358979323846264338327950288L;
+            const double beta = (double)(2.0L * cosl(2.0L * PI * pc / g.nx) +
+                                         2.0L * cosl(2.0L * PI * qc / g.nz) - 6.0L -
+                                         (long double)shift_h2);
+            const size_t cls = (size_t)pc * hz + qc, ncls = (size_t)hx * hz;
+            double prev = 0.0;
+            for (int j = 0; j < M; ++j) {
+                prev = 1.0 / (beta - prev);
+                tri[(size_t)j * ncls + cls] = prev;
+            }
+            tri[(size_t)M * ncls + cls] = beta;
+        }
+    return tri;
 }
 
 vs_status check_grid(const vs_grid* g) {
@@ -131,6 +160,10 @@ vs_status check_params(const vs_params* p) {
     for (double v : fin)
         if (!std::isfinite(v)) return fail(VS_E_ARG, "non-finite parameter");
     if (p->rate_V < 0.0 || p->k_A < 0.0) return fail(VS_E_ARG, "penalties must be >= 0");
+    if (!(p->rho >= 0.0) || !std::isfinite(p->rho)) return fail(VS_E_ARG, "rho must be >= 0");
+    if (p->rho > 0.0 && (p->precision != VS_FP64 || p->poisson_max_cycles != 1))
+        return fail(VS_E_UNSUPPORTED,
+                    "the inertial variant (rho > 0) runs in VS_FP64 with poisson_max_cycles = 1");
     return VS_OK;
 }
 
@@ -172,6 +205,8 @@ struct vs_state {
     double2* twx = nullptr;
     double2* twz = nullptr;
     double* tri = nullptr;
+    double* tri2 = nullptr;    // inertial variant: pivots of L_h - a for the vorticity
+    double tri2_dt = 0.0;      // the dt those pivots were made for (0: not yet)
     double* part = nullptr;
     double* prof = nullptr;   // [0, ny): psi_x profile, [ny, 2 ny): omega_x profile
     double* scal = nullptr;
@@ -302,11 +337,17 @@ void enqueue_va_mu(vs_state* S, const double* phi, int init) {
 // the transformed right-hand side of the stream-vector problem, so psi needs no forward
 // transform. Both fields are then verified against their own spatial residual; correction
 // cycles (normally never run in FP64) use the generic path.
-void enqueue_flow(vs_state* S, const double* phi, bool defer_check) {
+void enqueue_flow(vs_state* S, const double* phi, bool defer_check, double dt) {
     const Dims& d = S->d;
     const double rtol = S->p.poisson_rtol;
     const int mc = S->p.poisson_max_cycles;
-    timed(S, K_SOURCE, [&] { launch_source(S->stream, d, phi, S->mu, 1.0 / S->p.eta, S->src); });
+    // inertial variant (SM eq. (36)), implicit in time: (L_h - a) omega^{n+1} = S - a omega^n;
+    // dt = 0 (the initial state) solves eq. (5b)
+    const double a = (S->p.rho > 0.0 && dt > 0.0) ? S->p.rho / (S->p.eta * dt) : 0.0;
+    const double* const omc[3] = {S->om[0], S->om[1], S->om[2]};
+    timed(S, K_SOURCE, [&] {
+        launch_source(S->stream, d, phi, S->mu, 1.0 / S->p.eta, S->src, a, omc);
+    });
     RhsArgs rv{};
     rv.mode = RHS_FIELD;
     rv.f[0] = S->src[0];
@@ -332,8 +373,8 @@ void enqueue_flow(vs_state* S, const double* phi, bool defer_check) {
     });
     timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
     timed(S, K_TRIDIAG_PAIR, [&] {
-        launch_tridiag_pair(S->stream, d, S->tri, S->spec, S->spec2, S->om_wall_lo, S->om_wall_hi,
-                            S->psi_wall_lo, S->psi_wall_hi, false);
+        launch_tridiag_pair(S->stream, d, S->tri, a != 0.0 ? S->tri2 : nullptr, S->spec, S->spec2,
+                            S->om_wall_lo, S->om_wall_hi, S->psi_wall_lo, S->psi_wall_hi, false);
     });
     timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
     timed(S, K_DHT_Z_OUT, [&] {
@@ -350,7 +391,7 @@ void enqueue_flow(vs_state* S, const double* phi, bool defer_check) {
         const double* const co[3] = {S->om[0], S->om[1], S->om[2]};
         const double* const cs[3] = {S->src[0], S->src[1], S->src[2]};
         const double* const cp[3] = {S->ps[0], S->ps[1], S->ps[2]};
-        timed(S, K_RESID_FLOW, [&] { launch_resid_flow(S->stream, d, co, cs, cp, S->part); });
+        timed(S, K_RESID_FLOW, [&] { launch_resid_flow(S->stream, d, co, cs, cp, a, S->part); });
         if (defer_check)
             S->check_pending = true;
         else
@@ -388,7 +429,20 @@ void enqueue_step(vs_state* S, double dt, bool more_follow) {
     });
     S->cur = 1 - S->cur;
     enqueue_va_mu(S, out, 0);
-    enqueue_flow(S, out, more_follow);
+    enqueue_flow(S, out, more_follow, dt);
+}
+
+// The inertial variant's vorticity pivots depend on dt (a = rho/(eta dt)): made on the host
+// when dt changes, before anything is enqueued. The device-wide wait covers a batch graph
+// still replaying on its own streams with the old table.
+vs_status ensure_inertial_table(vs_state* S, double dt) {
+    if (!(S->p.rho > 0.0) || dt == S->tri2_dt) return VS_OK;
+    const double a = S->p.rho / (S->p.eta * dt);
+    const std::vector<double> t = pivot_table(S->g, a * S->g.h * S->g.h);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(S->tri2, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    S->tri2_dt = dt;
+    return VS_OK;
 }
 
 // No-body channel tables on the node rows (the wall data of "Boundary conditions", reading
@@ -471,7 +525,7 @@ vs_status vs_workspace_bytes(const vs_grid* grid, const vs_params* params, size_
     if (st != VS_OK) return st;
     if ((st = check_params(params)) != VS_OK) return st;
     if (!bytes) return fail(VS_E_ARG, "bytes is NULL");
-    *bytes = make_layout(*grid).total;
+    *bytes = make_layout(*grid, params->rho > 0.0).total;
     return VS_OK;
 }
 
@@ -485,7 +539,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     if ((st = check_walls(walls)) != VS_OK) return st;
     if ((st = check_params(params)) != VS_OK) return st;
     if (!phi0) return fail(VS_E_ARG, "phi0 is NULL");
-    const Layout L = make_layout(*grid);
+    const Layout L = make_layout(*grid, params->rho > 0.0);
     if (!workspace) return fail(VS_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)workspace) & 255) return fail(VS_E_WORKSPACE, "workspace must be 256-byte aligned");
     if (bytes < L.total) return fail(VS_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
@@ -525,6 +579,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     S->twx = (double2*)(S->ws + L.off_twx);
     S->twz = (double2*)(S->ws + L.off_twz);
     S->tri = (double*)(S->ws + L.off_tri);
+    S->tri2 = L.off_tri2 ? (double*)(S->ws + L.off_tri2) : nullptr;
     S->part = (double*)(S->ws + L.off_part);
     S->prof = (double*)(S->ws + L.off_prof);
     S->scal = (double*)(S->ws + L.off_scal);
@@ -541,21 +596,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
         return t;
     };
     std::vector<double2> twx = twiddles(grid->nx), twz = twiddles(grid->nz);
-    const int M = grid->ny - 2, hx = grid->nx / 2 + 1, hz = grid->nz / 2 + 1;
-    std::vector<double> tri((size_t)hx * hz * (M + 1));
-    for (int pc = 0; pc < hx; ++pc)
-        for (int qc = 0; qc < hz; ++qc) {
-            const long double PI = 3.14159265358979323846264338327950288L;
-            const double beta = (double)(2.0L * cosl(2.0L * PI * pc / grid->nx) +
-                                         2.0L * cosl(2.0L * PI * qc / grid->nz) - 6.0L);
-            const size_t cls = (size_t)pc * hz + qc, ncls = (size_t)hx * hz;
-            double prev = 0.0;
-            for (int j = 0; j < M; ++j) {
-                prev = 1.0 / (beta - prev);
-                tri[(size_t)j * ncls + cls] = prev;
-            }
-            tri[(size_t)M * ncls + cls] = beta;
-        }
+    const std::vector<double> tri = pivot_table(*grid, 0.0);
     std::vector<double> prof = wall_tables(*grid, *walls);
     set_wall_state(S, *walls, prof);
     S->gamma_host = params->gamma0;
@@ -585,7 +626,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     }
     INIT_TRY(hipGetLastError());
     enqueue_va_mu(S, S->phi[0], 1);
-    enqueue_flow(S, S->phi[0], false);
+    enqueue_flow(S, S->phi[0], false, 0.0);
     INIT_TRY(hipGetLastError());
     st = collect(S, "vs_init");
     if (st != VS_OK) return bail(st);
@@ -630,6 +671,8 @@ vs_status vs_step(vs_state* S, double dt, int32_t nsteps) {
         if (dt * rate > 2.0)
             return fail(VS_E_UNSTABLE, "dt = %.4g exceeds the forward-Euler bound %.4g", dt, 2.0 / rate);
     }
+    vs_status st = ensure_inertial_table(S, dt);
+    if (st != VS_OK) return st;
     timed(S, K_RESET, [&] { launch_reset_stats(S->stream, S->scal, S->istat); });
     for (int s = 0; s < nsteps; ++s) enqueue_step(S, dt, s + 1 < nsteps);
     HIP_TRY(hipGetLastError());
@@ -644,6 +687,8 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
     if (adj_next == adj_prev) return fail(VS_E_ARG, "adj_next and adj_prev must not alias");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(VS_E_ARG, "dt must be > 0");
     if (S->f32) return fail(VS_E_UNSUPPORTED, "vs_grad_step: the reverse step runs in the FP64 mode only");
+    if (S->p.rho > 0.0)
+        return fail(VS_E_UNSUPPORTED, "vs_grad_step: no reverse step for the inertial variant");
     const Dims& d = S->d;
     hipStream_t st = S->stream;
     const double rtol = S->p.poisson_rtol;
@@ -704,6 +749,8 @@ vs_status vs_set_walls(vs_state* S, const vs_walls* walls) {
     vs_status st = check_walls(walls);
     if (st != VS_OK) return st;
     if (walls->kind != S->w.kind) return fail(VS_E_ARG, "vs_set_walls: the wall kind cannot change");
+    if (S->p.rho > 0.0)
+        return fail(VS_E_UNSUPPORTED, "vs_set_walls: not for the inertial variant");
     const std::vector<double> prof = wall_tables(S->g, *walls);
     const int ny = S->g.ny;
     std::vector<double> dprof(2 * (size_t)ny);
@@ -1026,6 +1073,10 @@ vs_status vs_batch_step(vs_batch* B, const double* dt, int32_t nsteps) {
         if (!(S->p.flags & VS_ALLOW_UNSTABLE) && dt[i] * stability_rate(S) > 2.0)
             return fail(VS_E_UNSTABLE, "instance %zu: dt = %.4g exceeds the forward-Euler bound %.4g",
                         i, dt[i], 2.0 / stability_rate(S));
+    }
+    for (size_t i = 0; i < n; ++i) {
+        const vs_status st = ensure_inertial_table(B->st[i], dt[i]);
+        if (st != VS_OK) return st;
     }
     bool same = B->exec && B->dt.size() == n && B->gen.size() == n;
     for (size_t i = 0; same && i < n; ++i) same = B->dt[i] == dt[i] && B->gen[i] == B->st[i]->walls_gen;

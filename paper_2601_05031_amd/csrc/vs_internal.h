@@ -150,9 +150,12 @@ void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, cons
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof);
 // Zero the wall rows j = 0, ny-1 of nf <= 6 fields in one launch.
 void launch_zero_walls(hipStream_t s, const Dims& d, double* const f[], int nf);
-// S = (1/eta) D phi x D mu on the interior rows (main text eq. (5b)), into src[0..2].
+// S = (1/eta) D phi x D mu on the interior rows (main text eq. (5b)), into src[0..2]; with
+// a != 0 (the inertial variant, SM eq. (36)), S - a omega with omega[0..2] the previous
+// vorticity.
 void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                   double inv_eta, double* const src[3]);
+                   double inv_eta, double* const src[3], double a,
+                   const double* const omega[3]);
 void launch_reset_stats(hipStream_t s, double* scal, int* istat);
 
 // ---------------------------------------------------------------- spectral Poisson
@@ -175,17 +178,22 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* con
 // psi_hi at j = ny-1).
 // The vorticity right-hand side's wall terms, om_lo at j = 0 and om_hi at j = ny-1 (constant
 // over each wall plane), are added in mode (0, 0) (the transform read S alone).
-void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, void* const spec[3],
-                         void* const spec2[3], const double om_lo[3], const double om_hi[3],
-                         const double psi_lo[3], const double psi_hi[3], bool f32);
+// triw: the vorticity's pivot table (nullptr: tri; the inertial variant's shifted operator
+// L_h - a has its own); the stream-vector problem always uses tri.
+void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, const double* triw,
+                         void* const spec[3], void* const spec2[3], const double om_lo[3],
+                         const double om_hi[3], const double psi_lo[3], const double psi_hi[3],
+                         bool f32);
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
                       const int* gate);
 int resid_blocks(const Dims& d);
 // Both flow residuals (vorticity, eq. (5b): b = S; stream vector, eq. (5c): b = -omega) in
 // one pass, into partial slots 0-5 and 6-11 as two resid_norm launches would write them.
+// ashift != 0: the vorticity operator is L_h - ashift (the inertial variant).
 void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
-                       const double* const src[3], const double* const ps[3], double* partials);
+                       const double* const src[3], const double* const ps[3], double ashift,
+                       double* partials);
 
 // ---------------------------------------------------------------- reverse step (k_adjoint.hip)
 // a = dL/dphi^{n+1}; writes phibar (dL/dphi^n, partial), mubar and psibar(3); gathers

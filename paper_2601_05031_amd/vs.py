@@ -53,7 +53,8 @@ class VsParams(ctypes.Structure):
                 ("kappa", ctypes.c_double), ("sigma", ctypes.c_double), ("gamma0", ctypes.c_double),
                 ("rate_V", ctypes.c_double), ("k_A", ctypes.c_double),
                 ("bend_scale", ctypes.c_double), ("poisson_rtol", ctypes.c_double),
-                ("poisson_max_cycles", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("poisson_max_cycles", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("rho", ctypes.c_double)]
 
 
 class VsError(RuntimeError):
@@ -113,10 +114,10 @@ def _check(code: int, call: str):
 
 def make_params(model="bending", precision="fp64", eta=1.0, mobility=1.0, eps=1.0, kappa=1.0,
                 sigma=1.0, gamma0=0.0, rate_V=0.0, k_A=0.0, bend_scale=1.0, rtol=1e-10,
-                max_cycles=3, allow_unstable=False) -> VsParams:
+                max_cycles=3, allow_unstable=False, rho=0.0) -> VsParams:
     return VsParams(_MODELS[model], _PRECISIONS[precision], eta, mobility, eps, kappa, sigma,
                     gamma0, rate_V, k_A, bend_scale, rtol, max_cycles,
-                    VS_ALLOW_UNSTABLE if allow_unstable else 0)
+                    VS_ALLOW_UNSTABLE if allow_unstable else 0, rho)
 
 
 def workspace_bytes(grid, params: VsParams) -> int:

@@ -1,6 +1,7 @@
 """CPU-side checks of the C ABI: the library loads, exports every function include/vs.h
 declares, and rejects bad arguments on the host before touching the GPU."""
 import ctypes
+import math
 import os
 import re
 
@@ -58,11 +59,23 @@ def test_grid_validation(grid, code):
     (dict(eta=0.0), V.VS_E_ARG), (dict(mobility=-1.0), V.VS_E_ARG), (dict(eps=0.0), V.VS_E_ARG),
     (dict(rtol=0.0), V.VS_E_ARG), (dict(max_cycles=0), V.VS_E_ARG), (dict(max_cycles=17), V.VS_E_ARG),
     (dict(model="cahn_hilliard", sigma=0.0), V.VS_E_ARG), (dict(rate_V=-1.0), V.VS_E_ARG),
+    # inertial variant: rho >= 0 and finite; rho > 0 only in FP64 with one solve per step
+    (dict(rho=-1.0), V.VS_E_ARG), (dict(rho=math.inf), V.VS_E_ARG), (dict(rho=math.nan), V.VS_E_ARG),
+    (dict(rho=1.0), V.VS_E_UNSUPPORTED), (dict(rho=1.0, max_cycles=1, precision="fp32_refined"),
+                                         V.VS_E_UNSUPPORTED),
 ])
 def test_param_validation(kw, code):
     with pytest.raises(V.VsError) as e:
         P.workspace_bytes((32, 32, 32, 1.0), P.make_params(**kw))
     assert e.value.code == code
+
+
+def test_inertial_params_accepted():
+    # rho > 0 in FP64 with one solve per step: the layout gains one pivot table
+    g = (32, 32, 32, 1.0)
+    n0 = P.workspace_bytes(g, P.make_params(max_cycles=1))
+    n1 = P.workspace_bytes(g, P.make_params(max_cycles=1, rho=2.0))
+    assert n1 > n0
 
 
 def test_init_rejects_before_any_device_call():

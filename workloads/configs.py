@@ -52,6 +52,7 @@ class Workload:
     bend_scale: float = 1.0
     rtol: float = 1e-10
     max_cycles: int = 3
+    rho: float = 0.0             # fluid density of the inertial variant; 0 = Stokes flow
     dt: float = 1e-3
     nsteps: int = 5
     shape: str = "sh"            # "sh" | "prolate" | "sphere"
@@ -88,7 +89,7 @@ class Workload:
         return dict(model=self.model, eta=self.eta, mobility=self.mobility, eps=self.eps,
                     kappa=self.kappa, sigma=self.sigma, gamma0=self.gamma0, rate_V=self.rate_V,
                     k_A=self.k_A, bend_scale=self.bend_scale, rtol=self.rtol,
-                    max_cycles=self.max_cycles)
+                    max_cycles=self.max_cycles, rho=self.rho)
 
     def walls(self) -> dict:
         return dict(kind=self.wall_kind, u0=self.u0, u1=self.u1)
