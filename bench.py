@@ -265,6 +265,27 @@ def diagnostics_run(P, torch, base) -> dict:
     return {"workload": base.name, "ms_per_call": 1e3 * t, "values_after_20_steps": d}
 
 
+def inertial_run(P, torch, base, nsteps: int, rho: float = 1e-3) -> dict:
+    """The 128^3 vesicle with the inertial vorticity equation (SM eq. (36), implicit in time,
+    a = rho/(eta dt)): nsteps steps of the kappa = 1 instance, one verified solve per step."""
+    w = base.with_(rho=rho, max_cycles=1)
+    s = P.solver_for(w)
+    s.step(w.dt, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(w.dt, nsteps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    relres = s.scalars()["relres"]
+    s.close()
+    a = rho / (w.eta * w.dt)
+    print(f"bench: inertial {w.name} rho={rho} (a h^2 = {a * w.grid.h ** 2:.3g}): "
+          f"{1e3 * t / nsteps:.3f} ms/step", file=sys.stderr, flush=True)
+    return {"workload": w.name, "rho": rho, "a_h2": a * w.grid.h ** 2, "steps": nsteps,
+            "poisson_max_cycles": 1, "ms_per_step": 1e3 * t / nsteps,
+            "cell_updates_per_s": w.grid.N * nsteps / t, "max_relres": relres}
+
+
 def copy_ceiling(torch) -> float:
     """Device-to-device copy of a 1 GiB FP64 buffer (read + write bytes per second, GB/s): the
     practical streaming ceiling next to the nominal 8 TB/s."""
@@ -305,6 +326,8 @@ def main():
     ap.add_argument("--batch-streams", type=int, default=8)
     ap.add_argument("--adjoint-steps", type=int, default=50,
                     help="steps of the 96^3 rollout gradient (0 = skip)")
+    ap.add_argument("--inertial-steps", type=int, default=20,
+                    help="steps of the 128^3 vesicle with the inertial vorticity equation (0 = skip)")
     ap.add_argument("--no-diagnostics", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM counters)")
@@ -424,6 +447,10 @@ def main():
     if args.adjoint_steps > 0:
         adjoint = adjoint_run(P, torch, args.adjoint_steps)
 
+    inertial = None
+    if args.inertial_steps > 0:
+        inertial = inertial_run(P, torch, base, args.inertial_steps)
+
     diagnostics = None
     if not args.no_diagnostics:
         diagnostics = diagnostics_run(P, torch, base)
@@ -465,6 +492,7 @@ def main():
         "batched": batched,
         "adjoint": adjoint,
         "diagnostics": diagnostics,
+        "inertial": inertial,
     }
     print(json.dumps(out), flush=True)
 
