@@ -70,6 +70,28 @@ def test_param_validation(kw, code):
     assert e.value.code == code
 
 
+def test_accepted_transform_lengths():
+    """n_x and n_z: exactly the even 2^a 3^b in [4, 512] (the two-pass transform plans)."""
+    def smooth23(n):
+        while n % 2 == 0:
+            n //= 2
+        while n % 3 == 0:
+            n //= 3
+        return n == 1
+    expect = [n for n in range(4, 513, 2) if smooth23(n)]
+    for axis in (0, 2):
+        got = []
+        for n in range(1, 600):
+            g = [16, 8, 16, 1.0]
+            g[axis] = n
+            try:
+                P.workspace_bytes(tuple(g), P.make_params())
+                got.append(n)
+            except V.VsError as e:
+                assert e.code == V.VS_E_UNSUPPORTED
+        assert got == expect, axis
+
+
 def test_inertial_params_accepted():
     # rho > 0 in FP64 with one solve per step: the layout gains one pivot table
     g = (32, 32, 32, 1.0)

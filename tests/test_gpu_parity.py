@@ -99,6 +99,41 @@ def test_poisson_solve_matches_oracle(shape, h):
     assert np.array_equal(u[:, 0, :], u0[:, 0, :]) and np.array_equal(u[:, -1, :], u0[:, -1, :])
 
 
+# every transform length the library accepts (even 2^a 3^b in [4, 512]); each appears once along
+# x and once along z, paired so that short and long lengths meet
+def _smooth23(n):
+    while n % 2 == 0:
+        n //= 2
+    while n % 3 == 0:
+        n //= 3
+    return n == 1
+
+
+LENGTHS = [n for n in range(4, 513, 2) if _smooth23(n)]
+
+
+@pytest.mark.parametrize("i", range(len(LENGTHS)))
+def test_poisson_every_transform_length(i):
+    nx, nz = LENGTHS[i], LENGTHS[(i + 13) % len(LENGTHS)]
+    shape = (nx, 6, nz)
+    say(f"case poisson-length shape={shape}")
+    w = workload("vesicle32").with_(grid=GridSpec(*shape), shape="sphere", R0=1.5)
+    s = P.solver_for(w)
+    rng = np.random.default_rng(100 + i)
+    f = rng.standard_normal(shape)
+    u0 = rng.standard_normal(shape)
+    ft = torch.tensor(f, device="cuda")
+    ut = torch.tensor(u0, device="cuda")
+    code, cycles, rel = s.poisson_solve(ft, ut, rtol=1e-12, max_cycles=3)
+    u = ut.cpu().numpy()
+    s.close()
+    ref = O.poisson_solve(f[:, 1:-1, :], u0[:, 0, :], u0[:, -1, :], O.Grid(*shape))
+    err = rel_l2(u[:, 1:-1, :], ref)
+    say(f"  code={code} cycles={cycles} relres={rel:.2e} relL2={err:.2e}")
+    assert code == V.VS_OK and rel <= 1e-12
+    assert err <= 1e-12
+
+
 def test_poisson_zero_rhs_zero_walls_gives_zero():
     say("case poisson zero rhs")
     w = workload("vesicle32")
@@ -189,6 +224,15 @@ def test_step_parity_tall_channels(ny):
     w = workload("droplet256", grid=GridSpec(16, ny, 24), R0=R, nsteps=3)
     got, sc, ref = run_both(w, 3)
     compare(got, ref_fields(ref), label=f"ny={ny}")
+
+
+@pytest.mark.parametrize("shape", [(486, 6, 512), (512, 7, 432)])
+def test_step_parity_longest_transforms(shape):
+    """Whole steps at the longest transform lengths (the general Stockham plans, and z lines
+    of 512 and 432 nodes in the shuffle and plain residual paths)."""
+    w = workload("droplet256", grid=GridSpec(*shape), R0=2.0, nsteps=2)
+    got, sc, ref = run_both(w, 2)
+    compare(got, ref_fields(ref), label=f"{shape}")
 
 
 @pytest.mark.parametrize("kappa,nsteps", [(1.0, 10), (0.5, 3), (2.0, 3)])
