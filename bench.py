@@ -53,14 +53,22 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
     return table.get(name)
 
 
+def code_tokens(src: str) -> str:
+    """C++ source without comments, whitespace runs collapsed: what the compiler sees."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def source_hash(kernel: str) -> str:
-    """Hash of the source file that holds a kernel, to tie stored counters to the code."""
+    """Hash of the code (comments aside) of the source files that hold a kernel, to tie
+    stored counters to the code they were taken on."""
     names = (["k_explicit.hip"] if kernel in ("advance", "va_partials", "mu", "source")
              else ["k_spectral.hip", "fft_reg.h"])
     h = hashlib.sha256()
     for fname in names:
-        with open(os.path.join(ROOT, "paper_2601_05031_amd", "csrc", fname), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2601_05031_amd", "csrc", fname)) as f:
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -47,7 +47,7 @@ typedef enum {
     VS_E_NONFINITE = -5,    /* NaN or Inf seen in a residual norm or in V, A               */
     VS_E_UNSTABLE = -6,     /* dt above the linear forward-Euler bound; nothing enqueued   */
     VS_E_STATE = -7,        /* null or unusable state                                     */
-    VS_E_UNSUPPORTED = -8   /* feature not built (e.g. vs_grad_step) or size unsupported   */
+    VS_E_UNSUPPORTED = -8   /* call or mode not available for these parameters, or size   */
 } vs_status;
 
 /* vs_walls.kind */
@@ -173,7 +173,7 @@ vs_status vs_poisson_solve(vs_state* state, const double* f, double* u, double r
 vs_status vs_step(vs_state* state, double dt, int32_t nsteps);
 
 /* Reverse step of one time step (the discrete adjoint of vs_step's update, FP64 mode only;
- * VS_E_UNSUPPORTED in VS_FP32_REFINED). The state must hold level n as vs_step leaves it
+ * VS_E_UNSUPPORTED in VS_FP32_REFINED and for the inertial variant, rho > 0). The state must hold level n as vs_step leaves it
  * (phi^n with its mu^n, omega^n, psi^n and multipliers), e.g. reloaded from a vs_save_state
  * checkpoint and advanced to n. With a = dL/dphi^{n+1}:
  *   adj_prev = (d phi^{n+1} / d phi^n)^T a, where mu^n, psi^n (through the vorticity and
@@ -197,7 +197,8 @@ vs_status vs_grad_step(vs_state* state, double dt, const double* adj_next, doubl
  * of the no-body fields (equal to re-solving the flow with the new walls), and the next steps
  * use the new wall speeds. An oscillatory flow calls this before each vs_step. A batch that
  * holds the state re-captures its graph on its next vs_batch_step. Checkpoints carry the
- * walls. VS_E_ARG if the kind differs. Synchronises the stream. */
+ * walls. VS_E_ARG if the kind differs; VS_E_UNSUPPORTED for the inertial variant (rho > 0).
+ * Synchronises the stream. */
 vs_status vs_set_walls(vs_state* state, const vs_walls* walls);
 
 /* Diagnostics of the current state, on the device (synchronises the stream):

@@ -15,6 +15,9 @@
 //                      from them, scaled by h^2/(nx nz), into two spectral buffers
 //   dht_x, dht_z_out : Hartley along x, then z, for each of the two fields
 //   resid_flow, check: ||b - L_h u||^2 and ||b~||^2 of both problems, relative residuals
+// The inertial variant (SM eq. (36)) runs the same passes for (L_h - a) omega = S - a omega^n:
+// its vorticity modes take the pivots of the shifted diagonal, its residual the shifted
+// operator; the stream-vector problem is unchanged.
 // The general form of one vector solve (vs_poisson_solve, refinement cycles) starts with
 // rhs_dht_z (b~, or the residual b - L_h u, on the interior rows, Hartley along z) and runs
 // dht_x, tridiag_y, dht_x, dht_z_out, resid_norm and check for each cycle.
