@@ -448,15 +448,18 @@ __global__ __launch_bounds__(64) void k_tridiag_psi(Dims d, const double* __rest
 
 // ---------------------------------------------------------------- segmented tridiagonal solve
 // Partition solve of T x = f for one mode, T = tridiag(1, beta, 1) of size M with zero ends
-// (the walls are folded into f). The column is cut into S consecutive segments, one lane each
-// (the S lanes of a mode are adjacent in the wave); a segment of L rows lives in registers.
+// (the walls are folded into f). The column is cut into S consecutive segments, one lane each;
+// a segment of L rows lives in registers. A 256-lane block owns 256/S consecutive modes, and
+// its lanes are ordered mode-fastest, so each wave holds consecutive modes (consecutive q of
+// one spectral row) of one or more segments and every row load or store covers whole runs.
 // With G = T_L^{-1}, segment k obeys x_k = G (f_k - E_{k-1} e_1 - F_{k+1} e_L), where F_k, E_k
 // are the first and last unknowns of segment k (E_{-1} = F_S = 0). Its ends give the coupled
 // relations  F_k = p_k - g11 E_{k-1} - g1L F_{k+1},  E_k = q_k - g1L E_{k-1} - g11 F_{k+1}
 // (p, q: ends of G f_k; g11 = G_11 = G_LL, g1L = G_1L = G_L1 since T_L is symmetric and
 // persymmetric). A forward sweep over the segments, E_k = a_k - b_k F_{k+1},
-// F_k = phi_k - chi_k F_{k+1}, runs redundantly in every lane of the mode; the back sweep
-// passes F down the lanes. The segment is then finished from its forward-eliminated rows d'_j:
+// F_k = phi_k - chi_k F_{k+1}, and the back sweep both run redundantly in every lane of the
+// mode, after the segment ends are exchanged through LDS. The segment is then finished from
+// its forward-eliminated rows d'_j:
 // the corrections of f enter d' as -E_{k-1} pi_j (pi = forward elimination of e_1) and
 // -F_{k+1} c'_L at the last row. Pivots c'_j = 1/(beta - c'_{j-1}) come from the class table,
 // so no lane divides in the row loops; beta itself is the table's last row.
@@ -516,9 +519,11 @@ __device__ __forceinline__ void seg_coef(SegCoef<LMAX>& cf, const double* __rest
     }
 }
 
+// xch: 512 doubles of LDS for the exchange of the segment ends; every thread of the 256-thread
+// block calls this (it holds two barriers).
 template <int S, int LMAX>
 __device__ __forceinline__ void seg_solve(double (&x)[LMAX], const SegCoef<LMAX>& cf, int k,
-                                          bool shortl, int Lm, int nlong) {
+                                          bool shortl, int Lm, int nlong, double* xch) {
     const double* c = cf.c;
     // forward elimination in place; q = last d', piL = pi at the last row (phantom row zeroed)
     double acc = 0.0, pi = 0.0, q = 0.0, piL = 0.0;
@@ -545,16 +550,22 @@ __device__ __forceinline__ void seg_solve(double (&x)[LMAX], const SegCoef<LMAX>
 #pragma unroll
     for (int u = LMAX - 1; u >= 0; --u)
         if (u < Lm) p = x[u] - c[u] * p;
-    // reduced system. Every segment's p and q are gathered first (independent shuffles, in
-    // flight together); every lane then runs the forward sweep and the back substitution of
-    // the whole reduced system itself, keeping phi and chi of every segment, so no value has
-    // to travel between lanes after the gather.
+    // reduced system. Every segment's p and q are gathered first (through LDS: the S lanes of
+    // a mode sit 256/S lanes apart); every lane then runs the forward sweep and the back
+    // substitution of the whole reduced system itself, keeping phi and chi of every segment,
+    // so no value has to travel between lanes after the gather.
+    constexpr int NM = 256 / S;
+    const int m = (int)threadIdx.x % NM;
+    xch[threadIdx.x] = p;
+    xch[256 + threadIdx.x] = q;
+    __syncthreads();
     double P[S], Q[S];
 #pragma unroll
     for (int kk = 0; kk < S; ++kk) {
-        P[kk] = __shfl(p, kk, S);
-        Q[kk] = __shfl(q, kk, S);
+        P[kk] = xch[kk * NM + m];
+        Q[kk] = xch[256 + kk * NM + m];
     }
+    __syncthreads();   // xch is free again
     double a = 0.0, b = 0.0, alp = 0.0, bep = 0.0;
     double PH[S], CH[S];
 #pragma unroll
@@ -620,9 +631,12 @@ struct SegLane {
 template <int S>
 __device__ __forceinline__ SegLane<S> seg_lane(const Dims& d) {
     SegLane<S> sl;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int mode = t / S;
-    sl.k = t % S;
+    // a block owns 256/S consecutive modes; lane t of the block takes mode t % (256/S) and
+    // segment t / (256/S), so the lanes of a wave hold consecutive modes (consecutive q) of
+    // one or two segments, and a row's loads and stores cover whole runs of a spectral row
+    constexpr int NM = 256 / S;
+    const int mode = (int)blockIdx.x * NM + (int)threadIdx.x % NM;
+    sl.k = (int)threadIdx.x / NM;
     sl.act = mode < d.nx * d.nz;
     const int mm = sl.act ? mode : 0;
     sl.p = mm / d.nz;
@@ -683,46 +697,15 @@ __global__ __launch_bounds__(256) void k_tridiag_seg(Dims d, const double* __res
         sl.nlong = NLF;
         sl.shortl = NLF > 0 && sl.k >= NLF;
     }
+    __shared__ double xch[512];
     SegCoef<LMAX> cf;
     seg_coef<LMAX>(cf, tri, sl.cls, sl.ncls, d.M, sl.Lm);
     ST* col = spec.p[blockIdx.y];
     const unsigned N = (unsigned)(d.nx * d.ny * d.nz);
     double x[LMAX];
     seg_load<S, LMAX, ST>(x, col, N, sl.off, d.nz, sl.Lm, scale);
-    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
+    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong, xch);
     seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
-}
-
-// Store of a block's solved columns through LDS: the lanes put their segment rows into a
-// (row, mode) tile, then the block writes it row by row, so a wave stores whole runs of
-// consecutive modes (full cache lines) instead of 64-byte pieces of eight rows. A short
-// segment's phantom row is not put (it would land on the next segment's first row). The
-// tile holds rows x modes = M x (256 / S) values; every thread of the block calls this.
-template <int S, int LMAX>
-constexpr bool seg_tiled() {
-    return LMAX * (256 + S) * (int)sizeof(double) <= 48 * 1024;
-}
-template <int S, int LMAX, class ST>
-__device__ __forceinline__ void seg_store_tile(const double (&x)[LMAX], ST* base, double* tile,
-                                               const SegLane<S>& sl, const Dims& d) {
-    constexpr int NM = 256 / S;   // modes per block
-    constexpr int TS = NM + 1;    // padded tile row
-    const int m = (int)threadIdx.x / S;
-#pragma unroll
-    for (int u = 0; u < LMAX; ++u)
-        if (u < sl.Lm && (u < sl.Lm - 1 || !sl.shortl)) tile[(sl.a + u) * TS + m] = x[u];
-    __syncthreads();
-    const int nmodes = d.nx * d.nz;
-    const int mode0 = (int)blockIdx.x * NM;
-    for (int e = threadIdx.x; e < d.M * NM; e += 256) {
-        const int row = e / NM, mm = e - (e / NM) * NM;
-        const int mode = mode0 + mm;
-        if (mode < nmodes) {
-            const int pp = mode / d.nz, qq = mode - (mode / d.nz) * d.nz;
-            st(base + ((size_t)(pp * d.ny + 1 + row) * d.nz + qq), tile[row * TS + mm]);
-        }
-    }
-    __syncthreads();   // the tile is free again
 }
 
 // Segmented vorticity + stream-vector pair: the vorticity modes U_w (f = scale * B) are solved
@@ -743,8 +726,7 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
         sl.shortl = NLF > 0 && sl.k >= NLF;
     }
     const int c3 = blockIdx.y;
-    constexpr bool kTile = seg_tiled<S, LMAX>();
-    __shared__ double tile[kTile ? LMAX * (256 + S) : 1];
+    __shared__ double xch[512];
     SegCoef<LMAX> cf;
     seg_coef<LMAX>(cf, triw, sl.cls, sl.ncls, d.M, sl.Lm);
     ST* col = spec.p[c3];
@@ -764,11 +746,8 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
             if (m00 && sl.k == S - 1 && u == ulast) x[u] -= b;
         }
     }
-    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
-    if (kTile)
-        seg_store_tile<S, LMAX, ST>(x, col, tile, sl, d);
-    else
-        seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
+    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong, xch);
+    seg_store<S, LMAX, ST>(x, col, N, d.nz, sl);
     // the stream-vector problem has no shift: its own pivots when the vorticity's differ
     if (triw != tri) seg_coef<LMAX>(cf, tri, sl.cls, sl.ncls, d.M, sl.Lm);
     const double h2 = d.h * d.h;
@@ -781,11 +760,8 @@ __global__ __launch_bounds__(256) void k_tridiag_pair_seg(Dims d, const double* 
         if (m00 && sl.k == S - 1 && u == ulast) f -= whi;
         x[u] = f;
     }
-    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong);
-    if (kTile)
-        seg_store_tile<S, LMAX, ST>(x, spec2.p[c3], tile, sl, d);
-    else
-        seg_store<S, LMAX, ST>(x, spec2.p[c3], N, d.nz, sl);
+    seg_solve<S, LMAX>(x, cf, sl.k, sl.shortl, sl.Lm, sl.nlong, xch);
+    seg_store<S, LMAX, ST>(x, spec2.p[c3], N, d.nz, sl);
 }
 
 // dht_z_out: Hartley along z of the solved modes, then u = result (add = 0) or u += result.
