@@ -1264,6 +1264,103 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
     }
 }
 
+
+// resid_flow with two consecutive z per lane (n_z a multiple of 128, so a wave covers 128
+// consecutive z of one row): every load moves 16 bytes, half the load instructions of the
+// one-z form; the z neighbours inside the pair come from the pair itself, across lanes by
+// shuffles, and the wave's two edge values by one wave-uniform load each. Same sums per node
+// as k_resid_flow; a lane adds its two nodes' squares together.
+__global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, CPtr3 om, CPtr3 src, CPtr3 ps,
+                                                       SlabGrid sg, double ashift,
+                                                       double* __restrict__ partials) {
+    __shared__ double sh[4 * 4];
+    const int nb = sg.gx * sg.gi;
+    const int lb0 = xcd_block(blockIdx.x, 3 * nb);
+    const int c = lb0 / nb;
+    const int lb = lb0 - c * nb;
+    const int bi = lb / sg.gx;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
+    const double* wc = c == 0 ? om.p[0] : c == 1 ? om.p[1] : om.p[2];
+    const double* sc = c == 0 ? src.p[0] : c == 1 ? src.p[1] : src.p[2];
+    const double* pc = c == 0 ? ps.p[0] : c == 1 ? ps.p[1] : ps.p[2];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    const int hz = d.nz >> 1;
+    if (t < d.M * hz) {
+        const int jj = t / hz;
+        const int k = 2 * (t - jj * hz);
+        const int j = jj + 1;
+        const int plane = d.ny * d.nz;
+        const int off = j * d.nz + k;
+        const int ln = threadIdx.x & 63;
+        const int k0 = k - 2 * ln;
+        const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+        const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
+        auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
+        auto zn = [&](const double* u, int rb, double2 v, double& zm0, double& zp1) {
+            const double prev = __shfl_up(v.y, 1, 64), next = __shfl_down(v.x, 1, 64);
+            const double em = u[rb + kme], ep = u[rb + kpe];
+            zm0 = ln == 0 ? em : prev;
+            zp1 = ln == 63 ? ep : next;
+        };
+        const int i0 = bi * sg.ci;
+        const int i1 = min(d.nx, i0 + sg.ci);
+        const int im0 = (i0 == 0) ? d.nx - 1 : i0 - 1;
+        double2 wm = ld2v(wc + im0 * plane + off), wx = ld2v(wc + i0 * plane + off);
+        double2 pm = ld2v(pc + im0 * plane + off), px = ld2v(pc + i0 * plane + off);
+        const bool lo = j == 1, hi = j == d.M;
+#pragma unroll 2
+        for (int i = i0; i < i1; ++i) {
+            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+            const int rb = i * plane + j * d.nz;
+            const int c0 = rb + k;
+            const double2 wp = ld2v(wc + ip * plane + off);
+            const double2 pp = ld2v(pc + ip * plane + off);
+            {
+                const double2 b = ld2v(sc + c0);
+                const double2 ylo = ld2v(wc + c0 - d.nz), yhi = ld2v(wc + c0 + d.nz);
+                double zm0, zp1;
+                zn(wc, rb, wx, zm0, zp1);
+                const double l0 = (wp.x + wm.x + ylo.x + yhi.x + wx.y + zm0 - 6.0 * wx.x) * d.inv_h2;
+                const double l1 = (wp.y + wm.y + ylo.y + yhi.y + zp1 + wx.x - 6.0 * wx.y) * d.inv_h2;
+                const double r0 = b.x - (ashift != 0.0 ? l0 - ashift * wx.x : l0);
+                const double r1 = b.y - (ashift != 0.0 ? l1 - ashift * wx.y : l1);
+                const double t0 = b.x - ((lo ? ylo.x : 0.0) + (hi ? yhi.x : 0.0)) * d.inv_h2;
+                const double t1 = b.y - ((lo ? ylo.y : 0.0) + (hi ? yhi.y : 0.0)) * d.inv_h2;
+                a[0] += r0 * r0 + r1 * r1;
+                a[1] += t0 * t0 + t1 * t1;
+            }
+            {
+                const double2 ylo = ld2v(pc + c0 - d.nz), yhi = ld2v(pc + c0 + d.nz);
+                double zm0, zp1;
+                zn(pc, rb, px, zm0, zp1);
+                const double l0 = (pp.x + pm.x + ylo.x + yhi.x + px.y + zm0 - 6.0 * px.x) * d.inv_h2;
+                const double l1 = (pp.y + pm.y + ylo.y + yhi.y + zp1 + px.x - 6.0 * px.y) * d.inv_h2;
+                const double r0 = -wx.x - l0, r1 = -wx.y - l1;
+                const double t0 = -wx.x - ((lo ? ylo.x : 0.0) + (hi ? yhi.x : 0.0)) * d.inv_h2;
+                const double t1 = -wx.y - ((lo ? ylo.y : 0.0) + (hi ? yhi.y : 0.0)) * d.inv_h2;
+                a[2] += r0 * r0 + r1 * r1;
+                a[3] += t0 * t0 + t1 * t1;
+            }
+            wm = wx;
+            wx = wp;
+            pm = px;
+            px = pp;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double v = wave_sum(a[q]);
+        if (lane == 0) sh[4 * q + w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        partials[(3 * q + c) * kMaxPartialBlocks + lb] =
+            sh[4 * q + 0] + sh[4 * q + 1] + sh[4 * q + 2] + sh[4 * q + 3];
+    }
+}
+
 // check: relative residual sqrt(sum_c r^2 / sum_c b~^2) in a fixed summation order; sets the
 // convergence flag that gates the following cycles, counts the cycle and raises ST_NOCONV
 // on the last allowed cycle, ST_NONFINITE on NaN/Inf.
@@ -1553,6 +1650,15 @@ int resid_blocks(const Dims& d) {
     return g.gx * g.gi;
 }
 
+static SlabGrid resid_flow_grid(const Dims& d) {
+    return d.nz % 128 == 0 ? slab_grid(d.M * d.nz / 2, d.nx, 1024) : resid_grid(d);
+}
+
+int resid_flow_blocks(const Dims& d) {
+    const SlabGrid g = resid_flow_grid(d);
+    return g.gx * g.gi;
+}
+
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate,
                        int slot0) {
@@ -1566,9 +1672,12 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
                        const double* const src[3], const double* const ps[3], double ashift,
                        double* partials) {
     const CPtr3 o{{om[0], om[1], om[2]}}, f{{src[0], src[1], src[2]}}, p{{ps[0], ps[1], ps[2]}};
-    const SlabGrid g = resid_grid(d);
+    const SlabGrid g = resid_flow_grid(d);
+    if (d.nz % 128 == 0)
+        launch_kernel(k_resid_flow2, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
+                      ashift, partials);
     // a whole number of waves per row lets the z neighbours come from shuffles
-    if (d.nz % 64 == 0)
+    else if (d.nz % 64 == 0)
         launch_kernel(k_resid_flow<true>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p,
                       g, ashift, partials);
     else
@@ -1578,7 +1687,7 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
 
 void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,
                        double* scal, int* istat) {
-    launch_kernel(k_check_flow, dim3(1), dim3(1024), 0, s, partials, resid_blocks(d), rtol, scal,
+    launch_kernel(k_check_flow, dim3(1), dim3(1024), 0, s, partials, resid_flow_blocks(d), rtol, scal,
                   istat);
 }
 

@@ -420,7 +420,7 @@ void enqueue_step(vs_state* S, double dt, bool more_follow) {
     const double* const psc[3] = {S->ps[0], S->ps[1], S->ps[2]};
     PrevCheck ck{nullptr, 0, 0.0, nullptr};
     if (S->check_pending) {
-        ck = PrevCheck{S->part, resid_blocks(S->d), S->p.poisson_rtol, S->istat};
+        ck = PrevCheck{S->part, resid_flow_blocks(S->d), S->p.poisson_rtol, S->istat};
         S->check_pending = false;
     }
     timed(S, K_ADVANCE, [&] {

@@ -188,6 +188,7 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
                       void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
                       const int* gate);
 int resid_blocks(const Dims& d);
+int resid_flow_blocks(const Dims& d);
 // Both flow residuals (vorticity, eq. (5b): b = S; stream vector, eq. (5c): b = -omega) in
 // one pass, into partial slots 0-5 and 6-11 as two resid_norm launches would write them.
 // ashift != 0: the vorticity operator is L_h - ashift (the inertial variant).

@@ -188,13 +188,18 @@ def test_step_parity_one_cycle(seed):
     assert sc["relres"] <= w.rtol
 
 
-def test_combined_flow_residual_matches_separate_passes():
+@pytest.mark.parametrize("shape", [None, (16, 24, 64), (16, 24, 128), (12, 20, 256)])
+def test_combined_flow_residual_matches_separate_passes(shape):
     """With one cycle per solve the two flow residuals run as one combined pass; with two
     cycles each solve is verified by its own residual pass. The direct solve converges in
     cycle 0 either way, so the fields agree bit for bit and the largest relative residual
-    of the two verifications agrees to rounding."""
-    w = workload("vesicle32", seed=3)
-    say("case combined vs separate flow residuals vesicle32 seed=3")
+    of the two verifications agrees to rounding. The combined pass has three forms, by n_z:
+    one z per lane (32), z neighbours by shuffles (64), two z per lane (128, 256)."""
+    if shape is None:
+        w = workload("vesicle32", seed=3)
+    else:
+        w = workload("droplet256", grid=GridSpec(*shape), R0=5.0)
+    say(f"case combined vs separate flow residuals {w.name} {w.grid.shape}")
     one = P.solver_for(w, max_cycles=1)
     two = P.solver_for(w, max_cycles=2)
     one.step(w.dt, 3)
