@@ -76,6 +76,112 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
     }
 }
 
+
+// k_advance_x with two consecutive z per lane (n_z a multiple of 128, so a wave covers 128
+// consecutive z of one row): every field access moves 16 bytes, and the z neighbours inside
+// the pair come from the pair itself, across lanes by shuffles, and the wave's two edge values
+// by one wave-uniform load each. The psi values of the wall rows are loaded too (in bounds,
+// unused there), so that no branch guards a load. Same arithmetic per node as k_advance_x,
+// so the two forms agree bit for bit.
+constexpr int kAdvSlab2 = 4;
+
+__global__ __launch_bounds__(kBlock) void k_advance_x2(
+    const double* __restrict__ phi, const double* __restrict__ mu,
+    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
+    double* __restrict__ out, Dims d, SlabGrid sg, double* scal, double dt, double mob,
+    double vz_lo, double vz_hi, PrevCheck ck) {
+    if (ck.partials && blockIdx.x == 0) {
+        __shared__ double shc[4 * 16];
+        flow_check_block(ck.partials, ck.nblocks, ck.rtol, scal, ck.istat, shc);
+    }
+    const int nb = sg.gx * sg.gi;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int bi = lb / sg.gx;
+    const int hz = d.nz >> 1;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
+    if (t >= d.ny * hz) return;
+    const int j = t / hz, k = 2 * (t - (t / hz) * hz);
+    const int i0 = bi * sg.ci, i1 = min(d.nx, i0 + sg.ci);
+    const int plane = d.ny * d.nz;
+    const int jp = (j + 1 == d.ny) ? d.ny - 2 : j + 1;   // mirror ghosts (phi, mu)
+    const int jm = (j == 0) ? 1 : j - 1;
+    const int ln = threadIdx.x & 63;
+    const int k0 = k - 2 * ln;
+    const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+    const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
+    const int o = j * d.nz + k;
+    const int oyp = jp * d.nz + k, oym = jm * d.nz + k;
+    const int re = j * d.nz;                             // row start inside a plane
+    const double lam = scal[SC_LAMV];
+    auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
+    // z neighbours of the pair v at row offset rb: (zp, zm) of node k and of node k + 1
+    auto zn = [&](const double* u, size_t rb, double2 v, double& zpa, double& zma, double& zpb,
+                  double& zmb) {
+        const double prev = __shfl_up(v.y, 1, 64), next = __shfl_down(v.x, 1, 64);
+        const double em = u[rb + kme], ep = u[rb + kpe];
+        zpa = v.y;
+        zma = ln == 0 ? em : prev;
+        zpb = ln == 63 ? ep : next;
+        zmb = v.x;
+    };
+    auto pl = [&](int i) { return (size_t)((i + d.nx) % d.nx) * plane; };
+    size_t b = pl(i0 - 1);
+    double2 phm = ld2v(phi + b + o), mum = ld2v(mu + b + o), pym = ld2v(py + b + o),
+            pzm = ld2v(pz + b + o);
+    b = pl(i0);
+    double2 ph0 = ld2v(phi + b + o), mu0 = ld2v(mu + b + o), py0 = ld2v(py + b + o),
+            pz0 = ld2v(pz + b + o);
+    for (int i = i0; i < i1; ++i) {
+        const size_t bc = (size_t)i * plane, bn = pl(i + 1);
+        const double2 php = ld2v(phi + bn + o), mup = ld2v(mu + bn + o);
+        const double2 pyp = ld2v(py + bn + o), pzp = ld2v(pz + bn + o);
+        const double2 myp = ld2v(mu + bc + oyp), mym = ld2v(mu + bc + oym);
+        const double2 fyp = ld2v(phi + bc + oyp), fym = ld2v(phi + bc + oym);
+        const double2 zyp = ld2v(pz + bc + oyp), zym = ld2v(pz + bc + oym);
+        const double2 xyp = ld2v(px + bc + oyp), xym = ld2v(px + bc + oym);
+        const double2 pxc = ld2v(px + bc + o);
+        double mzpa, mzma, mzpb, mzmb, fzpa, fzma, fzpb, fzmb;
+        double yzpa, yzma, yzpb, yzmb, xzpa, xzma, xzpb, xzmb;
+        zn(mu, bc + re, mu0, mzpa, mzma, mzpb, mzmb);
+        zn(phi, bc + re, ph0, fzpa, fzma, fzpb, fzmb);
+        zn(py, bc + re, py0, yzpa, yzma, yzpb, yzmb);
+        zn(px, bc + re, pxc, xzpa, xzma, xzpb, xzmb);
+        double2 res;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double c_mup = h ? mup.y : mup.x, c_mum = h ? mum.y : mum.x;
+            const double c_mu0 = h ? mu0.y : mu0.x;
+            const double c_php = h ? php.y : php.x, c_phm = h ? phm.y : phm.x;
+            const double c_ph0 = h ? ph0.y : ph0.x;
+            const double lmu = (c_mup + c_mum + (h ? myp.y : myp.x) + (h ? mym.y : mym.x) +
+                                (h ? mzpb : mzpa) + (h ? mzmb : mzma) - 6.0 * c_mu0) * d.inv_h2;
+            const double dx = (c_php - c_phm) * d.inv_2h;
+            const double dy = ((h ? fyp.y : fyp.x) - (h ? fym.y : fym.x)) * d.inv_2h;
+            const double dz = ((h ? fzpb : fzpa) - (h ? fzmb : fzma)) * d.inv_2h;
+            double vx = 0.0, vy = 0.0, vz;
+            if (j == 0) {
+                vz = vz_lo;
+            } else if (j == d.ny - 1) {
+                vz = vz_hi;
+            } else {
+                vx = (((h ? zyp.y : zyp.x) - (h ? zym.y : zym.x)) -
+                      ((h ? yzpb : yzpa) - (h ? yzmb : yzma))) * d.inv_2h;
+                vy = (((h ? xzpb : xzpa) - (h ? xzmb : xzma)) -
+                      ((h ? pzp.y : pzp.x) - (h ? pzm.y : pzm.x))) * d.inv_2h;
+                vz = (((h ? pyp.y : pyp.x) - (h ? pym.y : pym.x)) -
+                      ((h ? xyp.y : xyp.x) - (h ? xym.y : xym.x))) * d.inv_2h;
+            }
+            const double r = c_ph0 + dt * (mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
+            if (h) res.y = r; else res.x = r;
+        }
+        *reinterpret_cast<double2*>(out + bc + o) = res;
+        phm = ph0; ph0 = php;
+        mum = mu0; mu0 = mup;
+        pym = py0; py0 = pyp;
+        pzm = pz0; pz0 = pzp;
+    }
+}
+
 // V = (|Omega| + h^3 sum_w phi)/2, A = 3/(2 sqrt 2) h^3 sum_w(...); then
 // lambda_V = 2 rate_V (V0 - V)/(M |Omega|) and gamma_A = gamma0 + k_A (A - A0)/A0
 // (off when k_A = 0 or A0 = 0); init also sets V0 = V, A0 = A. Every block of the calling
@@ -359,6 +465,67 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
     }
 }
 
+
+// k_va_partials with two consecutive z per lane (n_z a multiple of 128; as k_advance_x2):
+// 16-byte loads, z neighbours from the pair, shuffles and the wave's edge values.
+__global__ __launch_bounds__(kBlock) void k_va_partials2(const double* __restrict__ phi, Dims d,
+                                                        double eps, SlabGrid sg,
+                                                        double* __restrict__ partials) {
+    __shared__ double sh[2 * 16];
+    const int nb = sg.gx * sg.gi;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int bi = lb / sg.gx;
+    const int hz = d.nz >> 1;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (t < d.ny * hz) {
+        const int j = t / hz;
+        const int k = 2 * (t - j * hz);
+        const double w = (j == 0 || j == d.ny - 1) ? 0.5 : 1.0;
+        const double inv4e = 0.25 / eps;
+        const int i0 = bi * sg.ci, i1 = min(d.nx, (bi + 1) * sg.ci);
+        const int plane = d.ny * d.nz;
+        const int o = j * d.nz + k;
+        const int oyp = ((j + 1 == d.ny) ? d.ny - 2 : j + 1) * d.nz + k;
+        const int oym = ((j == 0) ? 1 : j - 1) * d.nz + k;
+        const int ln = threadIdx.x & 63;
+        const int k0 = k - 2 * ln;
+        const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+        const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
+        const int re = j * d.nz;
+        auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
+        double2 pm = ld2v(phi + (size_t)((i0 + d.nx - 1) % d.nx) * plane + o);
+        double2 p0 = ld2v(phi + (size_t)i0 * plane + o);
+#pragma unroll 2
+        for (int i = i0; i < i1; ++i) {
+            const size_t bc = (size_t)i * plane;
+            const int inx = (i + 1 == d.nx) ? 0 : i + 1;
+            const double2 pp = ld2v(phi + (size_t)inx * plane + o);
+            const double2 yp = ld2v(phi + bc + oyp), ym = ld2v(phi + bc + oym);
+            const double em = phi[bc + re + kme], ep = phi[bc + re + kpe];
+            const double prev = __shfl_up(p0.y, 1, 64), next = __shfl_down(p0.x, 1, 64);
+            const double zma = ln == 0 ? em : prev, zpb = ln == 63 ? ep : next;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double p = h ? p0.y : p0.x;
+                const double dx = ((h ? pp.y : pp.x) - (h ? pm.y : pm.x)) * d.inv_2h;
+                const double dy = ((h ? yp.y : yp.x) - (h ? ym.y : ym.x)) * d.inv_2h;
+                const double dz = ((h ? zpb : p0.y) - (h ? p0.x : zma)) * d.inv_2h;
+                const double q = p * p - 1.0;
+                acc[0] += w * p;
+                acc[1] += w * (0.5 * eps * (dx * dx + dy * dy + dz * dz) + q * q * inv4e);
+            }
+            pm = p0;
+            p0 = pp;
+        }
+    }
+    block_sum<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        partials[0 * kMaxPartialBlocks + blockIdx.x] = acc[0];
+        partials[1 * kMaxPartialBlocks + blockIdx.x] = acc[1];
+    }
+}
+
 struct Om3 {
     const double* p[3];
 };
@@ -392,6 +559,69 @@ __global__ __launch_bounds__(kBlock) void k_source(const double* __restrict__ ph
     sx[n.c] = s0;
     sy[n.c] = s1;
     sz[n.c] = s2;
+}
+
+
+// k_source with two consecutive z per lane (n_z a multiple of 128; as k_advance_x2): 16-byte
+// loads and stores, z neighbours from the pair, shuffles and the wave's edge values. Same
+// arithmetic per node as k_source.
+__global__ __launch_bounds__(kBlock) void k_source2(const double* __restrict__ phi,
+                                                   const double* __restrict__ mu, Dims d,
+                                                   double inv_eta, double* __restrict__ sx,
+                                                   double* __restrict__ sy, double* __restrict__ sz,
+                                                   double a, Om3 om) {
+    const int gx = gridDim.x;
+    const int lb = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
+    const int i = lb / gx;
+    const int hz = d.nz >> 1;
+    const int t = (lb - i * gx) * kBlock + threadIdx.x;
+    if (t >= d.ny * hz) return;
+    const int j = t / hz, k = 2 * (t - (t / hz) * hz);
+    if (j == 0 || j == d.ny - 1) return;   // whole waves: a wave covers part of one row
+    const int plane = d.ny * d.nz;
+    const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+    const int im = (i == 0) ? d.nx - 1 : i - 1;
+    const int ln = threadIdx.x & 63;
+    const int k0 = k - 2 * ln;
+    const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+    const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
+    const int rb = i * plane + j * d.nz;
+    const int c = rb + k;
+    auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
+    const double2 fxp = ld2v(phi + ip * plane + j * d.nz + k), fxm = ld2v(phi + im * plane + j * d.nz + k);
+    const double2 fyp = ld2v(phi + c + d.nz), fym = ld2v(phi + c - d.nz);
+    const double2 mxp = ld2v(mu + ip * plane + j * d.nz + k), mxm = ld2v(mu + im * plane + j * d.nz + k);
+    const double2 myp = ld2v(mu + c + d.nz), mym = ld2v(mu + c - d.nz);
+    const double2 fc = ld2v(phi + c), mc = ld2v(mu + c);
+    const double fem = phi[rb + kme], fep = phi[rb + kpe];
+    const double mem = mu[rb + kme], mep = mu[rb + kpe];
+    const double fprev = __shfl_up(fc.y, 1, 64), fnext = __shfl_down(fc.x, 1, 64);
+    const double mprev = __shfl_up(mc.y, 1, 64), mnext = __shfl_down(mc.x, 1, 64);
+    const double fzma = ln == 0 ? fem : fprev, fzpb = ln == 63 ? fep : fnext;
+    const double mzma = ln == 0 ? mem : mprev, mzpb = ln == 63 ? mep : mnext;
+    double2 r0, r1, r2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const double fx = ((h ? fxp.y : fxp.x) - (h ? fxm.y : fxm.x)) * d.inv_2h;
+        const double fy = ((h ? fyp.y : fyp.x) - (h ? fym.y : fym.x)) * d.inv_2h;
+        const double fz = ((h ? fzpb : fc.y) - (h ? fc.x : fzma)) * d.inv_2h;
+        const double mx = ((h ? mxp.y : mxp.x) - (h ? mxm.y : mxm.x)) * d.inv_2h;
+        const double my = ((h ? myp.y : myp.x) - (h ? mym.y : mym.x)) * d.inv_2h;
+        const double mz = ((h ? mzpb : mc.y) - (h ? mc.x : mzma)) * d.inv_2h;
+        const double s0 = (fy * mz - fz * my) * inv_eta;
+        const double s1 = (fz * mx - fx * mz) * inv_eta;
+        const double s2 = (fx * my - fy * mx) * inv_eta;
+        if (h) { r0.y = s0; r1.y = s1; r2.y = s2; } else { r0.x = s0; r1.x = s1; r2.x = s2; }
+    }
+    if (a != 0.0) {
+        const double2 w0 = ld2v(om.p[0] + c), w1 = ld2v(om.p[1] + c), w2 = ld2v(om.p[2] + c);
+        r0.x -= a * w0.x; r0.y -= a * w0.y;
+        r1.x -= a * w1.x; r1.y -= a * w1.y;
+        r2.x -= a * w2.x; r2.y -= a * w2.y;
+    }
+    *reinterpret_cast<double2*>(sx + c) = r0;
+    *reinterpret_cast<double2*>(sy + c) = r1;
+    *reinterpret_cast<double2*>(sz + c) = r2;
 }
 
 // dst[(i, j, k)] = prof[j]: the no-body channel fields as initial guesses and wall rows.
@@ -436,6 +666,14 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
                     const double* const psi[3], double* phi_out, double* scal, double dt,
                     double mobility, double vz_lo, double vz_hi, const PrevCheck& ck) {
     SlabGrid g;
+    if (d.nz % 128 == 0) {
+        g.gx = (d.ny * d.nz / 2 + kBlock - 1) / kBlock;
+        g.ci = kAdvSlab2;
+        g.gi = (d.nx + kAdvSlab2 - 1) / kAdvSlab2;
+        launch_kernel(k_advance_x2, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu, psi[0],
+                      psi[1], psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+        return;
+    }
     g.gx = (d.ny * d.nz + kBlock - 1) / kBlock;
     g.ci = kAdvSlab;
     g.gi = (d.nx + kAdvSlab - 1) / kAdvSlab;
@@ -445,16 +683,25 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
 
 constexpr int kVaMaxBlocks = 1024;   // longer x-slabs per lane, a shorter final sum
 
+// n_z a multiple of 128: two z per lane (k_va_partials2)
+static SlabGrid va_grid(const Dims& d) {
+    return slab_grid(d.nz % 128 == 0 ? d.ny * d.nz / 2 : d.ny * d.nz, d.nx, kVaMaxBlocks);
+}
+
 int va_partial_blocks(const Dims& d) {
-    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kVaMaxBlocks);
+    const SlabGrid g = va_grid(d);
     return g.gx * g.gi;
 }
 
 void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
                         double* partials) {
-    const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kVaMaxBlocks);
-    launch_kernel(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
-                       partials);
+    const SlabGrid g = va_grid(d);
+    if (d.nz % 128 == 0)
+        launch_kernel(k_va_partials2, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
+                      partials);
+    else
+        launch_kernel(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
+                      partials);
 }
 
 void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const VaFinal& va,
@@ -484,6 +731,12 @@ void launch_source(hipStream_t s, const Dims& d, const double* phi, const double
                    const double* const omega[3]) {
     Om3 om{{nullptr, nullptr, nullptr}};
     if (a != 0.0) om = Om3{{omega[0], omega[1], omega[2]}};
+    if (d.nz % 128 == 0) {
+        const dim3 g((unsigned)((d.ny * d.nz / 2 + kBlock - 1) / kBlock), (unsigned)d.nx, 1);
+        launch_kernel(k_source2, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
+                      src[2], a, om);
+        return;
+    }
     launch_kernel(k_source, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0],
                   src[1], src[2], a, om);
 }

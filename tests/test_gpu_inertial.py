@@ -73,6 +73,9 @@ CASES = [
     # bending membrane, Poiseuille, a h^2 = rho/(eta dt) h^2 = 1 and 500
     ("vesicle32-weak", workload("vesicle32", rho=1e-3, max_cycles=1, rate_V=10.0, k_A=1.0), 4),
     ("vesicle32-strong", workload("vesicle32", rho=0.5, max_cycles=1), 3),
+    # n_z = 128: the two-z-per-lane forms of the source, advance and residual kernels
+    ("vesicle-nz128", workload("vesicle32", grid=GridSpec(32, 34, 128), rho=0.05, max_cycles=1,
+                               rate_V=10.0, k_A=1.0), 3),
     # Cahn-Hilliard droplet in a ragged Couette channel (M = 31 rows, nz = 48)
     ("droplet-couette", workload("droplet256", grid=GridSpec(32, 33, 48), shape="sphere", R0=7.0,
                                  rho=0.02, max_cycles=1, eta=0.7), 4),
