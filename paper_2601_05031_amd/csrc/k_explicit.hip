@@ -81,8 +81,9 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
 // consecutive z of one row): every field access moves 16 bytes, and the z neighbours inside
 // the pair come from the pair itself, across lanes by shuffles, and the wave's two edge values
 // by one wave-uniform load each. The psi values of the wall rows are loaded too (in bounds,
-// unused there), so that no branch guards a load. Same arithmetic per node as k_advance_x,
-// so the two forms agree bit for bit.
+// unused there), so that no branch guards a load, and the next plane's centres are loaded
+// last (pinned by a scheduling barrier), so they stay in flight while the current plane is
+// computed. Same arithmetic per node as k_advance_x, so the two forms agree bit for bit.
 constexpr int kAdvSlab2 = 4;
 
 __global__ __launch_bounds__(kBlock) void k_advance_x2(
@@ -115,10 +116,9 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
     const double lam = scal[SC_LAMV];
     auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
     // z neighbours of the pair v at row offset rb: (zp, zm) of node k and of node k + 1
-    auto zn = [&](const double* u, size_t rb, double2 v, double& zpa, double& zma, double& zpb,
+    auto zn = [&](double2 v, double em, double ep, double& zpa, double& zma, double& zpb,
                   double& zmb) {
         const double prev = __shfl_up(v.y, 1, 64), next = __shfl_down(v.x, 1, 64);
-        const double em = u[rb + kme], ep = u[rb + kpe];
         zpa = v.y;
         zma = ln == 0 ? em : prev;
         zpb = ln == 63 ? ep : next;
@@ -133,19 +133,24 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
             pz0 = ld2v(pz + b + o);
     for (int i = i0; i < i1; ++i) {
         const size_t bc = (size_t)i * plane, bn = pl(i + 1);
-        const double2 php = ld2v(phi + bn + o), mup = ld2v(mu + bn + o);
-        const double2 pyp = ld2v(py + bn + o), pzp = ld2v(pz + bn + o);
         const double2 myp = ld2v(mu + bc + oyp), mym = ld2v(mu + bc + oym);
         const double2 fyp = ld2v(phi + bc + oyp), fym = ld2v(phi + bc + oym);
         const double2 zyp = ld2v(pz + bc + oyp), zym = ld2v(pz + bc + oym);
         const double2 xyp = ld2v(px + bc + oyp), xym = ld2v(px + bc + oym);
         const double2 pxc = ld2v(px + bc + o);
+        const size_t ro = bc + re;
+        const double emu = mu[ro + kme], epu = mu[ro + kpe], eph = phi[ro + kme], eph2 = phi[ro + kpe];
+        const double epy = py[ro + kme], epy2 = py[ro + kpe], epx = px[ro + kme], epx2 = px[ro + kpe];
+        // the next plane's centres last: they stay in flight while this plane is computed
+        const double2 php = ld2v(phi + bn + o), mup = ld2v(mu + bn + o);
+        const double2 pyp = ld2v(py + bn + o), pzp = ld2v(pz + bn + o);
+        __builtin_amdgcn_sched_barrier(0);
         double mzpa, mzma, mzpb, mzmb, fzpa, fzma, fzpb, fzmb;
         double yzpa, yzma, yzpb, yzmb, xzpa, xzma, xzpb, xzmb;
-        zn(mu, bc + re, mu0, mzpa, mzma, mzpb, mzmb);
-        zn(phi, bc + re, ph0, fzpa, fzma, fzpb, fzmb);
-        zn(py, bc + re, py0, yzpa, yzma, yzpb, yzmb);
-        zn(px, bc + re, pxc, xzpa, xzma, xzpb, xzmb);
+        zn(mu0, emu, epu, mzpa, mzma, mzpb, mzmb);
+        zn(ph0, eph, eph2, fzpa, fzma, fzpb, fzmb);
+        zn(py0, epy, epy2, yzpa, yzma, yzpb, yzmb);
+        zn(pxc, epx, epx2, xzpa, xzma, xzpb, xzmb);
         double2 res;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {

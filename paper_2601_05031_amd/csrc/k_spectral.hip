@@ -1268,8 +1268,10 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
 // resid_flow with two consecutive z per lane (n_z a multiple of 128, so a wave covers 128
 // consecutive z of one row): every load moves 16 bytes, half the load instructions of the
 // one-z form; the z neighbours inside the pair come from the pair itself, across lanes by
-// shuffles, and the wave's two edge values by one wave-uniform load each. Same sums per node
-// as k_resid_flow; a lane adds its two nodes' squares together.
+// shuffles, and the wave's two edge values by one wave-uniform load each. The next plane's
+// centres are loaded last (a scheduling barrier keeps them there), so they stay in flight
+// while the current plane is summed. Same sums per node as k_resid_flow; a lane adds its two
+// nodes' squares together.
 __global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, CPtr3 om, CPtr3 src, CPtr3 ps,
                                                        SlabGrid sg, double ashift,
                                                        double* __restrict__ partials) {
@@ -1296,9 +1298,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, CPtr3 om, CPtr3 
         const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
         const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
         auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
-        auto zn = [&](const double* u, int rb, double2 v, double& zm0, double& zp1) {
+        auto zn = [&](double2 v, double em, double ep, double& zm0, double& zp1) {
             const double prev = __shfl_up(v.y, 1, 64), next = __shfl_down(v.x, 1, 64);
-            const double em = u[rb + kme], ep = u[rb + kpe];
             zm0 = ln == 0 ? em : prev;
             zp1 = ln == 63 ? ep : next;
         };
@@ -1313,13 +1314,18 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, CPtr3 om, CPtr3 
             const int ip = (i + 1 == d.nx) ? 0 : i + 1;
             const int rb = i * plane + j * d.nz;
             const int c0 = rb + k;
+            const double2 b = ld2v(sc + c0);
+            const double2 ylo = ld2v(wc + c0 - d.nz), yhi = ld2v(wc + c0 + d.nz);
+            const double2 qlo = ld2v(pc + c0 - d.nz), qhi = ld2v(pc + c0 + d.nz);
+            const int ome = rb + kme, ope = rb + kpe;
+            const double wem = wc[ome], wep = wc[ope], pem = pc[ome], pep = pc[ope];
+            // the next plane's centres last: they stay in flight while this plane is summed
             const double2 wp = ld2v(wc + ip * plane + off);
             const double2 pp = ld2v(pc + ip * plane + off);
+            __builtin_amdgcn_sched_barrier(0);
             {
-                const double2 b = ld2v(sc + c0);
-                const double2 ylo = ld2v(wc + c0 - d.nz), yhi = ld2v(wc + c0 + d.nz);
                 double zm0, zp1;
-                zn(wc, rb, wx, zm0, zp1);
+                zn(wx, wem, wep, zm0, zp1);
                 const double l0 = (wp.x + wm.x + ylo.x + yhi.x + wx.y + zm0 - 6.0 * wx.x) * d.inv_h2;
                 const double l1 = (wp.y + wm.y + ylo.y + yhi.y + zp1 + wx.x - 6.0 * wx.y) * d.inv_h2;
                 const double r0 = b.x - (ashift != 0.0 ? l0 - ashift * wx.x : l0);
@@ -1330,9 +1336,9 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, CPtr3 om, CPtr3 
                 a[1] += t0 * t0 + t1 * t1;
             }
             {
-                const double2 ylo = ld2v(pc + c0 - d.nz), yhi = ld2v(pc + c0 + d.nz);
+                const double2 ylo = qlo, yhi = qhi;
                 double zm0, zp1;
-                zn(pc, rb, px, zm0, zp1);
+                zn(px, pem, pep, zm0, zp1);
                 const double l0 = (pp.x + pm.x + ylo.x + yhi.x + px.y + zm0 - 6.0 * px.x) * d.inv_h2;
                 const double l1 = (pp.y + pm.y + ylo.y + yhi.y + zp1 + px.x - 6.0 * px.y) * d.inv_h2;
                 const double r0 = -wx.x - l0, r1 = -wx.y - l1;
