@@ -46,6 +46,8 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
         "tridiag_y": 48 * Ni,         # 3 spectral fields in and out
         "tridiag_pair": 72 * Ni,      # source modes in; vorticity and stream-vector modes out
         "dht_z_out": 48 * Ni,         # 3 spectral fields in; 3 solution fields out
+        "dht_x_pair": 96 * Ni,        # omega and psi modes (6 fields) in and out
+        "dht_z_out_pair": 96 * Ni,    # 6 spectral fields in; omega(3), psi(3) out
         "resid_norm_omega": 48 * Ni,  # S(3), omega(3) in
         "resid_norm_psi": 48 * Ni,    # omega(3), psi(3) in
         "resid_norm_flow": 72 * Ni,   # omega(3), S(3), psi(3) in: both flow residuals

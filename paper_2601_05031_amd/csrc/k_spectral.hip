@@ -13,7 +13,8 @@
 //   dht_x            : Hartley along x, in place
 //   tridiag_pair     : vorticity modes (walls in mode (0, 0)), then the stream-vector modes
 //                      from them, scaled by h^2/(nx nz), into two spectral buffers
-//   dht_x, dht_z_out : Hartley along x, then z, for each of the two fields
+//   dht_x, dht_z_out : Hartley along x, then z, of both fields together (six components
+//                      per launch)
 //   resid_flow, check: ||b - L_h u||^2 and ||b~||^2 of both problems, relative residuals
 // The inertial variant (SM eq. (36)) runs the same passes for (L_h - a) omega = S - a omega^n:
 // its vorticity modes take the pivots of the shifted diagonal, its residual the shifted
@@ -46,6 +47,15 @@ struct CPtr3 {
 template <class ST>
 struct SPtr3 {
     ST* p[3];
+};
+// Up to six components for the two-pass transforms: the vorticity and stream-vector fields of
+// a step go through one launch per direction.
+template <class ST>
+struct SPtr6 {
+    ST* p[6];
+};
+struct Ptr6 {
+    double* p[6];
 };
 
 // Loads widen to double and stores narrow from double: inside a kernel all arithmetic is FP64.
@@ -1007,8 +1017,10 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
 
 // dht_x, two-pass form: block = (2L consecutive z-modes q, interior row j, component c);
 // lines are the q-pairs (q, q+1), read and written as one 16-byte value.
-template <int B, int A, class ST>
-__global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ tw, SPtr3<ST> spec,
+// NC: the component count of the launch (3, or 6 for the vorticity and stream-vector fields
+// together); the code is the same, the symbol tells the two launches apart in traces.
+template <int B, int A, class ST, int NC>
+__global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ tw, SPtr6<ST> spec,
                                           const int* gate) {
     if (gate && *gate) return;
     using P = TwoPass<B, A>;
@@ -1033,9 +1045,10 @@ __global__ __launch_bounds__(64) void k_hx(Dims d, const double2* __restrict__ t
 }
 
 // dht_z_out, two-pass form: block = (2L consecutive interior rows, component c).
-template <int B, int A, class ST>
-__global__ __launch_bounds__(64) void k_hz_out(Dims d, const double2* __restrict__ tw, SPtr3<ST> spec,
-                                              Ptr3 u, int add, const int* gate) {
+// NC as for k_hx.
+template <int B, int A, class ST, int NC>
+__global__ __launch_bounds__(64) void k_hz_out(Dims d, const double2* __restrict__ tw, SPtr6<ST> spec,
+                                              Ptr6 u, int add, const int* gate) {
     if (gate && *gate) return;
     using P = TwoPass<B, A>;
     __shared__ double2 Y[P::LDS];
@@ -1469,44 +1482,64 @@ void rhs_dht_z_t(hipStream_t s, const Dims& d, const FftPlan& pz, const double2*
 
 template <class ST>
 void dht_x_t(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
-             void* const spec[3], int ncomp, const int* gate) {
-    const SPtr3<ST> sp = sptr<ST>(spec, ncomp);
+             void* const spec[], int ncomp, const int* gate) {
+    SPtr6<ST> sp6{};
+    for (int c = 0; c < ncomp; ++c) sp6.p[c] = static_cast<ST*>(spec[c]);
     int B, A;
     two_pass_shape(d.nx, B, A);
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int qs = 2 * TwoPass<b, a>::L;                                                   \
-        launch_kernel((k_hx<b, a, ST>), dim3((d.nz + qs - 1) / qs, d.M, ncomp), dim3(64), \
-                           0, s, d, twx, sp, gate);                                            \
+        const dim3 g((d.nz + qs - 1) / qs, d.M, ncomp);                                        \
+        if (ncomp > 3)                                                                         \
+            launch_kernel((k_hx<b, a, ST, 6>), g, dim3(64), 0, s, d, twx, sp6, gate);          \
+        else                                                                                   \
+            launch_kernel((k_hx<b, a, ST, 3>), g, dim3(64), 0, s, d, twx, sp6, gate);          \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int kb = x_modes_per_block(d);
-    launch_kernel(k_dht_x<ST>, dim3((d.nz + kb - 1) / kb, d.M, ncomp), dim3(kBlock), 0, s, d,
-                       px, twx, sp, gate, kb);
+    for (int c0 = 0; c0 < ncomp; c0 += 3) {
+        const int nc = ncomp - c0 < 3 ? ncomp - c0 : 3;
+        launch_kernel(k_dht_x<ST>, dim3((d.nz + kb - 1) / kb, d.M, nc), dim3(kBlock), 0, s, d,
+                      px, twx, sptr<ST>(spec + c0, nc), gate, kb);
+    }
 }
 
 template <class ST>
 void dht_z_out_t(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
-                 void* const spec[3], double* const u[3], int ncomp, int add, const int* gate) {
+                 void* const spec[], double* const u[], int ncomp, int add, const int* gate) {
     const int nrows = d.nx * d.M;
-    const SPtr3<ST> sp = sptr<ST>(spec, ncomp);
-    Ptr3 uu{{u[0], ncomp > 1 ? u[1] : nullptr, ncomp > 2 ? u[2] : nullptr}};
+    SPtr6<ST> sp6{};
+    Ptr6 u6{};
+    for (int c = 0; c < ncomp; ++c) {
+        sp6.p[c] = static_cast<ST*>(spec[c]);
+        u6.p[c] = u[c];
+    }
     int B, A;
     two_pass_shape(d.nz, B, A);
 #define VS_CASE(b, a)                                                                          \
     if (B == b && A == a) {                                                                    \
         const int rows = 2 * TwoPass<b, a>::L;                                                 \
-        launch_kernel((k_hz_out<b, a, ST>), dim3((nrows + rows - 1) / rows, ncomp),       \
-                           dim3(64), 0, s, d, twz, sp, uu, add, gate);                         \
+        const dim3 g((nrows + rows - 1) / rows, ncomp);                                        \
+        if (ncomp > 3)                                                                         \
+            launch_kernel((k_hz_out<b, a, ST, 6>), g, dim3(64), 0, s, d, twz, sp6, u6, add,    \
+                          gate);                                                               \
+        else                                                                                   \
+            launch_kernel((k_hz_out<b, a, ST, 3>), g, dim3(64), 0, s, d, twz, sp6, u6, add,    \
+                          gate);                                                               \
         return;                                                                                \
     }
     VS_TWO_PASS_CASES(VS_CASE)
 #undef VS_CASE
     const int rpb = z_rows_per_block(d);
-    launch_kernel(k_dht_z_out<ST>, dim3((nrows + rpb - 1) / rpb, ncomp), dim3(kBlock), 0, s,
-                       d, pz, twz, sp, uu, add, gate, rpb);
+    for (int c0 = 0; c0 < ncomp; c0 += 3) {
+        const int nc = ncomp - c0 < 3 ? ncomp - c0 : 3;
+        Ptr3 uu{{u[c0], nc > 1 ? u[c0 + 1] : nullptr, nc > 2 ? u[c0 + 2] : nullptr}};
+        launch_kernel(k_dht_z_out<ST>, dim3((nrows + rpb - 1) / rpb, nc), dim3(kBlock), 0, s,
+                      d, pz, twz, sptr<ST>(spec + c0, nc), uu, add, gate, rpb);
+    }
 }
 
 }  // namespace
@@ -1521,7 +1554,7 @@ void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
 }
 
 void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
-                  void* const spec[3], int ncomp, bool f32, const int* gate) {
+                  void* const spec[], int ncomp, bool f32, const int* gate) {
     if (f32)
         dht_x_t<float>(s, d, px, twx, spec, ncomp, gate);
     else
@@ -1639,7 +1672,7 @@ void launch_dht_z_fwd(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
 }
 
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
-                      void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
+                      void* const spec[], double* const u[], int ncomp, int add, bool f32,
                       const int* gate) {
     if (f32)
         dht_z_out_t<float>(s, d, pz, twz, spec, u, ncomp, add, gate);

@@ -41,13 +41,14 @@ vs_status fail(vs_status code, const char* fmt, ...) {
 enum KClass {
     K_ADVANCE, K_VA_PARTIALS, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
-    K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_NCLASS
+    K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_DHT_X_PAIR, K_DHT_Z_OUT_PAIR,
+    K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
     "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
     "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
-    "resid_norm_flow"};
+    "resid_norm_flow", "dht_x_pair", "dht_z_out_pair"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -376,13 +377,12 @@ void enqueue_flow(vs_state* S, const double* phi, bool defer_check, double dt) {
         launch_tridiag_pair(S->stream, d, S->tri, a != 0.0 ? S->tri2 : nullptr, S->spec, S->spec2,
                             S->om_wall_lo, S->om_wall_hi, S->psi_wall_lo, S->psi_wall_hi, false);
     });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
-    timed(S, K_DHT_Z_OUT, [&] {
-        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec, S->om, 3, 0, false, nullptr);
-    });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec2, 3, false, nullptr); });
-    timed(S, K_DHT_Z_OUT, [&] {
-        launch_dht_z_out(S->stream, d, S->pz, S->twz, S->spec2, S->ps, 3, 0, false, nullptr);
+    // both fields back to physical space, six components per launch
+    void* const sp6[6] = {S->spec[0], S->spec[1], S->spec[2], S->spec2[0], S->spec2[1], S->spec2[2]};
+    double* const u6[6] = {S->om[0], S->om[1], S->om[2], S->ps[0], S->ps[1], S->ps[2]};
+    timed(S, K_DHT_X_PAIR, [&] { launch_dht_x(S->stream, d, S->px, S->twx, sp6, 6, false, nullptr); });
+    timed(S, K_DHT_Z_OUT_PAIR, [&] {
+        launch_dht_z_out(S->stream, d, S->pz, S->twz, sp6, u6, 6, 0, false, nullptr);
     });
     if (mc == 1) {
         // one cycle each: both residuals in one pass, then both checks in one launch, or, when

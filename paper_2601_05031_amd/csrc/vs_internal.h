@@ -165,8 +165,9 @@ void launch_reset_stats(hipStream_t s, double* scal, int* istat);
 void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
                       void* const spec[3], bool f32, const int* gate);
+// ncomp spectral fields spec[0 .. ncomp-1], ncomp <= 6.
 void launch_dht_x(hipStream_t s, const Dims& d, const FftPlan& px, const double2* twx,
-                  void* const spec[3], int ncomp, bool f32, const int* gate);
+                  void* const spec[], int ncomp, bool f32, const int* gate);
 // Hartley along z of FP64 fields on the interior rows into FP64 spectral storage (the direct
 // vorticity transform of the source S, whose wall terms are folded into mode (0, 0)).
 void launch_dht_z_fwd(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
@@ -184,8 +185,9 @@ void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, const 
                          void* const spec[3], void* const spec2[3], const double om_lo[3],
                          const double om_hi[3], const double psi_lo[3], const double psi_hi[3],
                          bool f32);
+// Hartley along z of spec[c] into u[c] (add: u[c] += result), c < ncomp <= 6.
 void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
-                      void* const spec[3], double* const u[3], int ncomp, int add, bool f32,
+                      void* const spec[], double* const u[], int ncomp, int add, bool f32,
                       const int* gate);
 int resid_blocks(const Dims& d);
 int resid_flow_blocks(const Dims& d);
