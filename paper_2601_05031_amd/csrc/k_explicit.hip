@@ -115,13 +115,14 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
     const int re = j * d.nz;                             // row start inside a plane
     const double lam = scal[SC_LAMV];
     auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
-    // z neighbours of the pair v at row offset rb: (zp, zm) of node k and of node k + 1
-    auto zn = [&](double2 v, double em, double ep, double& zpa, double& zma, double& zpb,
+    // z neighbours (zp, zm) of node k and of node k + 1 from the pair v; el, er: the values
+    // just before the wave's first z and just after its last
+    auto zn = [&](double2 v, double el, double er, double& zpa, double& zma, double& zpb,
                   double& zmb) {
         const double prev = __shfl_up(v.y, 1, 64), next = __shfl_down(v.x, 1, 64);
         zpa = v.y;
-        zma = ln == 0 ? em : prev;
-        zpb = ln == 63 ? ep : next;
+        zma = ln == 0 ? el : prev;
+        zpb = ln == 63 ? er : next;
         zmb = v.x;
     };
     auto pl = [&](int i) { return (size_t)((i + d.nx) % d.nx) * plane; };
@@ -139,18 +140,18 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
         const double2 xyp = ld2v(px + bc + oyp), xym = ld2v(px + bc + oym);
         const double2 pxc = ld2v(px + bc + o);
         const size_t ro = bc + re;
-        const double emu = mu[ro + kme], epu = mu[ro + kpe], eph = phi[ro + kme], eph2 = phi[ro + kpe];
-        const double epy = py[ro + kme], epy2 = py[ro + kpe], epx = px[ro + kme], epx2 = px[ro + kpe];
+        const double mu_l = mu[ro + kme], mu_r = mu[ro + kpe], ph_l = phi[ro + kme], ph_r = phi[ro + kpe];
+        const double py_l = py[ro + kme], py_r = py[ro + kpe], px_l = px[ro + kme], px_r = px[ro + kpe];
         // the next plane's centres last: they stay in flight while this plane is computed
         const double2 php = ld2v(phi + bn + o), mup = ld2v(mu + bn + o);
         const double2 pyp = ld2v(py + bn + o), pzp = ld2v(pz + bn + o);
         __builtin_amdgcn_sched_barrier(0);
         double mzpa, mzma, mzpb, mzmb, fzpa, fzma, fzpb, fzmb;
         double yzpa, yzma, yzpb, yzmb, xzpa, xzma, xzpb, xzmb;
-        zn(mu0, emu, epu, mzpa, mzma, mzpb, mzmb);
-        zn(ph0, eph, eph2, fzpa, fzma, fzpb, fzmb);
-        zn(py0, epy, epy2, yzpa, yzma, yzpb, yzmb);
-        zn(pxc, epx, epx2, xzpa, xzma, xzpb, xzmb);
+        zn(mu0, mu_l, mu_r, mzpa, mzma, mzpb, mzmb);
+        zn(ph0, ph_l, ph_r, fzpa, fzma, fzpb, fzmb);
+        zn(py0, py_l, py_r, yzpa, yzma, yzpb, yzmb);
+        zn(pxc, px_l, px_r, xzpa, xzma, xzpb, xzmb);
         double2 res;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
