@@ -271,11 +271,13 @@ __device__ __forceinline__ double va_final(const VaFinal& va, const Dims& d, con
 // walls are filled with the mirror image (j -> -j, ny-1+m -> ny-1-m), so g computed there is
 // the mirror ghost of g. Sums run in the order of lap7, so the result equals the plain
 // stencil's bit for bit.
-constexpr int kMuTY = 4, kMuTZ = 64, kMuNI = 8;
+constexpr int kMuTY = 8, kMuTZ = 32, kMuNI = 8;
 constexpr int kPY = kMuTY + 4, kPZ = kMuTZ + 4, kPN = kPY * kPZ;
 constexpr int kGY = kMuTY + 2, kGZ = kMuTZ + 2, kGN = kGY * kGZ;
 constexpr int kPre = (kPN + kBlock - 1) / kBlock;
-constexpr int kPS = kPre * kBlock;               // phi slot, padded: every lane loads and stores
+// phi slot: every lane loads and stores (padded to whole blocks), one block more so that the
+// padding elements of the g slot read inside it
+constexpr int kPS = (kPre + 1) * kBlock;
 constexpr int kGI = (kGN + kBlock - 1) / kBlock;
 constexpr int kGS = kGI * kBlock;                // g slot, padded likewise
 constexpr int kMuD = 2;                          // phi planes in flight ahead of their use
