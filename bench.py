@@ -99,16 +99,24 @@ def cpu_baseline(workload, budget_s: float):
     p = O.Params(model=w.model, eta=w.eta, mobility=w.mobility, eps=w.eps, kappa=1.0,
                  sigma=w.sigma, gamma0=w.gamma0, rate_V=w.rate_V, k_A=w.k_A, bend_scale=w.bend_scale)
     s = O.init_state(g, walls, p, w.phi0())
+    # one thread: scipy.fft runs with one worker by default; BLAS/OpenMP pools are held to one
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(1)
+    except ImportError:
+        limit = None
     t0 = time.perf_counter()
     n = 0
     while n < 2 or (time.perf_counter() - t0) < budget_s:
         s = O.step(s, w.dt, g, walls, p)
         n += 1
     t = time.perf_counter() - t0
+    if limit is not None:
+        limit.restore_original_limits()
     N = w.grid.N
     return {"value": N * n / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"vesicle128 kappa=1, {n} time steps at 128^3 after init, numpy/scipy FP64 "
-                      f"(single-threaded), {t:.1f} s",
+            "sample": f"{w.name} kappa=1, {n} time steps at {w.grid.nx}x{w.grid.ny}x{w.grid.nz} "
+                      f"after init, numpy/scipy FP64 (single-threaded), {t:.1f} s",
             "steps_per_s": n / t}
 
 
