@@ -862,24 +862,47 @@ __device__ __forceinline__ void two_pass_hartley(double2* Y, const double2* __re
         const auto pre = prep(line);
         const int pa = s;                          // s = 0 gives p2 = 0
         const int pb = (s == 0) ? B / 2 : B - s;
-        double2 xa[A], xb[A];
-        const double2* Ya = Y + line * P::LS + pa * P::RS;
+        double2* Ya = Y + line * P::LS + pa * P::RS;
         const double2* Yb = Y + line * P::LS + pb * P::RS;
+        if constexpr (A >= 16) {
+            // long lines: the a-line's transform goes back to its own LDS row (no other lane
+            // reads it), so only one line of registers is live at a time
+            double2 x[A];
 #pragma unroll
-        for (int k1 = 0; k1 < A; ++k1) {
-            xa[k1] = Ya[k1];
-            xb[k1] = Yb[k1];
-        }
-        fftr::DFT<A>::run(xa);
-        fftr::DFT<A>::run(xb);
+            for (int k1 = 0; k1 < A; ++k1) x[k1] = Ya[k1];
+            fftr::DFT<A>::run(x);
 #pragma unroll
-        for (int p1 = 0; p1 < A; ++p1) {
-            const double2 za = xa[p1];
-            const double2 ma = (s == 0) ? xa[(A - p1) % A] : xb[A - 1 - p1];
-            store(pre, pa + B * p1, 0.5 * (za.x + ma.x - za.y + ma.y), 0.5 * (za.x - ma.x + za.y + ma.y));
-            const double2 zb = xb[p1];
-            const double2 mb = (s == 0) ? xb[A - 1 - p1] : xa[A - 1 - p1];
-            store(pre, pb + B * p1, 0.5 * (zb.x + mb.x - zb.y + mb.y), 0.5 * (zb.x - mb.x + zb.y + mb.y));
+            for (int k1 = 0; k1 < A; ++k1) Ya[k1] = x[k1];
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) x[k1] = Yb[k1];
+            fftr::DFT<A>::run(x);
+#pragma unroll
+            for (int p1 = 0; p1 < A; ++p1) {
+                const double2 za = Ya[p1];
+                const double2 ma = (s == 0) ? Ya[(A - p1) % A] : x[A - 1 - p1];
+                store(pre, pa + B * p1, 0.5 * (za.x + ma.x - za.y + ma.y), 0.5 * (za.x - ma.x + za.y + ma.y));
+                const double2 zb = x[p1];
+                const double2 mb = (s == 0) ? x[A - 1 - p1] : Ya[A - 1 - p1];
+                store(pre, pb + B * p1, 0.5 * (zb.x + mb.x - zb.y + mb.y), 0.5 * (zb.x - mb.x + zb.y + mb.y));
+            }
+        } else {
+            double2 xa[A], xb[A];
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) {
+                xa[k1] = Ya[k1];
+                xb[k1] = Yb[k1];
+            }
+            fftr::DFT<A>::run(xa);
+            fftr::DFT<A>::run(xb);
+#pragma unroll
+            for (int p1 = 0; p1 < A; ++p1) {
+                const double2 za = xa[p1];
+                const double2 ma = (s == 0) ? xa[(A - p1) % A] : xb[A - 1 - p1];
+                store(pre, pa + B * p1, 0.5 * (za.x + ma.x - za.y + ma.y), 0.5 * (za.x - ma.x + za.y + ma.y));
+                const double2 zb = xb[p1];
+                const double2 mb = (s == 0) ? xb[A - 1 - p1] : xa[A - 1 - p1];
+                store(pre, pb + B * p1, 0.5 * (zb.x + mb.x - zb.y + mb.y), 0.5 * (zb.x - mb.x + zb.y + mb.y));
+            }
         }
     }
 }
