@@ -702,23 +702,49 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
     // advection, L_h mu and lambda_V terms; q = psi_bar
     launch_adj_advect(st, d, adj_next, phi, cps, dt, S->p.mobility, S->vz_lo, S->vz_hi, adj_prev,
                       mubar, q, S->part, S->scal);
-    // psi_int = P(-omega_int; psi walls): first adjoint solve, homogeneous walls (the solve
-    // writes the interior; only the wall rows need zeros)
-    launch_zero_walls(st, d, u1, 3);
-    RhsArgs r1{};
-    r1.mode = RHS_FIELD;
-    for (int c = 0; c < 3; ++c) r1.f[c] = q[c];
-    enqueue_solve(S, r1, u1, 3, rtol, mc, TAG_FIELD);
-    launch_adj_wall_couple(st, d, u1, S->ps, S->part, S->scal, SC_ADJ_PSIC);
-    // omega_int = P(S; omega walls): second adjoint solve of -u1, into q = S_bar
-    launch_zero_walls(st, d, q, 3);
-    RhsArgs r2{};
-    r2.mode = RHS_NEGW;
-    for (int c = 0; c < 3; ++c) r2.f[c] = u1[c];
-    enqueue_solve(S, r2, q, 3, rtol, mc, TAG_FIELD);
-    launch_adj_wall_couple(st, d, q, S->om, S->part, S->scal, SC_ADJ_OMC);
+    // psi_int = P(-omega_int; psi walls): first adjoint solve, homogeneous walls;
+    // omega_int = P(S; omega walls): second adjoint solve, of -u1, giving S_bar
+    double* sb[3] = {q[0], q[1], q[2]};          // S_bar
+    if (mc == 1) {
+        // one verified pass, as the forward flow solve: q transformed once, u1's modes solved
+        // and S_bar's from them in the pair kernel (zero walls), both inverse-transformed in
+        // place in the two spectral sets (u1 in spec, S_bar in spec2), then both residuals
+        // against q and -u1 in one pass and one check
+        double* const us[3] = {(double*)S->spec[0], (double*)S->spec[1], (double*)S->spec[2]};
+        double* const ss[3] = {(double*)S->spec2[0], (double*)S->spec2[1], (double*)S->spec2[2]};
+        double* const w6[6] = {us[0], us[1], us[2], ss[0], ss[1], ss[2]};
+        launch_zero_walls(st, d, w6, 6);
+        const double* const qc[3] = {q[0], q[1], q[2]};
+        launch_dht_z_fwd(st, d, S->pz, S->twz, qc, S->spec, 3);
+        launch_dht_x(st, d, S->px, S->twx, S->spec, 3, false, nullptr);
+        const double zero[3] = {0.0, 0.0, 0.0};
+        launch_tridiag_pair(st, d, S->tri, nullptr, S->spec, S->spec2, zero, zero, zero, zero, false);
+        void* const sp6[6] = {S->spec[0], S->spec[1], S->spec[2], S->spec2[0], S->spec2[1], S->spec2[2]};
+        launch_dht_x(st, d, S->px, S->twx, sp6, 6, false, nullptr);
+        launch_dht_z_out(st, d, S->pz, S->twz, sp6, w6, 6, 0, false, nullptr);
+        const double* const cu[3] = {us[0], us[1], us[2]};
+        const double* const cs[3] = {ss[0], ss[1], ss[2]};
+        launch_resid_flow(st, d, cu, qc, cs, 0.0, S->part);
+        launch_check_flow(st, d, S->part, rtol, S->scal, S->istat);
+        launch_adj_wall_couple(st, d, us, S->ps, S->part, S->scal, SC_ADJ_PSIC);
+        for (int c = 0; c < 3; ++c) sb[c] = ss[c];
+    } else {
+        // the solve writes the interior; only the wall rows need zeros
+        launch_zero_walls(st, d, u1, 3);
+        RhsArgs r1{};
+        r1.mode = RHS_FIELD;
+        for (int c = 0; c < 3; ++c) r1.f[c] = q[c];
+        enqueue_solve(S, r1, u1, 3, rtol, mc, TAG_FIELD);
+        launch_adj_wall_couple(st, d, u1, S->ps, S->part, S->scal, SC_ADJ_PSIC);
+        launch_zero_walls(st, d, q, 3);
+        RhsArgs r2{};
+        r2.mode = RHS_NEGW;
+        for (int c = 0; c < 3; ++c) r2.f[c] = u1[c];
+        enqueue_solve(S, r2, q, 3, rtol, mc, TAG_FIELD);
+    }
+    launch_adj_wall_couple(st, d, sb, S->om, S->part, S->scal, SC_ADJ_OMC);
     // S = (1/eta) D phi x D mu
-    launch_adj_source(st, d, phi, S->mu, q, 1.0 / S->p.eta, adj_prev, mubar);
+    launch_adj_source(st, d, phi, S->mu, sb, 1.0 / S->p.eta, adj_prev, mubar);
     // mu(phi)
     double* gbar = (double*)S->spec[0];
     const double dCb = S->p.bend_scale * 3.0 * std::sqrt(2.0) / (8.0 * S->p.eps * S->p.eps * S->p.eps);
