@@ -77,15 +77,16 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
 }
 
 
-// k_advance_x with two consecutive z per lane (n_z a multiple of 128, so a wave covers 128
-// consecutive z of one row): every field access moves 16 bytes, and the z neighbours inside
-// the pair come from the pair itself, across lanes by shuffles, and the wave's two edge values
-// by one wave-uniform load each. The psi values of the wall rows are loaded too (in bounds,
+// k_advance_x with two consecutive z per lane. W lanes (64, or 32) cover 2W consecutive z of
+// one row, n_z a multiple of 2W: every field access moves 16 bytes, and the z neighbours
+// inside the pair come from the pair itself, across lanes by width-W shuffles, and the
+// segment's two edge values by one load each (the same address in every lane of a segment). The psi values of the wall rows are loaded too (in bounds,
 // unused there), so that no branch guards a load, and the next plane's centres are loaded
 // last (pinned by a scheduling barrier), so they stay in flight while the current plane is
 // computed. Same arithmetic per node as k_advance_x, so the two forms agree bit for bit.
 constexpr int kAdvSlab2 = 4;
 
+template <int W>
 __global__ __launch_bounds__(kBlock) void k_advance_x2(
     const double* __restrict__ phi, const double* __restrict__ mu,
     const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
@@ -106,9 +107,9 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
     const int plane = d.ny * d.nz;
     const int jp = (j + 1 == d.ny) ? d.ny - 2 : j + 1;   // mirror ghosts (phi, mu)
     const int jm = (j == 0) ? 1 : j - 1;
-    const int ln = threadIdx.x & 63;
+    const int ln = threadIdx.x & (W - 1);
     const int k0 = k - 2 * ln;
-    const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+    const int kpe = (k0 + 2 * W == d.nz) ? 0 : k0 + 2 * W;
     const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
     const int o = j * d.nz + k;
     const int oyp = jp * d.nz + k, oym = jm * d.nz + k;
@@ -119,10 +120,10 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
     // just before the wave's first z and just after its last
     auto zn = [&](double2 v, double el, double er, double& zpa, double& zma, double& zpb,
                   double& zmb) {
-        const double prev = __shfl_up(v.y, 1, 64), next = __shfl_down(v.x, 1, 64);
+        const double prev = __shfl_up(v.y, 1, W), next = __shfl_down(v.x, 1, W);
         zpa = v.y;
         zma = ln == 0 ? el : prev;
-        zpb = ln == 63 ? er : next;
+        zpb = ln == W - 1 ? er : next;
         zmb = v.x;
     };
     auto pl = [&](int i) { return (size_t)((i + d.nx) % d.nx) * plane; };
@@ -474,8 +475,9 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
 }
 
 
-// k_va_partials with two consecutive z per lane (n_z a multiple of 128; as k_advance_x2):
+// k_va_partials with two consecutive z per lane (W-lane row segments, as k_advance_x2):
 // 16-byte loads, z neighbours from the pair, shuffles and the wave's edge values.
+template <int W>
 __global__ __launch_bounds__(kBlock) void k_va_partials2(const double* __restrict__ phi, Dims d,
                                                         double eps, SlabGrid sg,
                                                         double* __restrict__ partials) {
@@ -496,9 +498,9 @@ __global__ __launch_bounds__(kBlock) void k_va_partials2(const double* __restric
         const int o = j * d.nz + k;
         const int oyp = ((j + 1 == d.ny) ? d.ny - 2 : j + 1) * d.nz + k;
         const int oym = ((j == 0) ? 1 : j - 1) * d.nz + k;
-        const int ln = threadIdx.x & 63;
+        const int ln = threadIdx.x & (W - 1);
         const int k0 = k - 2 * ln;
-        const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+        const int kpe = (k0 + 2 * W == d.nz) ? 0 : k0 + 2 * W;
         const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
         const int re = j * d.nz;
         auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
@@ -511,8 +513,8 @@ __global__ __launch_bounds__(kBlock) void k_va_partials2(const double* __restric
             const double2 pp = ld2v(phi + (size_t)inx * plane + o);
             const double2 yp = ld2v(phi + bc + oyp), ym = ld2v(phi + bc + oym);
             const double em = phi[bc + re + kme], ep = phi[bc + re + kpe];
-            const double prev = __shfl_up(p0.y, 1, 64), next = __shfl_down(p0.x, 1, 64);
-            const double zma = ln == 0 ? em : prev, zpb = ln == 63 ? ep : next;
+            const double prev = __shfl_up(p0.y, 1, W), next = __shfl_down(p0.x, 1, W);
+            const double zma = ln == 0 ? em : prev, zpb = ln == W - 1 ? ep : next;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const double p = h ? p0.y : p0.x;
@@ -570,9 +572,10 @@ __global__ __launch_bounds__(kBlock) void k_source(const double* __restrict__ ph
 }
 
 
-// k_source with two consecutive z per lane (n_z a multiple of 128; as k_advance_x2): 16-byte
+// k_source with two consecutive z per lane (W-lane row segments, as k_advance_x2): 16-byte
 // loads and stores, z neighbours from the pair, shuffles and the wave's edge values. Same
 // arithmetic per node as k_source.
+template <int W>
 __global__ __launch_bounds__(kBlock) void k_source2(const double* __restrict__ phi,
                                                    const double* __restrict__ mu, Dims d,
                                                    double inv_eta, double* __restrict__ sx,
@@ -585,13 +588,13 @@ __global__ __launch_bounds__(kBlock) void k_source2(const double* __restrict__ p
     const int t = (lb - i * gx) * kBlock + threadIdx.x;
     if (t >= d.ny * hz) return;
     const int j = t / hz, k = 2 * (t - (t / hz) * hz);
-    if (j == 0 || j == d.ny - 1) return;   // whole waves: a wave covers part of one row
+    if (j == 0 || j == d.ny - 1) return;   // whole W-lane segments: each lies in one row
     const int plane = d.ny * d.nz;
     const int ip = (i + 1 == d.nx) ? 0 : i + 1;
     const int im = (i == 0) ? d.nx - 1 : i - 1;
-    const int ln = threadIdx.x & 63;
+    const int ln = threadIdx.x & (W - 1);
     const int k0 = k - 2 * ln;
-    const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+    const int kpe = (k0 + 2 * W == d.nz) ? 0 : k0 + 2 * W;
     const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
     const int rb = i * plane + j * d.nz;
     const int c = rb + k;
@@ -603,10 +606,10 @@ __global__ __launch_bounds__(kBlock) void k_source2(const double* __restrict__ p
     const double2 fc = ld2v(phi + c), mc = ld2v(mu + c);
     const double fem = phi[rb + kme], fep = phi[rb + kpe];
     const double mem = mu[rb + kme], mep = mu[rb + kpe];
-    const double fprev = __shfl_up(fc.y, 1, 64), fnext = __shfl_down(fc.x, 1, 64);
-    const double mprev = __shfl_up(mc.y, 1, 64), mnext = __shfl_down(mc.x, 1, 64);
-    const double fzma = ln == 0 ? fem : fprev, fzpb = ln == 63 ? fep : fnext;
-    const double mzma = ln == 0 ? mem : mprev, mzpb = ln == 63 ? mep : mnext;
+    const double fprev = __shfl_up(fc.y, 1, W), fnext = __shfl_down(fc.x, 1, W);
+    const double mprev = __shfl_up(mc.y, 1, W), mnext = __shfl_down(mc.x, 1, W);
+    const double fzma = ln == 0 ? fem : fprev, fzpb = ln == W - 1 ? fep : fnext;
+    const double mzma = ln == 0 ? mem : mprev, mzpb = ln == W - 1 ? mep : mnext;
     double2 r0, r1, r2;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -674,12 +677,16 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
                     const double* const psi[3], double* phi_out, double* scal, double dt,
                     double mobility, double vz_lo, double vz_hi, const PrevCheck& ck) {
     SlabGrid g;
-    if (d.nz % 128 == 0) {
+    if (d.nz % 64 == 0) {
         g.gx = (d.ny * d.nz / 2 + kBlock - 1) / kBlock;
         g.ci = kAdvSlab2;
         g.gi = (d.nx + kAdvSlab2 - 1) / kAdvSlab2;
-        launch_kernel(k_advance_x2, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu, psi[0],
-                      psi[1], psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+        if (d.nz % 128 == 0)
+            launch_kernel(k_advance_x2<64>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu,
+                          psi[0], psi[1], psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+        else
+            launch_kernel(k_advance_x2<32>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu,
+                          psi[0], psi[1], psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
         return;
     }
     g.gx = (d.ny * d.nz + kBlock - 1) / kBlock;
@@ -691,9 +698,9 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
 
 constexpr int kVaMaxBlocks = 1024;   // longer x-slabs per lane, a shorter final sum
 
-// n_z a multiple of 128: two z per lane (k_va_partials2)
+// n_z a multiple of 64: two z per lane (k_va_partials2)
 static SlabGrid va_grid(const Dims& d) {
-    return slab_grid(d.nz % 128 == 0 ? d.ny * d.nz / 2 : d.ny * d.nz, d.nx, kVaMaxBlocks);
+    return slab_grid(d.nz % 64 == 0 ? d.ny * d.nz / 2 : d.ny * d.nz, d.nx, kVaMaxBlocks);
 }
 
 int va_partial_blocks(const Dims& d) {
@@ -705,7 +712,10 @@ void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double 
                         double* partials) {
     const SlabGrid g = va_grid(d);
     if (d.nz % 128 == 0)
-        launch_kernel(k_va_partials2, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
+        launch_kernel(k_va_partials2<64>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
+                      partials);
+    else if (d.nz % 64 == 0)
+        launch_kernel(k_va_partials2<32>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
                       partials);
     else
         launch_kernel(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
@@ -739,10 +749,14 @@ void launch_source(hipStream_t s, const Dims& d, const double* phi, const double
                    const double* const omega[3]) {
     Om3 om{{nullptr, nullptr, nullptr}};
     if (a != 0.0) om = Om3{{omega[0], omega[1], omega[2]}};
-    if (d.nz % 128 == 0) {
+    if (d.nz % 64 == 0) {
         const dim3 g((unsigned)((d.ny * d.nz / 2 + kBlock - 1) / kBlock), (unsigned)d.nx, 1);
-        launch_kernel(k_source2, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
-                      src[2], a, om);
+        if (d.nz % 128 == 0)
+            launch_kernel(k_source2<64>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
+                          src[2], a, om);
+        else
+            launch_kernel(k_source2<32>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
+                          src[2], a, om);
         return;
     }
     launch_kernel(k_source, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0],

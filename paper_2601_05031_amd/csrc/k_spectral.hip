@@ -1301,13 +1301,14 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
 }
 
 
-// resid_flow with two consecutive z per lane (n_z a multiple of 128, so a wave covers 128
-// consecutive z of one row): every load moves 16 bytes, half the load instructions of the
+// resid_flow with two consecutive z per lane: W lanes (64, or 32) cover 2W consecutive z of
+// one row, n_z a multiple of 2W. Every load moves 16 bytes, half the load instructions of the
 // one-z form; the z neighbours inside the pair come from the pair itself, across lanes by
-// shuffles, and the wave's two edge values by one wave-uniform load each. The next plane's
+// width-W shuffles, and the segment's two edge values by one load each. The next plane's
 // centres are loaded last (a scheduling barrier keeps them there), so they stay in flight
 // while the current plane is summed. Same sums per node as k_resid_flow; a lane adds its two
 // nodes' squares together.
+template <int W>
 __global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, CPtr3 om, CPtr3 src, CPtr3 ps,
                                                        SlabGrid sg, double ashift,
                                                        double* __restrict__ partials) {
@@ -1329,15 +1330,15 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, CPtr3 om, CPtr3 
         const int j = jj + 1;
         const int plane = d.ny * d.nz;
         const int off = j * d.nz + k;
-        const int ln = threadIdx.x & 63;
+        const int ln = threadIdx.x & (W - 1);
         const int k0 = k - 2 * ln;
-        const int kpe = (k0 + 128 == d.nz) ? 0 : k0 + 128;
+        const int kpe = (k0 + 2 * W == d.nz) ? 0 : k0 + 2 * W;
         const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
         auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
         auto zn = [&](double2 v, double em, double ep, double& zm0, double& zp1) {
-            const double prev = __shfl_up(v.y, 1, 64), next = __shfl_down(v.x, 1, 64);
+            const double prev = __shfl_up(v.y, 1, W), next = __shfl_down(v.x, 1, W);
             zm0 = ln == 0 ? em : prev;
-            zp1 = ln == 63 ? ep : next;
+            zp1 = ln == W - 1 ? ep : next;
         };
         const int i0 = bi * sg.ci;
         const int i1 = min(d.nx, i0 + sg.ci);
@@ -1713,7 +1714,7 @@ int resid_blocks(const Dims& d) {
 }
 
 static SlabGrid resid_flow_grid(const Dims& d) {
-    return d.nz % 128 == 0 ? slab_grid(d.M * d.nz / 2, d.nx, 1024) : resid_grid(d);
+    return d.nz % 64 == 0 ? slab_grid(d.M * d.nz / 2, d.nx, 1024) : resid_grid(d);
 }
 
 int resid_flow_blocks(const Dims& d) {
@@ -1736,7 +1737,10 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
     const CPtr3 o{{om[0], om[1], om[2]}}, f{{src[0], src[1], src[2]}}, p{{ps[0], ps[1], ps[2]}};
     const SlabGrid g = resid_flow_grid(d);
     if (d.nz % 128 == 0)
-        launch_kernel(k_resid_flow2, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
+        launch_kernel(k_resid_flow2<64>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
+                      ashift, partials);
+    else if (d.nz % 64 == 0)
+        launch_kernel(k_resid_flow2<32>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
                       ashift, partials);
     // a whole number of waves per row lets the z neighbours come from shuffles
     else if (d.nz % 64 == 0)

@@ -231,6 +231,19 @@ def test_step_parity_tall_channels(ny):
     compare(got, ref_fields(ref), label=f"ny={ny}")
 
 
+# n_z a multiple of 64: the two-z-per-lane explicit and residual kernels with 32-lane row
+# segments (64, 192) or whole 64-lane segments (128), bending and Cahn-Hilliard, one solve
+@pytest.mark.parametrize("shape,name", [((32, 20, 64), "vesicle32"), ((24, 18, 192), "droplet256"),
+                                        ((16, 26, 128), "droplet256")])
+def test_step_parity_two_z_kernels(shape, name):
+    w = workload(name, grid=GridSpec(*shape), R0=5.0, nsteps=3, max_cycles=1)
+    if name == "vesicle32":
+        w = w.with_(rate_V=10.0, k_A=1.0)
+    got, sc, ref = run_both(w, 3)
+    compare(got, ref_fields(ref), label=f"{name} {shape}")
+    assert sc["cycles"] == 6 and sc["relres"] <= w.rtol
+
+
 @pytest.mark.parametrize("shape", [(486, 6, 512), (512, 7, 432)])
 def test_step_parity_longest_transforms(shape):
     """Whole steps at the longest transform lengths (the general Stockham plans, and z lines
