@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
 }
 
 
-// k_advance_x with two consecutive z per lane. W lanes (64, or 32) cover 2W consecutive z of
+// k_advance_x with two consecutive z per lane. W lanes (64, 32 or 16) cover 2W consecutive z of
 // one row, n_z a multiple of 2W: every field access moves 16 bytes, and the z neighbours
 // inside the pair come from the pair itself, across lanes by width-W shuffles, and the
 // segment's two edge values by one load each (the same address in every lane of a segment). The psi values of the wall rows are loaded too (in bounds,
@@ -677,16 +677,20 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
                     const double* const psi[3], double* phi_out, double* scal, double dt,
                     double mobility, double vz_lo, double vz_hi, const PrevCheck& ck) {
     SlabGrid g;
-    if (d.nz % 64 == 0) {
+    if (d.nz % 32 == 0) {
         g.gx = (d.ny * d.nz / 2 + kBlock - 1) / kBlock;
         g.ci = kAdvSlab2;
         g.gi = (d.nx + kAdvSlab2 - 1) / kAdvSlab2;
+        const dim3 gr(g.gx * g.gi);
         if (d.nz % 128 == 0)
-            launch_kernel(k_advance_x2<64>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu,
-                          psi[0], psi[1], psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+            launch_kernel(k_advance_x2<64>, gr, dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
+                          psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+        else if (d.nz % 64 == 0)
+            launch_kernel(k_advance_x2<32>, gr, dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
+                          psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
         else
-            launch_kernel(k_advance_x2<32>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu,
-                          psi[0], psi[1], psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+            launch_kernel(k_advance_x2<16>, gr, dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
+                          psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
         return;
     }
     g.gx = (d.ny * d.nz + kBlock - 1) / kBlock;
@@ -698,9 +702,9 @@ void launch_advance(hipStream_t s, const Dims& d, const double* phi, const doubl
 
 constexpr int kVaMaxBlocks = 1024;   // longer x-slabs per lane, a shorter final sum
 
-// n_z a multiple of 64: two z per lane (k_va_partials2)
+// n_z a multiple of 32: two z per lane (k_va_partials2)
 static SlabGrid va_grid(const Dims& d) {
-    return slab_grid(d.nz % 64 == 0 ? d.ny * d.nz / 2 : d.ny * d.nz, d.nx, kVaMaxBlocks);
+    return slab_grid(d.nz % 32 == 0 ? d.ny * d.nz / 2 : d.ny * d.nz, d.nx, kVaMaxBlocks);
 }
 
 int va_partial_blocks(const Dims& d) {
@@ -716,6 +720,9 @@ void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double 
                       partials);
     else if (d.nz % 64 == 0)
         launch_kernel(k_va_partials2<32>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
+                      partials);
+    else if (d.nz % 32 == 0)
+        launch_kernel(k_va_partials2<16>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
                       partials);
     else
         launch_kernel(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
@@ -749,13 +756,16 @@ void launch_source(hipStream_t s, const Dims& d, const double* phi, const double
                    const double* const omega[3]) {
     Om3 om{{nullptr, nullptr, nullptr}};
     if (a != 0.0) om = Om3{{omega[0], omega[1], omega[2]}};
-    if (d.nz % 64 == 0) {
+    if (d.nz % 32 == 0) {
         const dim3 g((unsigned)((d.ny * d.nz / 2 + kBlock - 1) / kBlock), (unsigned)d.nx, 1);
         if (d.nz % 128 == 0)
             launch_kernel(k_source2<64>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
                           src[2], a, om);
-        else
+        else if (d.nz % 64 == 0)
             launch_kernel(k_source2<32>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
+                          src[2], a, om);
+        else
+            launch_kernel(k_source2<16>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
                           src[2], a, om);
         return;
     }

@@ -1301,7 +1301,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
 }
 
 
-// resid_flow with two consecutive z per lane: W lanes (64, or 32) cover 2W consecutive z of
+// resid_flow with two consecutive z per lane: W lanes (64, 32 or 16) cover 2W consecutive z of
 // one row, n_z a multiple of 2W. Every load moves 16 bytes, half the load instructions of the
 // one-z form; the z neighbours inside the pair come from the pair itself, across lanes by
 // width-W shuffles, and the segment's two edge values by one load each. The next plane's
@@ -1714,7 +1714,7 @@ int resid_blocks(const Dims& d) {
 }
 
 static SlabGrid resid_flow_grid(const Dims& d) {
-    return d.nz % 64 == 0 ? slab_grid(d.M * d.nz / 2, d.nx, 1024) : resid_grid(d);
+    return d.nz % 32 == 0 ? slab_grid(d.M * d.nz / 2, d.nx, 1024) : resid_grid(d);
 }
 
 int resid_flow_blocks(const Dims& d) {
@@ -1741,6 +1741,9 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
                       ashift, partials);
     else if (d.nz % 64 == 0)
         launch_kernel(k_resid_flow2<32>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
+                      ashift, partials);
+    else if (d.nz % 32 == 0)
+        launch_kernel(k_resid_flow2<16>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
                       ashift, partials);
     // a whole number of waves per row lets the z neighbours come from shuffles
     else if (d.nz % 64 == 0)
