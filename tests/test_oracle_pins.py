@@ -4,6 +4,7 @@ Each test names the part it pins and what would break it. Grids are tiny or smal
 whole file runs in seconds on the CPU.
 """
 import math
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -403,3 +404,148 @@ def test_step_matches_node_loops(kind, u0, u1):
                            p.C_b, 0.3, (kind, u0, u1))
     for a, b in zip((s1.phi, s1.mu, s1.omega, s1.psi), ref):
         assert np.allclose(a, b, atol=1e-11, rtol=1e-11)
+
+
+# --------------------------------------------------------- penalty multipliers (SM (37)-(38))
+# The multipliers are a reading of SM "Lagrange multipliers" (penalty form, lambda_V driving V
+# to V0 at rate rate_V; gamma_A = gamma0 + k_A (A - A0)/A0). Two settings where the oracle's
+# whole step reduces to a scalar recurrence that is derived here from the discrete operators,
+# not from the oracle's code: a wrong sign, a lost factor 2, a missing mobility or domain
+# volume, or A in place of A0 in the denominator each changes the recurrence.
+
+def _volume_relaxation_error(mult=None, model=O.BENDING, h=1.0, mobility=1.0, steps=12):
+    """No flow, V0 offset by delta from V[phi0]. sum_w L_h mu = 0 (mirror ghosts, trapezoid
+    weights) and W h^3 = |Omega| make V^{n+1} = V^n + dt M lambda_V^n |Omega| / 2 exact, so
+    under the penalty reading V^n - V0 = (1 - dt rate_V)^n (V^0 - V0). Returns the largest
+    relative deviation from that geometric sequence (mult: a replacement multipliers()).
+    """
+    from workloads.shapes import GridSpec, alm_coefficients, phi_sh_vesicle
+    n = 12
+    g = O.Grid(n, n + 1, n, h=h)
+    spec = GridSpec(n, n + 1, n, h=h)
+    phi0 = phi_sh_vesicle(spec, 3.2 * h, alm_coefficients(2, sigma=0.05), math.sqrt(2) * h)
+    if model == O.BENDING:
+        p = O.Params(kappa=0.3, eps=h, mobility=mobility)
+        rate = mobility * 12 / h**2 * p.C_b * (2 + 12) ** 2
+    else:
+        p = O.Params(model=O.CAHN_HILLIARD, sigma=0.5 * h * h, mobility=mobility)
+        rate = mobility * 12 / h**2 * (2 + 12 * p.sigma / h**2)
+    dt = 0.25 * 2.0 / rate
+    rate_V = 0.15 / dt          # V relaxes by 15% of its offset per step
+    p = replace(p, rate_V=rate_V)
+    walls = O.Walls(O.POISEUILLE, 0.0)
+    orig = O.vsref.multipliers
+    if mult is not None:
+        O.vsref.multipliers = mult
+    try:
+        s = O.init_state(g, walls, p, phi0, flow=False)
+        delta = 0.01 * s.V0
+        V0 = s.V0 + delta
+        lam, gam = O.vsref.multipliers(s.V, s.A, V0, s.A0, g, p)
+        mu = O.chemical_potential(s.phi, g, p, gam)
+        s = replace(s, V0=V0, lam_V=lam, gamma_A=gam, mu=mu)
+        worst = 0.0
+        e0 = s.V - V0
+        for m in range(1, steps + 1):
+            s = O.step(s, dt, g, walls, p, flow=False)
+            pred = (1.0 - dt * rate_V) ** m * e0
+            worst = max(worst, abs((s.V - V0) - pred) / abs(e0))
+    finally:
+        O.vsref.multipliers = orig
+    assert 0.05 < dt * rate_V < 1.0   # a visible relaxation per step, below overshoot
+    return worst
+
+
+@pytest.mark.parametrize("model,h,mob", [(O.BENDING, 1.0, 1.0), (O.BENDING, 1.0, 0.6),
+                                         (O.CAHN_HILLIARD, 0.5, 1.7)])
+def test_volume_penalty_relaxes_geometrically(model, h, mob):
+    assert _volume_relaxation_error(model=model, h=h, mobility=mob) < 1e-10
+
+
+def _area_mode_error(mult=None, h=1.0, mobility=1.0, steps=15):
+    """kappa = 0, gamma0 = 0, no flow: mu = -gamma_A L_h phi. For phi = a cos(2 pi x/(6h))
+    (constant in y, z), L_h phi = -lam phi with lam = (2 - 2 cos(pi/3))/h^2, so each step
+    maps a -> a (1 - dt M gamma_A lam^2), and mu = gamma_A lam phi. The area of SM (32) for
+    this field has a closed form (sums of cos^2, cos^4, sin^2 over a period of 6 nodes):
+      A(a) = 3/(2 sqrt 2) h^3 W_yz [ (eps/2) a^2 (sin(pi/3)/h)^2 3 + (6 - 6 a^2 + 9 a^4/4)/(4 eps) ]
+    with W_yz = nz (ny - 1) the trapezoid weight of one x-column. A0 is set 20% below
+    A(a0), so gamma_A = k_A (A - A0)/A0 > 0 pulls the amplitude (and A) down. The first step
+    is the identity (mu^0 = 0 from the initial gamma_A = 0). Returns the largest relative
+    deviation of the oracle's amplitude and of its mu from the recurrence.
+    """
+    nx, ny, nz = 6, 4, 3
+    g = O.Grid(nx, ny, nz, h=h)
+    eps, k_A, a0 = 1.3 * h, 2.5, 0.9
+    x = np.arange(nx)[:, None, None] * np.ones((1, ny, nz))
+    mode = np.cos(2 * np.pi * x / nx)
+    lam = (2.0 - 2.0 * math.cos(math.pi / 3)) / h**2
+    Wyz = nz * (ny - 1)
+
+    def area_closed(a):
+        grad = 0.5 * eps * a * a * (math.sin(math.pi / 3) / h) ** 2 * 3.0
+        well = (6.0 - 6.0 * a * a + 9.0 * a**4 / 4.0) / (4.0 * eps)
+        return 3.0 / (2.0 * math.sqrt(2.0)) * h**3 * Wyz * (grad + well)
+
+    p = O.Params(kappa=0.0, eps=eps, mobility=mobility, gamma0=0.0, k_A=k_A)
+    # dt keeps every mode of the x line stable (largest lam^2 = (4/h^2)^2)
+    dt = 0.2 / (mobility * 1.0 * (4.0 / h**2) ** 2)
+    walls = O.Walls(O.POISEUILLE, 0.0)
+    orig = O.vsref.multipliers
+    if mult is not None:
+        O.vsref.multipliers = mult
+    try:
+        s = O.init_state(g, walls, p, a0 * mode, flow=False)
+        assert abs(s.A - area_closed(a0)) < 1e-12 * s.A
+        A0 = 0.8 * area_closed(a0)
+        s = replace(s, A0=A0)
+        a = a0
+        worst = 0.0
+        for m in range(steps):
+            gam_prev = k_A * (area_closed(a) - A0) / A0 if m > 0 else 0.0
+            a = a * (1.0 - dt * mobility * gam_prev * lam * lam)
+            s = O.step(s, dt, g, walls, p, flow=False)
+            gam = k_A * (area_closed(a) - A0) / A0
+            worst = max(worst, float(np.max(np.abs(s.phi - a * mode))) / a0,
+                        float(np.max(np.abs(s.mu - gam * lam * a * mode))) / (a0 * lam))
+    finally:
+        O.vsref.multipliers = orig
+    assert gam > 0.05 and a < 0.99 * a0   # the penalty acted
+    return worst
+
+
+@pytest.mark.parametrize("h,mob", [(1.0, 1.0), (0.5, 0.7)])
+def test_area_penalty_single_mode_recurrence(h, mob):
+    assert _area_mode_error(h=h, mobility=mob) < 1e-12
+
+
+def _mutants():
+    """Plausible mistakes in the multiplier formulas (planted on the CPU, in the oracle)."""
+    def base(V, A, V0, A0, grid, params, sv=1.0, fv=2.0, mob=True, vol=True, sa=1.0, den0=True):
+        lam = fv * sv * params.rate_V * (V0 - V) / ((params.mobility if mob else 1.0)
+                                                    * (grid.domain_volume if vol else 1.0))
+        gam = params.gamma0
+        if params.k_A != 0.0 and A0 > 0.0:
+            gam += sa * params.k_A * (A - A0) / (A0 if den0 else A)
+        return lam, gam
+    return {
+        "lambda sign": lambda *a: base(*a, sv=-1.0),
+        "lambda factor 1": lambda *a: base(*a, fv=1.0),
+        "lambda factor 4": lambda *a: base(*a, fv=4.0),
+        "lambda no mobility": lambda *a: base(*a, mob=False),
+        "gamma sign": lambda *a: base(*a, sa=-1.0),
+        "gamma factor 2": lambda *a: base(*a, sa=2.0),
+        "gamma over A": lambda *a: base(*a, den0=False),
+    }
+
+
+@pytest.mark.parametrize("name", list(_mutants()))
+def test_multiplier_pins_catch_planted_mistakes(name):
+    """Each planted mistake in the penalty formulas fails at least one of the two pins (the
+    volume pin at M = 0.6 for the mobility, the area pin at M = 1, h = 1)."""
+    mut = _mutants()[name]
+    ev = _volume_relaxation_error(mult=mut, mobility=0.6, steps=6)
+    try:
+        ea = _area_mode_error(mult=mut, steps=8)
+    except AssertionError:
+        ea = 1.0   # the penalty did not act as it must
+    assert max(ev, ea) > 1e-6, (name, ev, ea)
