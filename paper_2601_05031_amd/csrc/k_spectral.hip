@@ -1201,10 +1201,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(Dims d, RhsArgs rhs, CPtr
 // streams omega_c, S_c and psi_c: omega_c is read once for both problems (its stencil for
 // eq. (5b), its centre as the right-hand side -omega_c of eq. (5c)). Sums are those of
 // resid_norm, term for term.
-// ZS (n_z a multiple of 64, so a wave covers 64 consecutive z of one row): the z neighbours
-// come from the neighbouring lanes' centre values by shuffles, and the two row-edge values
-// from one wave-uniform load each, instead of two full loads per field and plane.
-template <bool ZS>
+// This one-z form serves n_z not a multiple of 32 (k_resid_flow2 below takes the others).
 __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 src, CPtr3 ps,
                                                       SlabGrid sg, double ashift,
                                                       double* __restrict__ partials) {
@@ -1227,21 +1224,10 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow(Dims d, CPtr3 om, CPtr3 s
         const int off = j * d.nz + k;
         const int kp = (k + 1 == d.nz) ? 0 : k + 1;
         const int km = (k == 0) ? d.nz - 1 : k - 1;
-        const int ln = threadIdx.x & 63;
-        const int k0 = k - ln;                               // first z of the wave (ZS)
-        const int kpe = (k0 + 64 == d.nz) ? 0 : k0 + 64;     // z after the wave's last
-        const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;       // z before the wave's first
-        // z neighbours of u at plane row rb, c its centre value
-        auto zpair = [&](const double* u, int rb, double cval, double& zp, double& zm) {
-            if (ZS) {
-                const double up = __shfl_down(cval, 1, 64), dn = __shfl_up(cval, 1, 64);
-                const double ep = u[rb + kpe], em = u[rb + kme];   // one line each
-                zp = ln == 63 ? ep : up;
-                zm = ln == 0 ? em : dn;
-            } else {
-                zp = u[rb + kp];
-                zm = u[rb + km];
-            }
+        // z neighbours of u at plane row rb
+        auto zpair = [&](const double* u, int rb, double, double& zp, double& zm) {
+            zp = u[rb + kp];
+            zm = u[rb + km];
         };
         const int i0 = bi * sg.ci;
         const int i1 = min(d.nx, i0 + sg.ci);
@@ -1745,13 +1731,9 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
     else if (d.nz % 32 == 0)
         launch_kernel(k_resid_flow2<16>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
                       ashift, partials);
-    // a whole number of waves per row lets the z neighbours come from shuffles
-    else if (d.nz % 64 == 0)
-        launch_kernel(k_resid_flow<true>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p,
-                      g, ashift, partials);
     else
-        launch_kernel(k_resid_flow<false>, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p,
-                      g, ashift, partials);
+        launch_kernel(k_resid_flow, dim3(3 * g.gx * g.gi), dim3(kBlock), 0, s, d, o, f, p, g,
+                      ashift, partials);
 }
 
 void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,
