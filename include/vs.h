@@ -159,6 +159,26 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
 vs_status vs_poisson_solve(vs_state* state, const double* f, double* u, double rtol,
                            int32_t max_cycles, int32_t* cycles_out, double* relres_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): vs_poisson_solve without a state or workspace.
+ * Same problem, arguments, convergence rule and results as vs_poisson_solve on a state of
+ * this grid (f, u: device, nx*ny*nz doubles; u in: initial guess and wall values, out:
+ * solution), enqueued on `stream` (a hipStream_t, NULL = default) and synchronised before the
+ * call returns. Its scratch (one FP64 spectral field, the twiddle and pivot tables, residual
+ * partials, status words) is a static device array of vs_noalloc_scratch_bytes() bytes
+ * (48 MiB), one per device, held until the process ends; grids whose scratch does not fit
+ * (8 nx ny nz bytes plus the tables: up to 128 x 128 x 256 at nx = nz = 128) return
+ * VS_E_WORKSPACE before anything is enqueued. The call allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine. The tables are uploaded (from host memory) only
+ * when the grid differs from the previous call's on that device. Every call on a device
+ * shares that device's scratch: calls that overlap on one device (other threads, other
+ * streams) race and must not be issued. */
+vs_status vs_poisson_solve_noalloc(const vs_grid* grid, const double* f, double* u, double rtol,
+                                   int32_t max_cycles, void* stream, int32_t* cycles_out,
+                                   double* relres_out);
+/* Size in bytes of the static scratch of vs_poisson_solve_noalloc on each device. */
+size_t vs_noalloc_scratch_bytes(void);
+
 /* Advance nsteps >= 1 time steps of size dt > 0 (main text eq. (5a)–(5c), forward Euler).
  * Per step: phi^{n+1} = phi^n + dt [M (L_h mu^n + lambda_V^n) - (curl psi^n) . D phi^n];
  * V, A, lambda_V, gamma_A and mu from phi^{n+1}; omega^{n+1} from

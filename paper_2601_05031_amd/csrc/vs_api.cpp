@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -122,6 +123,16 @@ std::vector<double> pivot_table(const vs_grid& g, double shift_h2) {
             tri[(size_t)M * ncls + cls] = beta;
         }
     return tri;
+}
+
+// Twiddles exp(-2 pi i m/n), m < n, computed in long double.
+std::vector<double2> twiddle_table(int n) {
+    std::vector<double2> t(n);
+    for (int m = 0; m < n; ++m) {
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * m / n;
+        t[m] = make_double2((double)cosl(a), (double)(-sinl(a)));
+    }
+    return t;
 }
 
 vs_status check_grid(const vs_grid* g) {
@@ -587,15 +598,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
 
     // Host tables: twiddles exp(-2 pi i m/n), Thomas pivots per Hartley mode class, and the
     // no-body channel profiles of psi_x and omega_x (main text "Boundary conditions").
-    auto twiddles = [](int n) {
-        std::vector<double2> t(n);
-        for (int m = 0; m < n; ++m) {
-            const long double a = 2.0L * 3.14159265358979323846264338327950288L * m / n;
-            t[m] = make_double2((double)cosl(a), (double)(-sinl(a)));
-        }
-        return t;
-    };
-    std::vector<double2> twx = twiddles(grid->nx), twz = twiddles(grid->nz);
+    std::vector<double2> twx = twiddle_table(grid->nx), twz = twiddle_table(grid->nz);
     const std::vector<double> tri = pivot_table(*grid, 0.0);
     std::vector<double> prof = wall_tables(*grid, *walls);
     set_wall_state(S, *walls, prof);
@@ -658,6 +661,149 @@ vs_status vs_poisson_solve(vs_state* S, const double* f, double* u, double rtol,
     if (ist[IS_FLAGS] & ST_NONFINITE) return fail(VS_E_NONFINITE, "vs_poisson_solve: non-finite residual");
     if (ist[IS_FLAGS] & ST_NOCONV)
         return fail(VS_E_NOCONV, "vs_poisson_solve: relative residual %.3g above rtol %.3g after %d cycles",
+                    sc[SC_RELRES_LAST], rtol, ist[IS_CYCLES]);
+    return VS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free solve
+// vs_poisson_solve_noalloc keeps its scratch (one FP64 spectral field, the twiddle and
+// pivot tables, the residual partials and the status words) in this file-scope device array
+// instead of a caller workspace. Each device holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress returns on that device.
+namespace {
+
+constexpr size_t kNoAllocBytes = size_t(48) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+// grid whose twiddle and pivot tables the device's scratch holds (nx = 0: none yet)
+vs_grid g_noalloc_tables[kNoAllocMaxDevices] = {};
+
+struct NoAllocLayout {
+    size_t off_spec, off_twx, off_twz, off_tri, off_part, off_scal, off_istat, total;
+};
+
+NoAllocLayout noalloc_layout(const vs_grid& g) {
+    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    const size_t M = (size_t)g.ny - 2;
+    NoAllocLayout L;
+    size_t o = 0;
+    L.off_spec = o;  o += align_up(N * sizeof(double));
+    L.off_twx = o;   o += align_up((size_t)g.nx * sizeof(double2));
+    L.off_twz = o;   o += align_up((size_t)g.nz * sizeof(double2));
+    L.off_tri = o;   o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * (M + 1) * sizeof(double));
+    L.off_part = o;  o += align_up((size_t)kMaxPartialBlocks * kPartialSlots * sizeof(double));
+    L.off_scal = o;  o += align_up(SC_NSCAL * sizeof(double));
+    L.off_istat = o; o += align_up(IS_NSTAT * sizeof(int));
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vs_noalloc_scratch_bytes(void) { return kNoAllocBytes; }
+
+vs_status vs_poisson_solve_noalloc(const vs_grid* grid, const double* f, double* u, double rtol,
+                                   int32_t max_cycles, void* stream, int32_t* cycles_out,
+                                   double* relres_out) {
+    vs_status st = check_grid(grid);
+    if (st != VS_OK) return st;
+    if (!f || !u) return fail(VS_E_ARG, "f and u must be device pointers");
+    if (!(rtol > 0.0)) return fail(VS_E_ARG, "rtol must be > 0");
+    if (max_cycles < 1 || max_cycles > 16) return fail(VS_E_ARG, "max_cycles must be in [1, 16]");
+    const NoAllocLayout L = noalloc_layout(*grid);
+    if (L.total > kNoAllocBytes)
+        return fail(VS_E_WORKSPACE,
+                    "vs_poisson_solve_noalloc: the %d x %d x %d grid needs %zu bytes of scratch; "
+                    "the static scratch holds %zu",
+                    grid->nx, grid->ny, grid->nz, L.total, kNoAllocBytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(VS_E_UNSUPPORTED, "vs_poisson_solve_noalloc: device %d out of range", dev);
+    hipStream_t hs = (hipStream_t)stream;
+    char* base = nullptr;
+    bool tables = false;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            void* p = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            if (!p) return fail(VS_E_HIP, "hipGetSymbolAddress returned no address for the scratch");
+            g_noalloc_ptr[dev] = p;
+        }
+        base = (char*)g_noalloc_ptr[dev];
+        const vs_grid& t = g_noalloc_tables[dev];
+        tables = t.nx == grid->nx && t.ny == grid->ny && t.nz == grid->nz && t.h == grid->h;
+        g_noalloc_tables[dev] = *grid;
+    }
+    vs_state S;
+    S.g = *grid;
+    S.stream = hs;
+    S.d.nx = grid->nx;
+    S.d.ny = grid->ny;
+    S.d.nz = grid->nz;
+    S.d.M = grid->ny - 2;
+    S.d.h = grid->h;
+    S.d.inv_h2 = 1.0 / (grid->h * grid->h);
+    S.d.inv_2h = 0.5 / grid->h;
+    fft_plan(grid->nx, &S.px);
+    fft_plan(grid->nz, &S.pz);
+    S.spec[0] = base + L.off_spec;
+    S.twx = (double2*)(base + L.off_twx);
+    S.twz = (double2*)(base + L.off_twz);
+    S.tri = (double*)(base + L.off_tri);
+    S.part = (double*)(base + L.off_part);
+    S.scal = (double*)(base + L.off_scal);
+    S.istat = (int*)(base + L.off_istat);
+    // host tables outlive their copies: the stream is synchronised before they go
+    std::vector<double2> twx, twz;
+    std::vector<double> tri;
+    if (!tables) {
+        twx = twiddle_table(grid->nx);
+        twz = twiddle_table(grid->nz);
+        tri = pivot_table(*grid, 0.0);
+        hipError_t e = hipMemcpyAsync(S.twx, twx.data(), twx.size() * sizeof(double2),
+                                      hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.twz, twz.data(), twz.size() * sizeof(double2),
+                               hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.tri, tri.data(), tri.size() * sizeof(double),
+                               hipMemcpyHostToDevice, hs);
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_noalloc_mu);
+            g_noalloc_tables[dev] = vs_grid{};
+            return fail(VS_E_HIP, "vs_poisson_solve_noalloc: table upload failed: %s",
+                        hipGetErrorString(e));
+        }
+    }
+    // status words and residual scalars start from zero (a kernel, not a memset)
+    launch_reset_stats(hs, S.scal, S.istat);
+    RhsArgs r{};
+    r.mode = RHS_FIELD;
+    r.f[0] = f;
+    double* const uu[3] = {u, nullptr, nullptr};
+    enqueue_solve(&S, r, uu, 1, rtol, max_cycles, TAG_FIELD);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(hs));
+    int ist[IS_NSTAT];
+    double sc[SC_NSCAL];
+    HIP_TRY(hipMemcpy(ist, S.istat, sizeof ist, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sc, S.scal, sizeof sc, hipMemcpyDeviceToHost));
+    if (cycles_out) *cycles_out = ist[IS_CYCLES];
+    if (relres_out) *relres_out = sc[SC_RELRES_LAST];
+    if (ist[IS_FLAGS] & ST_NONFINITE)
+        return fail(VS_E_NONFINITE, "vs_poisson_solve_noalloc: non-finite residual");
+    if (ist[IS_FLAGS] & ST_NOCONV)
+        return fail(VS_E_NOCONV,
+                    "vs_poisson_solve_noalloc: relative residual %.3g above rtol %.3g after %d cycles",
                     sc[SC_RELRES_LAST], rtol, ist[IS_CYCLES]);
     return VS_OK;
 }

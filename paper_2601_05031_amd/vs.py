@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         "vs_workspace_bytes": (i32, [P(VsGrid), P(VsParams), P(sz)]),
         "vs_init": (i32, [P(VsGrid), P(VsWalls), P(VsParams), vp, vp, sz, vp, P(vp)]),
         "vs_poisson_solve": (i32, [vp, vp, vp, dbl, i32, P(i32), P(dbl)]),
+        "vs_poisson_solve_noalloc": (i32, [P(VsGrid), vp, vp, dbl, i32, vp, P(i32), P(dbl)]),
+        "vs_noalloc_scratch_bytes": (sz, []),
         "vs_step": (i32, [vp, dbl, i32]),
         "vs_grad_step": (i32, [vp, dbl, vp, vp, P(dbl)]),
         "vs_field_offset": (i32, [vp, i32, P(sz)]),
@@ -126,6 +128,35 @@ def workspace_bytes(grid, params: VsParams) -> int:
     _check(lib().vs_workspace_bytes(ctypes.byref(g), ctypes.byref(params), ctypes.byref(n)),
            "vs_workspace_bytes")
     return n.value
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().vs_noalloc_scratch_bytes())
+
+
+def poisson_solve_noalloc(f, u, h=1.0, rtol=1e-10, max_cycles=3, stream=None):
+    """vs_poisson_solve_noalloc: solve L_h u = f in place in the float64 CUDA tensor u (walls
+    held fixed) with the library's static scratch; no workspace, no state. Returns (code,
+    cycles, relres); codes other than VS_OK and VS_E_NOCONV raise."""
+    import torch
+
+    for t in (f, u):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 3:
+            raise ValueError("f and u must be contiguous 3-d float64 tensors")
+    if tuple(f.shape) != tuple(u.shape):
+        raise ValueError("f and u must have the same shape")
+    g = VsGrid(int(u.shape[0]), int(u.shape[1]), int(u.shape[2]), float(h))
+    if stream is None:
+        stream = torch.cuda.current_stream(u.device)
+    cyc = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    code = lib().vs_poisson_solve_noalloc(ctypes.byref(g), ctypes.c_void_p(f.data_ptr()),
+                                          ctypes.c_void_p(u.data_ptr()), float(rtol),
+                                          int(max_cycles), ctypes.c_void_p(stream.cuda_stream),
+                                          ctypes.byref(cyc), ctypes.byref(rel))
+    if code not in (VS_OK, VS_E_NOCONV):
+        _check(code, "vs_poisson_solve_noalloc")
+    return code, cyc.value, rel.value
 
 
 class Solver:

@@ -141,3 +141,17 @@ def test_null_state_calls():
     L.vs_destroy(None)
     assert L.vs_profile_count() >= 10
     assert L.vs_profile_name(0) == b"advance"
+
+
+def test_noalloc_rejects_grids_beyond_its_scratch_on_the_host():
+    """vs_poisson_solve_noalloc checks the grid against its static scratch before any HIP
+    call (so this runs without a GPU): 256^3 needs far more than 48 MiB."""
+    g = V.VsGrid(256, 256, 256, 1.0)
+    code = P.lib().vs_poisson_solve_noalloc(ctypes.byref(g), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                            1e-10, 1, None, None, None)
+    assert code == V.VS_E_WORKSPACE
+    assert b"static scratch" in P.lib().vs_last_error()
+    assert P.lib().vs_noalloc_scratch_bytes() == 48 << 20
+    g = V.VsGrid(130, 16, 128, 1.0)
+    assert P.lib().vs_poisson_solve_noalloc(ctypes.byref(g), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                            1e-10, 1, None, None, None) == V.VS_E_UNSUPPORTED
