@@ -88,12 +88,13 @@ def stored_traffic(kernel: str, workload: str):
     return float(m_b.group(1))
 
 
-def cpu_baseline(workload, budget_s: float):
-    """The CPU oracle on the same 128^3 workload (kappa = 1): init, then as many steps as fit
-    in about budget_s seconds (at least 2)."""
+def _oracle_steps(budget_s: float):
+    """The CPU oracle on the vesicle128 workload (kappa = 1): init, then as many steps as fit in
+    about budget_s seconds (at least 2), on one thread. Returns (steps, seconds)."""
     import oracle as O
+    from workloads import workload
 
-    w = workload
+    w = workload("vesicle128")
     g = O.Grid(*w.grid.shape, h=w.grid.h)
     walls = O.Walls(w.wall_kind, w.u0, w.u1)
     p = O.Params(model=w.model, eta=w.eta, mobility=w.mobility, eps=w.eps, kappa=1.0,
@@ -113,11 +114,50 @@ def cpu_baseline(workload, budget_s: float):
     t = time.perf_counter() - t0
     if limit is not None:
         limit.restore_original_limits()
-    N = w.grid.N
-    return {"value": N * n / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.name} kappa=1, {n} time steps at {w.grid.nx}x{w.grid.ny}x{w.grid.nz} "
-                      f"after init, numpy/scipy FP64 (single-threaded), {t:.1f} s",
-            "steps_per_s": n / t}
+    return n, t
+
+
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(workload, budget_s: float, all_cores: bool = True):
+    """The CPU oracle (numpy/scipy FP64, one thread per process) on the same 128^3 workload:
+    first one process alone, then one process per host core, each stepping its own copy of
+    the workload (started as CPU-only copies of this script, `--cpu-worker`), aggregate
+    throughput. `value` is the all-core figure; the single-thread one is kept beside it."""
+    import subprocess
+
+    N = workload.grid.N
+    n1, t1 = _oracle_steps(budget_s)
+    single = {"value": N * n1 / t1, "steps_per_s": n1 / t1, "cores": 1,
+              "sample": f"{n1} time steps in {t1:.1f} s"}
+    out = {"value": single["value"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{workload.name} kappa=1, 128x128x128 after init, numpy/scipy FP64 "
+                     f"(one thread per process): {single['sample']}",
+           "single_thread": single}
+    ncore = host_cores()
+    if not all_cores or ncore < 2:
+        return out
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", str(budget_s)]
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env,
+                              text=True) for _ in range(ncore)]
+    steps, secs = 0, 0.0
+    for pr in procs:
+        o, _ = pr.communicate(timeout=30 * budget_s + 300)
+        r = json.loads(o.strip().splitlines()[-1])
+        steps += r["steps"]
+        secs = max(secs, r["seconds"])
+    out.update({"value": N * steps / secs, "cores": ncore, "steps_per_s": steps / secs,
+                "sample": f"{workload.name} kappa=1, 128x128x128 after init, numpy/scipy FP64, "
+                          f"{ncore} processes of one thread each ({steps} time steps, slowest "
+                          f"process {secs:.1f} s); one process alone: {single['sample']}"})
+    return out
 
 
 def compare_precisions(P, torch, steps: int) -> dict:
@@ -349,7 +389,18 @@ def main():
     ap.add_argument("--no-diagnostics", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM counters)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (no vs_autotune before the timed steps)")
+    ap.add_argument("--cpu-single-only", action="store_true",
+                    help="time the CPU oracle on one thread only")
+    ap.add_argument("--cpu-worker", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.cpu_worker > 0:
+        # a CPU-only worker of the all-core oracle baseline: no GPU, one JSON line
+        n, t = _oracle_steps(args.cpu_worker)
+        print(json.dumps({"steps": n, "seconds": t}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -374,6 +425,10 @@ def main():
     print(f"bench: building {len(KAPPAS)} solvers for {base.name} {base.grid.shape}", file=sys.stderr,
           flush=True)
     solvers = [P.solver_for(base, kappa=k) for k in KAPPAS]
+    tuning = None
+    if not args.no_autotune:
+        tuning = solvers[1].autotune()   # launch shapes of the 128^3 grid, shared by all three
+        print(f"bench: autotuned launch shapes {tuning}", file=sys.stderr, flush=True)
     for s in solvers:
         s.step(base.dt, args.warmup)
     torch.cuda.synchronize()
@@ -420,6 +475,8 @@ def main():
     traffic = stored_traffic(dom, base.name)
     ceiling = copy_ceiling(torch)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "timer": "per-launch start/stop events written by the dispatch packets "
+                         "(hipExtLaunchKernelGGL), mean over the profiled steps",
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes, "mean_launch_us": round(kern[dom]["mean_us"], 2),
                 "copy_ceiling": round(ceiling, 1), "frac_of_copy_ceiling": round(achieved / ceiling, 4)}
@@ -476,7 +533,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(base, args.cpu_budget)
+        cpu = cpu_baseline(base, args.cpu_budget, not args.cpu_single_only)
 
     out = {
         "metric": METRIC,
@@ -511,6 +568,7 @@ def main():
         "adjoint": adjoint,
         "diagnostics": diagnostics,
         "inertial": inertial,
+        "autotuned": tuning,
     }
     print(json.dumps(out), flush=True)
 

@@ -54,11 +54,18 @@ typedef enum {
 enum { VS_POISEUILLE = 1, VS_COUETTE = 2 };
 /* vs_params.model */
 enum { VS_BENDING = 1, VS_CAHN_HILLIARD = 2 };
-/* vs_params.precision: VS_FP64 solves each Poisson problem by one exact spectral pass in FP64;
- * VS_FP32_REFINED stores every spectral intermediate (transform outputs, tridiagonal data) in
- * FP32 and wraps each solve in FP64 defect correction (residual in FP64 from the previous
- * step's field, FP32-stored correction solve, FP64 update) until the FP64 relative residual
- * meets poisson_rtol. Stencils, fields and the volume/area integrals stay FP64 in both. */
+/* vs_params.precision: VS_FP64 runs every step in FP64 and solves each Poisson problem by one
+ * exact spectral pass. VS_FP32_REFINED (the reduced-precision mode) keeps phi, omega, psi and
+ * the vorticity source S in FP64 and stores mu and every spectral intermediate as FP32: the
+ * phi update is computed in FP32 arithmetic (the increment added to the FP64 phi); the
+ * chemical potential is computed in FP64 and stored as FP32 (FP32 arithmetic there costs ~1e-5
+ * in mu); the volume/area integrals are FP64; each step's two flow problems run
+ * defect-correction cycles from the previous step's fields: an FP64 residual, its correction
+ * solved in FP32 (transforms and tridiagonal solves), an FP64 update, an FP64 check, until the
+ * relative residuals meet poisson_rtol (up to poisson_max_cycles; the initial solve takes at
+ * least 4). S stays FP64 because FP32 rounding of S alone moves the small components of psi by
+ * ~3e-6. It needs nx, nz in {32, 48, 64, 96, 128, 192, 256} and 4 <= ny - 2 <= 256. In this
+ * mode vs_field_offset(VS_MU) points at nx*ny*nz floats. */
 enum { VS_FP64 = 1, VS_FP32_REFINED = 2 };
 /* vs_params.flags */
 enum { VS_ALLOW_UNSTABLE = 1 };
@@ -264,18 +271,35 @@ int32_t vs_profile_count(void);
 const char* vs_profile_name(int32_t kernel);
 vs_status vs_profile_read(vs_state* state, int32_t kernel, double* total_ms, int64_t* launches);
 
-/* Batches (many independent instances, e.g. vesicles of different grids and parameters).
- * vs_batch_create groups n states made by vs_init (each keeps its own workspace). It creates
- * nstreams HIP streams (instance i runs on stream i % nstreams) and moves every state onto its
- * stream; `stream` (a hipStream_t, NULL = default) is the origin the batch forks from and
- * joins to. vs_batch_step captures two time steps of every instance into one HIP graph (the
- * capture is redone when dt changes) and replays it nsteps/2 times on the origin stream, so a
- * whole batch step is one graph launch and independent instances run concurrently on the
- * GPU. nsteps must be even. dt: host array of n time steps. Each instance is checked against
- * its stability bound first; statuses are collected after one synchronisation (the first
- * failing instance's status is returned). vs_batch_destroy frees the batch and moves the
- * states back to the origin stream; the states stay valid and are destroyed by vs_destroy.
- * A state belongs to at most one batch; do not call vs_step on it while the batch exists. */
+/* Launch-shape autotuner. Times, on the state's own data, the candidate launch shapes of its
+ * grid: the x-slab length of the phi update (2, 4, 8 planes per lane), the block caps of the
+ * volume/area partials (256 .. 2048) and of the flow residual (512 .. 4096), and, for
+ * ny - 2 in {30, 46, 62, 94, 126, 254}, the segment layout of the tridiagonal solves (the
+ * default or one with twice/half the lanes per mode), one coordinate at a time, and keeps the
+ * fastest for every state of that grid in this process. The state's fields are not changed.
+ * picked (may be NULL): adv_slab, va_maxb, res_maxb, seg_alt. Synchronises. */
+vs_status vs_autotune(vs_state* state, int32_t picked[4]);
+
+/* Batches (many independent instances, e.g. vesicles of different grids and parameters; the
+ * batching extension of the benchmark spec, its persistent launch read as one launch per kernel
+ * and instance group). vs_batch_create groups n states made by vs_init (each keeps its own
+ * workspace) into grid classes (same grid, precision, model and poisson_max_cycles), and each
+ * class into groups of about 2^21 nodes (all instances of a small grid, one 128^3 instance):
+ * every kernel of a time step is launched once per group, each instance's pointers and
+ * parameters read from a device table of argument structs (allocated by the batch: a few KB
+ * per instance). Grids of a class not tuned yet are tuned first (vs_autotune on the class's
+ * first instance). Instances outside the fused forms (FP64 with poisson_max_cycles > 1) are
+ * stepped one by one. It creates min(nstreams, groups) HIP streams (group g runs on stream
+ * g % nstreams) and moves every state onto its stream; `stream` (a hipStream_t, NULL =
+ * default) is the origin the batch forks from and joins to. vs_batch_step captures two time
+ * steps of every group into one HIP graph (redone when a dt or a wall speed changes) and
+ * replays it nsteps/2 times on the origin stream. nsteps must be even. dt: host array of n
+ * time steps. Each instance is checked against its stability bound first; statuses are
+ * collected after one synchronisation (the first failing instance's status is returned).
+ * Results are bitwise those of stepping each instance alone. vs_batch_destroy frees the batch
+ * and moves the states back to the origin stream; the states stay valid and are destroyed by
+ * vs_destroy. A state belongs to at most one batch; do not call vs_step on it while the batch
+ * exists. */
 typedef struct vs_batch vs_batch;
 vs_status vs_batch_create(vs_state* const* states, int32_t n, void* stream, int32_t nstreams,
                           vs_batch** out);

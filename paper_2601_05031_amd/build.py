@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvs.so")
 
-SOURCES = ["k_explicit.hip", "k_spectral.hip", "k_adjoint.hip", "k_diag.hip", "vs_api.cpp"]
+SOURCES = ["k_explicit.hip", "k_spectral.hip", "k_solve.hip", "k_adjoint.hip", "k_diag.hip", "vs_api.cpp"]
 
 # Packed FP32 instructions are switched off for every device compilation (the host pass
 # warns that it does not know the feature; that is harmless).

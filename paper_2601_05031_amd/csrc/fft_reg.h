@@ -1,5 +1,5 @@
 // In-register complex DFTs of small compile-time sizes (2, 3, 4, 6, 8, 12, 16), natural order
-// in and out, forward sign exp(-2 pi i p k / R). Sizes 6, 8, 12, 16 are built by one
+// in and out, forward sign exp(-2 pi i p k / R), in FP64 (double2) or FP32 (float2). Sizes 6, 8, 12, 16 are built by one
 // Cooley-Tukey split R = R1 * R2 (input index k1 + R1 k2, output index p2 + R2 p1) with
 // compile-time twiddles exp(-2 pi i k1 p2 / R).
 #pragma once
@@ -62,10 +62,43 @@ __host__ __device__ constexpr cd wr(int R, int m) {
     return (16 % R == 0) ? w16((m % R) * (16 / R)) : w12((m % R) * (12 / R));
 }
 
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmulw(double2 a, cd w) {
-    return make_double2(a.x * w.re - a.y * w.im, a.x * w.im + a.y * w.re);
+// Complex values as HIP's double2 or float2: the transforms run in the precision of the data
+// they carry (FP64, or FP32 in the refined mode).
+template <class T>
+struct V2;
+template <>
+struct V2<double> {
+    using t = double2;
+    static __device__ __forceinline__ double2 mk(double a, double b) { return make_double2(a, b); }
+};
+template <>
+struct V2<float> {
+    using t = float2;
+    static __device__ __forceinline__ float2 mk(float a, float b) { return make_float2(a, b); }
+};
+
+template <class C>
+__device__ __forceinline__ C cadd(C a, C b) {
+    C r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <class C>
+__device__ __forceinline__ C csub(C a, C b) {
+    C r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+template <class C>
+__device__ __forceinline__ C cmulw(C a, cd w) {
+    using T = decltype(a.x);
+    const T wr_ = (T)w.re, wi = (T)w.im;
+    C r;
+    r.x = a.x * wr_ - a.y * wi;
+    r.y = a.x * wi + a.y * wr_;
+    return r;
 }
 
 template <int R>
@@ -73,8 +106,9 @@ struct DFT;
 
 template <>
 struct DFT<2> {
-    static __device__ __forceinline__ void run(double2* x) {
-        const double2 a = x[0], b = x[1];
+    template <class C>
+    static __device__ __forceinline__ void run(C* x) {
+        const C a = x[0], b = x[1];
         x[0] = cadd(a, b);
         x[1] = csub(a, b);
     }
@@ -82,38 +116,48 @@ struct DFT<2> {
 
 template <>
 struct DFT<3> {
-    static __device__ __forceinline__ void run(double2* x) {
-        const double c = 0.86602540378443864676;
-        const double2 s = cadd(x[1], x[2]);
-        const double2 e = csub(x[1], x[2]);
-        const double2 m = make_double2(x[0].x - 0.5 * s.x, x[0].y - 0.5 * s.y);
+    template <class C>
+    static __device__ __forceinline__ void run(C* x) {
+        using T = decltype(x[0].x);
+        const T c = (T)0.86602540378443864676;
+        const T half = (T)0.5;
+        const C s = cadd(x[1], x[2]);
+        const C e = csub(x[1], x[2]);
+        C m;
+        m.x = x[0].x - half * s.x;
+        m.y = x[0].y - half * s.y;
         x[0] = cadd(x[0], s);
-        x[1] = make_double2(m.x + c * e.y, m.y - c * e.x);
-        x[2] = make_double2(m.x - c * e.y, m.y + c * e.x);
+        x[1].x = m.x + c * e.y;
+        x[1].y = m.y - c * e.x;
+        x[2].x = m.x - c * e.y;
+        x[2].y = m.y + c * e.x;
     }
 };
 
 template <>
 struct DFT<4> {
-    static __device__ __forceinline__ void run(double2* x) {
-        const double2 a = cadd(x[0], x[2]);
-        const double2 b = csub(x[0], x[2]);
-        const double2 c = cadd(x[1], x[3]);
-        const double2 e = csub(x[1], x[3]);
+    template <class C>
+    static __device__ __forceinline__ void run(C* x) {
+        const C a = cadd(x[0], x[2]);
+        const C b = csub(x[0], x[2]);
+        const C c = cadd(x[1], x[3]);
+        const C e = csub(x[1], x[3]);
         x[0] = cadd(a, c);
         x[2] = csub(a, c);
-        x[1] = make_double2(b.x + e.y, b.y - e.x);
-        x[3] = make_double2(b.x - e.y, b.y + e.x);
+        x[1].x = b.x + e.y;
+        x[1].y = b.y - e.x;
+        x[3].x = b.x - e.y;
+        x[3].y = b.y + e.x;
     }
 };
 
-template <int R1, int R2>
-__device__ __forceinline__ void dft_split(double2* x) {
+template <int R1, int R2, class C>
+__device__ __forceinline__ void dft_split(C* x) {
     constexpr int R = R1 * R2;
-    double2 y[R];
+    C y[R];
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) {
-        double2 t[R2];
+        C t[R2];
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) t[k2] = x[k1 + R1 * k2];
         DFT<R2>::run(t);
@@ -123,7 +167,7 @@ __device__ __forceinline__ void dft_split(double2* x) {
     }
 #pragma unroll
     for (int p2 = 0; p2 < R2; ++p2) {
-        double2 t[R1];
+        C t[R1];
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) t[k1] = y[k1 * R2 + p2];
         DFT<R1>::run(t);
@@ -134,19 +178,23 @@ __device__ __forceinline__ void dft_split(double2* x) {
 
 template <>
 struct DFT<6> {
-    static __device__ __forceinline__ void run(double2* x) { dft_split<2, 3>(x); }
+    template <class C>
+    static __device__ __forceinline__ void run(C* x) { dft_split<2, 3>(x); }
 };
 template <>
 struct DFT<8> {
-    static __device__ __forceinline__ void run(double2* x) { dft_split<2, 4>(x); }
+    template <class C>
+    static __device__ __forceinline__ void run(C* x) { dft_split<2, 4>(x); }
 };
 template <>
 struct DFT<12> {
-    static __device__ __forceinline__ void run(double2* x) { dft_split<4, 3>(x); }
+    template <class C>
+    static __device__ __forceinline__ void run(C* x) { dft_split<4, 3>(x); }
 };
 template <>
 struct DFT<16> {
-    static __device__ __forceinline__ void run(double2* x) { dft_split<4, 4>(x); }
+    template <class C>
+    static __device__ __forceinline__ void run(C* x) { dft_split<4, 4>(x); }
 };
 
 }  // namespace fftr

@@ -16,9 +16,11 @@ __device__ __forceinline__ double fc_wave_sum(double v) {
 }
 
 // Call from every thread of one block (a multiple of 64 threads, at most 1024); sh holds
-// 4 * 16 doubles.
+// 4 * 16 doubles. last_cycle = 0 (a defect-correction cycle that may be followed by another):
+// the convergence flag gates the next cycle and the miss is not yet an error.
 __device__ inline void flow_check_block(const double* __restrict__ partials, int nblocks,
-                                        double rtol, double* scal, int* istat, double* sh) {
+                                        double rtol, double* scal, int* istat, double* sh,
+                                        int last_cycle = 1) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
@@ -40,23 +42,30 @@ __device__ inline void flow_check_block(const double* __restrict__ partials, int
             a[g] = 0.0;
             for (int q = 0; q < nw; ++q) a[g] += sh[g * 16 + q];
         }
+        double rel[2];
+        int conv = 1;
         for (int sidx = 0; sidx < 2; ++sidx) {
             const double rr = a[2 * sidx], bb = a[2 * sidx + 1];
-            double rel;
+            double r;
             if (bb > 0.0)
-                rel = sqrt(rr / bb);
+                r = sqrt(rr / bb);
             else
-                rel = (rr > 0.0) ? INFINITY : 0.0;
-            if (rr != rr || bb != bb) rel = NAN;
-            const int conv = (rel <= rtol) ? 1 : 0;
-            istat[IS_CONV] = conv;
+                r = (rr > 0.0) ? INFINITY : 0.0;
+            if (rr != rr || bb != bb) r = NAN;
+            rel[sidx] = r;
+            conv &= (r <= rtol) ? 1 : 0;
             istat[IS_CYCLES] += 1;
-            scal[SC_RELRES_LAST] = rel;
-            const double prev = scal[SC_RELRES_MAX];
-            scal[SC_RELRES_MAX] = (rel != rel || rel > prev) ? rel : prev;
-            if (!conv) istat[IS_FLAGS] |= ST_NOCONV;
+            scal[SC_RELRES_LAST] = r;
             if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
         }
+        istat[IS_CONV] = conv;
+        if (conv || last_cycle) {
+            for (int sidx = 0; sidx < 2; ++sidx) {
+                const double prev = scal[SC_RELRES_MAX];
+                scal[SC_RELRES_MAX] = (rel[sidx] != rel[sidx] || rel[sidx] > prev) ? rel[sidx] : prev;
+            }
+        }
+        if (!conv && last_cycle) istat[IS_FLAGS] |= ST_NOCONV;
     }
     __syncthreads();
 }

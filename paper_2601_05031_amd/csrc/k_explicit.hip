@@ -1,8 +1,12 @@
-// Explicit stencils of one time step on gfx950, FP64:
+// Explicit stencils of one time step on gfx950:
 //   phi-update (main text eq. (5a), SM (29a)/(38)) with the velocity v = curl psi (eq. (3))
 //   fused in registers; the chemical potential (SM eq. (35) bending, eq. F_CH / SM (31)
 //   Cahn-Hilliard); the volume and area integrals (SM eq. (37), (32)) with the penalty
-//   multipliers (SM "Lagrange multipliers"). Launch shape and wall handling: stencil.h.
+//   multipliers (SM "Lagrange multipliers"); the vorticity source of eq. (5b).
+// Each kernel runs in FP64, or in the refined mode's precision (T = float: mu and S stored as
+// float, the phi update and the source computed in FP32, phi kept in FP64), over one instance
+// or over every instance of a grid class in one launch (BATCH: per-instance arguments from a
+// device table; see Over in vs_internal.h). Launch shape and wall handling: stencil.h.
 #include "flow_check.h"
 #include "stencil.h"
 
@@ -10,26 +14,96 @@ namespace vs {
 
 namespace {
 
+// Pairs of two consecutive z values in the arithmetic type T.
+template <class T>
+struct P2;
+template <>
+struct P2<double> {
+    using t = double2;
+    typedef double v __attribute__((ext_vector_type(2)));   // the same pair for memory access
+};
+template <>
+struct P2<float> {
+    using t = float2;
+    typedef float v __attribute__((ext_vector_type(2)));
+};
+// Objects in global memory. Pointers that a batched launch reads from its device table are
+// generic; typing the accesses through them as global keeps them global loads and stores
+// (flat ones would also count against the LDS counter).
+template <class T>
+using Gl = __attribute__((address_space(1))) T;
+
+// An FP64 field's pair converted to T (identity in FP64).
+template <class T>
+__device__ __forceinline__ typename P2<T>::t cvt2(double2 v) {
+    typename P2<T>::t r;
+    r.x = (T)v.x;
+    r.y = (T)v.y;
+    return r;
+}
+template <class T>
+__device__ __forceinline__ typename P2<T>::t ldt2(const Gl<T>* q) {
+    const typename P2<T>::v m = *reinterpret_cast<const Gl<typename P2<T>::v>*>(q);
+    typename P2<T>::t r;
+    r.x = m.x;
+    r.y = m.y;
+    return r;
+}
+__device__ __forceinline__ double2 ldd2(const Gl<double>* q) { return ldt2<double>(q); }
+template <class T>
+__device__ __forceinline__ void stt2(Gl<T>* q, T a, T b) {
+    typename P2<T>::v m;
+    m.x = a;
+    m.y = b;
+    *reinterpret_cast<Gl<typename P2<T>::v>*>(q) = m;
+}
+
+// The instance of a block and its index inside the instance: logical blocks (after the XCD
+// order over the whole grid) are split into runs of nb per instance.
+template <bool BATCH>
+__device__ __forceinline__ int split_block(int lb, int nb, int& inst) {
+    if (!BATCH) {
+        inst = 0;
+        return lb;
+    }
+    inst = lb / nb;
+    return lb - inst * nb;
+}
+template <bool BATCH, class A>
+__device__ __forceinline__ A inst_args(const A& one, const A* __restrict__ tab, int inst) {
+    if constexpr (BATCH)
+        return tab[inst];
+    else
+        return one;
+}
+
 // phi_out = phi + dt [ M (L_h mu + lambda_V) - v . D phi ], v = curl psi (eq. (3)) on the
 // interior rows and the wall speed on the walls; D is the central difference, L_h the
 // 7-point Laplacian with mirror ghosts in y (phi[-1] = phi[1], phi[ny] = phi[ny-2]).
-// Marching along x: each lane owns one (j, k) and walks kAdvSlab consecutive x-planes,
+// Marching along x: each lane owns one (j, k) and walks a slab of consecutive x-planes (the
+// tuned adv_slab, 4 by default),
 // keeping phi, mu, psi_y and psi_z of the planes i-1, i, i+1 in registers, so the
-// x-neighbours are not re-read; the y and z neighbours come through the cache.
-constexpr int kAdvSlab = 4;
+// x-neighbours are not re-read; the y and z neighbours come through the cache. The increment
+// is computed in T and added to the FP64 phi.
 
-__global__ __launch_bounds__(kBlock) void k_advance_x(
-    const double* __restrict__ phi, const double* __restrict__ mu,
-    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
-    double* __restrict__ out, Dims d, SlabGrid sg, double* scal, double dt, double mob,
-    double vz_lo, double vz_hi, PrevCheck ck) {
-    if (ck.partials && blockIdx.x == 0) {
+template <bool BATCH, class T>
+__global__ __launch_bounds__(kBlock) void k_advance_x(Dims d, SlabGrid sg, AdvArgs one,
+                                                      const AdvArgs* __restrict__ tab) {
+    const int nb = sg.gx * sg.gi;
+    int inst;
+    const int lb = split_block<BATCH>(xcd_block(blockIdx.x, gridDim.x), nb, inst);
+    const AdvArgs a = inst_args<BATCH>(one, tab, inst);
+    if (a.ck_part && lb == 0) {
         // the previous step's flow check, off the critical path of this kernel's other blocks
         __shared__ double shc[4 * 16];
-        flow_check_block(ck.partials, ck.nblocks, ck.rtol, scal, ck.istat, shc);
+        flow_check_block(a.ck_part, a.ck_nb, a.ck_rtol, a.scal, a.ck_istat, shc);
     }
-    const int nb = sg.gx * sg.gi;
-    const int lb = xcd_block(blockIdx.x, nb);
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)a.phi;
+    const Gl<T>* __restrict__ mu = (const Gl<T>*)a.mu;
+    const Gl<double>* __restrict__ px = (const Gl<double>*)a.ps[0];
+    const Gl<double>* __restrict__ py = (const Gl<double>*)a.ps[1];
+    const Gl<double>* __restrict__ pz = (const Gl<double>*)a.ps[2];
+    Gl<double>* __restrict__ out = (Gl<double>*)a.out;
     const int bi = lb / sg.gx;
     const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
     if (t >= d.ny * d.nz) return;
@@ -43,32 +117,37 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
     const bool wall = (j == 0 || j == d.ny - 1);
     const int o = j * d.nz + k;                          // offset inside a plane
     const int oyp = jp * d.nz + k, oym = jm * d.nz + k, ozp = j * d.nz + kp, ozm = j * d.nz + km;
-    const double lam = scal[SC_LAMV];
+    const T lam = (T)a.scal[SC_LAMV];
+    const T i2h = (T)d.inv_2h, ih2 = (T)d.inv_h2;
     auto pl = [&](int i) { return (size_t)((i + d.nx) % d.nx) * plane; };
     size_t b = pl(i0 - 1);
-    double phm = phi[b + o], mum = mu[b + o], pym = wall ? 0.0 : py[b + o], pzm = wall ? 0.0 : pz[b + o];
+    double phm = phi[b + o];
+    T mum = mu[b + o], pym = wall ? (T)0 : (T)py[b + o], pzm = wall ? (T)0 : (T)pz[b + o];
     b = pl(i0);
-    double ph0 = phi[b + o], mu0 = mu[b + o], py0 = wall ? 0.0 : py[b + o], pz0 = wall ? 0.0 : pz[b + o];
+    double ph0 = phi[b + o];
+    T mu0 = mu[b + o], py0 = wall ? (T)0 : (T)py[b + o], pz0 = wall ? (T)0 : (T)pz[b + o];
     for (int i = i0; i < i1; ++i) {
         const size_t bc = (size_t)i * plane, bn = pl(i + 1);
-        const double php = phi[bn + o], mup = mu[bn + o];
-        const double pyp = wall ? 0.0 : py[bn + o], pzp = wall ? 0.0 : pz[bn + o];
-        const double lmu = (mup + mum + mu[bc + oyp] + mu[bc + oym] + mu[bc + ozp] + mu[bc + ozm] -
-                            6.0 * mu0) * d.inv_h2;
-        const double dx = (php - phm) * d.inv_2h;
-        const double dy = (phi[bc + oyp] - phi[bc + oym]) * d.inv_2h;
-        const double dz = (phi[bc + ozp] - phi[bc + ozm]) * d.inv_2h;
-        double vx = 0.0, vy = 0.0, vz;
+        const double php = phi[bn + o];
+        const T mup = mu[bn + o];
+        const T pyp = wall ? (T)0 : (T)py[bn + o], pzp = wall ? (T)0 : (T)pz[bn + o];
+        const T lmu = (mup + mum + mu[bc + oyp] + mu[bc + oym] + mu[bc + ozp] + mu[bc + ozm] -
+                       (T)6 * mu0) * ih2;
+        const T dx = ((T)php - (T)phm) * i2h;
+        const T dy = ((T)phi[bc + oyp] - (T)phi[bc + oym]) * i2h;
+        const T dz = ((T)phi[bc + ozp] - (T)phi[bc + ozm]) * i2h;
+        T vx = 0, vy = 0, vz;
         if (j == 0) {
-            vz = vz_lo;
+            vz = (T)a.vz_lo;
         } else if (j == d.ny - 1) {
-            vz = vz_hi;
+            vz = (T)a.vz_hi;
         } else {
-            vx = ((pz[bc + oyp] - pz[bc + oym]) - (py[bc + ozp] - py[bc + ozm])) * d.inv_2h;
-            vy = ((px[bc + ozp] - px[bc + ozm]) - (pzp - pzm)) * d.inv_2h;
-            vz = ((pyp - pym) - (px[bc + oyp] - px[bc + oym])) * d.inv_2h;
+            vx = (((T)pz[bc + oyp] - (T)pz[bc + oym]) - ((T)py[bc + ozp] - (T)py[bc + ozm])) * i2h;
+            vy = (((T)px[bc + ozp] - (T)px[bc + ozm]) - (pzp - pzm)) * i2h;
+            vz = ((pyp - pym) - ((T)px[bc + oyp] - (T)px[bc + oym])) * i2h;
         }
-        out[bc + o] = ph0 + dt * (mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
+        const T inc = (T)a.dt * ((T)a.mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
+        out[bc + o] = ph0 + (double)inc;
         phm = ph0; ph0 = php;
         mum = mu0; mu0 = mup;
         pym = py0; py0 = pyp;
@@ -76,28 +155,33 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(
     }
 }
 
-
 // k_advance_x with two consecutive z per lane. W lanes (64, 32 or 16) cover 2W consecutive z of
-// one row, n_z a multiple of 2W: every field access moves 16 bytes, and the z neighbours
+// one row, n_z a multiple of 2W: every FP64 field access moves 16 bytes, and the z neighbours
 // inside the pair come from the pair itself, across lanes by width-W shuffles, and the
-// segment's two edge values by one load each (the same address in every lane of a segment). The psi values of the wall rows are loaded too (in bounds,
-// unused there), so that no branch guards a load, and the next plane's centres are loaded
-// last (pinned by a scheduling barrier), so they stay in flight while the current plane is
-// computed. Same arithmetic per node as k_advance_x, so the two forms agree bit for bit.
-constexpr int kAdvSlab2 = 4;
+// segment's two edge values by one load each (the same address in every lane of a segment).
+// The psi values of the wall rows are loaded too (in bounds, unused there), so that no branch
+// guards a load, and the next plane's centres are loaded last (pinned by a scheduling
+// barrier), so they stay in flight while the current plane is computed. Same arithmetic per
+// node as k_advance_x, so the two forms agree bit for bit.
 
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_advance_x2(
-    const double* __restrict__ phi, const double* __restrict__ mu,
-    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz,
-    double* __restrict__ out, Dims d, SlabGrid sg, double* scal, double dt, double mob,
-    double vz_lo, double vz_hi, PrevCheck ck) {
-    if (ck.partials && blockIdx.x == 0) {
-        __shared__ double shc[4 * 16];
-        flow_check_block(ck.partials, ck.nblocks, ck.rtol, scal, ck.istat, shc);
-    }
+template <int W, bool BATCH, class T>
+__global__ __launch_bounds__(kBlock) void k_advance_x2(Dims d, SlabGrid sg, AdvArgs one,
+                                                       const AdvArgs* __restrict__ tab) {
+    using V = typename P2<T>::t;
     const int nb = sg.gx * sg.gi;
-    const int lb = xcd_block(blockIdx.x, nb);
+    int inst;
+    const int lb = split_block<BATCH>(xcd_block(blockIdx.x, gridDim.x), nb, inst);
+    const AdvArgs a = inst_args<BATCH>(one, tab, inst);
+    if (a.ck_part && lb == 0) {
+        __shared__ double shc[4 * 16];
+        flow_check_block(a.ck_part, a.ck_nb, a.ck_rtol, a.scal, a.ck_istat, shc);
+    }
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)a.phi;
+    const Gl<T>* __restrict__ mu = (const Gl<T>*)a.mu;
+    const Gl<double>* __restrict__ px = (const Gl<double>*)a.ps[0];
+    const Gl<double>* __restrict__ py = (const Gl<double>*)a.ps[1];
+    const Gl<double>* __restrict__ pz = (const Gl<double>*)a.ps[2];
+    Gl<double>* __restrict__ out = (Gl<double>*)a.out;
     const int bi = lb / sg.gx;
     const int hz = d.nz >> 1;
     const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
@@ -114,13 +198,12 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
     const int o = j * d.nz + k;
     const int oyp = jp * d.nz + k, oym = jm * d.nz + k;
     const int re = j * d.nz;                             // row start inside a plane
-    const double lam = scal[SC_LAMV];
-    auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
+    const T lam = (T)a.scal[SC_LAMV];
+    const T i2h = (T)d.inv_2h, ih2 = (T)d.inv_h2;
     // z neighbours (zp, zm) of node k and of node k + 1 from the pair v; el, er: the values
     // just before the wave's first z and just after its last
-    auto zn = [&](double2 v, double el, double er, double& zpa, double& zma, double& zpb,
-                  double& zmb) {
-        const double prev = __shfl_up(v.y, 1, W), next = __shfl_down(v.x, 1, W);
+    auto zn = [&](V v, T el, T er, T& zpa, T& zma, T& zpb, T& zmb) {
+        const T prev = __shfl_up(v.y, 1, W), next = __shfl_down(v.x, 1, W);
         zpa = v.y;
         zma = ln == 0 ? el : prev;
         zpb = ln == W - 1 ? er : next;
@@ -128,60 +211,65 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(
     };
     auto pl = [&](int i) { return (size_t)((i + d.nx) % d.nx) * plane; };
     size_t b = pl(i0 - 1);
-    double2 phm = ld2v(phi + b + o), mum = ld2v(mu + b + o), pym = ld2v(py + b + o),
-            pzm = ld2v(pz + b + o);
+    double2 phm = ldd2(phi + b + o);
+    V mum = ldt2<T>(mu + b + o), pym = cvt2<T>(ldd2(py + b + o)), pzm = cvt2<T>(ldd2(pz + b + o));
     b = pl(i0);
-    double2 ph0 = ld2v(phi + b + o), mu0 = ld2v(mu + b + o), py0 = ld2v(py + b + o),
-            pz0 = ld2v(pz + b + o);
+    double2 ph0 = ldd2(phi + b + o);
+    V mu0 = ldt2<T>(mu + b + o), py0 = cvt2<T>(ldd2(py + b + o)), pz0 = cvt2<T>(ldd2(pz + b + o));
     for (int i = i0; i < i1; ++i) {
         const size_t bc = (size_t)i * plane, bn = pl(i + 1);
-        const double2 myp = ld2v(mu + bc + oyp), mym = ld2v(mu + bc + oym);
-        const double2 fyp = ld2v(phi + bc + oyp), fym = ld2v(phi + bc + oym);
-        const double2 zyp = ld2v(pz + bc + oyp), zym = ld2v(pz + bc + oym);
-        const double2 xyp = ld2v(px + bc + oyp), xym = ld2v(px + bc + oym);
-        const double2 pxc = ld2v(px + bc + o);
+        const V myp = ldt2<T>(mu + bc + oyp), mym = ldt2<T>(mu + bc + oym);
+        const V fyp = cvt2<T>(ldd2(phi + bc + oyp)), fym = cvt2<T>(ldd2(phi + bc + oym));
+        const V zyp = cvt2<T>(ldd2(pz + bc + oyp)), zym = cvt2<T>(ldd2(pz + bc + oym));
+        const V xyp = cvt2<T>(ldd2(px + bc + oyp)), xym = cvt2<T>(ldd2(px + bc + oym));
+        const V pxc = cvt2<T>(ldd2(px + bc + o));
         const size_t ro = bc + re;
-        const double mu_l = mu[ro + kme], mu_r = mu[ro + kpe], ph_l = phi[ro + kme], ph_r = phi[ro + kpe];
-        const double py_l = py[ro + kme], py_r = py[ro + kpe], px_l = px[ro + kme], px_r = px[ro + kpe];
+        const T mu_l = mu[ro + kme], mu_r = mu[ro + kpe];
+        const T ph_l = (T)phi[ro + kme], ph_r = (T)phi[ro + kpe];
+        const T py_l = (T)py[ro + kme], py_r = (T)py[ro + kpe];
+        const T px_l = (T)px[ro + kme], px_r = (T)px[ro + kpe];
         // the next plane's centres last: they stay in flight while this plane is computed
-        const double2 php = ld2v(phi + bn + o), mup = ld2v(mu + bn + o);
-        const double2 pyp = ld2v(py + bn + o), pzp = ld2v(pz + bn + o);
+        const double2 php = ldd2(phi + bn + o);
+        const V mup = ldt2<T>(mu + bn + o);
+        const V pyp = cvt2<T>(ldd2(py + bn + o)), pzp = cvt2<T>(ldd2(pz + bn + o));
         __builtin_amdgcn_sched_barrier(0);
-        double mzpa, mzma, mzpb, mzmb, fzpa, fzma, fzpb, fzmb;
-        double yzpa, yzma, yzpb, yzmb, xzpa, xzma, xzpb, xzmb;
+        const V f0 = cvt2<T>(ph0), fp = cvt2<T>(php), fm = cvt2<T>(phm);
+        T mzpa, mzma, mzpb, mzmb, fzpa, fzma, fzpb, fzmb;
+        T yzpa, yzma, yzpb, yzmb, xzpa, xzma, xzpb, xzmb;
         zn(mu0, mu_l, mu_r, mzpa, mzma, mzpb, mzmb);
-        zn(ph0, ph_l, ph_r, fzpa, fzma, fzpb, fzmb);
+        zn(f0, ph_l, ph_r, fzpa, fzma, fzpb, fzmb);
         zn(py0, py_l, py_r, yzpa, yzma, yzpb, yzmb);
         zn(pxc, px_l, px_r, xzpa, xzma, xzpb, xzmb);
         double2 res;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const double c_mup = h ? mup.y : mup.x, c_mum = h ? mum.y : mum.x;
-            const double c_mu0 = h ? mu0.y : mu0.x;
-            const double c_php = h ? php.y : php.x, c_phm = h ? phm.y : phm.x;
+            const T c_mup = h ? mup.y : mup.x, c_mum = h ? mum.y : mum.x;
+            const T c_mu0 = h ? mu0.y : mu0.x;
+            const T c_php = h ? fp.y : fp.x, c_phm = h ? fm.y : fm.x;
             const double c_ph0 = h ? ph0.y : ph0.x;
-            const double lmu = (c_mup + c_mum + (h ? myp.y : myp.x) + (h ? mym.y : mym.x) +
-                                (h ? mzpb : mzpa) + (h ? mzmb : mzma) - 6.0 * c_mu0) * d.inv_h2;
-            const double dx = (c_php - c_phm) * d.inv_2h;
-            const double dy = ((h ? fyp.y : fyp.x) - (h ? fym.y : fym.x)) * d.inv_2h;
-            const double dz = ((h ? fzpb : fzpa) - (h ? fzmb : fzma)) * d.inv_2h;
-            double vx = 0.0, vy = 0.0, vz;
+            const T lmu = (c_mup + c_mum + (h ? myp.y : myp.x) + (h ? mym.y : mym.x) +
+                           (h ? mzpb : mzpa) + (h ? mzmb : mzma) - (T)6 * c_mu0) * ih2;
+            const T dx = (c_php - c_phm) * i2h;
+            const T dy = ((h ? fyp.y : fyp.x) - (h ? fym.y : fym.x)) * i2h;
+            const T dz = ((h ? fzpb : fzpa) - (h ? fzmb : fzma)) * i2h;
+            T vx = 0, vy = 0, vz;
             if (j == 0) {
-                vz = vz_lo;
+                vz = (T)a.vz_lo;
             } else if (j == d.ny - 1) {
-                vz = vz_hi;
+                vz = (T)a.vz_hi;
             } else {
                 vx = (((h ? zyp.y : zyp.x) - (h ? zym.y : zym.x)) -
-                      ((h ? yzpb : yzpa) - (h ? yzmb : yzma))) * d.inv_2h;
+                      ((h ? yzpb : yzpa) - (h ? yzmb : yzma))) * i2h;
                 vy = (((h ? xzpb : xzpa) - (h ? xzmb : xzma)) -
-                      ((h ? pzp.y : pzp.x) - (h ? pzm.y : pzm.x))) * d.inv_2h;
+                      ((h ? pzp.y : pzp.x) - (h ? pzm.y : pzm.x))) * i2h;
                 vz = (((h ? pyp.y : pyp.x) - (h ? pym.y : pym.x)) -
-                      ((h ? xyp.y : xyp.x) - (h ? xym.y : xym.x))) * d.inv_2h;
+                      ((h ? xyp.y : xyp.x) - (h ? xym.y : xym.x))) * i2h;
             }
-            const double r = c_ph0 + dt * (mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
+            const T inc = (T)a.dt * ((T)a.mob * (lmu + lam) - (vx * dx + vy * dy + vz * dz));
+            const double r = c_ph0 + (double)inc;
             if (h) res.y = r; else res.x = r;
         }
-        *reinterpret_cast<double2*>(out + bc + o) = res;
+        stt2<double>(out + bc + o, res.x, res.y);
         phm = ph0; ph0 = php;
         mum = mu0; mu0 = mup;
         pym = py0; py0 = pyp;
@@ -203,28 +291,29 @@ constexpr int kVaPer = 4;
 struct VaLoads {
     double v[2][kVaPer];
 };
-__device__ __forceinline__ void va_load(const VaFinal& va, VaLoads& L) {
+__device__ __forceinline__ void va_load(const MuArgs& va, int nblocks, VaLoads& L) {
 #pragma unroll
     for (int u = 0; u < kVaPer; ++u) {
         const int b = threadIdx.x + u * blockDim.x;
-        const int bc = b < va.nblocks ? b : 0;
-        L.v[0][u] = va.partials[0 * kMaxPartialBlocks + bc];
-        L.v[1][u] = va.partials[1 * kMaxPartialBlocks + bc];
+        const int bc = b < nblocks ? b : 0;
+        L.v[0][u] = va.part[0 * kMaxPartialBlocks + bc];
+        L.v[1][u] = va.part[1 * kMaxPartialBlocks + bc];
     }
 }
-__device__ __forceinline__ void va_reduce(const VaFinal& va, const VaLoads& L, double* sh) {
+__device__ __forceinline__ void va_reduce(const MuArgs& va, int nblocks, const VaLoads& L,
+                                          double* sh) {
     double acc[2] = {0.0, 0.0};
-    if (va.nblocks <= kVaPer * (int)blockDim.x) {
+    if (nblocks <= kVaPer * (int)blockDim.x) {
 #pragma unroll
         for (int u = 0; u < kVaPer; ++u) {
-            const bool ok = (int)(threadIdx.x + u * blockDim.x) < va.nblocks;
+            const bool ok = (int)(threadIdx.x + u * blockDim.x) < nblocks;
             acc[0] += ok ? L.v[0][u] : 0.0;
             acc[1] += ok ? L.v[1][u] : 0.0;
         }
     } else {
-        for (int b = threadIdx.x; b < va.nblocks; b += blockDim.x) {
-            acc[0] += va.partials[0 * kMaxPartialBlocks + b];
-            acc[1] += va.partials[1 * kMaxPartialBlocks + b];
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+            acc[0] += va.part[0 * kMaxPartialBlocks + b];
+            acc[1] += va.part[1 * kMaxPartialBlocks + b];
         }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -234,7 +323,8 @@ __device__ __forceinline__ void va_reduce(const VaFinal& va, const VaLoads& L, d
         if (lane == 0) sh[q * 16 + w] = s;
     }
 }
-__device__ __forceinline__ double va_final(const VaFinal& va, const Dims& d, const double* sh) {
+__device__ __forceinline__ double va_final(const MuArgs& va, const Dims& d, const double* sh,
+                                           bool writer) {
     const int nw = blockDim.x >> 6;
     double acc[2] = {0.0, 0.0};
     for (int q = 0; q < 2; ++q)
@@ -247,14 +337,14 @@ __device__ __forceinline__ double va_final(const VaFinal& va, const Dims& d, con
     const double A0 = va.init ? A : va.scal[SC_A0];
     double gamma = va.gamma0;
     if (va.k_A != 0.0 && A0 > 0.0) gamma += va.k_A * (A - A0) / A0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (writer && threadIdx.x == 0) {
         if (va.init) {
             va.scal[SC_V0] = V;
             va.scal[SC_A0] = A;
         }
         va.scal[SC_V] = V;
         va.scal[SC_A] = A;
-        va.scal[SC_LAMV] = 2.0 * va.rate_V * (V0 - V) / (va.mobility * vol);
+        va.scal[SC_LAMV] = 2.0 * va.rate_V * (V0 - V) / (va.mob * vol);
         va.scal[SC_GAMMA] = gamma;
         if (!isfinite(V) || !isfinite(A)) va.istat[IS_FLAGS] |= ST_NONFINITE;
     }
@@ -294,6 +384,12 @@ __device__ __forceinline__ void plane_store(double* plane_base, unsigned plane_b
         __builtin_amdgcn_make_buffer_rsrc(plane_base, 0, (int)plane_bytes, 0x00020000);
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, 0);
 }
+__device__ __forceinline__ void plane_store(float* plane_base, unsigned plane_bytes,
+                                            unsigned byte_off, double v) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(plane_base, 0, (int)plane_bytes, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), r, byte_off, 0, 0);
+}
 
 __device__ __forceinline__ int mirror_row(int j, int ny) {
     j = j < 0 ? -j : (j > ny - 1 ? 2 * (ny - 1) - j : j);
@@ -308,17 +404,23 @@ __device__ __forceinline__ int wrap_mod(int k, int n) {
 // around a load or a store (planes past the slab end are computed on wrapped planes and
 // their stores dropped; padding lanes load and store inside padded LDS slots). That keeps
 // the compiler's memory-counter waits exact, so the kMuD planes in flight are really in
-// flight while the block computes.
-template <bool BEND>
-__global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ phi,
-                                                   double* __restrict__ mu, Dims d, VaFinal va,
-                                                   double C_b, double eps, double sigma) {
+// flight while the block computes. Arithmetic is FP64; mu is stored as MT (double, or float
+// in the refined mode).
+template <bool BEND, bool BATCH, class MT>
+__global__ __launch_bounds__(kBlock) void k_mu_tile(Dims d, int va_nb, MuArgs one,
+                                                   const MuArgs* __restrict__ tab) {
     __shared__ double P[4][kPS];
     __shared__ double G[BEND ? 3 : 1][BEND ? kGS : 1];
     __shared__ double shv[2 * 16];
     const int tz_n = (d.nz + kMuTZ - 1) / kMuTZ;
     const int ty_n = (d.ny + kMuTY - 1) / kMuTY;
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int nbi = ty_n * tz_n * ((d.nx + kMuNI - 1) / kMuNI);
+    int inst;
+    const int lb = split_block<BATCH>(xcd_block(blockIdx.x, gridDim.x), nbi, inst);
+    const MuArgs va = inst_args<BATCH>(one, tab, inst);
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)va.phi;
+    MT* __restrict__ mu = (MT*)va.mu;   // stored through a buffer resource
+    const double C_b = va.C_b, eps = va.eps, sigma = va.sigma;
     const int ic = lb / (ty_n * tz_n);
     const int rem = lb - ic * ty_n * tz_n;
     const int j0 = (rem / tz_n) * kMuTY, k0 = (rem - (rem / tz_n) * tz_n) * kMuTZ;
@@ -334,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
         roff[q] = (e < kPN) ? mirror_row(j0 - 2 + r, d.ny) * d.nz + wrap_mod(k0 - 2 + c, d.nz) : 0;
     }
     auto fetch = [&](int i, double (&v)[kPre]) {
-        const double* src = phi + (size_t)wrap_mod(i, d.nx) * plane;
+        const Gl<double>* src = phi + (size_t)wrap_mod(i, d.nx) * plane;
 #pragma unroll
         for (int q = 0; q < kPre; ++q) v[q] = src[roff[q]];
     };
@@ -365,20 +467,20 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
     // volume/area partials, g planes i0-1, i0
     {
         VaLoads vl;
-        va_load(va, vl);                   // first, so their sums need not wait for phi
+        va_load(va, va_nb, vl);            // first, so their sums need not wait for phi
         double w0[kPre], w1[kPre], w2[kPre], w3[kPre];
         fetch(i0 - 2, w0);
         fetch(i0 - 1, w1);
         fetch(i0, w2);
         fetch(i0 + 1, w3);
-        va_reduce(va, vl, shv);
+        va_reduce(va, va_nb, vl, shv);
         put(P[slot(i0 + 2)], w0);
         put(P[slot(i0 + 3)], w1);
         put(P[slot(i0 + 4)], w2);
         put(P[slot(i0 + 5)], w3);
     }
     __syncthreads();
-    const double gamma = va_final(va, d, shv);
+    const double gamma = va_final(va, d, shv, lb == 0);
     if (BEND) {
         make_g(i0 - 1);
         make_g(i0);
@@ -390,8 +492,8 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
     const int tj = threadIdx.x / kMuTZ, tk = threadIdx.x - (threadIdx.x / kMuTZ) * kMuTZ;
     const int j = j0 + tj, k = k0 + tk;
     const bool out = j < d.ny && k < d.nz;
-    const unsigned pbytes = (unsigned)plane * 8u;
-    const unsigned oofs = (unsigned)(j * d.nz + k) * 8u;
+    const unsigned pbytes = (unsigned)plane * (unsigned)sizeof(MT);
+    const unsigned oofs = (unsigned)(j * d.nz + k) * (unsigned)sizeof(MT);
 #pragma unroll
     for (int s = 0; s < kMuNI; ++s) {
         const int i = i0 + s;
@@ -427,13 +529,17 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(const double* __restrict__ p
 // Block partials of sum_w phi and sum_w [(eps/2)|D phi|^2 + (phi^2-1)^2/(4 eps)]
 // (trapezoid weights w = 1/2 on the wall rows). Each thread owns one (j, k) and walks ci
 // consecutive x-planes, keeping phi of the planes i-1, i, i+1 in registers; the partial of
-// block b is written to slot b: fixed order, deterministic.
-__global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict__ phi, Dims d,
-                                                       double eps, SlabGrid sg,
-                                                       double* __restrict__ partials) {
+// the instance's logical block b is written to slot b: fixed order, deterministic.
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_va_partials(Dims d, SlabGrid sg, VaArgs one,
+                                                       const VaArgs* __restrict__ tab) {
     __shared__ double sh[2 * 16];
     const int nb = sg.gx * sg.gi;
-    const int lb = xcd_block(blockIdx.x, nb);
+    int inst;
+    const int lb = split_block<BATCH>(xcd_block(blockIdx.x, gridDim.x), nb, inst);
+    const VaArgs va = inst_args<BATCH>(one, tab, inst);
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)va.phi;
+    const double eps = va.eps;
     const int bi = lb / sg.gx;
     const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
     double acc[2] = {0.0, 0.0};
@@ -469,21 +575,25 @@ __global__ __launch_bounds__(kBlock) void k_va_partials(const double* __restrict
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
-        partials[0 * kMaxPartialBlocks + blockIdx.x] = acc[0];
-        partials[1 * kMaxPartialBlocks + blockIdx.x] = acc[1];
+        Gl<double>* part = (Gl<double>*)va.part;
+        part[0 * kMaxPartialBlocks + lb] = acc[0];
+        part[1 * kMaxPartialBlocks + lb] = acc[1];
     }
 }
 
 
 // k_va_partials with two consecutive z per lane (W-lane row segments, as k_advance_x2):
 // 16-byte loads, z neighbours from the pair, shuffles and the wave's edge values.
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_va_partials2(const double* __restrict__ phi, Dims d,
-                                                        double eps, SlabGrid sg,
-                                                        double* __restrict__ partials) {
+template <int W, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_va_partials2(Dims d, SlabGrid sg, VaArgs one,
+                                                        const VaArgs* __restrict__ tab) {
     __shared__ double sh[2 * 16];
     const int nb = sg.gx * sg.gi;
-    const int lb = xcd_block(blockIdx.x, nb);
+    int inst;
+    const int lb = split_block<BATCH>(xcd_block(blockIdx.x, gridDim.x), nb, inst);
+    const VaArgs va = inst_args<BATCH>(one, tab, inst);
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)va.phi;
+    const double eps = va.eps;
     const int bi = lb / sg.gx;
     const int hz = d.nz >> 1;
     const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
@@ -503,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_va_partials2(const double* __restric
         const int kpe = (k0 + 2 * W == d.nz) ? 0 : k0 + 2 * W;
         const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
         const int re = j * d.nz;
-        auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
+        auto ld2v = [](const Gl<double>* q) { return ldd2(q); };
         double2 pm = ld2v(phi + (size_t)((i0 + d.nx - 1) % d.nx) * plane + o);
         double2 p0 = ld2v(phi + (size_t)i0 * plane + o);
 #pragma unroll 2
@@ -531,64 +641,72 @@ __global__ __launch_bounds__(kBlock) void k_va_partials2(const double* __restric
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
-        partials[0 * kMaxPartialBlocks + blockIdx.x] = acc[0];
-        partials[1 * kMaxPartialBlocks + blockIdx.x] = acc[1];
+        Gl<double>* part = (Gl<double>*)va.part;
+        part[0 * kMaxPartialBlocks + lb] = acc[0];
+        part[1 * kMaxPartialBlocks + lb] = acc[1];
     }
 }
 
-struct Om3 {
-    const double* p[3];
-};
-
 // Vorticity source S = (1/eta) D phi x D mu (main text eq. (5b)) at the interior rows, stored
-// so that the transform and the residual of the vorticity solve read it as a plain field.
-// The inertial variant (SM eq. (36), implicit in time) stores S - a omega^n instead, the
-// right-hand side of (L_h - a) omega^{n+1}, a = rho / (eta dt).
-__global__ __launch_bounds__(kBlock) void k_source(const double* __restrict__ phi,
-                                                  const double* __restrict__ mu, Dims d,
-                                                  double inv_eta, double* __restrict__ sx,
-                                                  double* __restrict__ sy, double* __restrict__ sz,
-                                                  double a, Om3 om) {
-    int i, j, k;
-    bool ok;
-    plane_index(d, i, j, k, ok);
-    if (!ok || j == 0 || j == d.ny - 1) return;
+// so that the transform and the residual of the vorticity solve read it as a plain field. mu is
+// read as T (double, or float in the refined mode); S is computed and stored in FP64 in both
+// modes: the small components of psi respond to white noise in S far more than to S itself
+// (their spectrum has little weight in the lowest modes, which the two inverse Laplacians
+// amplify most), so FP32 rounding of S alone would cost them relative errors of order 1e-6.
+// The inertial variant (SM eq. (36), implicit in time, FP64 only) stores S - a omega^n
+// instead, the right-hand side of (L_h - a) omega^{n+1}, a = rho / (eta dt).
+template <bool BATCH, class T>
+__global__ __launch_bounds__(kBlock) void k_source(Dims d, SrcArgs one, const SrcArgs* __restrict__ tab) {
+    const int gx = gridDim.x;
+    const int lbg = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
+    const int ig = lbg / gx;                      // instance * nx + i
+    const int inst = BATCH ? ig / d.nx : 0;
+    const int i = ig - inst * d.nx;
+    const SrcArgs a = inst_args<BATCH>(one, tab, inst);
+    const int t = (lbg - ig * gx) * kBlock + threadIdx.x;
+    if (t >= d.ny * d.nz) return;
+    const int j = t / d.nz, k = t - (t / d.nz) * d.nz;
+    if (j == 0 || j == d.ny - 1) return;
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)a.phi;
+    const Gl<T>* __restrict__ mu = (const Gl<T>*)a.mu;
     const Nbr n = neighbours_mirror(d, i, j, k);
     const double fx = (phi[n.xp] - phi[n.xm]) * d.inv_2h, fy = (phi[n.yp] - phi[n.ym]) * d.inv_2h,
                  fz = (phi[n.zp] - phi[n.zm]) * d.inv_2h;
-    const double mx = (mu[n.xp] - mu[n.xm]) * d.inv_2h, my = (mu[n.yp] - mu[n.ym]) * d.inv_2h,
-                 mz = (mu[n.zp] - mu[n.zm]) * d.inv_2h;
-    double s0 = (fy * mz - fz * my) * inv_eta;
-    double s1 = (fz * mx - fx * mz) * inv_eta;
-    double s2 = (fx * my - fy * mx) * inv_eta;
-    if (a != 0.0) {
-        s0 -= a * om.p[0][n.c];
-        s1 -= a * om.p[1][n.c];
-        s2 -= a * om.p[2][n.c];
+    const double mx = ((double)mu[n.xp] - (double)mu[n.xm]) * d.inv_2h,
+                 my = ((double)mu[n.yp] - (double)mu[n.ym]) * d.inv_2h,
+                 mz = ((double)mu[n.zp] - (double)mu[n.zm]) * d.inv_2h;
+    double s0 = (fy * mz - fz * my) * a.inv_eta;
+    double s1 = (fz * mx - fx * mz) * a.inv_eta;
+    double s2 = (fx * my - fy * mx) * a.inv_eta;
+    if (a.a != 0.0) {
+        s0 -= a.a * ((const Gl<double>*)a.om[0])[n.c];
+        s1 -= a.a * ((const Gl<double>*)a.om[1])[n.c];
+        s2 -= a.a * ((const Gl<double>*)a.om[2])[n.c];
     }
-    sx[n.c] = s0;
-    sy[n.c] = s1;
-    sz[n.c] = s2;
+    ((Gl<double>*)a.src[0])[n.c] = s0;
+    ((Gl<double>*)a.src[1])[n.c] = s1;
+    ((Gl<double>*)a.src[2])[n.c] = s2;
 }
 
 
 // k_source with two consecutive z per lane (W-lane row segments, as k_advance_x2): 16-byte
-// loads and stores, z neighbours from the pair, shuffles and the wave's edge values. Same
-// arithmetic per node as k_source.
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_source2(const double* __restrict__ phi,
-                                                   const double* __restrict__ mu, Dims d,
-                                                   double inv_eta, double* __restrict__ sx,
-                                                   double* __restrict__ sy, double* __restrict__ sz,
-                                                   double a, Om3 om) {
+// loads and stores of FP64 fields, z neighbours from the pair, shuffles and the wave's edge
+// values. Same arithmetic per node as k_source.
+template <int W, bool BATCH, class T>
+__global__ __launch_bounds__(kBlock) void k_source2(Dims d, SrcArgs one, const SrcArgs* __restrict__ tab) {
     const int gx = gridDim.x;
-    const int lb = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
-    const int i = lb / gx;
+    const int lbg = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
+    const int ig = lbg / gx;                      // instance * nx + i
+    const int inst = BATCH ? ig / d.nx : 0;
+    const int i = ig - inst * d.nx;
+    const SrcArgs a = inst_args<BATCH>(one, tab, inst);
     const int hz = d.nz >> 1;
-    const int t = (lb - i * gx) * kBlock + threadIdx.x;
+    const int t = (lbg - ig * gx) * kBlock + threadIdx.x;
     if (t >= d.ny * hz) return;
     const int j = t / hz, k = 2 * (t - (t / hz) * hz);
     if (j == 0 || j == d.ny - 1) return;   // whole W-lane segments: each lies in one row
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)a.phi;
+    const Gl<T>* __restrict__ mu = (const Gl<T>*)a.mu;
     const int plane = d.ny * d.nz;
     const int ip = (i + 1 == d.nx) ? 0 : i + 1;
     const int im = (i == 0) ? d.nx - 1 : i - 1;
@@ -598,19 +716,22 @@ __global__ __launch_bounds__(kBlock) void k_source2(const double* __restrict__ p
     const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
     const int rb = i * plane + j * d.nz;
     const int c = rb + k;
-    auto ld2v = [](const double* q) { return *reinterpret_cast<const double2*>(q); };
-    const double2 fxp = ld2v(phi + ip * plane + j * d.nz + k), fxm = ld2v(phi + im * plane + j * d.nz + k);
-    const double2 fyp = ld2v(phi + c + d.nz), fym = ld2v(phi + c - d.nz);
-    const double2 mxp = ld2v(mu + ip * plane + j * d.nz + k), mxm = ld2v(mu + im * plane + j * d.nz + k);
-    const double2 myp = ld2v(mu + c + d.nz), mym = ld2v(mu + c - d.nz);
-    const double2 fc = ld2v(phi + c), mc = ld2v(mu + c);
+    auto ldm = [&](int q) {   // mu pair as FP64
+        const typename P2<T>::t v = ldt2<T>(mu + q);
+        return make_double2((double)v.x, (double)v.y);
+    };
+    const double2 fxp = ldd2(phi + ip * plane + j * d.nz + k), fxm = ldd2(phi + im * plane + j * d.nz + k);
+    const double2 fyp = ldd2(phi + c + d.nz), fym = ldd2(phi + c - d.nz);
+    const double2 mxp = ldm(ip * plane + j * d.nz + k), mxm = ldm(im * plane + j * d.nz + k);
+    const double2 myp = ldm(c + d.nz), mym = ldm(c - d.nz);
+    const double2 fc = ldd2(phi + c), mc = ldm(c);
     const double fem = phi[rb + kme], fep = phi[rb + kpe];
-    const double mem = mu[rb + kme], mep = mu[rb + kpe];
+    const double mem = (double)mu[rb + kme], mep = (double)mu[rb + kpe];
     const double fprev = __shfl_up(fc.y, 1, W), fnext = __shfl_down(fc.x, 1, W);
     const double mprev = __shfl_up(mc.y, 1, W), mnext = __shfl_down(mc.x, 1, W);
     const double fzma = ln == 0 ? fem : fprev, fzpb = ln == W - 1 ? fep : fnext;
     const double mzma = ln == 0 ? mem : mprev, mzpb = ln == W - 1 ? mep : mnext;
-    double2 r0, r1, r2;
+    double r[3][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const double fx = ((h ? fxp.y : fxp.x) - (h ? fxm.y : fxm.x)) * d.inv_2h;
@@ -619,20 +740,20 @@ __global__ __launch_bounds__(kBlock) void k_source2(const double* __restrict__ p
         const double mx = ((h ? mxp.y : mxp.x) - (h ? mxm.y : mxm.x)) * d.inv_2h;
         const double my = ((h ? myp.y : myp.x) - (h ? mym.y : mym.x)) * d.inv_2h;
         const double mz = ((h ? mzpb : mc.y) - (h ? mc.x : mzma)) * d.inv_2h;
-        const double s0 = (fy * mz - fz * my) * inv_eta;
-        const double s1 = (fz * mx - fx * mz) * inv_eta;
-        const double s2 = (fx * my - fy * mx) * inv_eta;
-        if (h) { r0.y = s0; r1.y = s1; r2.y = s2; } else { r0.x = s0; r1.x = s1; r2.x = s2; }
+        r[0][h] = (fy * mz - fz * my) * a.inv_eta;
+        r[1][h] = (fz * mx - fx * mz) * a.inv_eta;
+        r[2][h] = (fx * my - fy * mx) * a.inv_eta;
     }
-    if (a != 0.0) {
-        const double2 w0 = ld2v(om.p[0] + c), w1 = ld2v(om.p[1] + c), w2 = ld2v(om.p[2] + c);
-        r0.x -= a * w0.x; r0.y -= a * w0.y;
-        r1.x -= a * w1.x; r1.y -= a * w1.y;
-        r2.x -= a * w2.x; r2.y -= a * w2.y;
+    if (a.a != 0.0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double2 w = ldd2((const Gl<double>*)a.om[q] + c);
+            r[q][0] -= a.a * w.x;
+            r[q][1] -= a.a * w.y;
+        }
     }
-    *reinterpret_cast<double2*>(sx + c) = r0;
-    *reinterpret_cast<double2*>(sy + c) = r1;
-    *reinterpret_cast<double2*>(sz + c) = r2;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) stt2<double>((Gl<double>*)a.src[q] + c, r[q][0], r[q][1]);
 }
 
 // dst[(i, j, k)] = prof[j]: the no-body channel fields as initial guesses and wall rows.
@@ -673,38 +794,50 @@ __global__ void k_reset_stats(double* scal, int* istat) {
 
 }  // namespace
 
-void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                    const double* const psi[3], double* phi_out, double* scal, double dt,
-                    double mobility, double vz_lo, double vz_hi, const PrevCheck& ck) {
+// ------------------------------------------------------------------------------ launchers
+// A launch over n instances multiplies the instance's grid by n (in x, or in y for the
+// plane-indexed source kernel).
+template <class A>
+static unsigned nin(const Over<A>& o) { return (unsigned)(o.tab ? o.n : 1); }
+
+
+template <class T>
+static void advance_t(hipStream_t s, const Dims& d, const Over<AdvArgs>& a) {
     SlabGrid g;
+    const int slab = tuning_for(d).adv_slab;
     if (d.nz % 32 == 0) {
         g.gx = (d.ny * d.nz / 2 + kBlock - 1) / kBlock;
-        g.ci = kAdvSlab2;
-        g.gi = (d.nx + kAdvSlab2 - 1) / kAdvSlab2;
-        const dim3 gr(g.gx * g.gi);
-        if (d.nz % 128 == 0)
-            launch_kernel(k_advance_x2<64>, gr, dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
-                          psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
-        else if (d.nz % 64 == 0)
-            launch_kernel(k_advance_x2<32>, gr, dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
-                          psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
-        else
-            launch_kernel(k_advance_x2<16>, gr, dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
-                          psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+        g.ci = slab;
+        g.gi = (d.nx + slab - 1) / slab;
+        const dim3 gr(g.gx * g.gi * nin(a));
+        auto go = [&](auto kt, auto kf) {
+            if (a.tab) launch_kernel(kt, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
+            else launch_kernel(kf, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
+        };
+        if (d.nz % 128 == 0) go(k_advance_x2<64, true, T>, k_advance_x2<64, false, T>);
+        else if (d.nz % 64 == 0) go(k_advance_x2<32, true, T>, k_advance_x2<32, false, T>);
+        else go(k_advance_x2<16, true, T>, k_advance_x2<16, false, T>);
         return;
     }
     g.gx = (d.ny * d.nz + kBlock - 1) / kBlock;
-    g.ci = kAdvSlab;
-    g.gi = (d.nx + kAdvSlab - 1) / kAdvSlab;
-    launch_kernel(k_advance_x, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu, psi[0], psi[1],
-                  psi[2], phi_out, d, g, scal, dt, mobility, vz_lo, vz_hi, ck);
+    g.ci = slab;
+    g.gi = (d.nx + slab - 1) / slab;
+    const dim3 gr(g.gx * g.gi * nin(a));
+    if (a.tab) launch_kernel(k_advance_x<true, T>, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
+    else launch_kernel(k_advance_x<false, T>, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
 }
 
-constexpr int kVaMaxBlocks = 1024;   // longer x-slabs per lane, a shorter final sum
+void launch_advance(hipStream_t s, const Dims& d, Prec pr, const Over<AdvArgs>& a) {
+    if (pr == P32)
+        advance_t<float>(s, d, a);
+    else
+        advance_t<double>(s, d, a);
+}
 
-// n_z a multiple of 32: two z per lane (k_va_partials2)
+// n_z a multiple of 32: two z per lane (k_va_partials2). The block cap (tuned; 1024 by
+// default) trades longer x-slabs per lane against a longer final sum.
 static SlabGrid va_grid(const Dims& d) {
-    return slab_grid(d.nz % 32 == 0 ? d.ny * d.nz / 2 : d.ny * d.nz, d.nx, kVaMaxBlocks);
+    return slab_grid(d.nz % 32 == 0 ? d.ny * d.nz / 2 : d.ny * d.nz, d.nx, tuning_for(d).va_maxb);
 }
 
 int va_partial_blocks(const Dims& d) {
@@ -712,31 +845,36 @@ int va_partial_blocks(const Dims& d) {
     return g.gx * g.gi;
 }
 
-void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
-                        double* partials) {
+void launch_va_partials(hipStream_t s, const Dims& d, const Over<VaArgs>& a) {
     const SlabGrid g = va_grid(d);
-    if (d.nz % 128 == 0)
-        launch_kernel(k_va_partials2<64>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
-                      partials);
-    else if (d.nz % 64 == 0)
-        launch_kernel(k_va_partials2<32>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
-                      partials);
-    else if (d.nz % 32 == 0)
-        launch_kernel(k_va_partials2<16>, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
-                      partials);
-    else
-        launch_kernel(k_va_partials, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, d, eps, g,
-                      partials);
+    const dim3 gr(g.gx * g.gi * nin(a));
+    auto go = [&](auto kt, auto kf) {
+        if (a.tab) launch_kernel(kt, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
+        else launch_kernel(kf, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
+    };
+    if (d.nz % 128 == 0) go(k_va_partials2<64, true>, k_va_partials2<64, false>);
+    else if (d.nz % 64 == 0) go(k_va_partials2<32, true>, k_va_partials2<32, false>);
+    else if (d.nz % 32 == 0) go(k_va_partials2<16, true>, k_va_partials2<16, false>);
+    else go(k_va_partials<true>, k_va_partials<false>);
 }
 
-void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const VaFinal& va,
-               int model, double C_b, double eps, double sigma) {
+void launch_mu(hipStream_t s, const Dims& d, int model, Prec pr, const Over<MuArgs>& a) {
     const int nb = ((d.ny + kMuTY - 1) / kMuTY) * ((d.nz + kMuTZ - 1) / kMuTZ) *
                    ((d.nx + kMuNI - 1) / kMuNI);
-    if (model == VS_CAHN_HILLIARD)
-        launch_kernel(k_mu_tile<false>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, va, C_b, eps, sigma);
-    else
-        launch_kernel(k_mu_tile<true>, dim3(nb), dim3(kBlock), 0, s, phi, mu, d, va, C_b, eps, sigma);
+    const dim3 gr(nb * nin(a));
+    const int vnb = va_partial_blocks(d);
+    auto go = [&](auto kt, auto kf) {
+        if (a.tab) launch_kernel(kt, gr, dim3(kBlock), 0, s, d, vnb, a.one, a.tab);
+        else launch_kernel(kf, gr, dim3(kBlock), 0, s, d, vnb, a.one, a.tab);
+    };
+    const bool ch = model == VS_CAHN_HILLIARD;
+    if (pr == P32) {
+        if (ch) go(k_mu_tile<false, true, float>, k_mu_tile<false, false, float>);
+        else go(k_mu_tile<true, true, float>, k_mu_tile<true, false, float>);
+    } else {
+        if (ch) go(k_mu_tile<false, true, double>, k_mu_tile<false, false, double>);
+        else go(k_mu_tile<true, true, double>, k_mu_tile<true, false, double>);
+    }
 }
 
 void launch_zero_walls(hipStream_t s, const Dims& d, double* const f[], int nf) {
@@ -751,26 +889,29 @@ void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double
     launch_kernel(k_fill_profile, plane_grid(d), dim3(kBlock), 0, s, dst, d, prof);
 }
 
-void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                   double inv_eta, double* const src[3], double a,
-                   const double* const omega[3]) {
-    Om3 om{{nullptr, nullptr, nullptr}};
-    if (a != 0.0) om = Om3{{omega[0], omega[1], omega[2]}};
+template <class T>
+static void source_t(hipStream_t s, const Dims& d, const Over<SrcArgs>& a) {
+    auto go = [&](dim3 g, auto kt, auto kf) {
+        if (a.tab) launch_kernel(kt, g, dim3(kBlock), 0, s, d, a.one, a.tab);
+        else launch_kernel(kf, g, dim3(kBlock), 0, s, d, a.one, a.tab);
+    };
     if (d.nz % 32 == 0) {
-        const dim3 g((unsigned)((d.ny * d.nz / 2 + kBlock - 1) / kBlock), (unsigned)d.nx, 1);
-        if (d.nz % 128 == 0)
-            launch_kernel(k_source2<64>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
-                          src[2], a, om);
-        else if (d.nz % 64 == 0)
-            launch_kernel(k_source2<32>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
-                          src[2], a, om);
-        else
-            launch_kernel(k_source2<16>, g, dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0], src[1],
-                          src[2], a, om);
+        const dim3 g((unsigned)((d.ny * d.nz / 2 + kBlock - 1) / kBlock), (unsigned)d.nx * nin(a), 1);
+        if (d.nz % 128 == 0) go(g, k_source2<64, true, T>, k_source2<64, false, T>);
+        else if (d.nz % 64 == 0) go(g, k_source2<32, true, T>, k_source2<32, false, T>);
+        else go(g, k_source2<16, true, T>, k_source2<16, false, T>);
         return;
     }
-    launch_kernel(k_source, plane_grid(d), dim3(kBlock), 0, s, phi, mu, d, inv_eta, src[0],
-                  src[1], src[2], a, om);
+    dim3 g = plane_grid(d);
+    g.y *= nin(a);
+    go(g, k_source<true, T>, k_source<false, T>);
+}
+
+void launch_source(hipStream_t s, const Dims& d, Prec pr, const Over<SrcArgs>& a) {
+    if (pr == P32)
+        source_t<float>(s, d, a);
+    else
+        source_t<double>(s, d, a);
 }
 
 void launch_reset_stats(hipStream_t s, double* scal, int* istat) {

@@ -4,6 +4,7 @@
 // and per-kernel event timing. All device work is enqueued on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -43,13 +44,13 @@ enum KClass {
     K_ADVANCE, K_VA_PARTIALS, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
     K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_DHT_X_PAIR, K_DHT_Z_OUT_PAIR,
-    K_NCLASS
+    K_RHS_FLOW, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
     "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
     "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
-    "resid_norm_flow", "dht_x_pair", "dht_z_out_pair"};
+    "resid_norm_flow", "dht_x_pair", "dht_z_out_pair", "rhs_flow"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -258,6 +259,41 @@ LaunchProbe& vs::launch_probe() {
     return probe;
 }
 
+// Tuned launch shapes per grid (nx, ny, nz), shared by every state of that grid.
+namespace {
+struct TuneKey {
+    int nx, ny, nz;
+    bool operator==(const TuneKey& o) const { return nx == o.nx && ny == o.ny && nz == o.nz; }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, Tuning>> g_tune;
+constexpr Tuning kDefaultTuning{4, 1024, 1024, 0};
+
+void set_tuning(const Dims& d, const Tuning& t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneKey k{d.nx, d.ny, d.nz};
+    for (auto& e : g_tune)
+        if (e.first == k) {
+            e.second = t;
+            return;
+        }
+    g_tune.push_back({k, t});
+}
+bool tuned(const Dims& d) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& e : g_tune)
+        if (e.first == TuneKey{d.nx, d.ny, d.nz}) return true;
+    return false;
+}
+}  // namespace
+
+Tuning vs::tuning_for(const Dims& d) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& e : g_tune)
+        if (e.first == TuneKey{d.nx, d.ny, d.nz}) return e.second;
+    return kDefaultTuning;
+}
+
 namespace {
 
 // Run `launch` with its kernels timed by an event pair when the timer is on.
@@ -334,81 +370,262 @@ void enqueue_solve(vs_state* S, const RhsArgs& rhs, double* const u[3], int ncom
     }
 }
 
-void enqueue_va_mu(vs_state* S, const double* phi, int init) {
-    const int nb = va_partial_blocks(S->d);
-    timed(S, K_VA_PARTIALS, [&] { launch_va_partials(S->stream, S->d, phi, S->p.eps, S->part); });
-    const VaFinal va{S->part, nb, init, S->p.rate_V, S->p.k_A, S->p.gamma0, S->p.mobility,
-                     S->scal, S->istat};
-    timed(S, K_MU, [&] {
-        launch_mu(S->stream, S->d, phi, S->mu, va, S->p.model, S->C_b(), S->p.eps, S->p.sigma);
-    });
+// ------------------------------------------------------------------- one time step
+// Everything one time step launches, as per-kernel argument structs: by value for one
+// instance, or device tables for every instance of a batch class (Over in vs_internal.h).
+// Index [g] of the refined mode's correction-cycle passes: 0 = the first cycle (always runs),
+// 1 = later cycles (gated on the instance's convergence flag).
+struct StepArgs {
+    Over<AdvArgs> adv;
+    Over<VaArgs> va;
+    Over<MuArgs> mu;
+    Over<SrcArgs> src;
+    Over<ZArgs> zfwd;
+    Over<HxArgs> hx3, hx6;
+    Over<TriArgs> tri;
+    Over<ZArgs> zout6;
+    Over<ResArgs> res;
+    Over<ChkArgs> chk;
+    Over<RhsFlowArgs> rf[2];
+    Over<HxArgs> hxc[2];
+    Over<TriArgs> trc[2];
+    Over<ZArgs> zadd[2];
+    Over<ResArgs> resc[2];
+    Over<ChkArgs> chkc[2];
+};
+#define VS_STEP_FIELDS(X)                                                                   \
+    X(adv) X(va) X(mu) X(src) X(zfwd) X(hx3) X(hx6) X(tri) X(zout6) X(res) X(chk) X(rf[0])  \
+    X(rf[1]) X(hxc[0]) X(hxc[1]) X(trc[0]) X(trc[1]) X(zadd[0]) X(zadd[1]) X(resc[0])       \
+    X(resc[1]) X(chkc[0]) X(chkc[1])
+
+// The fused refined-mode cycle and the fused FP64 pass need two-pass transform lengths and a
+// segmented tridiagonal layout; the refined mode is offered only there.
+bool refined_fused(const vs_state* S) { return S->f32 && fused_flow_ok(S->d); }
+
+// Arguments of one step of S that reads phi[par] and writes phi[1 - par] (par = -1: the
+// initial state, phi[0] read in place: no advance). with_ck: the advance takes the previous
+// step's flow check. dt = 0: the initial solve.
+StepArgs step_args(vs_state* S, int par, double dt, bool with_ck) {
+    StepArgs A{};
+    const double* phi_in = S->phi[par < 0 ? 0 : par];
+    double* phi_new = par < 0 ? S->phi[0] : S->phi[1 - par];
+    const double a = (S->p.rho > 0.0 && dt > 0.0) ? S->p.rho / (S->p.eta * dt) : 0.0;
+    AdvArgs ad{};
+    ad.phi = phi_in;
+    ad.mu = S->mu;
+    for (int c = 0; c < 3; ++c) ad.ps[c] = S->ps[c];
+    ad.out = phi_new;
+    ad.scal = S->scal;
+    ad.dt = dt;
+    ad.mob = S->p.mobility;
+    ad.vz_lo = S->vz_lo;
+    ad.vz_hi = S->vz_hi;
+    if (with_ck) {
+        ad.ck_part = S->part;
+        ad.ck_istat = S->istat;
+        ad.ck_rtol = S->p.poisson_rtol;
+        ad.ck_nb = resid_flow_blocks(S->d);
+    }
+    A.adv = over_one(ad);
+    A.va = over_one(VaArgs{phi_new, S->part, S->p.eps});
+    MuArgs m{};
+    m.phi = phi_new;
+    m.mu = S->mu;
+    m.part = S->part;
+    m.scal = S->scal;
+    m.istat = S->istat;
+    m.rate_V = S->p.rate_V;
+    m.k_A = S->p.k_A;
+    m.gamma0 = S->p.gamma0;
+    m.mob = S->p.mobility;
+    m.C_b = S->C_b();
+    m.eps = S->p.eps;
+    m.sigma = S->p.sigma;
+    m.init = par < 0 ? 1 : 0;
+    A.mu = over_one(m);
+    SrcArgs sr{};
+    sr.phi = phi_new;
+    sr.mu = S->mu;
+    for (int c = 0; c < 3; ++c) {
+        sr.src[c] = S->src[c];
+        sr.om[c] = S->om[c];
+    }
+    sr.inv_eta = 1.0 / S->p.eta;
+    sr.a = a;
+    A.src = over_one(sr);
+    ZArgs zf{};
+    for (int c = 0; c < 3; ++c) {
+        zf.spec[c] = S->src[c];
+        zf.u[c] = (double*)S->spec[c];
+    }
+    zf.tw = S->twz;
+    A.zfwd = over_one(zf);
+    HxArgs h3{}, h6{};
+    for (int c = 0; c < 3; ++c) {
+        h3.spec[c] = S->spec[c];
+        h6.spec[c] = S->spec[c];
+        h6.spec[3 + c] = S->spec2[c];
+    }
+    h3.tw = h6.tw = S->twx;
+    A.hx3 = over_one(h3);
+    A.hx6 = over_one(h6);
+    TriArgs t{};
+    t.tri = S->tri;
+    t.triw = a != 0.0 ? S->tri2 : S->tri;
+    for (int c = 0; c < 3; ++c) {
+        t.spec[c] = S->spec[c];
+        t.spec2[c] = S->spec2[c];
+        t.olo[c] = S->om_wall_lo[c];
+        t.ohi[c] = S->om_wall_hi[c];
+        t.plo[c] = S->psi_wall_lo[c];
+        t.phi[c] = S->psi_wall_hi[c];
+    }
+    A.tri = over_one(t);
+    ZArgs z6{};
+    for (int c = 0; c < 3; ++c) {
+        z6.spec[c] = S->spec[c];
+        z6.spec[3 + c] = S->spec2[c];
+        z6.u[c] = S->om[c];
+        z6.u[3 + c] = S->ps[c];
+    }
+    z6.tw = S->twz;
+    A.zout6 = over_one(z6);
+    ResArgs r{};
+    for (int c = 0; c < 3; ++c) {
+        r.om[c] = S->om[c];
+        r.src[c] = S->src[c];
+        r.ps[c] = S->ps[c];
+    }
+    r.part = S->part;
+    r.ashift = a;
+    A.res = over_one(r);
+    ChkArgs ck{};
+    ck.part = S->part;
+    ck.scal = S->scal;
+    ck.istat = S->istat;
+    ck.rtol = S->p.poisson_rtol;
+    A.chk = over_one(ck);
+    for (int g = 0; g < 2; ++g) {
+        const int* gate = g ? S->istat + IS_CONV : nullptr;
+        RhsFlowArgs rf{};
+        for (int c = 0; c < 3; ++c) {
+            rf.src[c] = S->src[c];
+            rf.om[c] = S->om[c];
+            rf.ps[c] = S->ps[c];
+            rf.spec[c] = S->spec[c];
+            rf.spec2[c] = S->spec2[c];
+        }
+        rf.tw = S->twz;
+        rf.gate = gate;
+        A.rf[g] = over_one(rf);
+        HxArgs hc = h6;
+        hc.gate = gate;
+        A.hxc[g] = over_one(hc);
+        TriArgs tc = t;
+        tc.triw = S->tri;
+        tc.gate = gate;
+        A.trc[g] = over_one(tc);
+        ZArgs za = z6;
+        za.add = 1;
+        za.gate = gate;
+        A.zadd[g] = over_one(za);
+        ResArgs rc = r;
+        rc.gate = gate;
+        A.resc[g] = over_one(rc);
+        ChkArgs cc = ck;
+        cc.gate = gate;
+        A.chkc[g] = over_one(cc);
+    }
+    return A;
 }
 
-// The flow part of a step (main text eq. (5b), then (5c)). Cycle 0 of the two vector solves
-// shares one spectral pass: the vorticity modes after the tridiagonal solve are, up to -h^2,
-// the transformed right-hand side of the stream-vector problem, so psi needs no forward
-// transform. Both fields are then verified against their own spatial residual; correction
-// cycles (normally never run in FP64) use the generic path.
-void enqueue_flow(vs_state* S, const double* phi, bool defer_check, double dt) {
-    const Dims& d = S->d;
-    const double rtol = S->p.poisson_rtol;
-    const int mc = S->p.poisson_max_cycles;
-    // inertial variant (SM eq. (36)), implicit in time: (L_h - a) omega^{n+1} = S - a omega^n;
-    // dt = 0 (the initial state) solves eq. (5b)
-    const double a = (S->p.rho > 0.0 && dt > 0.0) ? S->p.rho / (S->p.eta * dt) : 0.0;
-    const double* const omc[3] = {S->om[0], S->om[1], S->om[2]};
-    timed(S, K_SOURCE, [&] {
-        launch_source(S->stream, d, phi, S->mu, 1.0 / S->p.eta, S->src, a, omc);
-    });
-    RhsArgs rv{};
-    rv.mode = RHS_FIELD;
-    rv.f[0] = S->src[0];
-    rv.f[1] = S->src[1];
-    rv.f[2] = S->src[2];
-    RhsArgs rp{};
-    rp.mode = RHS_NEGW;
-    rp.f[0] = S->om[0];
-    rp.f[1] = S->om[1];
-    rp.f[2] = S->om[2];
-    if (S->f32) {
-        // refined mode: FP32-stored spectral corrections of the FP64 residual, from the warm
-        // start, until the FP64 relative residual meets rtol
-        enqueue_solve(S, rv, S->om, 3, rtol, mc, TAG_OMEGA, 1);
-        enqueue_solve(S, rp, S->ps, 3, rtol, mc, TAG_PSI, 1);
-        return;
+// What a step enqueue needs besides the arguments: the class's grid, plans and settings, the
+// stream, and the state whose event timer (if on) times the launches.
+struct StepCfg {
+    hipStream_t st;
+    Dims d;
+    FftPlan px, pz;
+    bool f32;
+    int model, mc;
+    double rtol;
+    bool inertial;
+    vs_state* timer;   // null: no timing
+};
+
+StepCfg step_cfg(vs_state* S) {
+    return StepCfg{S->stream, S->d, S->px, S->pz, S->f32, S->p.model, S->p.poisson_max_cycles,
+                   S->p.poisson_rtol, S->p.rho > 0.0, S->prof_on ? S : nullptr};
+}
+
+template <class F>
+void timed_cfg(const StepCfg& c, int cls, F&& launch) {
+    if (c.timer)
+        timed(c.timer, cls, launch);
+    else
+        launch();
+}
+
+// V, A, the multipliers and mu from the new phi (SM (32), (37), "Lagrange multipliers", (35)).
+void enqueue_va_mu_args(const StepCfg& c, const StepArgs& A) {
+    timed_cfg(c, K_VA_PARTIALS, [&] { launch_va_partials(c.st, c.d, A.va); });
+    timed_cfg(c, K_MU, [&] { launch_mu(c.st, c.d, c.model, c.f32 ? P32 : P64, A.mu); });
+}
+
+// The flow part of a step (main text eq. (5b), then (5c)) through the fused passes.
+// FP64: one direct spectral pass (the vorticity modes after the tridiagonal solve are, up to
+// -h^2, the transformed right-hand side of the stream-vector problem, so psi needs no forward
+// transform), then both fields verified against their spatial residuals. Refined mode:
+// defect-correction cycles from the incoming fields, each a residual pass in FP64 whose result
+// is transformed and solved in FP32 and added to the FP64 fields, then verified; cycles after
+// the first are gated on the device flag of the previous check.
+// max_cycles > 1 in FP64: the verification is left to enqueue_fp64_corrections.
+// Returns true when the final check was left to the next step's advance (defer).
+bool enqueue_flow_args(const StepCfg& c, const StepArgs& A, bool defer, int max_cycles) {
+    timed_cfg(c, K_SOURCE, [&] { launch_source(c.st, c.d, c.f32 ? P32 : P64, A.src); });
+    if (c.f32) {
+        for (int cyc = 0; cyc < max_cycles; ++cyc) {
+            const int g = cyc ? 1 : 0;
+            timed_cfg(c, K_RHS_FLOW, [&] { launch_rhs_flow(c.st, c.d, A.rf[g]); });
+            timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
+            timed_cfg(c, K_TRIDIAG_PAIR, [&] { launch_tri_pair(c.st, c.d, true, true, A.trc[g]); });
+            timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
+            timed_cfg(c, K_DHT_Z_OUT_PAIR, [&] { launch_hz(c.st, c.d, c.pz, true, 6, A.zadd[g]); });
+            timed_cfg(c, K_RESID_FLOW, [&] { launch_resid_flow_over(c.st, c.d, false, A.resc[g]); });
+            if (max_cycles == 1 && defer) return true;
+            timed_cfg(c, K_CHECK, [&] {
+                launch_check_flow_over(c.st, c.d, cyc == max_cycles - 1 ? 1 : 0, A.chkc[g]);
+            });
+        }
+        return false;
     }
     // The direct transform reads S alone: the omega wall terms go into mode (0, 0) of the
     // tridiagonal solve.
-    timed(S, K_RHS_Z_OMEGA, [&] {
-        const double* const sv[3] = {S->src[0], S->src[1], S->src[2]};
-        launch_dht_z_fwd(S->stream, d, S->pz, S->twz, sv, S->spec, 3);
-    });
-    timed(S, K_DHT_X, [&] { launch_dht_x(S->stream, d, S->px, S->twx, S->spec, 3, false, nullptr); });
-    timed(S, K_TRIDIAG_PAIR, [&] {
-        launch_tridiag_pair(S->stream, d, S->tri, a != 0.0 ? S->tri2 : nullptr, S->spec, S->spec2,
-                            S->om_wall_lo, S->om_wall_hi, S->psi_wall_lo, S->psi_wall_hi, false);
-    });
+    timed_cfg(c, K_RHS_Z_OMEGA, [&] { launch_hz(c.st, c.d, c.pz, false, 3, A.zfwd); });
+    timed_cfg(c, K_DHT_X, [&] { launch_hx(c.st, c.d, c.px, false, 3, A.hx3); });
+    timed_cfg(c, K_TRIDIAG_PAIR, [&] { launch_tri_pair(c.st, c.d, false, false, A.tri); });
     // both fields back to physical space, six components per launch
-    void* const sp6[6] = {S->spec[0], S->spec[1], S->spec[2], S->spec2[0], S->spec2[1], S->spec2[2]};
-    double* const u6[6] = {S->om[0], S->om[1], S->om[2], S->ps[0], S->ps[1], S->ps[2]};
-    timed(S, K_DHT_X_PAIR, [&] { launch_dht_x(S->stream, d, S->px, S->twx, sp6, 6, false, nullptr); });
-    timed(S, K_DHT_Z_OUT_PAIR, [&] {
-        launch_dht_z_out(S->stream, d, S->pz, S->twz, sp6, u6, 6, 0, false, nullptr);
-    });
-    if (mc == 1) {
-        // one cycle each: both residuals in one pass, then both checks in one launch, or, when
-        // another step follows in the same call, in the first block of its advance kernel
-        // (no correction cycle waits on the result)
-        const double* const co[3] = {S->om[0], S->om[1], S->om[2]};
-        const double* const cs[3] = {S->src[0], S->src[1], S->src[2]};
-        const double* const cp[3] = {S->ps[0], S->ps[1], S->ps[2]};
-        timed(S, K_RESID_FLOW, [&] { launch_resid_flow(S->stream, d, co, cs, cp, a, S->part); });
-        if (defer_check)
-            S->check_pending = true;
-        else
-            timed(S, K_CHECK, [&] { launch_check_flow(S->stream, d, S->part, rtol, S->scal, S->istat); });
-        return;
-    }
+    timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, false, 6, A.hx6); });
+    timed_cfg(c, K_DHT_Z_OUT_PAIR, [&] { launch_hz(c.st, c.d, c.pz, false, 6, A.zout6); });
+    if (max_cycles > 1) return false;
+    // both residuals in one pass, then both checks in one launch, or, when another step
+    // follows in the same call, in the first block of its advance kernel
+    timed_cfg(c, K_RESID_FLOW, [&] { launch_resid_flow_over(c.st, c.d, false, A.res); });
+    if (defer) return true;
+    timed_cfg(c, K_CHECK, [&] { launch_check_flow_over(c.st, c.d, 1, A.chk); });
+    return false;
+}
+
+// FP64 correction cycles after the direct pass (poisson_max_cycles > 1), per solve, through
+// the general verified path (normally never needed: the direct pass is exact).
+void enqueue_fp64_corrections(vs_state* S) {
+    const double rtol = S->p.poisson_rtol;
+    const int mc = S->p.poisson_max_cycles;
+    RhsArgs rv{};
+    rv.mode = RHS_FIELD;
+    for (int c = 0; c < 3; ++c) rv.f[c] = (const double*)S->src[c];
+    RhsArgs rp{};
+    rp.mode = RHS_NEGW;
+    for (int c = 0; c < 3; ++c) rp.f[c] = S->om[c];
     enqueue_verify(S, rv, S->om, 3, rtol, 0, 0, TAG_OMEGA, nullptr);
     for (int cyc = 1; cyc < mc; ++cyc) {
         const int* gate = S->istat + IS_CONV;
@@ -423,24 +640,37 @@ void enqueue_flow(vs_state* S, const double* phi, bool defer_check, double dt) {
     }
 }
 
+// The initial state: V0, A0, mu^0, then omega^0 and psi^0 from the no-body fields. The refined
+// mode starts from those fields with no step behind it, so it takes enough correction cycles
+// for a full solve (its FP32 cycles each gain about six digits).
+void enqueue_init(vs_state* S) {
+    const StepCfg c = step_cfg(S);
+    const StepArgs A = step_args(S, -1, 0.0, false);
+    enqueue_va_mu_args(c, A);
+    if (S->f32) {
+        enqueue_flow_args(c, A, false, S->p.poisson_max_cycles > 4 ? S->p.poisson_max_cycles : 4);
+        return;
+    }
+    enqueue_flow_args(c, A, false, S->p.poisson_max_cycles);
+    if (S->p.poisson_max_cycles > 1) enqueue_fp64_corrections(S);
+}
+
 // One time step. more_follow: another step of the same call comes after this one, so its
 // advance kernel can take this step's flow check.
 void enqueue_step(vs_state* S, double dt, bool more_follow) {
-    const double* phi = S->phi[S->cur];
-    double* out = S->phi[1 - S->cur];
-    const double* const psc[3] = {S->ps[0], S->ps[1], S->ps[2]};
-    PrevCheck ck{nullptr, 0, 0.0, nullptr};
-    if (S->check_pending) {
-        ck = PrevCheck{S->part, resid_flow_blocks(S->d), S->p.poisson_rtol, S->istat};
-        S->check_pending = false;
-    }
-    timed(S, K_ADVANCE, [&] {
-        launch_advance(S->stream, S->d, phi, S->mu, psc, out, S->scal, dt, S->p.mobility,
-                       S->vz_lo, S->vz_hi, ck);
-    });
+    const StepCfg c = step_cfg(S);
+    const StepArgs A = step_args(S, S->cur, dt, S->check_pending);
+    S->check_pending = false;
+    timed_cfg(c, K_ADVANCE, [&] { launch_advance(c.st, c.d, c.f32 ? P32 : P64, A.adv); });
     S->cur = 1 - S->cur;
-    enqueue_va_mu(S, out, 0);
-    enqueue_flow(S, out, more_follow, dt);
+    enqueue_va_mu_args(c, A);
+    const int mc = S->p.poisson_max_cycles;
+    if (S->f32) {
+        S->check_pending = enqueue_flow_args(c, A, more_follow, mc);
+        return;
+    }
+    S->check_pending = enqueue_flow_args(c, A, more_follow && mc == 1, mc);
+    if (mc > 1) enqueue_fp64_corrections(S);
 }
 
 // The inertial variant's vorticity pivots depend on dt (a = rho/(eta dt)): made on the host
@@ -551,6 +781,13 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     if ((st = check_params(params)) != VS_OK) return st;
     if (!phi0) return fail(VS_E_ARG, "phi0 is NULL");
     const Layout L = make_layout(*grid, params->rho > 0.0);
+    {
+        Dims dd{grid->nx, grid->ny, grid->nz, grid->ny - 2, grid->h, 0.0, 0.0};
+        if (params->precision == VS_FP32_REFINED && !fused_flow_ok(dd))
+            return fail(VS_E_UNSUPPORTED,
+                        "VS_FP32_REFINED needs nx, nz in {32, 48, 64, 96, 128, 192, 256} and "
+                        "4 <= ny - 2 <= 256 (the fused transform and tridiagonal forms)");
+    }
     if (!workspace) return fail(VS_E_WORKSPACE, "workspace is NULL");
     if (((uintptr_t)workspace) & 255) return fail(VS_E_WORKSPACE, "workspace must be 256-byte aligned");
     if (bytes < L.total) return fail(VS_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
@@ -628,8 +865,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
         launch_fill_profile(S->stream, S->d, S->om[c], nullptr);
     }
     INIT_TRY(hipGetLastError());
-    enqueue_va_mu(S, S->phi[0], 1);
-    enqueue_flow(S, S->phi[0], false, 0.0);
+    enqueue_init(S);
     INIT_TRY(hipGetLastError());
     st = collect(S, "vs_init");
     if (st != VS_OK) return bail(st);
@@ -1118,16 +1354,128 @@ vs_status vs_profile_read(vs_state* S, int32_t kernel, double* total_ms, int64_t
 
 }  // extern "C"
 
+// ------------------------------------------------------------------------------ autotuner
+namespace {
+
+// Picks the tuned launch shapes of S's grid by timing each candidate on S's own data: the
+// phi update's x-slab length (written into the free phi buffer), the volume/area partials'
+// block cap (with the chemical potential that reduces them: it recomputes mu and the scalars
+// from the same phi, so they come out unchanged), the flow residual's block cap (partials
+// only) and the pair tridiagonal solves' segment layout (spectral scratch only). One
+// coordinate at a time, each candidate launched kReps times after one warm-up launch, the
+// fastest mean kept. Nothing of the state's fields changes.
+vs_status autotune_state(vs_state* S, Tuning* picked) {
+    constexpr int kReps = 5;
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    const StepCfg c = step_cfg(S);
+    const double dt = 1e-12;   // the advance's output buffer is scratch; any dt does
+    const StepArgs A = step_args(S, S->cur, dt, false);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(VS_E_HIP, "hipEventCreate failed");
+    }
+    hipError_t err = hipSuccess;
+    auto time = [&](auto launch) -> float {
+        launch();
+        (void)hipEventRecord(e0, S->stream);
+        for (int r = 0; r < kReps; ++r) launch();
+        (void)hipEventRecord(e1, S->stream);
+        hipError_t e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        return ms / kReps;
+    };
+    const Prec pr = S->f32 ? P32 : P64;
+    Tuning t = tuning_for(S->d);
+    auto pick = [&](int* field, std::initializer_list<int> cands, auto launch) {
+        int best = *field;
+        float tb = 1e30f;
+        for (int v : cands) {
+            *field = v;
+            set_tuning(S->d, t);
+            const float ms = time(launch);
+            if (ms < tb) {
+                tb = ms;
+                best = v;
+            }
+        }
+        *field = best;
+        set_tuning(S->d, t);
+    };
+    pick(&t.adv_slab, {2, 4, 8}, [&] { launch_advance(c.st, c.d, pr, A.adv); });
+    pick(&t.va_maxb, {256, 512, 1024, 2048}, [&] {
+        launch_va_partials(c.st, c.d, A.va);
+        launch_mu(c.st, c.d, c.model, pr, A.mu);
+    });
+    pick(&t.res_maxb, {512, 1024, 2048, 4096},
+         [&] { launch_resid_flow_over(c.st, c.d, false, S->f32 ? A.resc[0] : A.res); });
+    if (fused_flow_ok(S->d) && seg_has_alt(S->d.M))
+        pick(&t.seg_alt, {0, 1}, [&] {
+            launch_tri_pair(c.st, c.d, S->f32, S->f32, S->f32 ? A.trc[0] : A.tri);
+        });
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(VS_E_HIP, "autotune timing failed: %s", hipGetErrorString(err));
+    HIP_TRY(hipGetLastError());
+    // the timed mu launches rewrote the scalars from the same phi: the same values
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    if (picked) *picked = t;
+    return VS_OK;
+}
+
+}  // namespace
+
+extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[4]) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (S->prof_on) return fail(VS_E_ARG, "vs_autotune: switch the event timer off first");
+    Tuning t{};
+    const vs_status st = autotune_state(S, &t);
+    if (st != VS_OK) return st;
+    if (picked) {
+        picked[0] = t.adv_slab;
+        picked[1] = t.va_maxb;
+        picked[2] = t.res_maxb;
+        picked[3] = t.seg_alt;
+    }
+    return VS_OK;
+}
+
 // ------------------------------------------------------------------------------ batches
+// Instances of one grid class (same grid, precision, model and cycle count) step together:
+// each kernel of a step is launched once for a group of instances of the class, its
+// per-instance arguments read from device tables (Over in vs_internal.h). A group holds about
+// kGroupCells nodes (all instances of the smaller grids, one 128^3 instance), the size at
+// which one launch fills the GPU and the fields one kernel hands to the next still largely
+// sit in the 256 MB Infinity Cache; larger groups would stream every hand-off from HBM. Two
+// steps of every group are captured into one HIP graph (two steps bring every instance's phi
+// buffer back to where it started), the groups spread over the batch streams, and replayed.
+// Instances outside the fused forms (FP64 with more than one cycle per solve) are stepped one
+// by one inside the same graph.
+constexpr long long kGroupCells = 1ll << 21;
+struct BatchClass {
+    Dims d{};
+    FftPlan px{}, pz{};
+    bool f32 = false;
+    int model = 0, mc = 1;
+    std::vector<vs_state*> st;
+    StepArgs A[2];                      // the two captured steps, tables in vs_batch::dtab
+};
+
 struct vs_batch {
     std::vector<vs_state*> st;
-    std::vector<hipStream_t> streams;   // instance i runs on streams[i % streams.size()]
+    std::vector<BatchClass> cls;
+    std::vector<vs_state*> loose;       // stepped one by one (on the last stream)
+    std::vector<hipStream_t> streams;   // class c runs on streams[c % size]
     std::vector<hipEvent_t> ev;         // fork event + one join event per stream
     hipStream_t origin = nullptr;       // the caller's stream: graph launches go here
-    hipStream_t cap = nullptr;          // private stream the graph is captured from (the
-                                        // caller's may be the null stream, which cannot capture)
+    hipStream_t cap = nullptr;          // private stream the graph is captured from
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    char* dtab = nullptr;               // device argument tables of the class launches
+    size_t dtab_bytes = 0;
     std::vector<double> dt;             // time steps baked into the captured graph
     std::vector<long long> gen;         // each instance's walls_gen at capture
 };
@@ -1141,23 +1489,108 @@ void batch_release_graph(vs_batch* B) {
     B->graph = nullptr;
 }
 
-// Capture two time steps of every instance: fork from the origin stream to the instance
-// streams, enqueue, join back. Two steps return each state's phi buffer to its start, so the
-// graph can be replayed.
+bool same_class(const vs_state* a, const vs_state* b) {
+    return a->g.nx == b->g.nx && a->g.ny == b->g.ny && a->g.nz == b->g.nz && a->g.h == b->g.h &&
+           a->f32 == b->f32 && a->p.model == b->p.model &&
+           a->p.poisson_max_cycles == b->p.poisson_max_cycles;
+}
+
+bool class_eligible(const vs_state* S) {
+    return fused_flow_ok(S->d) && (S->f32 || S->p.poisson_max_cycles == 1);
+}
+
+
+double batch_dt(const vs_batch* B, const vs_state* S, const double* dt) {
+    for (size_t i = 0; i < B->st.size(); ++i)
+        if (B->st[i] == S) return dt[i];
+    return 0.0;
+}
+
+// Builds every class's two-step argument tables on the host (each instance with its own phi
+// buffers, dt, walls and parameters), uploads them in one copy, and points the classes'
+// launches at them.
+vs_status build_tables(vs_batch* B, const double* dt) {
+    std::vector<char> host;
+    std::vector<size_t> offs;   // table offsets, in the order of the classes, steps and fields
+    auto put = [&](const void* src, size_t bytes) {
+        const size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + bytes);
+        std::memcpy(host.data() + off, src, bytes);
+        return off;
+    };
+    for (BatchClass& C : B->cls) {
+        const int n = (int)C.st.size();
+        for (int k = 0; k < 2; ++k) {
+            std::vector<StepArgs> per;
+            for (vs_state* S : C.st) {
+                const int par = (S->cur + k) & 1;
+                per.push_back(step_args(S, par, batch_dt(B, S, dt), k == 1 && C.mc == 1));
+            }
+            StepArgs& A = C.A[k];
+#define VS_GATHER(F)                                                                        \
+            {                                                                               \
+                using AT = decltype(A.F.one);                                               \
+                std::vector<AT> v;                                                          \
+                for (const StepArgs& x : per) v.push_back(x.F.one);                         \
+                A.F.one = v[0];                                                             \
+                A.F.n = n;                                                                  \
+                A.F.tab = nullptr;                                                          \
+                offs.push_back(put(v.data(), v.size() * sizeof(AT)));                       \
+            }
+            VS_STEP_FIELDS(VS_GATHER)
+#undef VS_GATHER
+        }
+    }
+    if (host.size() > B->dtab_bytes) {
+        if (B->dtab) (void)hipFree(B->dtab);
+        B->dtab = nullptr;
+        B->dtab_bytes = 0;
+        HIP_TRY(hipMalloc((void**)&B->dtab, host.size()));
+        B->dtab_bytes = host.size();
+    }
+    if (!host.empty())
+        HIP_TRY(hipMemcpy(B->dtab, host.data(), host.size(), hipMemcpyHostToDevice));
+    size_t q = 0;
+    for (BatchClass& C : B->cls)
+        for (int k = 0; k < 2; ++k) {
+            StepArgs& A = C.A[k];
+#define VS_SETTAB(F)                                                                        \
+            A.F.tab = reinterpret_cast<decltype(A.F.tab)>(B->dtab + offs[q++]);
+            VS_STEP_FIELDS(VS_SETTAB)
+#undef VS_SETTAB
+        }
+    return VS_OK;
+}
+
+// One step of a class: every kernel launched once over the class's tables.
+void enqueue_class_step(const BatchClass& C, int k, hipStream_t st) {
+    const StepCfg c{st, C.d, C.px, C.pz, C.f32, C.model, C.mc, 0.0, false, nullptr};
+    const StepArgs& A = C.A[k];
+    launch_advance(st, C.d, C.f32 ? P32 : P64, A.adv);
+    enqueue_va_mu_args(c, A);
+    enqueue_flow_args(c, A, k == 0 && C.mc == 1, C.mc);
+}
+
+// Capture two time steps of every class and loose instance: fork from the capture stream to
+// the batch streams, enqueue, join back.
 vs_status batch_capture(vs_batch* B, const double* dt) {
     batch_release_graph(B);
+    vs_status st = build_tables(B, dt);
+    if (st != VS_OK) return st;
     const int ns = (int)B->streams.size();
     HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-    vs_status st = VS_OK;
     auto body = [&]() -> hipError_t {
         hipError_t e = hipEventRecord(B->ev[0], B->cap);
         if (e != hipSuccess) return e;
         for (int k = 0; k < ns; ++k)
             if ((e = hipStreamWaitEvent(B->streams[k], B->ev[0], 0)) != hipSuccess) return e;
-        for (size_t i = 0; i < B->st.size(); ++i) {
-            vs_state* S = B->st[i];
-            enqueue_step(S, dt[i], true);
-            enqueue_step(S, dt[i], false);
+        for (int k = 0; k < 2; ++k)
+            for (size_t c = 0; c < B->cls.size(); ++c)
+                enqueue_class_step(B->cls[c], k, B->streams[c % ns]);
+        for (vs_state* S : B->loose) {
+            const double d = batch_dt(B, S, dt);
+            enqueue_step(S, d, true);
+            enqueue_step(S, d, false);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         for (int k = 0; k < ns; ++k) {
@@ -1201,7 +1634,34 @@ vs_status vs_batch_create(vs_state* const* states, int32_t n, void* stream, int3
     vs_batch* B = new vs_batch();
     B->st.assign(states, states + n);
     B->origin = (hipStream_t)stream;
-    const int ns = nstreams < n ? nstreams : n;
+    for (vs_state* S : B->st) {
+        if (!class_eligible(S)) {
+            B->loose.push_back(S);
+            continue;
+        }
+        const long long cells = (long long)S->g.nx * S->g.ny * S->g.nz;
+        const size_t cap = (size_t)std::max(1ll, (kGroupCells + cells / 2) / cells);
+        bool placed = false;
+        for (BatchClass& C : B->cls)
+            if (same_class(C.st[0], S) && C.st.size() < cap) {
+                C.st.push_back(S);
+                placed = true;
+                break;
+            }
+        if (!placed) {
+            BatchClass C;
+            C.d = S->d;
+            C.px = S->px;
+            C.pz = S->pz;
+            C.f32 = S->f32;
+            C.model = S->p.model;
+            C.mc = S->p.poisson_max_cycles;
+            C.st.push_back(S);
+            B->cls.push_back(C);
+        }
+    }
+    const int groups = (int)B->cls.size() + (B->loose.empty() ? 0 : 1);
+    const int ns = nstreams < groups ? nstreams : groups;
     auto bail = [&](vs_status e) {
         if (B->cap) (void)hipStreamDestroy(B->cap);
         for (hipStream_t q : B->streams) (void)hipStreamDestroy(q);
@@ -1223,12 +1683,24 @@ vs_status vs_batch_create(vs_state* const* states, int32_t n, void* stream, int3
             return bail(fail(VS_E_HIP, "hipEventCreate failed"));
         B->ev.push_back(x);
     }
-    // finish each state's pending work, then move it onto its batch stream
+    // finish each state's pending work, then move it onto a batch stream (loose instances
+    // run on the last one)
     for (int i = 0; i < n; ++i) {
         vs_state* S = B->st[i];
         if (hipStreamSynchronize(S->stream) != hipSuccess) return bail(fail(VS_E_HIP, "sync failed"));
         S->prof_on = false;
-        S->stream = B->streams[i % ns];
+        S->stream = B->streams[ns - 1];
+    }
+    for (size_t c = 0; c < B->cls.size(); ++c)
+        for (vs_state* S : B->cls[c].st) S->stream = B->streams[c % ns];
+    // launch shapes of every grid class not tuned yet, on its first instance
+    for (BatchClass& C : B->cls) {
+        if (tuned(C.d)) continue;
+        const vs_status st = autotune_state(C.st[0], nullptr);
+        if (st != VS_OK) {
+            vs_batch_destroy(B);
+            return st;
+        }
     }
     *out = B;
     return VS_OK;
@@ -1274,6 +1746,7 @@ void vs_batch_destroy(vs_batch* B) {
     (void)hipStreamSynchronize(B->origin);
     for (hipStream_t q : B->streams) (void)hipStreamSynchronize(q);
     batch_release_graph(B);
+    if (B->dtab) (void)hipFree(B->dtab);
     for (hipEvent_t x : B->ev) (void)hipEventDestroy(x);
     // states keep working after the batch: give them back a valid stream (the origin)
     for (vs_state* S : B->st) S->stream = B->origin;

@@ -119,48 +119,174 @@ static inline SlabGrid slab_grid(int plane, int nx, int maxb) {
 }
 constexpr int kPartialSlots = 12;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
 
-// ---------------------------------------------------------------- explicit stencils
-// The flow check of the previous step (flow_check.h), taken by the first block of the
-// advance kernel when partials is not null.
-struct PrevCheck {
-    const double* partials;
-    int nblocks;
-    double rtol;
-    int* istat;
+// ---------------------------------------------------------------- tuned launch shapes
+// Launch shapes that the autotuner (vs_autotune) picks per grid by timing the kernels on a
+// state's own data; every launcher reads them at launch time. Defaults until a grid is tuned.
+struct Tuning {
+    int adv_slab;   // x-planes each lane of the phi update walks (2, 4 or 8)
+    int va_maxb;    // block cap of the volume/area partials (sets their x-slab length)
+    int res_maxb;   // block cap per component of the flow residual
+    int seg_alt;    // 0: the default segment layout of the tridiagonal solves, 1: the other
 };
-void launch_advance(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                    const double* const psi[3], double* phi_out, double* scal,
-                    double dt, double mobility, double vz_lo, double vz_hi, const PrevCheck& ck);
-void launch_va_partials(hipStream_t s, const Dims& d, const double* phi, double eps,
-                        double* partials);
+Tuning tuning_for(const Dims& d);
+bool seg_has_alt(int M);   // the pair solves of M interior rows have a second layout
+
+// ---------------------------------------------------------------- launches over instances
+// Every kernel of a time step takes its per-instance arguments as one struct. A launch covers
+// one instance (tab == nullptr: the struct is passed by value) or the n instances of one grid
+// class (tab: device table of n structs, one per instance; the instance is read from the
+// block index, so all instances run in one launch). Dims are those of the class.
+template <class A>
+struct Over {
+    A one;
+    const A* tab;   // device table of n entries, or nullptr
+    int n;
+};
+template <class A>
+inline Over<A> over_one(const A& a) {
+    return Over<A>{a, nullptr, 1};
+}
+
+// ---------------------------------------------------------------- explicit stencils
+// Precision of the explicit sweeps: FP64 (mu stored as double, FP64 arithmetic) or the refined
+// mode's FP32 (mu stored as float; the phi update in FP32 arithmetic, added to the FP64 phi;
+// the chemical potential in FP64 arithmetic, stored as float). The vorticity source is FP64
+// in both.
+enum Prec { P64 = 0, P32 = 1 };
+
+// phi update (+ the previous step's flow check when ck_part is set)
+struct AdvArgs {
+    const double* phi;
+    const void* mu;
+    const double* ps[3];
+    double* out;
+    double* scal;
+    double dt, mob, vz_lo, vz_hi;
+    const double* ck_part;   // flow check of the previous step: its residual partials, or null
+    int* ck_istat;
+    double ck_rtol;
+    int ck_nb;               // residual partial blocks of that check
+};
+void launch_advance(hipStream_t s, const Dims& d, Prec pr, const Over<AdvArgs>& a);
+int resid_flow_blocks(const Dims& d);
+
+struct VaArgs {
+    const double* phi;
+    double* part;
+    double eps;
+};
+void launch_va_partials(hipStream_t s, const Dims& d, const Over<VaArgs>& a);
 int va_partial_blocks(const Dims& d);
+
 // V, A and the penalty multipliers lambda_V, gamma_A (SM (32), (37), "Lagrange multipliers")
 // from the volume/area block partials, then mu from phi with that gamma_A: every mu block
-// reduces the partials itself (same fixed order in every block) and block 0 writes V, A,
-// lambda_V, gamma_A (and V0, A0 when init) to scal.
-struct VaFinal {
-    const double* partials;
-    int nblocks, init;
-    double rate_V, k_A, gamma0, mobility;
+// reduces the partials itself (same fixed order in every block) and block 0 of the instance
+// writes V, A, lambda_V, gamma_A (and V0, A0 when init) to scal.
+struct MuArgs {
+    const double* phi;
+    void* mu;
+    const double* part;
     double* scal;
     int* istat;
+    double rate_V, k_A, gamma0, mob, C_b, eps, sigma;
+    int init;
 };
-void launch_mu(hipStream_t s, const Dims& d, const double* phi, double* mu, const VaFinal& va,
-               int model, double C_b, double eps, double sigma);
+void launch_mu(hipStream_t s, const Dims& d, int model, Prec pr, const Over<MuArgs>& a);
+
+// S = (1/eta) D phi x D mu on the interior rows (main text eq. (5b)); with a != 0 (the
+// inertial variant, SM eq. (36)), S - a omega with om the previous vorticity (FP64 only).
+struct SrcArgs {
+    const double* phi;
+    const void* mu;
+    void* src[3];
+    const double* om[3];
+    double inv_eta, a;
+};
+void launch_source(hipStream_t s, const Dims& d, Prec pr, const Over<SrcArgs>& a);
+
 void launch_fill_profile(hipStream_t s, const Dims& d, double* dst, const double* prof);
 // Zero the wall rows j = 0, ny-1 of nf <= 6 fields in one launch.
 void launch_zero_walls(hipStream_t s, const Dims& d, double* const f[], int nf);
-// S = (1/eta) D phi x D mu on the interior rows (main text eq. (5b)), into src[0..2]; with
-// a != 0 (the inertial variant, SM eq. (36)), S - a omega with omega[0..2] the previous
-// vorticity.
-void launch_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                   double inv_eta, double* const src[3], double a,
-                   const double* const omega[3]);
 void launch_reset_stats(hipStream_t s, double* scal, int* istat);
 
 // ---------------------------------------------------------------- spectral Poisson
-// Spectral pipeline. The spectral intermediates (spec, spec2) are stored as double, or as
-// float when f32 is set (the refined mode); kernel arithmetic is FP64 either way.
+// Spectral pipeline. The spectral intermediates are stored as double, or as float in the
+// refined mode; the two-pass transforms and the segmented tridiagonal solves compute in the
+// precision of that storage (the general-length Stockham transforms and the two-lane solves
+// of very short or tall columns compute in FP64 either way).
+
+// z transforms (two-pass): spec[c] (ST) -> u[c] (FP64; add: u += result), c < ncomp <= 6.
+// The forward transform of the vorticity source uses it with spec = S, u = FP64 modes.
+struct ZArgs {
+    void* spec[6];
+    double* u[6];
+    const double2* tw;
+    const int* gate;     // skip when *gate != 0 (a converged defect-correction loop), or null
+    int add;
+};
+// x transforms, in place on spec[c], c < ncomp <= 6.
+struct HxArgs {
+    void* spec[6];
+    const double2* tw;
+    const int* gate;
+};
+// Segmented vorticity + stream-vector tridiagonal solves (see k_tridiag_pair_seg).
+struct TriArgs {
+    const double* tri;
+    const double* triw;
+    void* spec[3];
+    void* spec2[3];
+    double olo[3], ohi[3], plo[3], phi[3];
+    const int* gate;
+};
+// Both flow residuals (vorticity, eq. (5b): b = S; stream vector, eq. (5c): b = -omega) in
+// one pass, into partial slots 0-5 and 6-11 as two resid_norm launches would write them.
+// ashift != 0: the vorticity operator is L_h - ashift (the inertial variant).
+struct ResArgs {
+    const double* om[3];
+    const void* src[3];
+    const double* ps[3];
+    double* part;
+    double ashift;
+    const int* gate;
+};
+struct ChkArgs {
+    const double* part;
+    double* scal;
+    int* istat;
+    double rtol;
+    const int* gate;
+};
+// Residuals of both flow problems at the current fields, transformed along z into FP32
+// modes (the refined mode's defect-correction cycle): vorticity into spec, stream vector
+// into spec2.
+struct RhsFlowArgs {
+    const void* src[3];
+    const double* om[3];
+    const double* ps[3];
+    void* spec[3];
+    void* spec2[3];
+    const double2* tw;
+    const int* gate;
+};
+
+// True when both periodic lengths have two-pass transforms and M a segmented solve: the forms
+// the fused flow pass, the refined mode's fused cycle and batched launches use.
+bool fused_flow_ok(const Dims& d);
+void launch_hz(hipStream_t s, const Dims& d, const FftPlan& pz, bool f32, int ncomp,
+               const Over<ZArgs>& a);
+void launch_hx(hipStream_t s, const Dims& d, const FftPlan& px, bool f32, int ncomp,
+               const Over<HxArgs>& a);
+// corr: the correction form (homogeneous walls, stream-vector residual modes in spec2).
+void launch_tri_pair(hipStream_t s, const Dims& d, bool f32, bool corr, const Over<TriArgs>& a);
+void launch_rhs_flow(hipStream_t s, const Dims& d, const Over<RhsFlowArgs>& a);
+// f32src: S stored as float (the refined mode).
+void launch_resid_flow_over(hipStream_t s, const Dims& d, bool f32src, const Over<ResArgs>& a);
+// last_cycle = 0: a defect-correction cycle that may be followed by another (gated).
+void launch_check_flow_over(hipStream_t s, const Dims& d, int last_cycle, const Over<ChkArgs>& a);
+
+// Single-instance forms of the same passes (vs_poisson_solve, refinement cycles, the reverse
+// step).
 // Forward: b~ (direct) or r = b - L_h u (correct) on interior rows, 2D Hartley in z then x.
 void launch_rhs_dht_z(hipStream_t s, const Dims& d, const FftPlan& pz, const double2* twz,
                       const RhsArgs& rhs, const double* const u[3], int ncomp, int correct,
@@ -176,11 +302,10 @@ void launch_tridiag_y(hipStream_t s, const Dims& d, const double* tri, void* con
                       int ncomp, bool f32, const int* gate);
 // Vorticity modes solved in place in spec (as launch_tridiag_y), then the stream-vector modes
 // into spec2 from them (psi wall values constant over each wall plane: psi_lo at j = 0,
-// psi_hi at j = ny-1).
-// The vorticity right-hand side's wall terms, om_lo at j = 0 and om_hi at j = ny-1 (constant
-// over each wall plane), are added in mode (0, 0) (the transform read S alone).
-// triw: the vorticity's pivot table (nullptr: tri; the inertial variant's shifted operator
-// L_h - a has its own); the stream-vector problem always uses tri.
+// psi_hi at j = ny-1). The vorticity right-hand side's wall terms, om_lo at j = 0 and om_hi at
+// j = ny-1 (constant over each wall plane), are added in mode (0, 0) (the transform read S
+// alone). triw: the vorticity's pivot table (nullptr: tri; the inertial variant's shifted
+// operator L_h - a has its own); the stream-vector problem always uses tri.
 void launch_tridiag_pair(hipStream_t s, const Dims& d, const double* tri, const double* triw,
                          void* const spec[3], void* const spec2[3], const double om_lo[3],
                          const double om_hi[3], const double psi_lo[3], const double psi_hi[3],
@@ -190,10 +315,6 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
                       void* const spec[], double* const u[], int ncomp, int add, bool f32,
                       const int* gate);
 int resid_blocks(const Dims& d);
-int resid_flow_blocks(const Dims& d);
-// Both flow residuals (vorticity, eq. (5b): b = S; stream vector, eq. (5c): b = -omega) in
-// one pass, into partial slots 0-5 and 6-11 as two resid_norm launches would write them.
-// ashift != 0: the vorticity operator is L_h - ashift (the inertial variant).
 void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
                        const double* const src[3], const double* const ps[3], double ashift,
                        double* partials);

@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
         "vs_destroy": (None, [vp]),
         "vs_set_walls": (i32, [vp, P(VsWalls)]),
         "vs_diagnostics": (i32, [vp, vp, P(dbl)]),
+        "vs_autotune": (i32, [vp, P(i32)]),
         "vs_batch_create": (i32, [P(vp), i32, vp, i32, P(vp)]),
         "vs_batch_step": (i32, [vp, P(dbl), i32]),
         "vs_batch_destroy": (None, [vp]),
@@ -226,10 +227,14 @@ class Solver:
         _check(lib().vs_field_offset(self._st, FIELDS[name], ctypes.byref(off)), "vs_field_offset")
         n = self.shape[0] * self.shape[1] * self.shape[2]
         start = self._pad + off.value
+        if name == "mu" and self.params.precision == VS_FP32_REFINED:
+            # the refined mode keeps mu as FP32 (include/vs.h)
+            return self._ws[start:start + 4 * n].view(self.torch.float32).view(*self.shape)
         return self._ws[start:start + 8 * n].view(self.torch.float64).view(*self.shape)
 
     def fields(self):
-        return {k: self.field(k).cpu().numpy() for k in FIELDS}
+        """Every field as a float64 numpy array."""
+        return {k: self.field(k).double().cpu().numpy() for k in FIELDS}
 
     def scalars(self) -> dict:
         out = (ctypes.c_double * len(SCALARS))()
@@ -278,6 +283,12 @@ class Solver:
                "vs_load_state")
 
     # ---------------------------------------------------------------- measurement
+    def autotune(self) -> dict:
+        """vs_autotune: pick this grid's launch shapes by timing them on this state's data."""
+        out = (ctypes.c_int32 * 4)()
+        _check(lib().vs_autotune(self._st, out), "vs_autotune")
+        return {"adv_slab": out[0], "va_maxb": out[1], "res_maxb": out[2], "seg_alt": out[3]}
+
     def profile(self, on: bool):
         _check(lib().vs_profile(self._st, 1 if on else 0), "vs_profile")
 

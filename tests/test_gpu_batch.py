@@ -45,15 +45,21 @@ def test_batch_instances_recipe():
         assert 0.5 <= w.kappa <= 2.0 and 0.7 <= w.prolate_Vr <= 0.95
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
-def test_batch_bitwise_equals_single_instances(precision):
-    ws = small_instances(5)
+# (fp64, 1) and (fp32_refined, 3): every kernel launched once per grid class over the device
+# argument tables; (fp64, 3): FP64 with correction cycles, stepped instance by instance inside
+# the graph
+@pytest.mark.parametrize("precision,mc", [("fp64", 1), ("fp64", 3), ("fp32_refined", 3)])
+def test_batch_bitwise_equals_single_instances(precision, mc):
+    ws = [w.with_(max_cycles=mc) for w in small_instances(5)]
     nsteps = 4
-    say(f"case batch-vs-single precision={precision} n={len(ws)} "
+    say(f"case batch-vs-single precision={precision} max_cycles={mc} n={len(ws)} "
         f"grids={[w.grid.nx for w in ws]} seeds={[w.seed for w in ws]} nsteps={nsteps}")
     singles = []
     for w in ws:
         s = P.solver_for(w, precision=precision)
+        # the batch tunes the launch shapes of every grid it has not seen (vs_autotune), and
+        # bitwise equality needs the same shapes (block partial layouts) on both sides
+        s.autotune()
         s.step(w.dt, nsteps)
         singles.append((s.fields(), s.scalars()))
         s.close()
@@ -73,11 +79,13 @@ def test_batch_bitwise_equals_single_instances(precision):
         s.close()
 
 
-def test_batch_matches_oracle():
-    ws = small_instances(3)
+@pytest.mark.parametrize("precision,mc,tol", [("fp64", 1, 1e-9), ("fp32_refined", 4, 1e-6)])
+def test_batch_matches_oracle(precision, mc, tol):
+    ws = [w.with_(max_cycles=mc) for w in small_instances(3)]
     nsteps = 2
-    say(f"case batch-vs-oracle n={len(ws)} grids={[w.grid.nx for w in ws]} nsteps={nsteps}")
-    solvers = [P.solver_for(w) for w in ws]
+    say(f"case batch-vs-oracle precision={precision} n={len(ws)} grids={[w.grid.nx for w in ws]} "
+        f"nsteps={nsteps}")
+    solvers = [P.solver_for(w, precision=precision) for w in ws]
     b = V.Batch(solvers, nstreams=8)
     b.step([w.dt for w in ws], nsteps)
     b.close()
@@ -96,7 +104,7 @@ def test_batch_matches_oracle():
             refd["psi_" + ax] = ref.psi[c]
         errs = {k: rel_l2(got[k], refd[k]) for k in FIELD_NAMES}
         say(f"  {w.name} n={w.grid.nx} " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
-        assert max(errs.values()) <= 1e-9, errs
+        assert max(errs.values()) <= tol, errs
 
 
 def test_batch_rejects_odd_steps_and_unstable_dt():

@@ -485,21 +485,34 @@ def test_refined_step_parity_vesicle32(seed):
     assert sc["relres"] <= w.rtol
 
 
+_DROPLET_REF = {}
+
+
+def _droplet256_oracle(nsteps):
+    """The oracle's droplet256 run (about 6 s a step), shared by both precision cases."""
+    if nsteps not in _DROPLET_REF:
+        w = workload("droplet256", nsteps=nsteps)
+        g, walls, p = oracle_objs(w)
+        _DROPLET_REF[nsteps] = ref_fields(O.run(g, walls, p, w.phi0(), w.dt, nsteps))
+    return _DROPLET_REF[nsteps]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
 def test_droplet256_full_size(precision):
-    """The Cahn-Hilliard droplet in Couette flow at its full 128 x 128 x 256 size, first 2
+    """The Cahn-Hilliard droplet in Couette flow at its full 128 x 128 x 256 size, first 10
     steps, against the FP64 oracle: FP64 in the benchmark's launch configuration (one verified
-    solve; 256-long z lines, two z per lane), and the refined mode."""
+    solve; 256-long z lines, two z per lane) at the FP64 bar, and the refined mode (FP32
+    sweeps and corrections, FP64 defect correction to rtol = 1e-10) at 1e-6 per field."""
+    nsteps = 10
     mc = 1 if precision == "fp64" else 4
-    w = workload("droplet256", nsteps=2, max_cycles=mc)
-    say(f"case droplet256 {w.grid.shape} precision={precision} max_cycles={mc}")
+    w = workload("droplet256", nsteps=nsteps, max_cycles=mc)
+    say(f"case droplet256 {w.grid.shape} precision={precision} max_cycles={mc} nsteps={nsteps}")
     s = P.solver_for(w, precision=precision)
-    s.step(w.dt, 2)
+    s.step(w.dt, nsteps)
     got = s.fields()
     sc = s.scalars()
     s.close()
-    g, walls, p = oracle_objs(w)
-    ref = O.run(g, walls, p, w.phi0(), w.dt, 2)
-    compare(got, ref_fields(ref), tol=TOL if precision == "fp64" else TOL_REFINED,
-            label=f"droplet256 {precision} 2 steps")
+    ref = _droplet256_oracle(nsteps)
+    compare(got, ref, tol=TOL if precision == "fp64" else TOL_REFINED,
+            label=f"droplet256 {precision} {nsteps} steps")
     assert sc["relres"] <= w.rtol
