@@ -65,8 +65,8 @@ def code_tokens(src: str) -> str:
 def source_hash(kernel: str) -> str:
     """Hash of the code (comments aside) of the source files that hold a kernel, to tie
     stored counters to the code they were taken on."""
-    names = (["k_explicit.hip"] if kernel in ("advance", "va_partials", "mu", "source")
-             else ["k_spectral.hip", "fft_reg.h"])
+    names = (["k_explicit.hip", "stencil.h"] if kernel in ("advance", "va_partials", "mu", "source")
+             else ["k_spectral.hip", "k_solve.hip", "spectral.h", "fft_reg.h", "flow_check.h"])
     h = hashlib.sha256()
     for fname in names:
         with open(os.path.join(ROOT, "paper_2601_05031_amd", "csrc", fname)) as f:
@@ -288,6 +288,14 @@ def adjoint_run(P, torch, nsteps: int, checkpoint_every: int = 10) -> dict:
         s2.grad_step(w.dt, a, b)
     torch.cuda.synchronize()
     t_rev = (time.perf_counter() - t0) / reps
+    # per-kernel event timing of the reverse step (a separate pass)
+    s2.profile(True)
+    for _ in range(5):
+        s2.grad_step(w.dt, a, b)
+    prof = s2.profile_read()
+    s2.profile(False)
+    rev_kernels = {k: {"mean_us": round(1e3 * ms / n, 2), "launches_per_step": n / 5}
+                   for k, (ms, n) in prof.items() if n}
     s.close()
     s2.close()
     ce = max(1, checkpoint_every)
@@ -299,7 +307,7 @@ def adjoint_run(P, torch, nsteps: int, checkpoint_every: int = 10) -> dict:
            "reverse_cell_updates_per_s": N / t_rev,
            "rollout_gradient_s": t_grad,
            "rollout_forward_steps": nsteps + recompute, "rollout_reverse_steps": nsteps,
-           "loss": L, "dL_dkappa": kb, "dL_dscale": sb}
+           "loss": L, "dL_dkappa": kb, "dL_dscale": sb, "reverse_kernels": rev_kernels}
     print(f"bench: adjoint96 forward {1e3 * t_fwd / nsteps:.3f} ms/step, reverse "
           f"{1e3 * t_rev:.3f} ms/step, rollout gradient of {nsteps} steps {t_grad:.2f} s",
           file=sys.stderr, flush=True)
@@ -381,7 +389,7 @@ def main():
                     help="steps of the headline instances replayed as one graph (-1: --steps, 0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="steps of the 64-instance batch (0 = skip)")
-    ap.add_argument("--batch-streams", type=int, default=8)
+    ap.add_argument("--batch-streams", type=int, default=2)
     ap.add_argument("--adjoint-steps", type=int, default=50,
                     help="steps of the 96^3 rollout gradient (0 = skip)")
     ap.add_argument("--inertial-steps", type=int, default=20,
@@ -391,6 +399,9 @@ def main():
                     help="also run one 256 MiB device-to-device copy (calibrates HBM counters)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (no vs_autotune before the timed steps)")
+    ap.add_argument("--launch-shapes", type=str, default="",
+                    help="fixed launch shapes of the 128^3 grid instead of vs_autotune, as "
+                         "adv_slab=8,va_maxb=512,... (profiler runs: no candidate launches)")
     ap.add_argument("--cpu-single-only", action="store_true",
                     help="time the CPU oracle on one thread only")
     ap.add_argument("--cpu-worker", type=float, default=0.0, help=argparse.SUPPRESS)
@@ -426,7 +437,11 @@ def main():
           flush=True)
     solvers = [P.solver_for(base, kappa=k) for k in KAPPAS]
     tuning = None
-    if not args.no_autotune:
+    if args.launch_shapes:
+        tuning = {k: int(v) for k, v in (kv.split("=") for kv in args.launch_shapes.split(","))}
+        P.set_launch_shapes(base.grid.shape + (base.grid.h,), tuning)
+        print(f"bench: fixed launch shapes {tuning}", file=sys.stderr, flush=True)
+    elif not args.no_autotune:
         tuning = solvers[1].autotune()   # launch shapes of the 128^3 grid, shared by all three
         print(f"bench: autotuned launch shapes {tuning}", file=sys.stderr, flush=True)
     for s in solvers:

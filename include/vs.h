@@ -273,12 +273,20 @@ vs_status vs_profile_read(vs_state* state, int32_t kernel, double* total_ms, int
 
 /* Launch-shape autotuner. Times, on the state's own data, the candidate launch shapes of its
  * grid: the x-slab length of the phi update (2, 4, 8 planes per lane), the block caps of the
- * volume/area partials (256 .. 2048) and of the flow residual (512 .. 4096), and, for
+ * volume/area partials (256 .. 2048) and of the flow residual (512 .. 4096), the form of the
+ * chemical potential (LDS tiles, or for nz in {64, 128, 256} register marching with 1 or 2
+ * rows per wave and 4 .. 16 planes per slab; all forms give the same bits) and, for
  * ny - 2 in {30, 46, 62, 94, 126, 254}, the segment layout of the tridiagonal solves (the
  * default or one with twice/half the lanes per mode), one coordinate at a time, and keeps the
  * fastest for every state of that grid in this process. The state's fields are not changed.
- * picked (may be NULL): adv_slab, va_maxb, res_maxb, seg_alt. Synchronises. */
-vs_status vs_autotune(vs_state* state, int32_t picked[4]);
+ * picked (may be NULL): adv_slab, va_maxb, res_maxb, seg_alt, mu_kind, mu_ni. Synchronises. */
+vs_status vs_autotune(vs_state* state, int32_t picked[6]);
+/* Set the launch shapes of a grid by hand (the six values vs_autotune reports, e.g. from an
+ * earlier tuning run), for every state of that grid in this process from the next launch on.
+ * Shapes that the grid cannot use fall back to the default form (the register-marching
+ * chemical potential needs nz in {64, 128, 256}; seg_alt needs ny - 2 in the list above).
+ * Checks ranges only; results are unchanged except in the order of the partial sums. */
+vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[6]);
 
 /* Batches (many independent instances, e.g. vesicles of different grids and parameters; the
  * batching extension of the benchmark spec, its persistent launch read as one launch per kernel

@@ -10,6 +10,7 @@ from .vs import (  # noqa: F401
     make_params,
     rollout_gradient,
     rollout_loss,
+    set_launch_shapes,
     solver_for,
     workspace_bytes,
 )

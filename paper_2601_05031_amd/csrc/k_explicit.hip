@@ -526,6 +526,153 @@ __global__ __launch_bounds__(kBlock) void k_mu_tile(Dims d, int va_nb, MuArgs on
     }
 }
 
+// mu by register marching, for n_z = 64 ZPL (ZPL in {1, 2, 4}): one wave covers whole z rows,
+// ZPL consecutive z per lane, so the periodic z neighbours come from the lane's own values and,
+// at its ends, from the previous and next lane (a rotation across the whole wave). A wave owns
+// RJ consecutive rows and walks ni consecutive x-planes; the phi planes i .. i+3 of the rows
+// j0-2 .. j0+RJ+1 (mirror rows past the walls, so g there is the mirror ghost of g) and g of the
+// planes i-1 .. i+1 stay in registers, and L_h phi of a plane is kept from the g computation
+// of that plane. The phi plane three ahead is loaded first in each step, so it is in flight
+// while the step computes. No LDS: the halo rows of a wave are read again by its neighbours
+// through the cache. Same sums in the same order as k_mu_tile, so the two agree bit for bit.
+// Four waves per block share the volume/area reduction.
+template <bool BEND, bool BATCH, class MT, int ZPL, int RJ>
+__global__ __launch_bounds__(kBlock) void k_mu_reg(Dims d, int va_nb, int ni, MuArgs one,
+                                                  const MuArgs* __restrict__ tab) {
+    constexpr int NR = RJ + 4;                    // phi rows j0-2 .. j0+RJ+1
+    __shared__ double shv[2 * 16];
+    const int ngr = (d.ny + 4 * RJ - 1) / (4 * RJ);   // groups of four waves' rows
+    const int nsl = (d.nx + ni - 1) / ni;
+    int inst;
+    const int lb = split_block<BATCH>(xcd_block(blockIdx.x, gridDim.x), ngr * nsl, inst);
+    const MuArgs va = inst_args<BATCH>(one, tab, inst);
+    const Gl<double>* __restrict__ phi = (const Gl<double>*)va.phi;
+    MT* __restrict__ mu = (MT*)va.mu;   // stored through a buffer resource
+    const int sl = lb / ngr, gr = lb - sl * ngr;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j0 = (gr * 4 + wv) * RJ;
+    const int i0 = sl * ni, i1 = min(d.nx, i0 + ni);
+    const int plane = d.ny * d.nz;
+    const int zo = lane * ZPL;
+    const double eps2 = va.eps * va.eps, C_b = va.C_b, sigma = va.sigma;
+    const int lprev = (lane + 63) & 63, lnext = (lane + 1) & 63;
+    int roff[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) roff[r] = mirror_row(j0 - 2 + r, d.ny) * d.nz + zo;
+    auto fetch = [&](int i, double (&v)[NR][ZPL]) {
+        const Gl<double>* src = phi + (size_t)wrap_mod(i, d.nx) * plane;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if constexpr (ZPL == 1) {
+                v[r][0] = src[roff[r]];
+            } else {
+#pragma unroll
+                for (int q = 0; q < ZPL; q += 2) {
+                    const double2 t = ldd2(src + roff[r] + q);
+                    v[r][q] = t.x;
+                    v[r][q + 1] = t.y;
+                }
+            }
+        }
+    };
+    // z neighbours of value q of a row held as ZPL values per lane (periodic over the wave)
+    auto zpair = [&](const double (&v)[ZPL], int q, double& zp, double& zm) {
+        zm = q > 0 ? v[q > 0 ? q - 1 : 0] : __shfl(v[ZPL - 1], lprev, 64);
+        zp = q < ZPL - 1 ? v[q < ZPL - 1 ? q + 1 : 0] : __shfl(v[0], lnext, 64);
+    };
+    // g and L_h phi of the plane held in b (x neighbours a, c) on the rows j0-1+r0 ..
+    // j0-1+r0+n-1; rows are indexed from j0-2 in the phi arrays
+    auto make_g = [&](const double (&a)[NR][ZPL], const double (&b)[NR][ZPL],
+                      const double (&c)[NR][ZPL], double (&g)[RJ + 2][ZPL],
+                      double (&lp)[RJ + 2][ZPL]) {
+#pragma unroll
+        for (int r = 0; r < RJ + 2; ++r) {
+            const int R = r + 1;                  // phi row of g row j0-1+r
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q) {
+                double zp, zm;
+                zpair(b[R], q, zp, zm);
+                const double p = b[R][q];
+                const double l = (c[R][q] + a[R][q] + b[R + 1][q] + b[R - 1][q] + zp + zm - 6.0 * p) * d.inv_h2;
+                lp[r][q] = l;
+                g[r][q] = p * p * p - p - eps2 * l;
+            }
+        }
+    };
+    // volume/area scalars and gamma_A, shared by the block (every block sums the partials)
+    double gamma;
+    {
+        VaLoads vl;
+        va_load(va, va_nb, vl);
+        va_reduce(va, va_nb, vl, shv);
+        __syncthreads();
+        gamma = va_final(va, d, shv, lb == 0);
+    }
+    double A[NR][ZPL], B[NR][ZPL], C[NR][ZPL], D[NR][ZPL];
+    double g0[RJ + 2][ZPL], g1[RJ + 2][ZPL], g2[RJ + 2][ZPL];
+    double L1[RJ + 2][ZPL], L2[RJ + 2][ZPL];
+    // warm-up: phi(i0-2 .. i0+2); g(i0-1) from phi(i0-2 .. i0), g(i0) from phi(i0-1 .. i0+1)
+    fetch(i0 - 2, A);
+    fetch(i0 - 1, B);
+    fetch(i0, C);
+    fetch(i0 + 1, D);
+    if (BEND) make_g(A, B, C, g0, L1);           // g(i0-1) (L1 overwritten below)
+    make_g(B, C, D, g1, L1);                      // g(i0), L_h phi(i0)
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int q = 0; q < ZPL; ++q) {
+            A[r][q] = C[r][q];
+            B[r][q] = D[r][q];
+        }
+    fetch(i0 + 2, C);                             // A = phi(i0), B = phi(i0+1), C = phi(i0+2)
+    const unsigned pbytes = (unsigned)plane * (unsigned)sizeof(MT);
+    for (int i = i0; i < i1; ++i) {
+        fetch(i + 3, D);                          // in flight during this step
+        if (BEND) make_g(A, B, C, g2, L2);        // g(i+1), L_h phi(i+1)
+        else make_g(A, B, C, g2, L2);             // (CH: only L_h phi(i+1) is used)
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+            const int j = j0 + r;
+            const bool keep = j < d.ny;
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q) {
+                const double p = A[r + 2][q];
+                const double lphi = L1[r + 1][q];
+                double m;
+                if (!BEND) {
+                    m = p * p * p - p - sigma * lphi;
+                } else {
+                    double zp, zm;
+                    zpair(g1[r + 1], q, zp, zm);
+                    const double g = g1[r + 1][q];
+                    const double gs = g2[r + 1][q] + g0[r + 1][q] + g1[r + 2][q] + g1[r][q] + zp + zm;
+                    const double lg = (gs - 6.0 * g) * d.inv_h2;
+                    m = C_b * ((3.0 * p * p - 1.0) * g - eps2 * lg) - gamma * lphi;
+                }
+                const unsigned off = (unsigned)(j * d.nz + zo + q) * (unsigned)sizeof(MT);
+                plane_store(mu + (size_t)i * plane, pbytes, keep ? off : pbytes, m);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RJ + 2; ++r)
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q) {
+                g0[r][q] = g1[r][q];
+                g1[r][q] = g2[r][q];
+                L1[r][q] = L2[r][q];
+            }
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int q = 0; q < ZPL; ++q) {
+                A[r][q] = B[r][q];
+                B[r][q] = C[r][q];
+                C[r][q] = D[r][q];
+            }
+    }
+}
+
 // Block partials of sum_w phi and sum_w [(eps/2)|D phi|^2 + (phi^2-1)^2/(4 eps)]
 // (trapezoid weights w = 1/2 on the wall rows). Each thread owns one (j, k) and walks ci
 // consecutive x-planes, keeping phi of the planes i-1, i, i+1 in registers; the partial of
@@ -858,22 +1005,46 @@ void launch_va_partials(hipStream_t s, const Dims& d, const Over<VaArgs>& a) {
     else go(k_va_partials<true>, k_va_partials<false>);
 }
 
-void launch_mu(hipStream_t s, const Dims& d, int model, Prec pr, const Over<MuArgs>& a) {
+// The chemical potential runs as x-marching LDS tiles (k_mu_tile, any grid) or, for n_z in
+// {64, 128, 256}, by register marching (k_mu_reg) with RJ rows per wave and mu_ni planes per
+// slab; the autotuner picks (mu_kind: 0 tiles, 1 or 2 register marching with RJ = 1 or 2).
+template <bool BEND, class MT>
+static void mu_t(hipStream_t s, const Dims& d, const Over<MuArgs>& a) {
+    const unsigned ni_ = a.tab ? (unsigned)a.n : 1u;
+    const int vnb = va_partial_blocks(d);
+    const Tuning tu = tuning_for(d);
+    const int zpl = d.nz / 64;
+    if (tu.mu_kind > 0 && d.nz % 64 == 0 && (zpl == 1 || zpl == 2 || zpl == 4)) {
+        const int RJ = tu.mu_kind;
+        const int ni = tu.mu_ni > 0 ? tu.mu_ni : 8;
+        const int nb = ((d.ny + 4 * RJ - 1) / (4 * RJ)) * ((d.nx + ni - 1) / ni);
+        const dim3 gr(nb * ni_);
+        auto go = [&](auto kt, auto kf) {
+            if (a.tab) launch_kernel(kt, gr, dim3(kBlock), 0, s, d, vnb, ni, a.one, a.tab);
+            else launch_kernel(kf, gr, dim3(kBlock), 0, s, d, vnb, ni, a.one, a.tab);
+        };
+#define VS_MUREG(Z, R) go(k_mu_reg<BEND, true, MT, Z, R>, k_mu_reg<BEND, false, MT, Z, R>)
+        if (zpl == 1) { if (RJ == 1) VS_MUREG(1, 1); else VS_MUREG(1, 2); }
+        else if (zpl == 2) { if (RJ == 1) VS_MUREG(2, 1); else VS_MUREG(2, 2); }
+        else { if (RJ == 1) VS_MUREG(4, 1); else VS_MUREG(4, 2); }
+#undef VS_MUREG
+        return;
+    }
     const int nb = ((d.ny + kMuTY - 1) / kMuTY) * ((d.nz + kMuTZ - 1) / kMuTZ) *
                    ((d.nx + kMuNI - 1) / kMuNI);
-    const dim3 gr(nb * nin(a));
-    const int vnb = va_partial_blocks(d);
-    auto go = [&](auto kt, auto kf) {
-        if (a.tab) launch_kernel(kt, gr, dim3(kBlock), 0, s, d, vnb, a.one, a.tab);
-        else launch_kernel(kf, gr, dim3(kBlock), 0, s, d, vnb, a.one, a.tab);
-    };
+    const dim3 gr(nb * ni_);
+    if (a.tab) launch_kernel(k_mu_tile<BEND, true, MT>, gr, dim3(kBlock), 0, s, d, vnb, a.one, a.tab);
+    else launch_kernel(k_mu_tile<BEND, false, MT>, gr, dim3(kBlock), 0, s, d, vnb, a.one, a.tab);
+}
+
+void launch_mu(hipStream_t s, const Dims& d, int model, Prec pr, const Over<MuArgs>& a) {
     const bool ch = model == VS_CAHN_HILLIARD;
     if (pr == P32) {
-        if (ch) go(k_mu_tile<false, true, float>, k_mu_tile<false, false, float>);
-        else go(k_mu_tile<true, true, float>, k_mu_tile<true, false, float>);
+        if (ch) mu_t<false, float>(s, d, a);
+        else mu_t<true, float>(s, d, a);
     } else {
-        if (ch) go(k_mu_tile<false, true, double>, k_mu_tile<false, false, double>);
-        else go(k_mu_tile<true, true, double>, k_mu_tile<true, false, double>);
+        if (ch) mu_t<false, double>(s, d, a);
+        else mu_t<true, double>(s, d, a);
     }
 }
 

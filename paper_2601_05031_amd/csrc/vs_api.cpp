@@ -44,13 +44,14 @@ enum KClass {
     K_ADVANCE, K_VA_PARTIALS, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
     K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_DHT_X_PAIR, K_DHT_Z_OUT_PAIR,
-    K_RHS_FLOW, K_NCLASS
+    K_RHS_FLOW, K_ADJ_ADVECT, K_ADJ_WALLS, K_ADJ_SOURCE, K_ADJ_MU1, K_ADJ_MU2, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
     "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
     "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
-    "resid_norm_flow", "dht_x_pair", "dht_z_out_pair", "rhs_flow"};
+    "resid_norm_flow", "dht_x_pair", "dht_z_out_pair", "rhs_flow", "adj_advect",
+    "adj_wall_couple", "adj_source", "adj_mu1", "adj_mu2"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -267,7 +268,7 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<TuneKey, Tuning>> g_tune;
-constexpr Tuning kDefaultTuning{4, 1024, 1024, 0};
+constexpr Tuning kDefaultTuning{4, 1024, 1024, 0, 0, 8};
 
 void set_tuning(const Dims& d, const Tuning& t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1082,8 +1083,10 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
     const double* const cps[3] = {S->ps[0], S->ps[1], S->ps[2]};
     timed(S, K_RESET, [&] { launch_reset_stats(st, S->scal, S->istat); });
     // advection, L_h mu and lambda_V terms; q = psi_bar
-    launch_adj_advect(st, d, adj_next, phi, cps, dt, S->p.mobility, S->vz_lo, S->vz_hi, adj_prev,
-                      mubar, q, S->part, S->scal);
+    timed(S, K_ADJ_ADVECT, [&] {
+        launch_adj_advect(st, d, adj_next, phi, cps, dt, S->p.mobility, S->vz_lo, S->vz_hi,
+                          adj_prev, mubar, q, S->part, S->scal);
+    });
     // psi_int = P(-omega_int; psi walls): first adjoint solve, homogeneous walls;
     // omega_int = P(S; omega walls): second adjoint solve, of -u1, giving S_bar
     double* sb[3] = {q[0], q[1], q[2]};          // S_bar
@@ -1095,20 +1098,22 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
         double* const us[3] = {(double*)S->spec[0], (double*)S->spec[1], (double*)S->spec[2]};
         double* const ss[3] = {(double*)S->spec2[0], (double*)S->spec2[1], (double*)S->spec2[2]};
         double* const w6[6] = {us[0], us[1], us[2], ss[0], ss[1], ss[2]};
-        launch_zero_walls(st, d, w6, 6);
+        timed(S, K_FILL, [&] { launch_zero_walls(st, d, w6, 6); });
         const double* const qc[3] = {q[0], q[1], q[2]};
-        launch_dht_z_fwd(st, d, S->pz, S->twz, qc, S->spec, 3);
-        launch_dht_x(st, d, S->px, S->twx, S->spec, 3, false, nullptr);
+        timed(S, K_RHS_Z_FIELD, [&] { launch_dht_z_fwd(st, d, S->pz, S->twz, qc, S->spec, 3); });
+        timed(S, K_DHT_X, [&] { launch_dht_x(st, d, S->px, S->twx, S->spec, 3, false, nullptr); });
         const double zero[3] = {0.0, 0.0, 0.0};
-        launch_tridiag_pair(st, d, S->tri, nullptr, S->spec, S->spec2, zero, zero, zero, zero, false);
+        timed(S, K_TRIDIAG_PAIR, [&] {
+            launch_tridiag_pair(st, d, S->tri, nullptr, S->spec, S->spec2, zero, zero, zero, zero, false);
+        });
         void* const sp6[6] = {S->spec[0], S->spec[1], S->spec[2], S->spec2[0], S->spec2[1], S->spec2[2]};
-        launch_dht_x(st, d, S->px, S->twx, sp6, 6, false, nullptr);
-        launch_dht_z_out(st, d, S->pz, S->twz, sp6, w6, 6, 0, false, nullptr);
+        timed(S, K_DHT_X_PAIR, [&] { launch_dht_x(st, d, S->px, S->twx, sp6, 6, false, nullptr); });
+        timed(S, K_DHT_Z_OUT_PAIR, [&] { launch_dht_z_out(st, d, S->pz, S->twz, sp6, w6, 6, 0, false, nullptr); });
         const double* const cu[3] = {us[0], us[1], us[2]};
         const double* const cs[3] = {ss[0], ss[1], ss[2]};
-        launch_resid_flow(st, d, cu, qc, cs, 0.0, S->part);
-        launch_check_flow(st, d, S->part, rtol, S->scal, S->istat);
-        launch_adj_wall_couple(st, d, us, S->ps, S->part, S->scal, SC_ADJ_PSIC);
+        timed(S, K_RESID_FLOW, [&] { launch_resid_flow(st, d, cu, qc, cs, 0.0, S->part); });
+        timed(S, K_CHECK, [&] { launch_check_flow(st, d, S->part, rtol, S->scal, S->istat); });
+        timed(S, K_ADJ_WALLS, [&] { launch_adj_wall_couple(st, d, us, S->ps, S->part, S->scal, SC_ADJ_PSIC); });
         for (int c = 0; c < 3; ++c) sb[c] = ss[c];
     } else {
         // the solve writes the interior; only the wall rows need zeros
@@ -1124,16 +1129,20 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
         for (int c = 0; c < 3; ++c) r2.f[c] = u1[c];
         enqueue_solve(S, r2, q, 3, rtol, mc, TAG_FIELD);
     }
-    launch_adj_wall_couple(st, d, sb, S->om, S->part, S->scal, SC_ADJ_OMC);
+    timed(S, K_ADJ_WALLS, [&] { launch_adj_wall_couple(st, d, sb, S->om, S->part, S->scal, SC_ADJ_OMC); });
     // S = (1/eta) D phi x D mu
-    launch_adj_source(st, d, phi, S->mu, sb, 1.0 / S->p.eta, adj_prev, mubar);
+    timed(S, K_ADJ_SOURCE, [&] { launch_adj_source(st, d, phi, S->mu, sb, 1.0 / S->p.eta, adj_prev, mubar); });
     // mu(phi)
     double* gbar = (double*)S->spec[0];
     const double dCb = S->p.bend_scale * 3.0 * std::sqrt(2.0) / (8.0 * S->p.eps * S->p.eps * S->p.eps);
     if (S->p.model == VS_BENDING)
-        launch_adj_mu1(st, d, phi, mubar, S->C_b(), dCb, S->p.eps, gbar, S->part, S->scal);
-    launch_adj_mu2(st, d, phi, mubar, gbar, S->scal, S->p.model, S->C_b(), S->p.eps, S->p.sigma, dt,
-                   S->p.mobility, S->p.rate_V, S->p.k_A, adj_prev);
+        timed(S, K_ADJ_MU1, [&] {
+            launch_adj_mu1(st, d, phi, mubar, S->C_b(), dCb, S->p.eps, gbar, S->part, S->scal);
+        });
+    timed(S, K_ADJ_MU2, [&] {
+        launch_adj_mu2(st, d, phi, mubar, gbar, S->scal, S->p.model, S->C_b(), S->p.eps, S->p.sigma,
+                       dt, S->p.mobility, S->p.rate_V, S->p.k_A, adj_prev);
+    });
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     int ist[IS_NSTAT];
@@ -1359,14 +1368,20 @@ namespace {
 
 // Picks the tuned launch shapes of S's grid by timing each candidate on S's own data: the
 // phi update's x-slab length (written into the free phi buffer), the volume/area partials'
-// block cap (with the chemical potential that reduces them: it recomputes mu and the scalars
-// from the same phi, so they come out unchanged), the flow residual's block cap (partials
-// only) and the pair tridiagonal solves' segment layout (spectral scratch only). One
-// coordinate at a time, each candidate launched kReps times after one warm-up launch, the
-// fastest mean kept. Nothing of the state's fields changes.
+// block cap and the chemical potential's form (they recompute mu and the scalars from the same
+// phi; the partial sums' order differs with the cap, so mu and the scalars are saved first, mu
+// in the source buffer, which every step rewrites before use, and restored at the end), the
+// flow residual's block cap (partials only) and the pair tridiagonal solves' segment layout
+// (spectral scratch only). One coordinate at a time, each candidate launched kReps times after
+// one warm-up launch, the fastest mean kept. The state's fields and scalars come out as they
+// went in.
 vs_status autotune_state(vs_state* S, Tuning* picked) {
     constexpr int kReps = 5;
     HIP_TRY(hipStreamSynchronize(S->stream));
+    const size_t fbytes = (size_t)S->g.nx * S->g.ny * S->g.nz * sizeof(double);
+    double sc_save[SC_NSCAL];
+    HIP_TRY(hipMemcpy(sc_save, S->scal, sizeof sc_save, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(S->src[2], S->mu, fbytes, hipMemcpyDeviceToDevice, S->stream));
     const StepCfg c = step_cfg(S);
     const double dt = 1e-12;   // the advance's output buffer is scratch; any dt does
     const StepArgs A = step_args(S, S->cur, dt, false);
@@ -1410,6 +1425,33 @@ vs_status autotune_state(vs_state* S, Tuning* picked) {
         launch_va_partials(c.st, c.d, A.va);
         launch_mu(c.st, c.d, c.model, pr, A.mu);
     });
+    // the chemical potential's form: LDS tiles, or register marching (n_z in {64, 128, 256})
+    // with 1 or 2 rows per wave and 4 .. 16 planes per slab, as one coordinate
+    {
+        const int zpl = S->d.nz / 64;
+        const bool reg_ok = S->d.nz % 64 == 0 && (zpl == 1 || zpl == 2 || zpl == 4);
+        const int cand[][2] = {{0, 8}, {1, 4}, {1, 8}, {1, 16}, {2, 4}, {2, 8}, {2, 16}};
+        int bk = t.mu_kind, bn = t.mu_ni;
+        float tb = 1e30f;
+        for (const auto& cd : cand) {
+            if (cd[0] > 0 && !reg_ok) continue;
+            t.mu_kind = cd[0];
+            t.mu_ni = cd[1];
+            set_tuning(S->d, t);
+            const float ms = time([&] {
+                launch_va_partials(c.st, c.d, A.va);
+                launch_mu(c.st, c.d, c.model, pr, A.mu);
+            });
+            if (ms < tb) {
+                tb = ms;
+                bk = cd[0];
+                bn = cd[1];
+            }
+        }
+        t.mu_kind = bk;
+        t.mu_ni = bn;
+        set_tuning(S->d, t);
+    }
     pick(&t.res_maxb, {512, 1024, 2048, 4096},
          [&] { launch_resid_flow_over(c.st, c.d, false, S->f32 ? A.resc[0] : A.res); });
     if (fused_flow_ok(S->d) && seg_has_alt(S->d.M))
@@ -1420,7 +1462,8 @@ vs_status autotune_state(vs_state* S, Tuning* picked) {
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return fail(VS_E_HIP, "autotune timing failed: %s", hipGetErrorString(err));
     HIP_TRY(hipGetLastError());
-    // the timed mu launches rewrote the scalars from the same phi: the same values
+    HIP_TRY(hipMemcpyAsync(S->mu, S->src[2], fbytes, hipMemcpyDeviceToDevice, S->stream));
+    HIP_TRY(hipMemcpyAsync(S->scal, sc_save, sizeof sc_save, hipMemcpyHostToDevice, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
     if (picked) *picked = t;
     return VS_OK;
@@ -1428,7 +1471,25 @@ vs_status autotune_state(vs_state* S, Tuning* picked) {
 
 }  // namespace
 
-extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[4]) {
+extern "C" vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[6]) {
+    vs_status st = check_grid(grid);
+    if (st != VS_OK) return st;
+    if (!shapes) return fail(VS_E_ARG, "shapes is NULL");
+    const Tuning t{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5]};
+    if (t.adv_slab < 1 || t.adv_slab > 64) return fail(VS_E_ARG, "adv_slab must be in [1, 64]");
+    if (t.va_maxb < 64 || t.va_maxb > kMaxPartialBlocks)
+        return fail(VS_E_ARG, "va_maxb must be in [64, %d]", kMaxPartialBlocks);
+    if (t.res_maxb < 64 || t.res_maxb > kMaxPartialBlocks)
+        return fail(VS_E_ARG, "res_maxb must be in [64, %d]", kMaxPartialBlocks);
+    if (t.seg_alt != 0 && t.seg_alt != 1) return fail(VS_E_ARG, "seg_alt must be 0 or 1");
+    if (t.mu_kind < 0 || t.mu_kind > 2) return fail(VS_E_ARG, "mu_kind must be 0, 1 or 2");
+    if (t.mu_ni < 1 || t.mu_ni > 64) return fail(VS_E_ARG, "mu_ni must be in [1, 64]");
+    Dims d{grid->nx, grid->ny, grid->nz, grid->ny - 2, grid->h, 0.0, 0.0};
+    set_tuning(d, t);
+    return VS_OK;
+}
+
+extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[6]) {
     if (!S) return fail(VS_E_STATE, "state is NULL");
     if (S->prof_on) return fail(VS_E_ARG, "vs_autotune: switch the event timer off first");
     Tuning t{};
@@ -1439,6 +1500,8 @@ extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[4]) {
         picked[1] = t.va_maxb;
         picked[2] = t.res_maxb;
         picked[3] = t.seg_alt;
+        picked[4] = t.mu_kind;
+        picked[5] = t.mu_ni;
     }
     return VS_OK;
 }

@@ -127,6 +127,8 @@ struct Tuning {
     int va_maxb;    // block cap of the volume/area partials (sets their x-slab length)
     int res_maxb;   // block cap per component of the flow residual
     int seg_alt;    // 0: the default segment layout of the tridiagonal solves, 1: the other
+    int mu_kind;    // chemical potential: 0 LDS tiles; 1, 2 register marching, rows per wave
+    int mu_ni;      // x-planes per wave of the register-marching form
 };
 Tuning tuning_for(const Dims& d);
 bool seg_has_alt(int M);   // the pair solves of M interior rows have a second layout

@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
         "vs_set_walls": (i32, [vp, P(VsWalls)]),
         "vs_diagnostics": (i32, [vp, vp, P(dbl)]),
         "vs_autotune": (i32, [vp, P(i32)]),
+        "vs_set_launch_shapes": (i32, [P(VsGrid), P(i32)]),
         "vs_batch_create": (i32, [P(vp), i32, vp, i32, P(vp)]),
         "vs_batch_step": (i32, [vp, P(dbl), i32]),
         "vs_batch_destroy": (None, [vp]),
@@ -129,6 +130,16 @@ def workspace_bytes(grid, params: VsParams) -> int:
     _check(lib().vs_workspace_bytes(ctypes.byref(g), ctypes.byref(params), ctypes.byref(n)),
            "vs_workspace_bytes")
     return n.value
+
+
+SHAPE_KEYS = ("adv_slab", "va_maxb", "res_maxb", "seg_alt", "mu_kind", "mu_ni")
+
+
+def set_launch_shapes(grid, shapes: dict):
+    """vs_set_launch_shapes: launch shapes for every state of this grid (nx, ny, nz[, h])."""
+    g = VsGrid(grid[0], grid[1], grid[2], float(grid[3]) if len(grid) > 3 else 1.0)
+    arr = (ctypes.c_int32 * 6)(*[int(shapes[k]) for k in SHAPE_KEYS])
+    _check(lib().vs_set_launch_shapes(ctypes.byref(g), arr), "vs_set_launch_shapes")
 
 
 def noalloc_scratch_bytes() -> int:
@@ -285,9 +296,9 @@ class Solver:
     # ---------------------------------------------------------------- measurement
     def autotune(self) -> dict:
         """vs_autotune: pick this grid's launch shapes by timing them on this state's data."""
-        out = (ctypes.c_int32 * 4)()
+        out = (ctypes.c_int32 * 6)()
         _check(lib().vs_autotune(self._st, out), "vs_autotune")
-        return {"adv_slab": out[0], "va_maxb": out[1], "res_maxb": out[2], "seg_alt": out[3]}
+        return dict(zip(SHAPE_KEYS, list(out)))
 
     def profile(self, on: bool):
         _check(lib().vs_profile(self._st, 1 if on else 0), "vs_profile")

@@ -54,12 +54,14 @@ def test_batch_bitwise_equals_single_instances(precision, mc):
     nsteps = 4
     say(f"case batch-vs-single precision={precision} max_cycles={mc} n={len(ws)} "
         f"grids={[w.grid.nx for w in ws]} seeds={[w.seed for w in ws]} nsteps={nsteps}")
+    # the batch tunes the launch shapes of every grid it has not seen (vs_autotune); bitwise
+    # equality needs the same shapes (block partial layouts) on both sides: fix them first
+    for w in ws:
+        V.set_launch_shapes(w.grid.shape + (w.grid.h,), dict(adv_slab=2, va_maxb=512, res_maxb=2048,
+                                                             seg_alt=1, mu_kind=0, mu_ni=8))
     singles = []
     for w in ws:
         s = P.solver_for(w, precision=precision)
-        # the batch tunes the launch shapes of every grid it has not seen (vs_autotune), and
-        # bitwise equality needs the same shapes (block partial layouts) on both sides
-        s.autotune()
         s.step(w.dt, nsteps)
         singles.append((s.fields(), s.scalars()))
         s.close()
