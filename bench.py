@@ -51,6 +51,8 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int) -> float | None:
         "resid_norm_omega": 48 * Ni,  # S(3), omega(3) in
         "resid_norm_psi": 48 * Ni,    # omega(3), psi(3) in
         "resid_norm_flow": 72 * Ni,   # omega(3), S(3), psi(3) in: both flow residuals
+        "dht_zx": 48 * Ni,            # plane form: S(3) in; 3 spectral fields out
+        "dht_xz_pair": 96 * Ni,       # plane form: 6 spectral fields in; omega(3), psi(3) out
     }
     return table.get(name)
 
@@ -406,6 +408,7 @@ def main():
                     help="time the CPU oracle on one thread only")
     ap.add_argument("--cpu-worker", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    args.profile_steps = max(1, args.profile_steps)   # the roofline needs one profiled step
 
     if args.cpu_worker > 0:
         # a CPU-only worker of the all-core oracle baseline: no GPU, one JSON line

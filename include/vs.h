@@ -277,20 +277,24 @@ vs_status vs_profile_read(vs_state* state, int32_t kernel, double* total_ms, int
  * chemical potential (LDS tiles, or for nz in {64, 128, 256} register marching with 1 or 2
  * rows per wave and 4 .. 16 planes per slab; all forms give the same bits) and, for
  * ny - 2 in {30, 46, 62, 94, 126, 254}, the segment layout of the tridiagonal solves (the
- * default or one with twice/half the lanes per mode), one coordinate at a time, and keeps the
- * fastest for every state of that grid in this process. The state's fields are not changed.
- * picked (may be NULL): adv_slab, va_maxb, res_maxb, seg_alt, mu_kind, mu_ni. Synchronises. */
-vs_status vs_autotune(vs_state* state, int32_t picked[6]);
-/* Set the launch shapes of a grid by hand (the six values vs_autotune reports, e.g. from an
+ * default or one with twice/half the lanes per mode) and, in FP64 with nx = nz in
+ * {32, 48, 64, 96, 128}, whether the x and z transforms of a direction run as one pass over
+ * each (x, z) plane held in LDS (plane = 1) or as two line passes (0), one coordinate at a
+ * time, and keeps the fastest for every state of that grid in this process. The state's fields
+ * are not changed. picked (may be NULL): adv_slab, va_maxb, res_maxb, seg_alt, mu_kind, mu_ni,
+ * plane. Synchronises. */
+vs_status vs_autotune(vs_state* state, int32_t picked[7]);
+/* Set the launch shapes of a grid by hand (the seven values vs_autotune reports, e.g. from an
  * earlier tuning run), for every state of that grid in this process from the next launch on.
  * Shapes that the grid cannot use fall back to the default form (the register-marching
  * chemical potential needs nz in {64, 128, 256}; seg_alt needs ny - 2 in the list above).
- * Checks ranges only; results are unchanged except in the order of the partial sums. */
-vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[6]);
+ * Checks ranges only; results are unchanged except in the order of the partial sums and, with
+ * plane = 1, in the rounding of the z transforms (their rows are paired differently). */
+vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[7]);
 
-/* Batches (many independent instances, e.g. vesicles of different grids and parameters; the
- * batching extension of the benchmark spec, its persistent launch read as one launch per kernel
- * and instance group). vs_batch_create groups n states made by vs_init (each keeps its own
+/* Batches (many independent instances, e.g. vesicles of different grids and parameters,
+ * stepped together: one launch per kernel and instance group instead of one persistent
+ * launch). vs_batch_create groups n states made by vs_init (each keeps its own
  * workspace) into grid classes (same grid, precision, model and poisson_max_cycles), and each
  * class into groups of about 2^21 nodes (all instances of a small grid, one 128^3 instance):
  * every kernel of a time step is launched once per group, each instance's pointers and

@@ -629,6 +629,146 @@ __global__ __launch_bounds__(64) void k_hz_out(Dims d, ZArgs one, const ZArgs* _
     two_pass_hartley<B, A, false, T>(Y, a.tw, prep, load, store);
 }
 
+// ---------------------------------------------------------------------------------------
+// Both transform directions of one interior row in one pass: the whole (x, z) plane of row j
+// and one component sits in LDS (n_x (n_z + 2) doubles, up to 135 KB at 128 x 128: one block
+// per CU), so the spectral data crosses HBM once per direction instead of twice. Each 1D
+// transform is the two-pass form above done in place in the plane: pass 1 overwrites the B
+// inputs of its (line pair, k1) with their twiddled B-point DFT, pass 2 reads the A values of
+// rows pa, pb, and after a barrier writes the Hartley values. z lines are pairs of x-rows
+// (i, i+1), x lines pairs of z-columns (q, q+1) as in k_hx.
+constexpr int kPlaneThreads = 512;
+constexpr int kPlanePad = 2;
+
+// One 1D Hartley transform of every line pair of the plane. ROWS: lines are x-rows (element m
+// at P[row * RS + m]); otherwise z-columns (element m at P[m * RS + col]).
+template <int B, int A, int NLP, int RS, bool ROWS>
+__device__ __forceinline__ void plane_hartley(double* __restrict__ P, const Gl<tw2v>* __restrict__ tw) {
+    using C = double2;
+    static_assert(NLP * A <= kPlaneThreads && NLP * (B / 2) <= kPlaneThreads, "one item per lane");
+    auto ld = [&](int lp, int m) -> C {
+        if constexpr (ROWS) return make_double2(P[(2 * lp) * RS + m], P[(2 * lp + 1) * RS + m]);
+        else return *reinterpret_cast<const double2*>(&P[m * RS + 2 * lp]);
+    };
+    auto st = [&](int lp, int m, double a, double b) {
+        if constexpr (ROWS) {
+            P[(2 * lp) * RS + m] = a;
+            P[(2 * lp + 1) * RS + m] = b;
+        } else {
+            *reinterpret_cast<double2*>(&P[m * RS + 2 * lp]) = make_double2(a, b);
+        }
+    };
+    const int it = threadIdx.x;
+    // pass 1: B-point DFTs over k2, twiddled, back to the same positions k1 + A p2
+    if (it < NLP * A) {
+        const int lp = ROWS ? it / A : it % NLP;
+        const int k1 = ROWS ? it % A : it / NLP;
+        C x[B];
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) x[k2] = ld(lp, k1 + A * k2);
+        fftr::DFT<B>::run(x);
+#pragma unroll
+        for (int p2 = 1; p2 < B; ++p2) x[p2] = cmul_tw<double>(x[p2], tw[k1 * p2]);
+#pragma unroll
+        for (int p2 = 0; p2 < B; ++p2) st(lp, k1 + A * p2, x[p2].x, x[p2].y);
+    }
+    __syncthreads();
+    // pass 2: A-point DFTs of rows pa and pb, then the Hartley values of both lines
+    const bool act = it < NLP * (B / 2);
+    const int lp = act ? (ROWS ? it / (B / 2) : it % NLP) : 0;
+    const int s = act ? (ROWS ? it % (B / 2) : it / NLP) : 0;
+    const int pa = s, pb = (s == 0) ? B / 2 : B - s;
+    // every lane computes (an idle one on line pair 0), so the arrays stay in registers
+    C xa[A], xb[A];
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        xa[k1] = ld(lp, k1 + A * pa);
+        xb[k1] = ld(lp, k1 + A * pb);
+    }
+    fftr::DFT<A>::run(xa);
+    fftr::DFT<A>::run(xb);
+    __syncthreads();
+    if (act) {
+        const double half = 0.5;
+        // the partner Z_{n-p} comes from the lane's other row, except for s = 0 (rows 0 and
+        // B/2, each its own partner); blended as f*u + (1-f)*v, exact for finite values (a
+        // select here is turned into an indexed load from scratch memory)
+        const double f = (s == 0) ? 1.0 : 0.0, g = 1.0 - f;
+        auto blend = [&](const C& u, const C& v) -> C {
+            return make_double2(__builtin_fma(f, u.x, g * v.x), __builtin_fma(f, u.y, g * v.y));
+        };
+#pragma unroll
+        for (int p1 = 0; p1 < A; ++p1) {
+            const C za = xa[p1];
+            const C ma = blend(xa[(A - p1) % A], xb[A - 1 - p1]);
+            st(lp, pa + B * p1, half * (za.x + ma.x - za.y + ma.y), half * (za.x - ma.x + za.y + ma.y));
+            const C zb = xb[p1];
+            const C mb = blend(xb[A - 1 - p1], xa[A - 1 - p1]);
+            st(lp, pb + B * p1, half * (zb.x + mb.x - zb.y + mb.y), half * (zb.x - mb.x + zb.y + mb.y));
+        }
+    }
+    __syncthreads();
+}
+
+// ZFIRST (the source's forward transform): z then x, from the field z.spec[c] (FP64, the
+// interior rows) into the spectral buffer x.spec[c]. Otherwise (the inverse of the omega and
+// psi modes): x then z, from x.spec[c] into the field z.u[c]. Block = (interior row j - 1,
+// instance * NC + component). FP64 only; no gate, no accumulation.
+template <int BX, int AX, int BZ, int AZ, bool ZFIRST, int NC, bool BATCH>
+__global__ __launch_bounds__(kPlaneThreads) void k_hxz_plane(Dims d, ZArgs zone,
+                                                           const ZArgs* __restrict__ ztab,
+                                                           HxArgs xone,
+                                                           const HxArgs* __restrict__ xtab) {
+    constexpr int NX = BX * AX, NZ = BZ * AZ, RS = NZ + kPlanePad;
+    constexpr int NV = NX * NZ / 2;                          // double2 values of the plane
+    constexpr int NR = (NV + kPlaneThreads - 1) / kPlaneThreads;
+    __shared__ double P[NX * RS];
+    const int j = 1 + (int)blockIdx.x;
+    const int inst = BATCH ? (int)blockIdx.y / NC : 0;
+    const int c = (int)blockIdx.y - inst * NC;
+    const ZArgs& za = inst_args<BATCH>(zone, ztab, inst);
+    const HxArgs& xa = inst_args<BATCH>(xone, xtab, inst);
+    const Gl<double>* in = (const Gl<double>*)(ZFIRST ? pick(za.spec, c) : pick(xa.spec, c));
+    Gl<double>* out = (Gl<double>*)(ZFIRST ? pick(xa.spec, c) : pick(za.u, c));
+    const size_t pstride = (size_t)d.ny * NZ;
+    const size_t row0 = (size_t)j * NZ;
+    // the plane: x-row i at P[i * RS], 16-byte loads (one row holds NZ / 2 of them)
+    double2 v[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int t = min((int)threadIdx.x + r * kPlaneThreads, NV - 1);
+        const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+        v[r] = ldg2(in + i * pstride + row0 + 2 * k2);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int t = threadIdx.x + r * kPlaneThreads;
+        if (t < NV) {
+            const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+            *reinterpret_cast<double2*>(&P[i * RS + 2 * k2]) = v[r];
+        }
+    }
+    __syncthreads();
+    const Gl<tw2v>* twz = (const Gl<tw2v>*)za.tw;
+    const Gl<tw2v>* twx = (const Gl<tw2v>*)xa.tw;
+    if constexpr (ZFIRST) {
+        plane_hartley<BZ, AZ, NX / 2, RS, true>(P, twz);
+        plane_hartley<BX, AX, NZ / 2, RS, false>(P, twx);
+    } else {
+        plane_hartley<BX, AX, NZ / 2, RS, false>(P, twx);
+        plane_hartley<BZ, AZ, NX / 2, RS, true>(P, twz);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int t = threadIdx.x + r * kPlaneThreads;
+        if (t < NV) {
+            const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+            const double2 w = *reinterpret_cast<const double2*>(&P[i * RS + 2 * k2]);
+            stc<double>(out + i * pstride + row0 + 2 * k2, w.x, w.y);
+        }
+    }
+}
+
 // Rows per block of the z kernels: 2 * (kTileElems / nz), i.e. kTileElems / nz complex lines.
 int z_rows_per_block(const Dims& d) {
     int lines = kTileElems / d.nz;
@@ -752,6 +892,49 @@ void launch_hx(hipStream_t s, const Dims& d, const FftPlan& px, bool f32, int nc
         dht_x_t<float>(s, d, px, a, ncomp);
     else
         dht_x_t<double>(s, d, px, a, ncomp);
+}
+
+bool plane_fits(const Dims& d) {
+    int bx, ax, bz, az;
+    two_pass_shape(d.nx, bx, ax);
+    two_pass_shape(d.nz, bz, az);
+    return d.nx == d.nz && bx > 0 && bz > 0 && d.nx <= 128 && d.nx >= 32;
+}
+
+bool launch_plane(hipStream_t s, const Dims& d, bool zfirst, int ncomp, const Over<ZArgs>& z,
+                  const Over<HxArgs>& x) {
+    if (!plane_fits(d) || (ncomp != 3 && ncomp != 6)) return false;
+    if (z.one.gate || z.one.add || x.one.gate) return false;
+    const bool batch = z.tab != nullptr;
+    if (batch != (x.tab != nullptr) || (batch && z.n != x.n)) return false;
+    const unsigned ni = batch ? (unsigned)z.n : 1u;
+    const dim3 g((unsigned)d.M, (unsigned)ncomp * ni);
+    auto go = [&](auto kf3, auto kf6, auto kt3, auto kt6) {
+        if (batch) {
+            if (ncomp == 3) launch_kernel(kt3, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
+            else launch_kernel(kt6, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
+        } else {
+            if (ncomp == 3) launch_kernel(kf3, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
+            else launch_kernel(kf6, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
+        }
+    };
+#define VS_PLANE(n, b, a_)                                                                       \
+    if (d.nx == n) {                                                                             \
+        if (zfirst)                                                                              \
+            go(k_hxz_plane<b, a_, b, a_, true, 3, false>, k_hxz_plane<b, a_, b, a_, true, 6, false>, \
+               k_hxz_plane<b, a_, b, a_, true, 3, true>, k_hxz_plane<b, a_, b, a_, true, 6, true>); \
+        else                                                                                     \
+            go(k_hxz_plane<b, a_, b, a_, false, 3, false>, k_hxz_plane<b, a_, b, a_, false, 6, false>, \
+               k_hxz_plane<b, a_, b, a_, false, 3, true>, k_hxz_plane<b, a_, b, a_, false, 6, true>); \
+        return true;                                                                             \
+    }
+    VS_PLANE(32, 8, 4)
+    VS_PLANE(48, 16, 3)
+    VS_PLANE(64, 16, 4)
+    VS_PLANE(96, 16, 6)
+    VS_PLANE(128, 16, 8)
+#undef VS_PLANE
+    return false;
 }
 
 void launch_hz(hipStream_t s, const Dims& d, const FftPlan& pz, bool f32, int ncomp,

@@ -44,14 +44,15 @@ enum KClass {
     K_ADVANCE, K_VA_PARTIALS, K_MU, K_SOURCE, K_RHS_Z_OMEGA, K_RHS_Z_PSI,
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
     K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_DHT_X_PAIR, K_DHT_Z_OUT_PAIR,
-    K_RHS_FLOW, K_ADJ_ADVECT, K_ADJ_WALLS, K_ADJ_SOURCE, K_ADJ_MU1, K_ADJ_MU2, K_NCLASS
+    K_RHS_FLOW, K_ADJ_ADVECT, K_ADJ_WALLS, K_ADJ_SOURCE, K_ADJ_MU1, K_ADJ_MU2, K_ADJ_SUMS, K_DHT_ZX,
+    K_DHT_XZ_PAIR, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
     "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
     "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
     "resid_norm_flow", "dht_x_pair", "dht_z_out_pair", "rhs_flow", "adj_advect",
-    "adj_wall_couple", "adj_source", "adj_mu1", "adj_mu2"};
+    "adj_wall_couple", "adj_source", "adj_mu1", "adj_mu2", "adj_sums", "dht_zx", "dht_xz_pair"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -236,6 +237,12 @@ struct vs_state {
     bool prof_on = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
     std::vector<hipEvent_t> ev_pool;
+    // pinned host copy of the scalars and status words (one transfer per synchronisation)
+    char* host_stat = nullptr;
+
+    ~vs_state() {
+        if (host_stat) (void)hipHostFree(host_stat);
+    }
 
     double C_b() const { return p.bend_scale * 3.0 * std::sqrt(2.0) * p.kappa / (8.0 * p.eps * p.eps * p.eps); }
 };
@@ -268,7 +275,7 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<TuneKey, Tuning>> g_tune;
-constexpr Tuning kDefaultTuning{4, 1024, 1024, 0, 0, 8};
+constexpr Tuning kDefaultTuning{4, 1024, 1024, 0, 0, 8, 0};
 
 void set_tuning(const Dims& d, const Tuning& t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -601,12 +608,22 @@ bool enqueue_flow_args(const StepCfg& c, const StepArgs& A, bool defer, int max_
     }
     // The direct transform reads S alone: the omega wall terms go into mode (0, 0) of the
     // tridiagonal solve.
-    timed_cfg(c, K_RHS_Z_OMEGA, [&] { launch_hz(c.st, c.d, c.pz, false, 3, A.zfwd); });
-    timed_cfg(c, K_DHT_X, [&] { launch_hx(c.st, c.d, c.px, false, 3, A.hx3); });
+    // With the plane form (tuned, n_x = n_z up to 128) each direction is one pass.
+    const bool plane = tuning_for(c.d).plane && plane_fits(c.d);
+    if (plane) {
+        timed_cfg(c, K_DHT_ZX, [&] { launch_plane(c.st, c.d, true, 3, A.zfwd, A.hx3); });
+    } else {
+        timed_cfg(c, K_RHS_Z_OMEGA, [&] { launch_hz(c.st, c.d, c.pz, false, 3, A.zfwd); });
+        timed_cfg(c, K_DHT_X, [&] { launch_hx(c.st, c.d, c.px, false, 3, A.hx3); });
+    }
     timed_cfg(c, K_TRIDIAG_PAIR, [&] { launch_tri_pair(c.st, c.d, false, false, A.tri); });
     // both fields back to physical space, six components per launch
-    timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, false, 6, A.hx6); });
-    timed_cfg(c, K_DHT_Z_OUT_PAIR, [&] { launch_hz(c.st, c.d, c.pz, false, 6, A.zout6); });
+    if (plane) {
+        timed_cfg(c, K_DHT_XZ_PAIR, [&] { launch_plane(c.st, c.d, false, 6, A.zout6, A.hx6); });
+    } else {
+        timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, false, 6, A.hx6); });
+        timed_cfg(c, K_DHT_Z_OUT_PAIR, [&] { launch_hz(c.st, c.d, c.pz, false, 6, A.zout6); });
+    }
     if (max_cycles > 1) return false;
     // both residuals in one pass, then both checks in one launch, or, when another step
     // follows in the same call, in the first block of its advance kernel
@@ -730,12 +747,23 @@ void set_wall_state(vs_state* S, const vs_walls& w, const std::vector<double>& p
 }
 
 // Reads the device status and scalars after a synchronisation; maps flags to a status.
-vs_status collect(vs_state* S, const char* what) {
+// Waits for S's stream and copies the scalars and status words (adjacent in the workspace) to
+// the host in one transfer through the pinned buffer.
+vs_status read_status(vs_state* S, double* sc, int* ist) {
+    const size_t ioff = (size_t)((char*)S->istat - (char*)S->scal);
+    const size_t span = ioff + IS_NSTAT * sizeof(int);
+    HIP_TRY(hipMemcpyAsync(S->host_stat, S->scal, span, hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
+    if (sc) std::memcpy(sc, S->host_stat, SC_NSCAL * sizeof(double));
+    if (ist) std::memcpy(ist, S->host_stat + ioff, IS_NSTAT * sizeof(int));
+    return VS_OK;
+}
+
+vs_status collect(vs_state* S, const char* what) {
     int ist[IS_NSTAT];
     double sc[SC_NSCAL];
-    HIP_TRY(hipMemcpy(ist, S->istat, sizeof ist, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    const vs_status rs = read_status(S, sc, ist);
+    if (rs != VS_OK) return rs;
     S->gamma_host = sc[SC_GAMMA];
     S->last_relres = sc[SC_RELRES_MAX];
     S->last_cycles = ist[IS_CYCLES];
@@ -852,6 +880,9 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
         if (e_ != hipSuccess)                                                               \
             return bail(fail(VS_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)));    \
     } while (0)
+    INIT_TRY(hipHostMalloc((void**)&S->host_stat,
+                           (size_t)((char*)S->istat - (char*)S->scal) + IS_NSTAT * sizeof(int),
+                           hipHostMallocDefault));
     INIT_TRY(hipMemcpyAsync(S->twx, twx.data(), twx.size() * sizeof(double2), hipMemcpyHostToDevice, S->stream));
     INIT_TRY(hipMemcpyAsync(S->twz, twz.data(), twz.size() * sizeof(double2), hipMemcpyHostToDevice, S->stream));
     INIT_TRY(hipMemcpyAsync(S->tri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice, S->stream));
@@ -888,11 +919,10 @@ vs_status vs_poisson_solve(vs_state* S, const double* f, double* u, double rtol,
     double* const uu[3] = {u, nullptr, nullptr};
     enqueue_solve(S, r, uu, 1, rtol, max_cycles, TAG_FIELD);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(S->stream));
     int ist[IS_NSTAT];
     double sc[SC_NSCAL];
-    HIP_TRY(hipMemcpy(ist, S->istat, sizeof ist, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    const vs_status rs = read_status(S, sc, ist);
+    if (rs != VS_OK) return rs;
     if (cycles_out) *cycles_out = ist[IS_CYCLES];
     if (relres_out) *relres_out = sc[SC_RELRES_LAST];
     if (ist[IS_FLAGS] & ST_NONFINITE) return fail(VS_E_NONFINITE, "vs_poisson_solve: non-finite residual");
@@ -1081,15 +1111,19 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
     double* const q[3] = {S->src[0], S->src[1], S->src[2]};
     double* const u1[3] = {(double*)S->spec2[0], (double*)S->spec2[1], (double*)S->spec2[2]};
     const double* const cps[3] = {S->ps[0], S->ps[1], S->ps[2]};
-    timed(S, K_RESET, [&] { launch_reset_stats(st, S->scal, S->istat); });
+    // the one-pass solve below writes the two spectral sets inside only: their wall rows are
+    // zeroed by the advection kernel, which also clears the status words
+    double* const w6[6] = {(double*)S->spec[0], (double*)S->spec[1], (double*)S->spec[2],
+                           (double*)S->spec2[0], (double*)S->spec2[1], (double*)S->spec2[2]};
     // advection, L_h mu and lambda_V terms; q = psi_bar
     timed(S, K_ADJ_ADVECT, [&] {
         launch_adj_advect(st, d, adj_next, phi, cps, dt, S->p.mobility, S->vz_lo, S->vz_hi,
-                          adj_prev, mubar, q, S->part, S->scal);
+                          adj_prev, mubar, q, S->part, S->scal, S->istat, mc == 1 ? w6 : nullptr);
     });
     // psi_int = P(-omega_int; psi walls): first adjoint solve, homogeneous walls;
     // omega_int = P(S; omega walls): second adjoint solve, of -u1, giving S_bar
     double* sb[3] = {q[0], q[1], q[2]};          // S_bar
+    const double* u1w[3] = {nullptr, nullptr, nullptr};   // u1 for the source kernel's wall term
     if (mc == 1) {
         // one verified pass, as the forward flow solve: q transformed once, u1's modes solved
         // and S_bar's from them in the pair kernel (zero walls), both inverse-transformed in
@@ -1097,24 +1131,51 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
         // against q and -u1 in one pass and one check
         double* const us[3] = {(double*)S->spec[0], (double*)S->spec[1], (double*)S->spec[2]};
         double* const ss[3] = {(double*)S->spec2[0], (double*)S->spec2[1], (double*)S->spec2[2]};
-        double* const w6[6] = {us[0], us[1], us[2], ss[0], ss[1], ss[2]};
-        timed(S, K_FILL, [&] { launch_zero_walls(st, d, w6, 6); });
         const double* const qc[3] = {q[0], q[1], q[2]};
-        timed(S, K_RHS_Z_FIELD, [&] { launch_dht_z_fwd(st, d, S->pz, S->twz, qc, S->spec, 3); });
-        timed(S, K_DHT_X, [&] { launch_dht_x(st, d, S->px, S->twx, S->spec, 3, false, nullptr); });
+        // the transforms as in the forward flow pass: one plane pass per direction when tuned so
+        const bool plane = tuning_for(d).plane && plane_fits(d);
+        ZArgs zf{};
+        HxArgs xf{};
+        ZArgs zi{};
+        HxArgs xi{};
+        for (int c = 0; c < 3; ++c) {
+            zf.spec[c] = (void*)q[c];
+            zf.u[c] = (double*)S->spec[c];
+            xf.spec[c] = S->spec[c];
+        }
+        for (int c = 0; c < 6; ++c) {
+            void* sp = c < 3 ? S->spec[c] : S->spec2[c - 3];
+            zi.spec[c] = sp;
+            zi.u[c] = (double*)sp;
+            xi.spec[c] = sp;
+        }
+        zf.tw = zi.tw = S->twz;
+        xf.tw = xi.tw = S->twx;
+        if (plane) {
+            timed(S, K_DHT_ZX, [&] { launch_plane(st, d, true, 3, over_one(zf), over_one(xf)); });
+        } else {
+            timed(S, K_RHS_Z_FIELD, [&] { launch_dht_z_fwd(st, d, S->pz, S->twz, qc, S->spec, 3); });
+            timed(S, K_DHT_X, [&] { launch_dht_x(st, d, S->px, S->twx, S->spec, 3, false, nullptr); });
+        }
         const double zero[3] = {0.0, 0.0, 0.0};
         timed(S, K_TRIDIAG_PAIR, [&] {
             launch_tridiag_pair(st, d, S->tri, nullptr, S->spec, S->spec2, zero, zero, zero, zero, false);
         });
         void* const sp6[6] = {S->spec[0], S->spec[1], S->spec[2], S->spec2[0], S->spec2[1], S->spec2[2]};
-        timed(S, K_DHT_X_PAIR, [&] { launch_dht_x(st, d, S->px, S->twx, sp6, 6, false, nullptr); });
-        timed(S, K_DHT_Z_OUT_PAIR, [&] { launch_dht_z_out(st, d, S->pz, S->twz, sp6, w6, 6, 0, false, nullptr); });
+        if (plane) {
+            timed(S, K_DHT_XZ_PAIR, [&] { launch_plane(st, d, false, 6, over_one(zi), over_one(xi)); });
+        } else {
+            timed(S, K_DHT_X_PAIR, [&] { launch_dht_x(st, d, S->px, S->twx, sp6, 6, false, nullptr); });
+            timed(S, K_DHT_Z_OUT_PAIR, [&] { launch_dht_z_out(st, d, S->pz, S->twz, sp6, w6, 6, 0, false, nullptr); });
+        }
         const double* const cu[3] = {us[0], us[1], us[2]};
         const double* const cs[3] = {ss[0], ss[1], ss[2]};
         timed(S, K_RESID_FLOW, [&] { launch_resid_flow(st, d, cu, qc, cs, 0.0, S->part); });
         timed(S, K_CHECK, [&] { launch_check_flow(st, d, S->part, rtol, S->scal, S->istat); });
-        timed(S, K_ADJ_WALLS, [&] { launch_adj_wall_couple(st, d, us, S->ps, S->part, S->scal, SC_ADJ_PSIC); });
-        for (int c = 0; c < 3; ++c) sb[c] = ss[c];
+        for (int c = 0; c < 3; ++c) {
+            sb[c] = ss[c];
+            u1w[c] = us[c];
+        }
     } else {
         // the solve writes the interior; only the wall rows need zeros
         launch_zero_walls(st, d, u1, 3);
@@ -1122,33 +1183,41 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
         r1.mode = RHS_FIELD;
         for (int c = 0; c < 3; ++c) r1.f[c] = q[c];
         enqueue_solve(S, r1, u1, 3, rtol, mc, TAG_FIELD);
-        launch_adj_wall_couple(st, d, u1, S->ps, S->part, S->scal, SC_ADJ_PSIC);
+        timed(S, K_ADJ_WALLS, [&] { launch_adj_wall_couple(st, d, u1, S->ps, S->part, S->scal, SC_ADJ_PSIC); });
         launch_zero_walls(st, d, q, 3);
         RhsArgs r2{};
         r2.mode = RHS_NEGW;
         for (int c = 0; c < 3; ++c) r2.f[c] = u1[c];
         enqueue_solve(S, r2, q, 3, rtol, mc, TAG_FIELD);
     }
-    timed(S, K_ADJ_WALLS, [&] { launch_adj_wall_couple(st, d, sb, S->om, S->part, S->scal, SC_ADJ_OMC); });
-    // S = (1/eta) D phi x D mu
-    timed(S, K_ADJ_SOURCE, [&] { launch_adj_source(st, d, phi, S->mu, sb, 1.0 / S->p.eta, adj_prev, mubar); });
+    // S = (1/eta) D phi x D mu; the wall couplings of the adjoint solves as block partials
+    const double* const cpsw[3] = {S->ps[0], S->ps[1], S->ps[2]};
+    const double* const comw[3] = {S->om[0], S->om[1], S->om[2]};
+    timed(S, K_ADJ_SOURCE, [&] {
+        launch_adj_source(st, d, phi, S->mu, sb, 1.0 / S->p.eta, adj_prev, mubar,
+                          u1w[0] ? u1w : nullptr, cpsw, comw, S->part);
+    });
     // mu(phi)
     double* gbar = (double*)S->spec[0];
     const double dCb = S->p.bend_scale * 3.0 * std::sqrt(2.0) / (8.0 * S->p.eps * S->p.eps * S->p.eps);
     if (S->p.model == VS_BENDING)
         timed(S, K_ADJ_MU1, [&] {
-            launch_adj_mu1(st, d, phi, mubar, S->C_b(), dCb, S->p.eps, gbar, S->part, S->scal);
+            launch_adj_mu1(st, d, phi, mubar, S->C_b(), dCb, S->p.eps, gbar, S->part);
         });
+    // the wall couplings (slot 0 unless the general path summed it already) and, for bending,
+    // the kappa and gamma_A terms
+    timed(S, K_ADJ_SUMS, [&] {
+        launch_adj_sums(st, d, S->part, u1w[0] ? 0 : 1, S->p.model == VS_BENDING ? 4 : 2, S->scal);
+    });
     timed(S, K_ADJ_MU2, [&] {
         launch_adj_mu2(st, d, phi, mubar, gbar, S->scal, S->p.model, S->C_b(), S->p.eps, S->p.sigma,
                        dt, S->p.mobility, S->p.rate_V, S->p.k_A, adj_prev);
     });
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(st));
     int ist[IS_NSTAT];
     double sc[SC_NSCAL];
-    HIP_TRY(hipMemcpy(ist, S->istat, sizeof ist, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    const vs_status rs = read_status(S, sc, ist);
+    if (rs != VS_OK) return rs;
     if (ist[IS_FLAGS] & ST_NONFINITE) return fail(VS_E_NONFINITE, "vs_grad_step: non-finite residual");
     if (ist[IS_FLAGS] & ST_NOCONV)
         return fail(VS_E_NOCONV, "vs_grad_step: an adjoint Poisson solve missed rtol %.3g", rtol);
@@ -1190,9 +1259,9 @@ vs_status vs_diagnostics(vs_state* S, double* sigma_t, double out[6]) {
     launch_diagnostics(S->stream, d, S->phi[S->cur], S->om, S->ps, S->prof, S->vz_lo, S->vz_hi,
                        S->p.eta, S->p.model, S->p.eps, S->p.sigma, sigma_t, S->part, S->scal);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(S->stream));
     double sc[SC_NSCAL];
-    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    const vs_status rs = read_status(S, sc, nullptr);
+    if (rs != VS_OK) return rs;
     const double h3 = d.h * d.h * d.h;
     const double cF = 3.0 * std::sqrt(2.0) * S->p.kappa / (8.0 * S->p.eps * S->p.eps * S->p.eps);
     out[0] = h3 * sc[SC_DG_OMEGA];
@@ -1223,8 +1292,8 @@ vs_status vs_get_scalars(vs_state* S, double out[VS_NSCALARS]) {
     if (!S) return fail(VS_E_STATE, "state is NULL");
     if (!out) return fail(VS_E_ARG, "out is NULL");
     double sc[SC_NSCAL];
-    HIP_TRY(hipStreamSynchronize(S->stream));
-    HIP_TRY(hipMemcpy(sc, S->scal, sizeof sc, hipMemcpyDeviceToHost));
+    const vs_status rs = read_status(S, sc, nullptr);
+    if (rs != VS_OK) return rs;
     out[VS_S_V] = sc[SC_V];
     out[VS_S_A] = sc[SC_A];
     out[VS_S_V0] = sc[SC_V0];
@@ -1458,6 +1527,24 @@ vs_status autotune_state(vs_state* S, Tuning* picked) {
         pick(&t.seg_alt, {0, 1}, [&] {
             launch_tri_pair(c.st, c.d, S->f32, S->f32, S->f32 ? A.trc[0] : A.tri);
         });
+    // the transforms of the FP64 flow pass: two 1D passes per direction, or one plane pass;
+    // timed with the inverse writing back into the spectral buffers it reads (each block, or
+    // the plane pass's each row, reads all it transforms before it writes), so no field changes
+    if (!S->f32 && fused_flow_ok(S->d) && plane_fits(S->d)) {
+        Over<ZArgs> zin = A.zout6;
+        for (int q = 0; q < 6; ++q) zin.one.u[q] = (double*)A.hx6.one.spec[q];
+        pick(&t.plane, {0, 1}, [&] {
+            if (t.plane) {
+                launch_plane(c.st, c.d, true, 3, A.zfwd, A.hx3);
+                launch_plane(c.st, c.d, false, 6, zin, A.hx6);
+            } else {
+                launch_hz(c.st, c.d, c.pz, false, 3, A.zfwd);
+                launch_hx(c.st, c.d, c.px, false, 3, A.hx3);
+                launch_hx(c.st, c.d, c.px, false, 6, A.hx6);
+                launch_hz(c.st, c.d, c.pz, false, 6, zin);
+            }
+        });
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return fail(VS_E_HIP, "autotune timing failed: %s", hipGetErrorString(err));
@@ -1471,11 +1558,11 @@ vs_status autotune_state(vs_state* S, Tuning* picked) {
 
 }  // namespace
 
-extern "C" vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[6]) {
+extern "C" vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[7]) {
     vs_status st = check_grid(grid);
     if (st != VS_OK) return st;
     if (!shapes) return fail(VS_E_ARG, "shapes is NULL");
-    const Tuning t{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5]};
+    const Tuning t{shapes[0], shapes[1], shapes[2], shapes[3], shapes[4], shapes[5], shapes[6]};
     if (t.adv_slab < 1 || t.adv_slab > 64) return fail(VS_E_ARG, "adv_slab must be in [1, 64]");
     if (t.va_maxb < 64 || t.va_maxb > kMaxPartialBlocks)
         return fail(VS_E_ARG, "va_maxb must be in [64, %d]", kMaxPartialBlocks);
@@ -1484,12 +1571,13 @@ extern "C" vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t sha
     if (t.seg_alt != 0 && t.seg_alt != 1) return fail(VS_E_ARG, "seg_alt must be 0 or 1");
     if (t.mu_kind < 0 || t.mu_kind > 2) return fail(VS_E_ARG, "mu_kind must be 0, 1 or 2");
     if (t.mu_ni < 1 || t.mu_ni > 64) return fail(VS_E_ARG, "mu_ni must be in [1, 64]");
+    if (t.plane != 0 && t.plane != 1) return fail(VS_E_ARG, "plane must be 0 or 1");
     Dims d{grid->nx, grid->ny, grid->nz, grid->ny - 2, grid->h, 0.0, 0.0};
     set_tuning(d, t);
     return VS_OK;
 }
 
-extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[6]) {
+extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[7]) {
     if (!S) return fail(VS_E_STATE, "state is NULL");
     if (S->prof_on) return fail(VS_E_ARG, "vs_autotune: switch the event timer off first");
     Tuning t{};
@@ -1502,6 +1590,7 @@ extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[6]) {
         picked[3] = t.seg_alt;
         picked[4] = t.mu_kind;
         picked[5] = t.mu_ni;
+        picked[6] = t.plane;
     }
     return VS_OK;
 }

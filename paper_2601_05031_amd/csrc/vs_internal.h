@@ -129,6 +129,7 @@ struct Tuning {
     int seg_alt;    // 0: the default segment layout of the tridiagonal solves, 1: the other
     int mu_kind;    // chemical potential: 0 LDS tiles; 1, 2 register marching, rows per wave
     int mu_ni;      // x-planes per wave of the register-marching form
+    int plane;      // 1: both transform directions of the FP64 flow pass in one plane pass
 };
 Tuning tuning_for(const Dims& d);
 bool seg_has_alt(int M);   // the pair solves of M interior rows have a second layout
@@ -275,6 +276,14 @@ struct RhsFlowArgs {
 // True when both periodic lengths have two-pass transforms and M a segmented solve: the forms
 // the fused flow pass, the refined mode's fused cycle and batched launches use.
 bool fused_flow_ok(const Dims& d);
+// Both transform directions in one pass per (interior row, component), the (x, z) plane in
+// LDS: zfirst, z then x from z.spec into x.spec (the source's forward transform); otherwise x
+// then z from x.spec into z.u (the inverse of the omega and psi modes). FP64 spectral data,
+// n_x = n_z in {32, 48, 64, 96, 128}, no gate or accumulation; returns false (nothing
+// launched) otherwise.
+bool plane_fits(const Dims& d);
+bool launch_plane(hipStream_t s, const Dims& d, bool zfirst, int ncomp, const Over<ZArgs>& z,
+                  const Over<HxArgs>& x);
 void launch_hz(hipStream_t s, const Dims& d, const FftPlan& pz, bool f32, int ncomp,
                const Over<ZArgs>& a);
 void launch_hx(hipStream_t s, const Dims& d, const FftPlan& px, bool f32, int ncomp,
@@ -323,23 +332,37 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
 
 // ---------------------------------------------------------------- reverse step (k_adjoint.hip)
 // a = dL/dphi^{n+1}; writes phibar (dL/dphi^n, partial), mubar and psibar(3); gathers
-// SC_ADJ_SUM_A, SC_ADJ_WALLV, SC_ADJ_PSIW.
+// SC_ADJ_SUM_A, SC_ADJ_WALLV, SC_ADJ_PSIW. Also clears the status words and residual scalars
+// (as launch_reset_stats) and, if zero_walls is given, the wall rows of those (non-NULL) fields.
 void launch_adj_advect(hipStream_t s, const Dims& d, const double* a, const double* phi,
                        const double* const psi[3], double dt, double mobility, double vz_lo,
                        double vz_hi, double* phibar, double* mubar, double* const psibar[3],
-                       double* part, double* scal);
+                       double* part, double* scal, int* istat, double* const zero_walls[6]);
 // scal[slot] = -(1/h^2) sum_c sum_{i,k} [u_c(i,1,k) wall_c(i,0,k) + u_c(i,M,k) wall_c(i,ny-1,k)]
 void launch_adj_wall_couple(hipStream_t s, const Dims& d, double* const u[3],
                             double* const wall[3], double* part, double* scal, int slot);
+// Wall couplings carried by the source's reverse kernel (u may be NULL: no slot-0 term).
+struct WallPairs {
+    const double* u[3];    // u1 of the first adjoint solve
+    const double* uw[3];   // psi (its wall planes)
+    const double* sw[3];   // omega (its wall planes), against Sbar
+};
 // phibar += sum_c D_c^T abar_c, mubar += sum_c D_c^T bbar_c with abar = (1/eta) D mu x Sbar,
-// bbar = (1/eta) Sbar x D phi on the interior rows.
+// bbar = (1/eta) Sbar x D phi on the interior rows; block partials: slot 0 the wall coupling of
+// u1 (if given) with the psi walls, slot 1 that of Sbar with the omega walls (each as
+// launch_adj_wall_couple defines it).
 void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
-                       double* const sbar[3], double inv_eta, double* phibar, double* mubar);
-// Bending: gbar = C_b [(3 phi^2 - 1) mubar - eps^2 L^T mubar]; gathers SC_ADJ_KAPPA,
-// SC_ADJ_GAMMA.
+                       double* const sbar[3], double inv_eta, double* phibar, double* mubar,
+                       const double* const u1[3], const double* const psi_walls[3],
+                       const double* const om_walls[3], double* part);
+// Bending: gbar = C_b [(3 phi^2 - 1) mubar - eps^2 L^T mubar]; block partials of
+// SC_ADJ_KAPPA (slot 2) and SC_ADJ_GAMMA (slot 3), on the block layout of launch_adj_source.
 void launch_adj_mu1(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
-                    double C_b, double dCb_dkappa, double eps, double* gbar, double* part,
-                    double* scal);
+                    double C_b, double dCb_dkappa, double eps, double* gbar, double* part);
+// scal[SC_ADJ_PSIC + q] = sum of the partial slot q over the blocks of launch_adj_source and
+// launch_adj_mu1, for q in [first, nslots).
+void launch_adj_sums(hipStream_t s, const Dims& d, const double* part, int first, int nslots,
+                     double* scal);
 // Diagnostics (k_diag.hip): sigma_t (device field or NULL) and SC_DG_* sums.
 void launch_diagnostics(hipStream_t s, const Dims& d, const double* phi, double* const omega[3],
                         double* const psi[3], const double* prof, double vz_lo, double vz_hi,

@@ -132,13 +132,13 @@ def workspace_bytes(grid, params: VsParams) -> int:
     return n.value
 
 
-SHAPE_KEYS = ("adv_slab", "va_maxb", "res_maxb", "seg_alt", "mu_kind", "mu_ni")
+SHAPE_KEYS = ("adv_slab", "va_maxb", "res_maxb", "seg_alt", "mu_kind", "mu_ni", "plane")
 
 
 def set_launch_shapes(grid, shapes: dict):
     """vs_set_launch_shapes: launch shapes for every state of this grid (nx, ny, nz[, h])."""
     g = VsGrid(grid[0], grid[1], grid[2], float(grid[3]) if len(grid) > 3 else 1.0)
-    arr = (ctypes.c_int32 * 6)(*[int(shapes[k]) for k in SHAPE_KEYS])
+    arr = (ctypes.c_int32 * 7)(*[int(shapes[k]) for k in SHAPE_KEYS])
     _check(lib().vs_set_launch_shapes(ctypes.byref(g), arr), "vs_set_launch_shapes")
 
 
@@ -296,7 +296,7 @@ class Solver:
     # ---------------------------------------------------------------- measurement
     def autotune(self) -> dict:
         """vs_autotune: pick this grid's launch shapes by timing them on this state's data."""
-        out = (ctypes.c_int32 * 6)()
+        out = (ctypes.c_int32 * 7)()
         _check(lib().vs_autotune(self._st, out), "vs_autotune")
         return dict(zip(SHAPE_KEYS, list(out)))
 

@@ -47,18 +47,19 @@ def test_batch_instances_recipe():
 
 # (fp64, 1) and (fp32_refined, 3): every kernel launched once per grid class over the device
 # argument tables; (fp64, 3): FP64 with correction cycles, stepped instance by instance inside
-# the graph
-@pytest.mark.parametrize("precision,mc", [("fp64", 1), ("fp64", 3), ("fp32_refined", 3)])
-def test_batch_bitwise_equals_single_instances(precision, mc):
+# the graph; plane = 1: the FP64 transforms as plane passes over the tables
+@pytest.mark.parametrize("precision,mc,plane", [("fp64", 1, 0), ("fp64", 1, 1), ("fp64", 3, 1),
+                                                ("fp32_refined", 3, 0)])
+def test_batch_bitwise_equals_single_instances(precision, mc, plane):
     ws = [w.with_(max_cycles=mc) for w in small_instances(5)]
     nsteps = 4
-    say(f"case batch-vs-single precision={precision} max_cycles={mc} n={len(ws)} "
+    say(f"case batch-vs-single precision={precision} max_cycles={mc} plane={plane} n={len(ws)} "
         f"grids={[w.grid.nx for w in ws]} seeds={[w.seed for w in ws]} nsteps={nsteps}")
     # the batch tunes the launch shapes of every grid it has not seen (vs_autotune); bitwise
     # equality needs the same shapes (block partial layouts) on both sides: fix them first
     for w in ws:
         V.set_launch_shapes(w.grid.shape + (w.grid.h,), dict(adv_slab=2, va_maxb=512, res_maxb=2048,
-                                                             seg_alt=1, mu_kind=0, mu_ni=8))
+                                                             seg_alt=1, mu_kind=0, mu_ni=8, plane=plane))
     singles = []
     for w in ws:
         s = P.solver_for(w, precision=precision)
