@@ -265,6 +265,7 @@ def adjoint_run(P, torch, nsteps: int, checkpoint_every: int = 10) -> dict:
     w = workload("adjoint96", max_cycles=1)   # one verified cycle per solve, as the headline
     N = w.grid.N
     st = P.solver_for(w.with_(kappa=1.5, u0=1.2 * w.u0))
+    tuning = st.autotune()   # launch shapes of the 96^3 grid, for the forward and reverse steps
     st.step(w.dt, nsteps)
     target = st.field("phi").clone()
     st.close()
@@ -309,7 +310,8 @@ def adjoint_run(P, torch, nsteps: int, checkpoint_every: int = 10) -> dict:
            "reverse_cell_updates_per_s": N / t_rev,
            "rollout_gradient_s": t_grad,
            "rollout_forward_steps": nsteps + recompute, "rollout_reverse_steps": nsteps,
-           "loss": L, "dL_dkappa": kb, "dL_dscale": sb, "reverse_kernels": rev_kernels}
+           "loss": L, "dL_dkappa": kb, "dL_dscale": sb, "reverse_kernels": rev_kernels,
+           "autotuned": tuning}
     print(f"bench: adjoint96 forward {1e3 * t_fwd / nsteps:.3f} ms/step, reverse "
           f"{1e3 * t_rev:.3f} ms/step, rollout gradient of {nsteps} steps {t_grad:.2f} s",
           file=sys.stderr, flush=True)

@@ -637,13 +637,13 @@ __global__ __launch_bounds__(64) void k_hz_out(Dims d, ZArgs one, const ZArgs* _
 // inputs of its (line pair, k1) with their twiddled B-point DFT, pass 2 reads the A values of
 // rows pa, pb, and after a barrier writes the Hartley values. z lines are pairs of x-rows
 // (i, i+1), x lines pairs of z-columns (q, q+1) as in k_hx.
-constexpr int kPlaneThreads = 512;
 constexpr int kPlanePad = 2;
+constexpr int kPlaneThreads = 512;
 
 // One 1D Hartley transform of every line pair of the plane. ROWS: lines are x-rows (element m
 // at P[row * RS + m]); otherwise z-columns (element m at P[m * RS + col]).
 template <int B, int A, int NLP, int RS, bool ROWS>
-__device__ __forceinline__ void plane_hartley(double* __restrict__ P, const Gl<tw2v>* __restrict__ tw) {
+__device__ __forceinline__ void plane_hartley(double* __restrict__ P, const tw2v* __restrict__ tw, int it) {
     using C = double2;
     static_assert(NLP * A <= kPlaneThreads && NLP * (B / 2) <= kPlaneThreads, "one item per lane");
     auto ld = [&](int lp, int m) -> C {
@@ -658,7 +658,6 @@ __device__ __forceinline__ void plane_hartley(double* __restrict__ P, const Gl<t
             *reinterpret_cast<double2*>(&P[m * RS + 2 * lp]) = make_double2(a, b);
         }
     };
-    const int it = threadIdx.x;
     // pass 1: B-point DFTs over k2, twiddled, back to the same positions k1 + A p2
     if (it < NLP * A) {
         const int lp = ROWS ? it / A : it % NLP;
@@ -712,60 +711,105 @@ __device__ __forceinline__ void plane_hartley(double* __restrict__ P, const Gl<t
 
 // ZFIRST (the source's forward transform): z then x, from the field z.spec[c] (FP64, the
 // interior rows) into the spectral buffer x.spec[c]. Otherwise (the inverse of the omega and
-// psi modes): x then z, from x.spec[c] into the field z.u[c]. Block = (interior row j - 1,
-// instance * NC + component). FP64 only; no gate, no accumulation.
+// psi modes): x then z, from x.spec[c] into the field z.u[c]. FP64 only; no gate, no
+// accumulation. Persistent: block b takes the planes b, b + G, ... (G = gridDim.x; plane
+// p = (instance * NC + component) * M + j - 1) and keeps the loads of its next plane in flight
+// in registers while it works on the current one: the first half (NR1 values per lane) during
+// the transforms, the rest during the stores (the whole plane beside a transform pass would
+// not fit in the registers). The twiddles sit in LDS, so no global load inside the transforms
+// waits behind the prefetch.
 template <int BX, int AX, int BZ, int AZ, bool ZFIRST, int NC, bool BATCH>
 __global__ __launch_bounds__(kPlaneThreads) void k_hxz_plane(Dims d, ZArgs zone,
                                                            const ZArgs* __restrict__ ztab,
                                                            HxArgs xone,
-                                                           const HxArgs* __restrict__ xtab) {
+                                                           const HxArgs* __restrict__ xtab,
+                                                           int nplanes) {
     constexpr int NX = BX * AX, NZ = BZ * AZ, RS = NZ + kPlanePad;
+    constexpr int NT = kPlaneThreads;
     constexpr int NV = NX * NZ / 2;                          // double2 values of the plane
-    constexpr int NR = (NV + kPlaneThreads - 1) / kPlaneThreads;
+    constexpr int NR = (NV + NT - 1) / NT;
     __shared__ double P[NX * RS];
-    const int j = 1 + (int)blockIdx.x;
-    const int inst = BATCH ? (int)blockIdx.y / NC : 0;
-    const int c = (int)blockIdx.y - inst * NC;
-    const ZArgs& za = inst_args<BATCH>(zone, ztab, inst);
-    const HxArgs& xa = inst_args<BATCH>(xone, xtab, inst);
-    const Gl<double>* in = (const Gl<double>*)(ZFIRST ? pick(za.spec, c) : pick(xa.spec, c));
-    Gl<double>* out = (Gl<double>*)(ZFIRST ? pick(xa.spec, c) : pick(za.u, c));
+    __shared__ tw2v TWX[NX], TWZ[NZ];
     const size_t pstride = (size_t)d.ny * NZ;
-    const size_t row0 = (size_t)j * NZ;
-    // the plane: x-row i at P[i * RS], 16-byte loads (one row holds NZ / 2 of them)
+    // twiddles of the two lengths (the same table for every instance)
+    {
+        const ZArgs& z0 = inst_args<BATCH>(zone, ztab, 0);
+        const HxArgs& x0 = inst_args<BATCH>(xone, xtab, 0);
+        const Gl<tw2v>* gz = (const Gl<tw2v>*)z0.tw;
+        const Gl<tw2v>* gx = (const Gl<tw2v>*)x0.tw;
+        for (int t = threadIdx.x; t < NX; t += NT) TWX[t] = gx[t];
+        for (int t = threadIdx.x; t < NZ; t += NT) TWZ[t] = gz[t];
+    }
+    // the source and destination of plane p
+    auto src_of = [&](int p) -> const Gl<double>* {
+        const int cg = p / d.M;
+        const int j = 1 + (p - cg * d.M);
+        const int inst = BATCH ? cg / NC : 0;
+        const int c = cg - inst * NC;
+        const ZArgs& za = inst_args<BATCH>(zone, ztab, inst);
+        const HxArgs& xa = inst_args<BATCH>(xone, xtab, inst);
+        return (const Gl<double>*)(ZFIRST ? pick(za.spec, c) : pick(xa.spec, c)) + (size_t)j * NZ;
+    };
+    auto dst_of = [&](int p) -> Gl<double>* {
+        const int cg = p / d.M;
+        const int j = 1 + (p - cg * d.M);
+        const int inst = BATCH ? cg / NC : 0;
+        const int c = cg - inst * NC;
+        const ZArgs& za = inst_args<BATCH>(zone, ztab, inst);
+        const HxArgs& xa = inst_args<BATCH>(xone, xtab, inst);
+        return (Gl<double>*)(ZFIRST ? pick(xa.spec, c) : pick(za.u, c)) + (size_t)j * NZ;
+    };
+    // x-row i of a plane at P[i * RS]; 16-byte values, NZ / 2 per row
+    constexpr int NR1 = (NR + 1) / 2;
     double2 v[NR];
+    auto load = [&](int p, int r0, int r1) {
+        const Gl<double>* in = src_of(p);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int t = min((int)threadIdx.x + r * kPlaneThreads, NV - 1);
-        const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
-        v[r] = ldg2(in + i * pstride + row0 + 2 * k2);
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int t = threadIdx.x + r * kPlaneThreads;
-        if (t < NV) {
+        for (int r = 0; r < NR; ++r) {
+            if (r < r0 || r >= r1) continue;
+            const int t = min((int)threadIdx.x + r * NT, NV - 1);
             const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
-            *reinterpret_cast<double2*>(&P[i * RS + 2 * k2]) = v[r];
+            v[r] = ldg2(in + i * pstride + 2 * k2);
         }
-    }
-    __syncthreads();
-    const Gl<tw2v>* twz = (const Gl<tw2v>*)za.tw;
-    const Gl<tw2v>* twx = (const Gl<tw2v>*)xa.tw;
-    if constexpr (ZFIRST) {
-        plane_hartley<BZ, AZ, NX / 2, RS, true>(P, twz);
-        plane_hartley<BX, AX, NZ / 2, RS, false>(P, twx);
-    } else {
-        plane_hartley<BX, AX, NZ / 2, RS, false>(P, twx);
-        plane_hartley<BZ, AZ, NX / 2, RS, true>(P, twz);
-    }
+    };
+    int p = blockIdx.x;
+    if (p < nplanes) load(p, 0, NR);
+    while (p < nplanes) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int t = threadIdx.x + r * kPlaneThreads;
-        if (t < NV) {
-            const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
-            const double2 w = *reinterpret_cast<const double2*>(&P[i * RS + 2 * k2]);
-            stc<double>(out + i * pstride + row0 + 2 * k2, w.x, w.y);
+        for (int r = 0; r < NR; ++r) {
+            const int t = threadIdx.x + r * NT;
+            if (t < NV) {
+                const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+                *reinterpret_cast<double2*>(&P[i * RS + 2 * k2]) = v[r];
+            }
         }
+        __syncthreads();
+        const int pn = p + (int)gridDim.x;
+        if (pn < nplanes) load(pn, 0, NR1);   // in flight while this plane is transformed
+        // the lane index through an empty asm statement: the transforms' LDS offsets are then
+        // recomputed in every round instead of held (and spilled) across the loop
+        int it = threadIdx.x;
+        asm volatile("" : "+v"(it));
+        if constexpr (ZFIRST) {
+            plane_hartley<BZ, AZ, NX / 2, RS, true>(P, TWZ, it);
+            plane_hartley<BX, AX, NZ / 2, RS, false>(P, TWX, it);
+        } else {
+            plane_hartley<BX, AX, NZ / 2, RS, false>(P, TWX, it);
+            plane_hartley<BZ, AZ, NX / 2, RS, true>(P, TWZ, it);
+        }
+        if (pn < nplanes) load(pn, NR1, NR);  // in flight while this plane is stored
+        Gl<double>* out = dst_of(p);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int t = threadIdx.x + r * NT;
+            if (t < NV) {
+                const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+                const double2 w = *reinterpret_cast<const double2*>(&P[i * RS + 2 * k2]);
+                stc<double>(out + i * pstride + 2 * k2, w.x, w.y);
+            }
+        }
+        __syncthreads();   // the plane's LDS is read out before the next one is written
+        p = pn;
     }
 }
 
@@ -894,6 +938,20 @@ void launch_hx(hipStream_t s, const Dims& d, const FftPlan& px, bool f32, int nc
         dht_x_t<double>(s, d, px, a, ncomp);
 }
 
+// Blocks of a persistent plane launch: the compute units of the current device.
+int plane_blocks() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            n = cus;
+        else
+            n = 256;
+    }
+    return n;
+}
+
 bool plane_fits(const Dims& d) {
     int bx, ax, bz, az;
     two_pass_shape(d.nx, bx, ax);
@@ -907,15 +965,18 @@ bool launch_plane(hipStream_t s, const Dims& d, bool zfirst, int ncomp, const Ov
     if (z.one.gate || z.one.add || x.one.gate) return false;
     const bool batch = z.tab != nullptr;
     if (batch != (x.tab != nullptr) || (batch && z.n != x.n)) return false;
-    const unsigned ni = batch ? (unsigned)z.n : 1u;
-    const dim3 g((unsigned)d.M, (unsigned)ncomp * ni);
+    const int ni = batch ? z.n : 1;
+    const int nplanes = d.M * ncomp * ni;
+    // persistent: one block per CU (the plane takes most of the LDS) up to the plane count
+    const dim3 g((unsigned)std::min(nplanes, plane_blocks()));
+    const dim3 blk((unsigned)kPlaneThreads);   // the kernels' launch bound
     auto go = [&](auto kf3, auto kf6, auto kt3, auto kt6) {
         if (batch) {
-            if (ncomp == 3) launch_kernel(kt3, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
-            else launch_kernel(kt6, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
+            if (ncomp == 3) launch_kernel(kt3, g, blk, 0, s, d, z.one, z.tab, x.one, x.tab, nplanes);
+            else launch_kernel(kt6, g, blk, 0, s, d, z.one, z.tab, x.one, x.tab, nplanes);
         } else {
-            if (ncomp == 3) launch_kernel(kf3, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
-            else launch_kernel(kf6, g, dim3(kPlaneThreads), 0, s, d, z.one, z.tab, x.one, x.tab);
+            if (ncomp == 3) launch_kernel(kf3, g, blk, 0, s, d, z.one, z.tab, x.one, x.tab, nplanes);
+            else launch_kernel(kf6, g, blk, 0, s, d, z.one, z.tab, x.one, x.tab, nplanes);
         }
     };
 #define VS_PLANE(n, b, a_)                                                                       \
