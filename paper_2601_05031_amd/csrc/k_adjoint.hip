@@ -12,18 +12,73 @@
 //     with the forward solver); their wall values enter rows 1 and ny-2 with weight 1/h^2;
 //   * V (SM eq. (37)), A (SM eq. (32)) and the penalty multipliers are differentiated directly.
 // The node loops are plain one-node-per-lane stencils (the reverse step is off the timed path).
+#include "flow_check.h"
 #include "stencil.h"
 
 namespace vs {
 
 namespace {
 
+// Block layout of the tiled reverse kernels (see adj_tile_block).
+struct AdjTile {
+    int tj;      // rows per tile: max(1, 512 / nz), at most ny
+    int ci;      // x-planes per slab
+    int ntile;   // tiles per plane
+    int nslab;   // slabs
+};
+// Block-partial slots of the reverse kernels: the wall couplings above the flow residual's
+// twelve (which the source kernel's block 0 may still be reading), kappa and gamma_A below.
+constexpr int kAdjSlotPsi = 12;
+constexpr int kAdjSlotOm = 13;
+constexpr int kAdjSlotKappa = 2;
+constexpr int kAdjSlotGamma = 3;
+static_assert(kAdjSlotOm < kPartialSlots, "partial slots");
+struct AdjCheck {
+    const double* part;   // residual partials of the two adjoint solves, or NULL: no check
+    int nblocks;
+    double rtol;
+    double* scal;
+    int* istat;
+};
+inline AdjTile adj_tile(const Dims& d) {
+    AdjTile t;
+    t.tj = d.nz >= 512 ? 1 : 512 / d.nz;
+    if (t.tj > d.ny) t.tj = d.ny;
+    t.ntile = (d.ny + t.tj - 1) / t.tj;
+    // slabs of four planes, longer where the block partials would not fit
+    t.ci = 4;
+    while (t.ntile * ((d.nx + t.ci - 1) / t.ci) > kMaxPartialBlocks && t.ci < d.nx) ++t.ci;
+    t.nslab = (d.nx + t.ci - 1) / t.ci;
+    return t;
+}
+
+// Tiles of the reverse node kernels: a block of kBlock lanes owns tj consecutive rows (all z)
+// of an x-slab of ci planes and walks the slab. Per plane, every quantity a node's outputs take
+// from its y and z neighbours is computed once per node of the tile and of its two halo rows and
+// exchanged through LDS; the x neighbours' come from registers kept from plane to plane. A lane
+// owns at most kAdjOwn nodes of the tile (tj nz <= kAdjOwn kBlock) and kAdjHalo halo nodes.
+constexpr int kAdjOwn = 2;
+constexpr int kAdjHalo = 4;
+
+__device__ __forceinline__ void adj_tile_block(const Dims& d, const AdjTile& tl, int& j0, int& tjr,
+                                               int& i0, int& i1) {
+    const int nb = tl.ntile * tl.nslab;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int slab = lb / tl.ntile;
+    const int tile = lb - slab * tl.ntile;
+    j0 = tile * tl.tj;
+    tjr = min(tl.tj, d.ny - j0);
+    i0 = slab * tl.ci;
+    i1 = min(d.nx, i0 + tl.ci);
+}
+
 // Reverse of phi' = phi + dt [M (L_h mu + lambda_V) - v . D phi] with respect to phi (through
-// D phi), mu, lambda_V and psi (through v = curl psi), and the wall speed. Each lane owns one
-// (j, k) column and walks an x-slab: the quantities it needs at its own column in the planes
-// i - 1 and i + 1 (a, a v_x, b_y, b_z with b_c = -dt a D_c phi on the interior rows, 0 on the
-// walls) are computed once per plane and kept; those of the y and z neighbours are computed
-// from the plane i through the cache. Two pieces of set-up of the reverse step ride along: the
+// D phi), mu, lambda_V and psi (through v = curl psi), and the wall speed, on the tiles above.
+// Per node: a, A = a v (v = curl psi on the interior rows, (0, 0, wall speed) on the walls) and
+// b = -dt a D phi (0 on the walls); the outputs are phibar = a - dt sum_c D_c^T A_c,
+// mubar = dt M L_h^T a and psibar = curl^T b. A lane keeps a, A_x, b_y, b_z of its nodes in
+// the planes i - 1, i, i + 1 (the next plane's computed one step ahead); a, A_y, A_z, b_x, b_y,
+// b_z of the plane i go through LDS. Two pieces of set-up of the reverse step ride along: the
 // lanes of the wall rows zero those rows of up to six other fields (the spectral sets the
 // adjoint solves write only inside), and block 0 clears the status words and residual scalars.
 struct AdjZero {
@@ -31,11 +86,11 @@ struct AdjZero {
 };
 __global__ __launch_bounds__(kBlock) void k_adj_advect(
     const double* __restrict__ a, const double* __restrict__ phi, Vel vel, Dims d, double dt,
-    double mob, SlabGrid sg, double* __restrict__ phibar, double* __restrict__ mubar,
+    double mob, AdjTile tl, double* __restrict__ phibar, double* __restrict__ mubar,
     double* __restrict__ qx, double* __restrict__ qy, double* __restrict__ qz,
     double* __restrict__ partials, AdjZero zw, double* scal, int* istat) {
+    extern __shared__ double lds[];
     __shared__ double sh[3 * 16];
-    double acc[3] = {0.0, 0.0, 0.0};
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         scal[SC_RELRES_MAX] = 0.0;
         scal[SC_RELRES_LAST] = 0.0;
@@ -43,106 +98,156 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(
         istat[IS_CYCLES] = 0;
         istat[IS_CONV] = 0;
     }
-    const SlabIter it = slab_iter(d, sg);
-    if (it.ok && zw.p[0] && (it.j == 0 || it.j == d.ny - 1)) {
-        for (int i = it.i0; i < it.i1; ++i) {
-            const size_t c = (size_t)i * d.ny * d.nz + (size_t)it.j * d.nz + it.k;
+    const int nz = d.nz;
+    const size_t plane = (size_t)d.ny * nz;
+    const double r2h = d.inv_2h;
+    int j0, tjr, i0, i1;
+    adj_tile_block(d, tl, j0, tjr, i0, i1);
+    const int R = tl.tj + 2;   // LDS rows: halo, tile rows, halo
+    double* sa = lds;
+    double* say = sa + R * nz;
+    double* sbx = say + R * nz;
+    double* sbz = sbx + R * nz;
+    double* saz = sbz + R * nz;
+    double* sby = saz + R * nz;
+    // own nodes
+    bool ok[kAdjOwn];
+    int oj[kAdjOwn], ok_[kAdjOwn], orow[kAdjOwn];
+    double am[kAdjOwn], axm[kAdjOwn], bym[kAdjOwn], bzm[kAdjOwn];
+    double a0[kAdjOwn], ax0[kAdjOwn], by0[kAdjOwn], bz0[kAdjOwn];
 #pragma unroll
-            for (int f = 0; f < 6; ++f)
-                if (zw.p[f]) zw.p[f][c] = 0.0;
+    for (int m = 0; m < kAdjOwn; ++m) {
+        const int idx = threadIdx.x + m * kBlock;
+        ok[m] = idx < tjr * nz;
+        const int r = ok[m] ? idx / nz : 0;
+        oj[m] = j0 + r;
+        ok_[m] = ok[m] ? idx - r * nz : 0;
+        orow[m] = r + 1;
+    }
+    // a, a v_x, b_y, b_z at node (j, k) of the plane base b
+    auto xsub = [&](size_t b, int j, int k, double& av, double& ax, double& by, double& bz) {
+        const int o = j * nz + k;
+        av = a[b + o];
+        ax = by = bz = 0.0;
+        if (j >= 1 && j <= d.ny - 2) {
+            const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+            const int okp = j * nz + kp, okm = j * nz + km;
+            const double vx = ((vel.pz[b + o + nz] - vel.pz[b + o - nz]) - (vel.py[b + okp] - vel.py[b + okm])) * r2h;
+            ax = av * vx;
+            by = -dt * av * ((phi[b + o + nz] - phi[b + o - nz]) * r2h);
+            bz = -dt * av * ((phi[b + okp] - phi[b + okm]) * r2h);
+        }
+    };
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i0 < i1) {
+#pragma unroll
+        for (int m = 0; m < kAdjOwn; ++m) {
+            am[m] = axm[m] = bym[m] = bzm[m] = a0[m] = ax0[m] = by0[m] = bz0[m] = 0.0;
+            if (!ok[m]) continue;
+            xsub((size_t)wrap(i0 - 1, d.nx) * plane, oj[m], ok_[m], am[m], axm[m], bym[m], bzm[m]);
+            xsub((size_t)i0 * plane, oj[m], ok_[m], a0[m], ax0[m], by0[m], bz0[m]);
         }
     }
-    if (it.ok) {
-        const int j = it.j, k = it.k, nz = d.nz;
-        const size_t plane = (size_t)d.ny * nz;
-        const double r2h = d.inv_2h;
-        const int kp = wrap(k + 1, nz), km = wrap(k - 1, nz);
-        const bool wall = (j == 0 || j == d.ny - 1);
-        // neighbour rows: mirrored past the walls (the L_h^T stencil); the y-neighbour terms
-        // of the advection and of b are taken only where that row is interior
-        const int jm = (j == 0) ? 1 : j - 1, jp = (j == d.ny - 1) ? d.ny - 2 : j + 1;
-        const bool in_m = j >= 2, in_p = j <= d.ny - 3;
-        const int o = j * nz + k, okm = j * nz + km, okp = j * nz + kp;
-        const int ojm = jm * nz + k, ojp = jp * nz + k;
-        const double vw = j == 0 ? vel.vz_lo : vel.vz_hi;
-        // a, a v_x, b_y, b_z at (ii, j, k)
-        auto xnode = [&](int ii, double& av, double& ax, double& by, double& bz) {
-            const size_t b = (size_t)ii * plane;
-            av = a[b + o];
-            ax = by = bz = 0.0;
-            if (!wall) {
-                const double vx = ((vel.pz[b + ojp] - vel.pz[b + ojm]) - (vel.py[b + okp] - vel.py[b + okm])) * r2h;
-                ax = av * vx;
-                by = -dt * av * ((phi[b + ojp] - phi[b + ojm]) * r2h);
-                bz = -dt * av * ((phi[b + okp] - phi[b + okm]) * r2h);
+    for (int i = i0; i < i1; ++i) {
+        const int ip = (i + 1 == d.nx) ? 0 : i + 1, im = (i == 0) ? d.nx - 1 : i - 1;
+        const size_t b = (size_t)i * plane, bm = (size_t)im * plane, bp = (size_t)ip * plane;
+        double ap[kAdjOwn], axp[kAdjOwn], byp[kAdjOwn], bzp[kAdjOwn];
+        // the next plane's x quantities, then the rest of this plane's into LDS
+#pragma unroll
+        for (int m = 0; m < kAdjOwn; ++m) {
+            ap[m] = axp[m] = byp[m] = bzp[m] = 0.0;
+            if (!ok[m]) continue;
+            xsub(bp, oj[m], ok_[m], ap[m], axp[m], byp[m], bzp[m]);
+            const int j = oj[m], k = ok_[m], o = j * nz + k;
+            const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+            double Ay = 0.0, Az, bx = 0.0;
+            if (j >= 1 && j <= d.ny - 2) {
+                const double vy = ((vel.px[b + j * nz + kp] - vel.px[b + j * nz + km]) - (vel.pz[bp + o] - vel.pz[bm + o])) * r2h;
+                const double vz = ((vel.py[bp + o] - vel.py[bm + o]) - (vel.px[b + o + nz] - vel.px[b + o - nz])) * r2h;
+                Ay = a0[m] * vy;
+                Az = a0[m] * vz;
+                bx = -dt * a0[m] * ((phi[bp + o] - phi[bm + o]) * r2h);
+            } else {
+                Az = a0[m] * (j == 0 ? vel.vz_lo : vel.vz_hi);
             }
-        };
-        double a_m, ax_m, by_m, bz_m, a_0, ax_0, by_0, bz_0;
-        xnode(wrap(it.i0 - 1, d.nx), a_m, ax_m, by_m, bz_m);
-        xnode(it.i0, a_0, ax_0, by_0, bz_0);
-        const double wj = wrow(d, j), rwm = 1.0 / wrow(d, jm), rwp = 1.0 / wrow(d, jp);
-        for (int i = it.i0; i < it.i1; ++i) {
-            const int ip = (i + 1 == d.nx) ? 0 : i + 1, im = (i == 0) ? d.nx - 1 : i - 1;
-            double a_p, ax_p, by_p, bz_p;
-            xnode(ip, a_p, ax_p, by_p, bz_p);
-            const size_t b = (size_t)i * plane, bm = (size_t)im * plane, bp = (size_t)ip * plane;
-            const size_t c = b + o;
-            const double a_km = a[b + okm], a_kp = a[b + okp];
-            const double a_jm = a[b + ojm], a_jp = a[b + ojp];
-            // a v_z at k -/+ 1 (the wall speed on the walls)
-            double vz_km = vw, vz_kp = vw;
-            if (!wall) {
-                vz_km = ((vel.py[bp + okm] - vel.py[bm + okm]) - (vel.px[b + jp * nz + km] - vel.px[b + jm * nz + km])) * r2h;
-                vz_kp = ((vel.py[bp + okp] - vel.py[bm + okp]) - (vel.px[b + jp * nz + kp] - vel.px[b + jm * nz + kp])) * r2h;
+            const int q = orow[m] * nz + k;
+            sa[q] = a0[m];
+            say[q] = Ay;
+            sbx[q] = bx;
+            sbz[q] = bz0[m];
+            saz[q] = Az;
+            sby[q] = by0[m];
+        }
+        // halo rows j0 - 1 and j0 + tjr: a, A_y, b_x, b_z
+#pragma unroll 1
+        for (int h = 0; h < kAdjHalo; ++h) {
+            const int idx = threadIdx.x + h * kBlock;
+            if (idx >= 2 * nz) continue;
+            const int side = idx / nz, k = idx - side * nz;
+            const int j = side ? j0 + tjr : j0 - 1;
+            if (j < 0 || j >= d.ny) continue;
+            const int o = j * nz + k;
+            const double av = a[b + o];
+            double Ay = 0.0, bx = 0.0, bz = 0.0;
+            if (j >= 1 && j <= d.ny - 2) {
+                const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+                const double vy = ((vel.px[b + j * nz + kp] - vel.px[b + j * nz + km]) - (vel.pz[bp + o] - vel.pz[bm + o])) * r2h;
+                Ay = av * vy;
+                bx = -dt * av * ((phi[bp + o] - phi[bm + o]) * r2h);
+                bz = -dt * av * ((phi[b + j * nz + kp] - phi[b + j * nz + km]) * r2h);
             }
-            // a v_y, b_x, b_z at j -/+ 1 (interior rows only)
-            double ay_jm = 0.0, ay_jp = 0.0, bx_jm = 0.0, bx_jp = 0.0, bz_jm = 0.0, bz_jp = 0.0;
-            if (in_m) {
-                const int r = jm * nz;
-                const double vy = ((vel.px[b + r + kp] - vel.px[b + r + km]) - (vel.pz[bp + ojm] - vel.pz[bm + ojm])) * r2h;
-                ay_jm = a_jm * vy;
-                bx_jm = -dt * a_jm * ((phi[bp + ojm] - phi[bm + ojm]) * r2h);
-                bz_jm = -dt * a_jm * ((phi[b + r + kp] - phi[b + r + km]) * r2h);
-            }
-            if (in_p) {
-                const int r = jp * nz;
-                const double vy = ((vel.px[b + r + kp] - vel.px[b + r + km]) - (vel.pz[bp + ojp] - vel.pz[bm + ojp])) * r2h;
-                ay_jp = a_jp * vy;
-                bx_jp = -dt * a_jp * ((phi[bp + ojp] - phi[bm + ojp]) * r2h);
-                bz_jp = -dt * a_jp * ((phi[b + r + kp] - phi[b + r + km]) * r2h);
-            }
-            // b_x, b_y at k -/+ 1 (row j, interior only)
-            double bx_km = 0.0, bx_kp = 0.0, by_km = 0.0, by_kp = 0.0;
-            if (!wall) {
-                bx_km = -dt * a_km * ((phi[bp + okm] - phi[bm + okm]) * r2h);
-                bx_kp = -dt * a_kp * ((phi[bp + okp] - phi[bm + okp]) * r2h);
-                by_km = -dt * a_km * ((phi[b + jp * nz + km] - phi[b + jm * nz + km]) * r2h);
-                by_kp = -dt * a_kp * ((phi[b + jp * nz + kp] - phi[b + jm * nz + kp]) * r2h);
-            }
+            const int q = (side ? tjr + 1 : 0) * nz + k;
+            sa[q] = av;
+            say[q] = Ay;
+            sbx[q] = bx;
+            sbz[q] = bz;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kAdjOwn; ++m) {
+            if (!ok[m]) continue;
+            const int j = oj[m], k = ok_[m];
+            const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+            const int rr = orow[m];
+            const int qc = rr * nz + k, qkm = rr * nz + km, qkp = rr * nz + kp;
+            const int qjm = qc - nz, qjp = qc + nz;   // rows j - 1, j + 1 (valid where they exist)
+            const bool has_m = j >= 1, has_p = j <= d.ny - 2;
+            const bool wall = (j == 0 || j == d.ny - 1);
             // phibar = a - dt sum_c D_c^T (a v_c)
-            double t = (ax_m - ax_p) + (a_km * vz_km - a_kp * vz_kp);
-            t += ay_jm;
-            t -= ay_jp;
-            phibar[c] = a_0 - dt * t * r2h;
-            // mubar = dt M L_h^T a
-            const double xz = a_p + a_m + a_kp + a_km;
-            mubar[c] = dt * mob * ((xz + wj * (a_jp * rwp + a_jm * rwm) - 6.0 * a_0) * d.inv_h2);
+            double t = (axm[m] - axp[m]) + (saz[qkm] - saz[qkp]);
+            if (has_m) t += say[qjm];
+            if (has_p) t -= say[qjp];
+            const size_t c = b + (size_t)j * nz + k;
+            phibar[c] = a0[m] - dt * t * r2h;
+            // mubar = dt M L_h^T a (mirrored rows past the walls)
+            const int jm_l = (j == 0) ? 1 : j - 1, jp_l = (j == d.ny - 1) ? d.ny - 2 : j + 1;
+            const double xz = ap[m] + am[m] + sa[qkp] + sa[qkm];
+            const double yy = sa[qc + (jp_l - j) * nz] / wrow(d, jp_l) + sa[qc + (jm_l - j) * nz] / wrow(d, jm_l);
+            mubar[c] = dt * mob * ((xz + wrow(d, j) * yy - 6.0 * a0[m]) * d.inv_h2);
             // psibar = curl^T b
-            const double sx = ((by_km - by_kp) - (bz_jm - bz_jp)) * r2h;
-            const double sy = ((bz_m - bz_p) - (bx_km - bx_kp)) * r2h;
-            const double sz = ((bx_jm - bx_jp) - (by_m - by_p)) * r2h;
+            const double bzjm = has_m ? sbz[qjm] : 0.0, bzjp = has_p ? sbz[qjp] : 0.0;
+            const double bxjm = has_m ? sbx[qjm] : 0.0, bxjp = has_p ? sbx[qjp] : 0.0;
+            const double sx = ((sby[qkm] - sby[qkp]) - (bzjm - bzjp)) * r2h;
+            const double sy = ((bzm[m] - bzp[m]) - (sbx[qkm] - sbx[qkp])) * r2h;
+            const double sz = ((bxjm - bxjp) - (bym[m] - byp[m])) * r2h;
             qx[c] = sx;
             qy[c] = sy;
             qz[c] = sz;
-            acc[0] += a_0;
+            acc[0] += a0[m];
             if (wall) {
-                const double dz = (phi[b + okp] - phi[b + okm]) * r2h;
-                acc[1] += a_0 * vw * dz;
+                const double dz = (phi[b + (size_t)j * nz + kp] - phi[b + (size_t)j * nz + km]) * r2h;
+                acc[1] += a0[m] * (j == 0 ? vel.vz_lo : vel.vz_hi) * dz;
                 acc[2] += sx * vel.px[c] + sy * vel.py[c] + sz * vel.pz[c];
+                if (zw.p[0]) {
+#pragma unroll
+                    for (int f = 0; f < 6; ++f)
+                        if (zw.p[f]) zw.p[f][c] = 0.0;
+                }
             }
-            a_m = a_0; ax_m = ax_0; by_m = by_0; bz_m = bz_0;
-            a_0 = a_p; ax_0 = ax_p; by_0 = by_p; bz_0 = bz_p;
+            am[m] = a0[m]; axm[m] = ax0[m]; bym[m] = by0[m]; bzm[m] = bz0[m];
+            a0[m] = ap[m]; ax0[m] = axp[m]; by0[m] = byp[m]; bz0[m] = bzp[m];
         }
+        __syncthreads();
     }
     block_sum<3>(acc, sh);
     if (threadIdx.x == 0) {
@@ -151,13 +256,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(
     }
 }
 
-// scal[dst + q] = sum_b partials[q][b] for q in [first, nslots), fixed order.
-__global__ __launch_bounds__(1024) void k_adj_sum(const double* __restrict__ partials, int nblocks,
-                                                  int first, int nslots, double* scal, int dst) {
+// scal[dst + q] = sum_b partials[q][b] for q in [first, nslots), fixed order; slots below
+// split have nb_lo blocks, the others nb_hi.
+__global__ __launch_bounds__(1024) void k_adj_sum(const double* __restrict__ partials, int nb_lo,
+                                                  int nb_hi, int split, int first, int nslots,
+                                                  double* scal, int dst) {
     __shared__ double sh[4 * 16];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-        for (int q = first; q < nslots; ++q) acc[q] += partials[q * kMaxPartialBlocks + b];
+    const int nbmax = nb_lo > nb_hi ? nb_lo : nb_hi;
+    for (int b = threadIdx.x; b < nbmax; b += blockDim.x)
+        for (int q = first; q < nslots; ++q)
+            if (b < (q < split ? nb_lo : nb_hi)) acc[q] += partials[q * kMaxPartialBlocks + b];
     block_sum<4>(acc, sh);
     if (threadIdx.x == 0)
         for (int q = first; q < nslots; ++q) scal[dst + q] = acc[q];
@@ -190,81 +299,147 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_couple(const double* __rest
 
 // Reverse of S = (1/eta) D phi x D mu on the interior rows: phibar -= D . abar and
 // mubar -= D . bbar (central differences transposed), abar = (1/eta) D mu x Sbar,
-// bbar = (1/eta) Sbar x D phi at each interior node (so the wall rows receive the y terms of
-// rows 1 and M). Each lane owns one (j, k) column and walks an x-slab; the x components of
-// abar, bbar at its column in the planes i -/+ 1 are kept from plane to plane, the y and z
-// components at the neighbours are computed from the plane i. The
-// wall couplings of the two adjoint solves ride along as block partials (slot 0: u1 on rows 1
-// and M against the psi walls, skipped when u1 is NULL; slot 1: Sbar against the omega walls).
+// bbar = (1/eta) Sbar x D phi at each interior node, 0 on the walls (so the wall rows receive
+// the y terms of rows 1 and M). On the tiles of k_adj_advect: a lane keeps the x components of
+// abar, bbar of its nodes in the planes i - 1 and i + 1 (with the y and z differences and Sbar
+// of the next plane, computed one step ahead); the y and z components of the plane i go
+// through LDS. The wall couplings of the two adjoint solves ride along as block partials
+// (slot kAdjSlotPsi: u1 on rows 1 and M against the psi walls, skipped when u1 is NULL; slot
+// kAdjSlotOm: Sbar against the omega walls), and, when chk.part is given, block 0 first takes
+// the convergence check of the two adjoint solves from their residual partials (as
+// k_check_flow does; the slots of this kernel lie above the residual's).
 __global__ __launch_bounds__(kBlock) void k_adj_source(
     const double* __restrict__ phi, const double* __restrict__ mu, const double* __restrict__ s0,
     const double* __restrict__ s1, const double* __restrict__ s2, Dims d, double inv_eta,
-    SlabGrid sg, double* __restrict__ phibar, double* __restrict__ mubar, WallPairs wp,
-    double* __restrict__ partials) {
-    __shared__ double sh[2 * 16];
+    AdjTile tl, double* __restrict__ phibar, double* __restrict__ mubar, WallPairs wp,
+    double* __restrict__ partials, AdjCheck chk) {
+    extern __shared__ double lds[];
+    __shared__ double sh[4 * 16];
+    if (chk.part && blockIdx.x == 0)
+        flow_check_block(chk.part, chk.nblocks, chk.rtol, chk.scal, chk.istat, sh, 1);
+    const int nz = d.nz;
+    const size_t plane = (size_t)d.ny * nz;
+    const double r2h = d.inv_2h;
+    int j0, tjr, i0, i1;
+    adj_tile_block(d, tl, j0, tjr, i0, i1);
+    const int R = tl.tj + 2;
+    double* sab_y = lds;
+    double* sbb_y = sab_y + R * nz;
+    double* sab_z = sbb_y + R * nz;
+    double* sbb_z = sab_z + R * nz;
+    bool ok[kAdjOwn], in[kAdjOwn];
+    int oj[kAdjOwn], ok_[kAdjOwn], orow[kAdjOwn];
+#pragma unroll
+    for (int m = 0; m < kAdjOwn; ++m) {
+        const int idx = threadIdx.x + m * kBlock;
+        ok[m] = idx < tjr * nz;
+        const int r = ok[m] ? idx / nz : 0;
+        oj[m] = j0 + r;
+        ok_[m] = ok[m] ? idx - r * nz : 0;
+        orow[m] = r + 1;
+        in[m] = ok[m] && oj[m] >= 1 && oj[m] <= d.ny - 2;
+    }
+    // y, z differences of phi and mu and Sbar_1, Sbar_2 at (j, k) of the plane base b (interior)
+    struct Yz {
+        double f1, f2, m1, m2, S1, S2;
+    };
+    auto yz = [&](size_t b, int j, int k) -> Yz {
+        const int o = j * nz + k;
+        const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+        Yz r;
+        r.f1 = (phi[b + o + nz] - phi[b + o - nz]) * r2h;
+        r.f2 = (phi[b + j * nz + kp] - phi[b + j * nz + km]) * r2h;
+        r.m1 = (mu[b + o + nz] - mu[b + o - nz]) * r2h;
+        r.m2 = (mu[b + j * nz + kp] - mu[b + j * nz + km]) * r2h;
+        r.S1 = s1[b + o];
+        r.S2 = s2[b + o];
+        return r;
+    };
+    double abm[kAdjOwn], bbm[kAdjOwn], ab0[kAdjOwn], bb0[kAdjOwn];
+    Yz y0[kAdjOwn];
     double acc[2] = {0.0, 0.0};
-    const SlabIter it = slab_iter(d, sg);
-    if (it.ok) {
-        const int j = it.j, k = it.k, nz = d.nz;
-        const bool inr = j >= 1 && j <= d.ny - 2;
-        const size_t plane = (size_t)d.ny * nz;
-        const double r2h = d.inv_2h;
-        const int kp = wrap(k + 1, nz), km = wrap(k - 1, nz);
-        const int o = j * nz + k, okm = j * nz + km, okp = j * nz + kp;
-        const int ojm = (j - 1) * nz + k, ojp = (j + 1) * nz + k;
-        const bool in_m = j >= 2, in_p = j <= d.ny - 3;   // rows j -/+ 1 interior
-        // abar_x, bbar_x at (ii, j, k): D_y, D_z of mu and phi (0 on the wall rows)
-        auto xnode = [&](int ii, double& ab, double& bb) {
-            ab = bb = 0.0;
-            if (!inr) return;
-            const size_t b = (size_t)ii * plane;
-            const double S1 = s1[b + o], S2 = s2[b + o];
-            const double f1 = (phi[b + ojp] - phi[b + ojm]) * r2h, f2 = (phi[b + okp] - phi[b + okm]) * r2h;
-            const double m1 = (mu[b + ojp] - mu[b + ojm]) * r2h, m2 = (mu[b + okp] - mu[b + okm]) * r2h;
-            ab = (m1 * S2 - m2 * S1) * inv_eta;
-            bb = (S1 * f2 - S2 * f1) * inv_eta;
-        };
-        double ab_m, bb_m, ab_0, bb_0;
-        xnode(wrap(it.i0 - 1, d.nx), ab_m, bb_m);
-        xnode(it.i0, ab_0, bb_0);
-        for (int i = it.i0; i < it.i1; ++i) {
-            const int ip = (i + 1 == d.nx) ? 0 : i + 1, im = (i == 0) ? d.nx - 1 : i - 1;
-            double ab_p, bb_p;
-            xnode(ip, ab_p, bb_p);
-            const size_t b = (size_t)i * plane, bm = (size_t)im * plane, bp = (size_t)ip * plane;
-            // abar_z, bbar_z at k -/+ 1: D_x, D_y
-            double abz[2] = {0.0, 0.0}, bbz[2] = {0.0, 0.0};
+    if (i0 < i1) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (!inr) continue;
-                const int kk = h ? kp : km;
-                const int q = j * nz + kk;
-                const double S0 = s0[b + q], S1 = s1[b + q];
-                const double f0 = (phi[bp + q] - phi[bm + q]) * r2h;
-                const double f1 = (phi[b + (j + 1) * nz + kk] - phi[b + (j - 1) * nz + kk]) * r2h;
-                const double m0 = (mu[bp + q] - mu[bm + q]) * r2h;
-                const double m1 = (mu[b + (j + 1) * nz + kk] - mu[b + (j - 1) * nz + kk]) * r2h;
-                abz[h] = (m0 * S1 - m1 * S0) * inv_eta;
-                bbz[h] = (S0 * f1 - S1 * f0) * inv_eta;
-            }
-            // abar_y, bbar_y at j -/+ 1 (interior rows only): D_z, D_x
-            double aby[2] = {0.0, 0.0}, bby[2] = {0.0, 0.0};
+        for (int m = 0; m < kAdjOwn; ++m) {
+            abm[m] = bbm[m] = ab0[m] = bb0[m] = 0.0;
+            y0[m] = Yz{0, 0, 0, 0, 0, 0};
+            if (!in[m]) continue;
+            const Yz t = yz((size_t)wrap(i0 - 1, d.nx) * plane, oj[m], ok_[m]);
+            abm[m] = (t.m1 * t.S2 - t.m2 * t.S1) * inv_eta;
+            bbm[m] = (t.S1 * t.f2 - t.S2 * t.f1) * inv_eta;
+            y0[m] = yz((size_t)i0 * plane, oj[m], ok_[m]);
+            ab0[m] = (y0[m].m1 * y0[m].S2 - y0[m].m2 * y0[m].S1) * inv_eta;
+            bb0[m] = (y0[m].S1 * y0[m].f2 - y0[m].S2 * y0[m].f1) * inv_eta;
+        }
+    }
+    for (int i = i0; i < i1; ++i) {
+        const int ip = (i + 1 == d.nx) ? 0 : i + 1, im = (i == 0) ? d.nx - 1 : i - 1;
+        const size_t b = (size_t)i * plane, bm = (size_t)im * plane, bp = (size_t)ip * plane;
+        double abp[kAdjOwn], bbp[kAdjOwn];
+        Yz yp[kAdjOwn];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (h ? !in_p : !in_m) continue;
-                const int r = (h ? j + 1 : j - 1) * nz;
-                const int q = r + k;
-                const double S0 = s0[b + q], S2 = s2[b + q];
-                const double f0 = (phi[bp + q] - phi[bm + q]) * r2h;
-                const double f2 = (phi[b + r + kp] - phi[b + r + km]) * r2h;
-                const double m0 = (mu[bp + q] - mu[bm + q]) * r2h;
-                const double m2 = (mu[b + r + kp] - mu[b + r + km]) * r2h;
-                aby[h] = (m2 * S0 - m0 * S2) * inv_eta;
-                bby[h] = (S2 * f0 - S0 * f2) * inv_eta;
+        for (int m = 0; m < kAdjOwn; ++m) {
+            abp[m] = bbp[m] = 0.0;
+            yp[m] = Yz{0, 0, 0, 0, 0, 0};
+            if (!ok[m]) continue;
+            double aby = 0.0, bby = 0.0, abz = 0.0, bbz = 0.0;
+            if (in[m]) {
+                yp[m] = yz(bp, oj[m], ok_[m]);
+                abp[m] = (yp[m].m1 * yp[m].S2 - yp[m].m2 * yp[m].S1) * inv_eta;
+                bbp[m] = (yp[m].S1 * yp[m].f2 - yp[m].S2 * yp[m].f1) * inv_eta;
+                const int o = oj[m] * nz + ok_[m];
+                const double f0 = (phi[bp + o] - phi[bm + o]) * r2h;
+                const double m0 = (mu[bp + o] - mu[bm + o]) * r2h;
+                const double S0 = s0[b + o];
+                const Yz& t = y0[m];
+                aby = (t.m2 * S0 - m0 * t.S2) * inv_eta;
+                bby = (t.S2 * f0 - S0 * t.f2) * inv_eta;
+                abz = (m0 * t.S1 - t.m1 * S0) * inv_eta;
+                bbz = (S0 * t.f1 - t.S1 * f0) * inv_eta;
             }
-            const double tp = ((ab_m - ab_p) + (abz[0] - abz[1])) + (aby[0] - aby[1]);
-            const double tm = ((bb_m - bb_p) + (bbz[0] - bbz[1])) + (bby[0] - bby[1]);
-            const size_t c = b + o;
+            const int q = orow[m] * nz + ok_[m];
+            sab_y[q] = aby;
+            sbb_y[q] = bby;
+            sab_z[q] = abz;
+            sbb_z[q] = bbz;
+        }
+        // halo rows j0 - 1 and j0 + tjr: abar_y, bbar_y
+#pragma unroll 1
+        for (int h = 0; h < kAdjHalo; ++h) {
+            const int idx = threadIdx.x + h * kBlock;
+            if (idx >= 2 * nz) continue;
+            const int side = idx / nz, k = idx - side * nz;
+            const int j = side ? j0 + tjr : j0 - 1;
+            if (j < 0 || j >= d.ny) continue;
+            double aby = 0.0, bby = 0.0;
+            if (j >= 1 && j <= d.ny - 2) {
+                const int o = j * nz + k;
+                const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+                const double f0 = (phi[bp + o] - phi[bm + o]) * r2h;
+                const double m0 = (mu[bp + o] - mu[bm + o]) * r2h;
+                const double f2 = (phi[b + j * nz + kp] - phi[b + j * nz + km]) * r2h;
+                const double m2 = (mu[b + j * nz + kp] - mu[b + j * nz + km]) * r2h;
+                const double S0 = s0[b + o], S2 = s2[b + o];
+                aby = (m2 * S0 - m0 * S2) * inv_eta;
+                bby = (S2 * f0 - S0 * f2) * inv_eta;
+            }
+            const int q = (side ? tjr + 1 : 0) * nz + k;
+            sab_y[q] = aby;
+            sbb_y[q] = bby;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kAdjOwn; ++m) {
+            if (!ok[m]) continue;
+            const int j = oj[m], k = ok_[m];
+            const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+            const int rr = orow[m];
+            const int qc = rr * nz + k, qkm = rr * nz + km, qkp = rr * nz + kp;
+            const double abjm = j >= 1 ? sab_y[qc - nz] : 0.0, abjp = j <= d.ny - 2 ? sab_y[qc + nz] : 0.0;
+            const double bbjm = j >= 1 ? sbb_y[qc - nz] : 0.0, bbjp = j <= d.ny - 2 ? sbb_y[qc + nz] : 0.0;
+            const double tp = ((abm[m] - abp[m]) + (sab_z[qkm] - sab_z[qkp])) + (abjm - abjp);
+            const double tm = ((bbm[m] - bbp[m]) + (sbb_z[qkm] - sbb_z[qkp])) + (bbjm - bbjp);
+            const size_t c = b + (size_t)j * nz + k;
             phibar[c] += tp * r2h;
             mubar[c] += tm * r2h;
             // wall couplings: rows 1 and M against the wall planes 0 and ny - 1
@@ -278,14 +453,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_source(
                     acc[1] -= (s0[c] * wp.sw[0][w] + s1[c] * wp.sw[1][w] + s2[c] * wp.sw[2][w]) * d.inv_h2;
                 }
             }
-            ab_m = ab_0; bb_m = bb_0;
-            ab_0 = ab_p; bb_0 = bb_p;
+            abm[m] = ab0[m]; bbm[m] = bb0[m];
+            ab0[m] = abp[m]; bb0[m] = bbp[m];
+            y0[m] = yp[m];
         }
+        __syncthreads();
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
-        partials[0 * kMaxPartialBlocks + blockIdx.x] = acc[0];
-        partials[1 * kMaxPartialBlocks + blockIdx.x] = acc[1];
+        partials[kAdjSlotPsi * kMaxPartialBlocks + blockIdx.x] = acc[0];
+        partials[kAdjSlotOm * kMaxPartialBlocks + blockIdx.x] = acc[1];
     }
 }
 
@@ -319,21 +496,54 @@ __global__ __launch_bounds__(kBlock) void k_adj_mu1(const double* __restrict__ p
     }
     block_sum<2>(acc, sh);
     if (threadIdx.x == 0) {
-        partials[2 * kMaxPartialBlocks + blockIdx.x] = acc[0];
-        partials[3 * kMaxPartialBlocks + blockIdx.x] = acc[1];
+        partials[kAdjSlotKappa * kMaxPartialBlocks + blockIdx.x] = acc[0];
+        partials[kAdjSlotGamma * kMaxPartialBlocks + blockIdx.x] = acc[1];
     }
 }
 
 // phibar += (d mu / d phi)^T mubar + lambda_bar d lambda_V/d phi + A_bar dA/d phi. Each lane
 // owns one (j, k) column and walks an x-slab with phi of the planes i-2 .. i+2 and mubar, gbar
 // of the planes i-1 .. i+1 in registers.
+// Sums of the reverse step's block partials (fixed order, the same in every block): nb_src
+// blocks of k_adj_source, nb_mu1 of k_adj_mu1 (0: not launched).
+struct AdjSums {
+    const double* part;
+    int nb_src, nb_mu1;
+    int psi_on;       // the psi-wall coupling came from k_adj_source (else it is in scal already)
+    double* scal;     // block 0 writes SC_ADJ_PSIC, SC_ADJ_OMC, SC_ADJ_KAPPA, SC_ADJ_GAMMA
+};
 __global__ __launch_bounds__(kBlock) void k_adj_mu2(const double* __restrict__ phi,
                                                    const double* __restrict__ mubar,
                                                    const double* __restrict__ gbar,
                                                    const double* __restrict__ scal, Dims d,
                                                    int model, double C_b, double eps, double sigma,
                                                    double dt, double mob, double rate_V, double k_A,
-                                                   SlabGrid sg, double* __restrict__ phibar) {
+                                                   SlabGrid sg, double* __restrict__ phibar,
+                                                   AdjSums sums) {
+    // gamma_A's adjoint (needed by every block) and, in block 0, the step's other scalars
+    __shared__ double sh[4 * 16];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool b0 = blockIdx.x == 0;
+    for (int b = threadIdx.x; b < sums.nb_mu1; b += blockDim.x) {
+        v[0] += sums.part[kAdjSlotGamma * kMaxPartialBlocks + b];
+        if (b0) v[1] += sums.part[kAdjSlotKappa * kMaxPartialBlocks + b];
+    }
+    if (b0) {
+        for (int b = threadIdx.x; b < sums.nb_src; b += blockDim.x) {
+            if (sums.psi_on) v[2] += sums.part[kAdjSlotPsi * kMaxPartialBlocks + b];
+            v[3] += sums.part[kAdjSlotOm * kMaxPartialBlocks + b];
+        }
+    }
+    block_sum<4>(v, sh);
+    if (threadIdx.x == 0) sh[4 * 16 - 1] = v[0];
+    __syncthreads();
+    const double gamma_bar = sh[4 * 16 - 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sums.scal[SC_ADJ_GAMMA] = v[0];
+        sums.scal[SC_ADJ_KAPPA] = v[1];
+        if (sums.psi_on) sums.scal[SC_ADJ_PSIC] = v[2];
+        sums.scal[SC_ADJ_OMC] = v[3];
+    }
     const SlabIter it = slab_iter(d, sg);
     if (!it.ok) return;
     const int j = it.j, k = it.k, nz = d.nz;
@@ -348,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_mu2(const double* __restrict__ p
     const double gam = scal[SC_GAMMA];
     const double A0 = scal[SC_A0];
     const bool area = !ch && k_A != 0.0 && A0 > 0.0;
-    const double Abar = area ? scal[SC_ADJ_GAMMA] * k_A / A0 : 0.0;
+    const double Abar = area ? gamma_bar * k_A / A0 : 0.0;
     const int kp = wrap(k + 1, nz), km = wrap(k - 1, nz);
     const int kp2 = wrap(k + 2, nz), km2 = wrap(k - 2, nz);
     const int jm = (j == 0) ? 1 : j - 1, jp = (j == d.ny - 1) ? d.ny - 2 : j + 1;   // mirrored
@@ -416,14 +626,15 @@ void launch_adj_advect(hipStream_t s, const Dims& d, const double* a, const doub
                        const double* const psi[3], double dt, double mobility, double vz_lo,
                        double vz_hi, double* phibar, double* mubar, double* const psibar[3],
                        double* part, double* scal, int* istat, double* const zero_walls[6]) {
-    const SlabGrid g = adj_slab_grid(d);
+    const AdjTile tl = adj_tile(d);
     const Vel vel{psi[0], psi[1], psi[2], vz_lo, vz_hi};
-    const int nb = g.gx * g.gi;
+    const int nb = tl.ntile * tl.nslab;
     AdjZero zw{};
     for (int f = 0; f < 6; ++f) zw.p[f] = zero_walls ? zero_walls[f] : nullptr;
-    launch_kernel(k_adj_advect, dim3(nb), dim3(kBlock), 0, s, a, phi, vel, d, dt, mobility, g,
+    const size_t lds = (size_t)6 * (tl.tj + 2) * d.nz * sizeof(double);
+    launch_kernel(k_adj_advect, dim3(nb), dim3(kBlock), lds, s, a, phi, vel, d, dt, mobility, tl,
                   phibar, mubar, psibar[0], psibar[1], psibar[2], part, zw, scal, istat);
-    launch_kernel(k_adj_sum, dim3(1), dim3(1024), 0, s, (const double*)part, nb, 0, 3, scal,
+    launch_kernel(k_adj_sum, dim3(1), dim3(1024), 0, s, (const double*)part, nb, nb, 0, 0, 3, scal,
                   (int)SC_ADJ_SUM_A);
 }
 
@@ -432,23 +643,27 @@ void launch_adj_wall_couple(hipStream_t s, const Dims& d, double* const u[3],
     const int nb = (3 * d.nx * d.nz + kBlock - 1) / kBlock;
     launch_kernel(k_adj_wall_couple, dim3(nb), dim3(kBlock), 0, s, u[0], u[1], u[2], wall[0],
                   wall[1], wall[2], d, part);
-    launch_kernel(k_adj_sum, dim3(1), dim3(1024), 0, s, (const double*)part, nb, 0, 1, scal, slot);
+    launch_kernel(k_adj_sum, dim3(1), dim3(1024), 0, s, (const double*)part, nb, nb, 0, 0, 1, scal, slot);
 }
 
 void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
                        double* const sbar[3], double inv_eta, double* phibar, double* mubar,
                        const double* const u1[3], const double* const psi_walls[3],
-                       const double* const om_walls[3], double* part) {
-    const SlabGrid g = adj_slab_grid(d);
+                       const double* const om_walls[3], double* part, const double* chk_part,
+                       double rtol, double* scal, int* istat) {
+    const AdjTile tl = adj_tile(d);
+    AdjCheck chk{};
+    if (chk_part) chk = AdjCheck{chk_part, resid_flow_blocks(d), rtol, scal, istat};
     WallPairs wp{};
     for (int c = 0; c < 3; ++c) {
         wp.u[c] = u1 ? u1[c] : nullptr;
         wp.uw[c] = psi_walls[c];
         wp.sw[c] = om_walls[c];
     }
-    launch_kernel(k_adj_source, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mu,
+    const size_t lds = (size_t)4 * (tl.tj + 2) * d.nz * sizeof(double);
+    launch_kernel(k_adj_source, dim3(tl.ntile * tl.nslab), dim3(kBlock), lds, s, phi, mu,
                   (const double*)sbar[0], (const double*)sbar[1], (const double*)sbar[2], d, inv_eta,
-                  g, phibar, mubar, wp, part);
+                  tl, phibar, mubar, wp, part, chk);
 }
 
 void launch_adj_mu1(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
@@ -458,23 +673,18 @@ void launch_adj_mu1(hipStream_t s, const Dims& d, const double* phi, const doubl
                   eps, g, gbar, part);
 }
 
-void launch_adj_sums(hipStream_t s, const Dims& d, const double* part, int first, int nslots,
-                     double* scal) {
-    const SlabGrid g = adj_slab_grid(d);
-    static_assert(SC_ADJ_OMC == SC_ADJ_PSIC + 1 && SC_ADJ_KAPPA == SC_ADJ_PSIC + 2 &&
-                      SC_ADJ_GAMMA == SC_ADJ_PSIC + 3,
-                  "adjoint sums: slots 0-3 map onto consecutive scalars");
-    launch_kernel(k_adj_sum, dim3(1), dim3(1024), 0, s, part, g.gx * g.gi, first, nslots, scal,
-                  (int)SC_ADJ_PSIC);
-}
-
 void launch_adj_mu2(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
                     const double* gbar, const double* scal, int model, double C_b, double eps,
                     double sigma, double dt, double mobility, double rate_V, double k_A,
-                    double* phibar) {
+                    double* phibar, double* part, bool mu1_ran, bool psi_from_source,
+                    double* scal_out) {
+    const AdjTile tl = adj_tile(d);
+    const SlabGrid g1 = adj_slab_grid(d);
+    const AdjSums sums{part, tl.ntile * tl.nslab, mu1_ran ? g1.gx * g1.gi : 0, psi_from_source ? 1 : 0,
+                       scal_out};
     const SlabGrid g = adj_slab_grid(d);
     launch_kernel(k_adj_mu2, dim3(g.gx * g.gi), dim3(kBlock), 0, s, phi, mubar, gbar, scal, d, model,
-                  C_b, eps, sigma, dt, mobility, rate_V, k_A, g, phibar);
+                  C_b, eps, sigma, dt, mobility, rate_V, k_A, g, phibar, sums);
 }
 
 }  // namespace vs

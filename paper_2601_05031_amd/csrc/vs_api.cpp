@@ -1170,8 +1170,8 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
         }
         const double* const cu[3] = {us[0], us[1], us[2]};
         const double* const cs[3] = {ss[0], ss[1], ss[2]};
+        // both residuals in one pass; their check is taken by block 0 of the source kernel
         timed(S, K_RESID_FLOW, [&] { launch_resid_flow(st, d, cu, qc, cs, 0.0, S->part); });
-        timed(S, K_CHECK, [&] { launch_check_flow(st, d, S->part, rtol, S->scal, S->istat); });
         for (int c = 0; c < 3; ++c) {
             sb[c] = ss[c];
             u1w[c] = us[c];
@@ -1195,7 +1195,8 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
     const double* const comw[3] = {S->om[0], S->om[1], S->om[2]};
     timed(S, K_ADJ_SOURCE, [&] {
         launch_adj_source(st, d, phi, S->mu, sb, 1.0 / S->p.eta, adj_prev, mubar,
-                          u1w[0] ? u1w : nullptr, cpsw, comw, S->part);
+                          u1w[0] ? u1w : nullptr, cpsw, comw, S->part,
+                          mc == 1 ? S->part : nullptr, rtol, S->scal, S->istat);
     });
     // mu(phi)
     double* gbar = (double*)S->spec[0];
@@ -1204,14 +1205,12 @@ vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* a
         timed(S, K_ADJ_MU1, [&] {
             launch_adj_mu1(st, d, phi, mubar, S->C_b(), dCb, S->p.eps, gbar, S->part);
         });
-    // the wall couplings (slot 0 unless the general path summed it already) and, for bending,
-    // the kappa and gamma_A terms
-    timed(S, K_ADJ_SUMS, [&] {
-        launch_adj_sums(st, d, S->part, u1w[0] ? 0 : 1, S->p.model == VS_BENDING ? 4 : 2, S->scal);
-    });
+    // the sums of the wall couplings (the psi one unless the general path summed it already)
+    // and, for bending, of the kappa and gamma_A terms ride in the mu2 kernel
     timed(S, K_ADJ_MU2, [&] {
         launch_adj_mu2(st, d, phi, mubar, gbar, S->scal, S->p.model, S->C_b(), S->p.eps, S->p.sigma,
-                       dt, S->p.mobility, S->p.rate_V, S->p.k_A, adj_prev);
+                       dt, S->p.mobility, S->p.rate_V, S->p.k_A, adj_prev, S->part,
+                       S->p.model == VS_BENDING, u1w[0] != nullptr, S->scal);
     });
     HIP_TRY(hipGetLastError());
     int ist[IS_NSTAT];

@@ -117,7 +117,7 @@ static inline SlabGrid slab_grid(int plane, int nx, int maxb) {
     g.gi = (nx + g.ci - 1) / g.ci;
     return g;
 }
-constexpr int kPartialSlots = 12;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
+constexpr int kPartialSlots = 14;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
 
 // ---------------------------------------------------------------- tuned launch shapes
 // Launch shapes that the autotuner (vs_autotune) picks per grid by timing the kernels on a
@@ -348,21 +348,20 @@ struct WallPairs {
     const double* sw[3];   // omega (its wall planes), against Sbar
 };
 // phibar += sum_c D_c^T abar_c, mubar += sum_c D_c^T bbar_c with abar = (1/eta) D mu x Sbar,
-// bbar = (1/eta) Sbar x D phi on the interior rows; block partials: slot 0 the wall coupling of
-// u1 (if given) with the psi walls, slot 1 that of Sbar with the omega walls (each as
-// launch_adj_wall_couple defines it).
+// bbar = (1/eta) Sbar x D phi on the interior rows; block partials of the wall coupling of u1
+// (if given) with the psi walls and of Sbar with the omega walls (each as
+// launch_adj_wall_couple defines it). With chk_part, block 0 first checks the two adjoint
+// solves from their residual partials (launch_check_flow).
 void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
                        double* const sbar[3], double inv_eta, double* phibar, double* mubar,
                        const double* const u1[3], const double* const psi_walls[3],
-                       const double* const om_walls[3], double* part);
-// Bending: gbar = C_b [(3 phi^2 - 1) mubar - eps^2 L^T mubar]; block partials of
-// SC_ADJ_KAPPA (slot 2) and SC_ADJ_GAMMA (slot 3), on the block layout of launch_adj_source.
+                       const double* const om_walls[3], double* part, const double* chk_part,
+                       double rtol, double* scal, int* istat);
+// Bending: gbar = C_b [(3 phi^2 - 1) mubar - eps^2 L^T mubar]; block partials of the kappa and
+// gamma_A terms.
 void launch_adj_mu1(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
                     double C_b, double dCb_dkappa, double eps, double* gbar, double* part);
-// scal[SC_ADJ_PSIC + q] = sum of the partial slot q over the blocks of launch_adj_source and
-// launch_adj_mu1, for q in [first, nslots).
-void launch_adj_sums(hipStream_t s, const Dims& d, const double* part, int first, int nslots,
-                     double* scal);
+int resid_flow_blocks(const Dims& d);
 // Diagnostics (k_diag.hip): sigma_t (device field or NULL) and SC_DG_* sums.
 void launch_diagnostics(hipStream_t s, const Dims& d, const double* phi, double* const omega[3],
                         double* const psi[3], const double* prof, double vz_lo, double vz_hi,
@@ -371,11 +370,14 @@ void launch_diagnostics(hipStream_t s, const Dims& d, const double* phi, double*
 // omega_x += dprof[ny + j], psi_x += dprof[j] at every node (a wall-speed change).
 void launch_shift_profiles(hipStream_t s, const Dims& d, double* omega_x, double* psi_x,
                            const double* dprof);
-// phibar += (d mu/d phi)^T mubar + the volume and area multiplier terms.
+// phibar += (d mu/d phi)^T mubar + the volume and area multiplier terms. Every block sums the
+// gamma_A partials of launch_adj_mu1 (if mu1_ran) itself; block 0 writes SC_ADJ_GAMMA,
+// SC_ADJ_KAPPA, SC_ADJ_OMC and, if psi_from_source, SC_ADJ_PSIC of scal_out from the partials.
 void launch_adj_mu2(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
                     const double* gbar, const double* scal, int model, double C_b, double eps,
                     double sigma, double dt, double mobility, double rate_V, double k_A,
-                    double* phibar);
+                    double* phibar, double* part, bool mu1_ran, bool psi_from_source,
+                    double* scal_out);
 // Residual-norm partials of a solve into slots slot0 .. slot0+5.
 void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
                        const double* const u[3], int ncomp, double* partials, const int* gate,
