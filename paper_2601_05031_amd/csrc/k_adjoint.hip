@@ -32,13 +32,21 @@ constexpr int kAdjSlotPsi = 12;
 constexpr int kAdjSlotOm = 13;
 constexpr int kAdjSlotKappa = 2;
 constexpr int kAdjSlotGamma = 3;
-static_assert(kAdjSlotOm < kPartialSlots, "partial slots");
+constexpr int kAdjSlotAdv = 14;   // three slots: sum a, the wall-speed term, psibar . psi on the walls
+static_assert(kAdjSlotAdv + 3 <= kPartialSlots, "partial slots");
+static_assert(SC_ADJ_WALLV == SC_ADJ_SUM_A + 1 && SC_ADJ_PSIW == SC_ADJ_SUM_A + 2,
+              "the advection sums map onto consecutive scalars");
+// Work of block 0 of the source kernel before its tile: the sums of the advection kernel's
+// partials (into SC_ADJ_SUM_A .. SC_ADJ_PSIW) and, if part is given, the check of the two
+// adjoint solves from their residual partials.
 struct AdjCheck {
     const double* part;   // residual partials of the two adjoint solves, or NULL: no check
     int nblocks;
     double rtol;
     double* scal;
     int* istat;
+    const double* adv;    // partials of k_adj_advect (slots kAdjSlotAdv ..)
+    int adv_nb;
 };
 inline AdjTile adj_tile(const Dims& d) {
     AdjTile t;
@@ -252,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(
     block_sum<3>(acc, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) partials[q * kMaxPartialBlocks + blockIdx.x] = acc[q];
+        for (int q = 0; q < 3; ++q) partials[(kAdjSlotAdv + q) * kMaxPartialBlocks + blockIdx.x] = acc[q];
     }
 }
 
@@ -315,8 +323,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_source(
     double* __restrict__ partials, AdjCheck chk) {
     extern __shared__ double lds[];
     __shared__ double sh[4 * 16];
-    if (chk.part && blockIdx.x == 0)
-        flow_check_block(chk.part, chk.nblocks, chk.rtol, chk.scal, chk.istat, sh, 1);
+    if (blockIdx.x == 0) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int b = threadIdx.x; b < chk.adv_nb; b += blockDim.x) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[q] += chk.adv[(kAdjSlotAdv + q) * kMaxPartialBlocks + b];
+        }
+        block_sum<3>(v, sh);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) chk.scal[SC_ADJ_SUM_A + q] = v[q];
+        }
+        __syncthreads();
+        if (chk.part) flow_check_block(chk.part, chk.nblocks, chk.rtol, chk.scal, chk.istat, sh, 1);
+    }
     const int nz = d.nz;
     const size_t plane = (size_t)d.ny * nz;
     const double r2h = d.inv_2h;
@@ -520,7 +540,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_mu2(const double* __restrict__ p
                                                    double dt, double mob, double rate_V, double k_A,
                                                    SlabGrid sg, double* __restrict__ phibar,
                                                    AdjSums sums) {
-    // gamma_A's adjoint (needed by every block) and, in block 0, the step's other scalars
+    // gamma_A's adjoint (needed by every block; a device-wide fence to let one block gather it
+    // costs more here) and, in block 0, the step's other scalars
     __shared__ double sh[4 * 16];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const bool b0 = blockIdx.x == 0;
@@ -538,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_mu2(const double* __restrict__ p
     if (threadIdx.x == 0) sh[4 * 16 - 1] = v[0];
     __syncthreads();
     const double gamma_bar = sh[4 * 16 - 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (b0 && threadIdx.x == 0) {
         sums.scal[SC_ADJ_GAMMA] = v[0];
         sums.scal[SC_ADJ_KAPPA] = v[1];
         if (sums.psi_on) sums.scal[SC_ADJ_PSIC] = v[2];
@@ -634,8 +655,6 @@ void launch_adj_advect(hipStream_t s, const Dims& d, const double* a, const doub
     const size_t lds = (size_t)6 * (tl.tj + 2) * d.nz * sizeof(double);
     launch_kernel(k_adj_advect, dim3(nb), dim3(kBlock), lds, s, a, phi, vel, d, dt, mobility, tl,
                   phibar, mubar, psibar[0], psibar[1], psibar[2], part, zw, scal, istat);
-    launch_kernel(k_adj_sum, dim3(1), dim3(1024), 0, s, (const double*)part, nb, nb, 0, 0, 3, scal,
-                  (int)SC_ADJ_SUM_A);
 }
 
 void launch_adj_wall_couple(hipStream_t s, const Dims& d, double* const u[3],
@@ -653,7 +672,10 @@ void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const do
                        double rtol, double* scal, int* istat) {
     const AdjTile tl = adj_tile(d);
     AdjCheck chk{};
-    if (chk_part) chk = AdjCheck{chk_part, resid_flow_blocks(d), rtol, scal, istat};
+    if (chk_part) chk = AdjCheck{chk_part, resid_flow_blocks(d), rtol, scal, istat, nullptr, 0};
+    chk.scal = scal;
+    chk.adv = part;
+    chk.adv_nb = tl.ntile * tl.nslab;   // the advection kernel's tiles are the same
     WallPairs wp{};
     for (int c = 0; c < 3; ++c) {
         wp.u[c] = u1 ? u1[c] : nullptr;

@@ -117,7 +117,7 @@ static inline SlabGrid slab_grid(int plane, int nx, int maxb) {
     g.gi = (nx + g.ci - 1) / g.ci;
     return g;
 }
-constexpr int kPartialSlots = 14;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
+constexpr int kPartialSlots = 17;     // values per block; stored value-major: part[q * kMaxPartialBlocks + b]
 
 // ---------------------------------------------------------------- tuned launch shapes
 // Launch shapes that the autotuner (vs_autotune) picks per grid by timing the kernels on a
@@ -331,9 +331,10 @@ void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],
                        double* partials);
 
 // ---------------------------------------------------------------- reverse step (k_adjoint.hip)
-// a = dL/dphi^{n+1}; writes phibar (dL/dphi^n, partial), mubar and psibar(3); gathers
-// SC_ADJ_SUM_A, SC_ADJ_WALLV, SC_ADJ_PSIW. Also clears the status words and residual scalars
-// (as launch_reset_stats) and, if zero_walls is given, the wall rows of those (non-NULL) fields.
+// a = dL/dphi^{n+1}; writes phibar (dL/dphi^n, partial), mubar and psibar(3); block partials
+// of SC_ADJ_SUM_A, SC_ADJ_WALLV, SC_ADJ_PSIW, which launch_adj_source sums. Also clears the
+// status words and residual scalars (as launch_reset_stats) and, if zero_walls is given, the
+// wall rows of those (non-NULL) fields.
 void launch_adj_advect(hipStream_t s, const Dims& d, const double* a, const double* phi,
                        const double* const psi[3], double dt, double mobility, double vz_lo,
                        double vz_hi, double* phibar, double* mubar, double* const psibar[3],
@@ -350,8 +351,9 @@ struct WallPairs {
 // phibar += sum_c D_c^T abar_c, mubar += sum_c D_c^T bbar_c with abar = (1/eta) D mu x Sbar,
 // bbar = (1/eta) Sbar x D phi on the interior rows; block partials of the wall coupling of u1
 // (if given) with the psi walls and of Sbar with the omega walls (each as
-// launch_adj_wall_couple defines it). With chk_part, block 0 first checks the two adjoint
-// solves from their residual partials (launch_check_flow).
+// launch_adj_wall_couple defines it). Block 0 first sums the advection kernel's partials into
+// SC_ADJ_SUM_A .. SC_ADJ_PSIW and, with chk_part, checks the two adjoint solves from their
+// residual partials (launch_check_flow).
 void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const double* mu,
                        double* const sbar[3], double inv_eta, double* phibar, double* mubar,
                        const double* const u1[3], const double* const psi_walls[3],
