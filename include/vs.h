@@ -275,7 +275,7 @@ vs_status vs_profile_read(vs_state* state, int32_t kernel, double* total_ms, int
  * grid: the x-slab length of the phi update (2, 4, 8 planes per lane), the block caps of the
  * volume/area partials (256 .. 2048) and of the flow residual (512 .. 4096), the form of the
  * chemical potential (LDS tiles, or for nz in {64, 128, 256} register marching with 1 or 2
- * rows per wave and 4 .. 16 planes per slab; all forms give the same bits) and, for
+ * rows per wave and 2 .. 16 planes per slab; all forms give the same bits) and, for
  * ny - 2 in {30, 46, 62, 94, 126, 254}, the segment layout of the tridiagonal solves (the
  * default or one with twice/half the lanes per mode) and, in FP64 with nx = nz in
  * {32, 48, 64, 96, 128}, whether the x and z transforms of a direction run as one pass over

@@ -1494,11 +1494,11 @@ vs_status autotune_state(vs_state* S, Tuning* picked) {
         launch_mu(c.st, c.d, c.model, pr, A.mu);
     });
     // the chemical potential's form: LDS tiles, or register marching (n_z in {64, 128, 256})
-    // with 1 or 2 rows per wave and 4 .. 16 planes per slab, as one coordinate
+    // with 1 or 2 rows per wave and 2 .. 16 planes per slab, as one coordinate
     {
         const int zpl = S->d.nz / 64;
         const bool reg_ok = S->d.nz % 64 == 0 && (zpl == 1 || zpl == 2 || zpl == 4);
-        const int cand[][2] = {{0, 8}, {1, 4}, {1, 8}, {1, 16}, {2, 4}, {2, 8}, {2, 16}};
+        const int cand[][2] = {{0, 8}, {1, 2}, {1, 4}, {1, 8}, {1, 16}, {2, 2}, {2, 4}, {2, 8}, {2, 16}};
         int bk = t.mu_kind, bn = t.mu_ni;
         float tb = 1e30f;
         for (const auto& cd : cand) {

@@ -44,7 +44,7 @@ def run(w, shapes, nsteps, precision="fp64"):
 # Cahn-Hilliard; ragged row groups (ny not a multiple of 2 or 8)
 @pytest.mark.parametrize("name,shape", [("vesicle32", (24, 34, 64)), ("vesicle32", (16, 21, 128)),
                                         ("droplet256", (12, 19, 256)), ("droplet256", (24, 26, 128))])
-@pytest.mark.parametrize("mu_kind,mu_ni", [(1, 4), (1, 16), (2, 8), (2, 5)])
+@pytest.mark.parametrize("mu_kind,mu_ni", [(1, 2), (1, 16), (2, 8), (2, 5), (2, 2)])
 def test_register_mu_is_bitwise_the_tile_mu(name, shape, mu_kind, mu_ni):
     w = workload(name, grid=GridSpec(*shape), R0=4.0, nsteps=3, max_cycles=1)
     if name == "vesicle32":
