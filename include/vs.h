@@ -300,7 +300,8 @@ vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[7]);
  * every kernel of a time step is launched once per group, each instance's pointers and
  * parameters read from a device table of argument structs (allocated by the batch: a few KB
  * per instance). Grids of a class not tuned yet are tuned first (vs_autotune on the class's
- * first instance). Instances outside the fused forms (FP64 with poisson_max_cycles > 1) are
+ * first instance; for an FP64 class, a grid tuned only by FP32-refined states is tuned again,
+ * since its transform form was left at the default). Instances outside the fused forms (FP64 with poisson_max_cycles > 1) are
  * stepped one by one. It creates min(nstreams, groups) HIP streams (group g runs on stream
  * g % nstreams) and moves every state onto its stream; `stream` (a hipStream_t, NULL =
  * default) is the origin the batch forks from and joins to. vs_batch_step captures two time

@@ -273,24 +273,33 @@ struct TuneKey {
     int nx, ny, nz;
     bool operator==(const TuneKey& o) const { return nx == o.nx && ny == o.ny && nz == o.nz; }
 };
+// One entry per grid; fp64 records that the FP64-only coordinate (the transform form) was
+// tuned too: an FP32-refined state's tuning leaves it at its default.
+struct TuneEntry {
+    TuneKey k;
+    Tuning t;
+    bool fp64;
+};
 std::mutex g_tune_mu;
-std::vector<std::pair<TuneKey, Tuning>> g_tune;
+std::vector<TuneEntry> g_tune;
 constexpr Tuning kDefaultTuning{4, 1024, 1024, 0, 0, 8, 0};
 
-void set_tuning(const Dims& d, const Tuning& t) {
+void set_tuning(const Dims& d, const Tuning& t, bool fp64 = false) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const TuneKey k{d.nx, d.ny, d.nz};
     for (auto& e : g_tune)
-        if (e.first == k) {
-            e.second = t;
+        if (e.k == k) {
+            e.t = t;
+            e.fp64 = e.fp64 || fp64;
             return;
         }
-    g_tune.push_back({k, t});
+    g_tune.push_back({k, t, fp64});
 }
-bool tuned(const Dims& d) {
+// Tuned for states of this precision (an FP64 state needs the FP64 coordinate tuned as well).
+bool tuned(const Dims& d, bool f32) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& e : g_tune)
-        if (e.first == TuneKey{d.nx, d.ny, d.nz}) return true;
+        if (e.k == TuneKey{d.nx, d.ny, d.nz}) return f32 || e.fp64;
     return false;
 }
 }  // namespace
@@ -298,7 +307,7 @@ bool tuned(const Dims& d) {
 Tuning vs::tuning_for(const Dims& d) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& e : g_tune)
-        if (e.first == TuneKey{d.nx, d.ny, d.nz}) return e.second;
+        if (e.k == TuneKey{d.nx, d.ny, d.nz}) return e.t;
     return kDefaultTuning;
 }
 
@@ -1551,6 +1560,7 @@ vs_status autotune_state(vs_state* S, Tuning* picked) {
     HIP_TRY(hipMemcpyAsync(S->mu, S->src[2], fbytes, hipMemcpyDeviceToDevice, S->stream));
     HIP_TRY(hipMemcpyAsync(S->scal, sc_save, sizeof sc_save, hipMemcpyHostToDevice, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
+    set_tuning(S->d, t, !S->f32);
     if (picked) *picked = t;
     return VS_OK;
 }
@@ -1572,7 +1582,7 @@ extern "C" vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t sha
     if (t.mu_ni < 1 || t.mu_ni > 64) return fail(VS_E_ARG, "mu_ni must be in [1, 64]");
     if (t.plane != 0 && t.plane != 1) return fail(VS_E_ARG, "plane must be 0 or 1");
     Dims d{grid->nx, grid->ny, grid->nz, grid->ny - 2, grid->h, 0.0, 0.0};
-    set_tuning(d, t);
+    set_tuning(d, t, true);
     return VS_OK;
 }
 
@@ -1846,7 +1856,7 @@ vs_status vs_batch_create(vs_state* const* states, int32_t n, void* stream, int3
         for (vs_state* S : B->cls[c].st) S->stream = B->streams[c % ns];
     // launch shapes of every grid class not tuned yet, on its first instance
     for (BatchClass& C : B->cls) {
-        if (tuned(C.d)) continue;
+        if (tuned(C.d, C.st[0]->f32)) continue;
         const vs_status st = autotune_state(C.st[0], nullptr);
         if (st != VS_OK) {
             vs_batch_destroy(B);
