@@ -60,12 +60,17 @@ enum { VS_BENDING = 1, VS_CAHN_HILLIARD = 2 };
  * phi update is computed in FP32 arithmetic (the increment added to the FP64 phi); the
  * chemical potential is computed in FP64 and stored as FP32 (FP32 arithmetic there costs ~1e-5
  * in mu); the volume/area integrals are FP64; each step's two flow problems run
- * defect-correction cycles from the previous step's fields: an FP64 residual, its correction
- * solved in FP32 (transforms and tridiagonal solves), an FP64 update, an FP64 check, until the
- * relative residuals meet poisson_rtol (up to poisson_max_cycles; the initial solve takes at
- * least 4). S stays FP64 because FP32 rounding of S alone moves the small components of psi by
- * ~3e-6. It needs nx, nz in {32, 48, 64, 96, 128, 192, 256} and 4 <= ny - 2 <= 256. In this
- * mode vs_field_offset(VS_MU) points at nx*ny*nz floats. */
+ * defect-correction cycles: an FP64 residual, its correction solved in FP32 (transforms and
+ * tridiagonal solves), an FP64 update, an FP64 check, until the relative residuals meet
+ * poisson_rtol (up to poisson_max_cycles; the initial solve takes at least 4). The first cycle
+ * of a step starts from omega and psi extrapolated in time from the last two steps'
+ * increments (held in FP32 in the workspace: 48 bytes per node more than VS_FP64): quadratic
+ * extrapolation leaves a residual small enough that one FP32 cycle usually meets rtol = 1e-10,
+ * where the previous step's fields alone need two. The first two steps after vs_init or
+ * vs_load_state (checkpoints hold no increments) extrapolate from fewer steps. S stays FP64
+ * because FP32 rounding of S alone moves the small components of psi by ~3e-6. It needs nx, nz
+ * in {32, 48, 64, 96, 128, 192, 256} and 4 <= ny - 2 <= 256. In this mode
+ * vs_field_offset(VS_MU) points at nx*ny*nz floats. */
 enum { VS_FP64 = 1, VS_FP32_REFINED = 2 };
 /* vs_params.flags */
 enum { VS_ALLOW_UNSTABLE = 1 };
@@ -258,7 +263,9 @@ vs_status vs_get_scalars(vs_state* state, double out[VS_NSCALARS]);
  * blob == NULL only *bytes is set to the size needed. Synchronises. */
 vs_status vs_save_state(vs_state* state, void* blob, size_t* bytes);
 /* Restore a checkpoint written by vs_save_state for the same grid and wall kind, from host or
- * device memory. Synchronises. */
+ * device memory. In VS_FP32_REFINED the time extrapolation of the flow fields starts over (the
+ * next steps may take more cycles; the fields agree with an uninterrupted run to within the
+ * solve tolerance, not bit for bit). Synchronises. */
 vs_status vs_load_state(vs_state* state, const void* blob, size_t bytes);
 
 /* Per-kernel timing with HIP events on the state's stream, for measurement tools:

@@ -1,6 +1,8 @@
 // Tridiagonal solves in y of the Poisson problems of the main text, eq. (5b) and (5c), per
 // Hartley mode (the spectral transforms are in k_spectral.hip), and the residual norms and
 // convergence checks that verify every solve on the device.
+#include <type_traits>
+
 #include "spectral.h"
 
 namespace vs {
@@ -787,6 +789,119 @@ __global__ __launch_bounds__(kBlock) void k_resid_flow2(Dims d, SlabGrid sg, Res
     }
 }
 
+// The first step of the refined mode's first correction cycle: both flow residuals at the
+// predicted fields u* = u + p (p of order H: 0, the last increment i1, or 2 i1 - i2; the same
+// arithmetic as the update of k_hz_out), r_w = S - L_h omega* (eq. (5b)) and
+// r_psi = -omega* - L_h psi* (eq. (5c)), formed in FP64 and stored in FP32 at the node offsets of
+// spec (vorticity) and spec2 (stream vector) for the z transform that follows. The walk of
+// k_resid_flow2: a block owns one component, W lanes cover 2W consecutive z of one interior
+// row, the slab marches along x with the x-neighbours in registers. Wall rows enter as stored
+// (their increments are zero).
+template <int W, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_rhs_pred(Dims d, SlabGrid sg, RhsFlowArgs one,
+                                                    const RhsFlowArgs* __restrict__ tab) {
+    const int nb = sg.gx * sg.gi;
+    const int lbi = xcd_block(blockIdx.x, gridDim.x);
+    const int inst = BATCH ? lbi / (3 * nb) : 0;
+    const RhsFlowArgs& a = inst_args<BATCH>(one, tab, inst);
+    if (a.gate && *a.gate) return;
+    const int lb0 = lbi - inst * 3 * nb;
+    const int c = lb0 / nb;
+    const int lb = lb0 - c * nb;
+    const int bi = lb / sg.gx;
+    const int t = (lb - bi * sg.gx) * kBlock + threadIdx.x;
+    const int hz = d.nz >> 1;
+    if (t >= d.M * hz) return;
+    const Gl<double>* wc = (const Gl<double>*)pick(a.om, c);
+    const Gl<double>* pc = (const Gl<double>*)pick(a.ps, c);
+    const Gl<double>* sc = (const Gl<double>*)pick(a.src, c);
+    const Gl<float>* w1 = (const Gl<float>*)pick(a.i1, c);
+    const Gl<float>* w2 = (const Gl<float>*)pick(a.i2, c);
+    const Gl<float>* p1 = (const Gl<float>*)pick(a.i1, 3 + c);
+    const Gl<float>* p2 = (const Gl<float>*)pick(a.i2, 3 + c);
+    Gl<float>* ow = (Gl<float>*)pick(a.spec, c);
+    Gl<float>* op = (Gl<float>*)pick(a.spec2, c);
+    const int h = a.hist ? *a.hist : 0;
+    const int jj = t / hz;
+    const int k = 2 * (t - jj * hz);
+    const int j = jj + 1;
+    const int plane = d.ny * d.nz;
+    const int off = j * d.nz + k;
+    const int ln = threadIdx.x & (W - 1);
+    const int k0 = k - 2 * ln;
+    const int kpe = (k0 + 2 * W == d.nz) ? 0 : k0 + 2 * W;
+    const int kme = (k0 == 0) ? d.nz - 1 : k0 - 1;
+    const int i0 = bi * sg.ci;
+    const int i1 = min(d.nx, i0 + sg.ci);
+    const int im0 = (i0 == 0) ? d.nx - 1 : i0 - 1;
+    auto walk = [&](auto hc) {
+        constexpr int H = decltype(hc)::value;
+        // u* at a pair of nodes and at one node
+        auto ld2 = [&](const Gl<double>* u, const Gl<float>* f1, const Gl<float>* f2, int o) -> double2 {
+            double2 v = ldg2(u + o);
+            if constexpr (H == 1) {
+                const double2 e = ldg2(f1 + o);
+                v.x = v.x + e.x;
+                v.y = v.y + e.y;
+            } else if constexpr (H == 2) {
+                const double2 e1 = ldg2(f1 + o), e2 = ldg2(f2 + o);
+                v.x = v.x + (2.0 * e1.x - e2.x);
+                v.y = v.y + (2.0 * e1.y - e2.y);
+            }
+            return v;
+        };
+        auto ld1 = [&](const Gl<double>* u, const Gl<float>* f1, const Gl<float>* f2, int o) -> double {
+            if constexpr (H == 0) return u[o];
+            else if constexpr (H == 1) return u[o] + (double)f1[o];
+            else return u[o] + (2.0 * (double)f1[o] - (double)f2[o]);
+        };
+        auto zn = [&](double2 v, double em, double ep, double& zm0, double& zp1) {
+            const double prev = __shfl_up(v.y, 1, W), next = __shfl_down(v.x, 1, W);
+            zm0 = ln == 0 ? em : prev;
+            zp1 = ln == W - 1 ? ep : next;
+        };
+        double2 wm = ld2(wc, w1, w2, im0 * plane + off), wx = ld2(wc, w1, w2, i0 * plane + off);
+        double2 pm = ld2(pc, p1, p2, im0 * plane + off), px = ld2(pc, p1, p2, i0 * plane + off);
+#pragma unroll 2
+        for (int i = i0; i < i1; ++i) {
+            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+            const int rb = i * plane + j * d.nz;
+            const int c0 = rb + k;
+            const double2 b = ldg2(sc + c0);
+            const double2 ylo = ld2(wc, w1, w2, c0 - d.nz), yhi = ld2(wc, w1, w2, c0 + d.nz);
+            const double2 qlo = ld2(pc, p1, p2, c0 - d.nz), qhi = ld2(pc, p1, p2, c0 + d.nz);
+            const int ome = rb + kme, ope = rb + kpe;
+            const double wem = ld1(wc, w1, w2, ome), wep = ld1(wc, w1, w2, ope);
+            const double pem = ld1(pc, p1, p2, ome), pep = ld1(pc, p1, p2, ope);
+            // the next plane's centres last: they stay in flight while this plane is formed
+            const double2 wp = ld2(wc, w1, w2, ip * plane + off);
+            const double2 pp = ld2(pc, p1, p2, ip * plane + off);
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                double zm0, zp1;
+                zn(wx, wem, wep, zm0, zp1);
+                const double l0 = (wp.x + wm.x + ylo.x + yhi.x + wx.y + zm0 - 6.0 * wx.x) * d.inv_h2;
+                const double l1 = (wp.y + wm.y + ylo.y + yhi.y + zp1 + wx.x - 6.0 * wx.y) * d.inv_h2;
+                stc<float>(ow + c0, (float)(b.x - l0), (float)(b.y - l1));
+            }
+            {
+                double zm0, zp1;
+                zn(px, pem, pep, zm0, zp1);
+                const double l0 = (pp.x + pm.x + qlo.x + qhi.x + px.y + zm0 - 6.0 * px.x) * d.inv_h2;
+                const double l1 = (pp.y + pm.y + qlo.y + qhi.y + zp1 + px.x - 6.0 * px.y) * d.inv_h2;
+                stc<float>(op + c0, (float)(-wx.x - l0), (float)(-wx.y - l1));
+            }
+            wm = wx;
+            wx = wp;
+            pm = px;
+            px = pp;
+        }
+    };
+    if (h == 0) walk(std::integral_constant<int, 0>{});
+    else if (h == 1) walk(std::integral_constant<int, 1>{});
+    else walk(std::integral_constant<int, 2>{});
+}
+
 // check: relative residual sqrt(sum_c r^2 / sum_c b~^2) in a fixed summation order; sets the
 // convergence flag that gates the following cycles, counts the cycle and raises ST_NOCONV
 // on the last allowed cycle, ST_NONFINITE on NaN/Inf.
@@ -1058,6 +1173,20 @@ void launch_resid_flow_over(hipStream_t s, const Dims& d, bool f32src, const Ove
         resid_flow_t<float>(s, d, a);
     else
         resid_flow_t<double>(s, d, a);
+}
+
+void launch_rhs_pred(hipStream_t s, const Dims& d, const Over<RhsFlowArgs>& a) {
+    const SlabGrid g = slab_grid(d.M * (d.nz / 2), d.nx, tuning_for(d).res_maxb);
+    const unsigned ni = a.tab ? (unsigned)a.n : 1u;
+    const dim3 gr(3 * g.gx * g.gi * ni);
+    auto go = [&](auto kt, auto kf) {
+        if (a.tab) launch_kernel(kt, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
+        else launch_kernel(kf, gr, dim3(kBlock), 0, s, d, g, a.one, a.tab);
+    };
+    if (d.nz % 128 == 0) go(k_rhs_pred<64, true>, k_rhs_pred<64, false>);
+    else if (d.nz % 64 == 0) go(k_rhs_pred<32, true>, k_rhs_pred<32, false>);
+    else if (d.nz % 32 == 0) go(k_rhs_pred<16, true>, k_rhs_pred<16, false>);
+    else go(k_rhs_pred<8, true>, k_rhs_pred<8, false>);
 }
 
 void launch_resid_flow(hipStream_t s, const Dims& d, const double* const om[3],

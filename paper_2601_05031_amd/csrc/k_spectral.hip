@@ -27,6 +27,8 @@
 // and likewise for b. Line lengths n = B A (B in {8, 16}, A in {3, 4, 6, 8, 12, 16}) use a
 // two-pass register FFT; other 2^a 3^b lengths a Stockham transform in LDS with radix-4/2/3
 // passes. Twiddles come from a table exp(-2 pi i m/n).
+#include <type_traits>
+
 #include "spectral.h"
 
 namespace vs {
@@ -480,86 +482,6 @@ __global__ __launch_bounds__(64) void k_rhs_hz(Dims d, const double2* __restrict
     two_pass_hartley<B, A, false, T>(Y, tw, prep, load, store);
 }
 
-// Residuals of both flow problems at the current fields, Hartley-transformed along z: the
-// first step of a defect-correction cycle of the refined mode. Components 0-2: the vorticity
-// residual r_w = S - L_h omega (eq. (5b)), into spec; 3-5: the stream-vector residual
-// r_psi = -omega - L_h psi (eq. (5c)), into spec2. The residual is formed in FP64 from the
-// FP64 fields and source (the wall rows of omega and psi are the Dirichlet data), then
-// transformed in the storage precision ST. Block = (2L consecutive interior rows, component) [x instances],
-// ordered per XCD; the row values are evaluated lane-consecutively into the LDS tile first.
-template <int B, int A, class ST, bool BATCH>
-__global__ __launch_bounds__(64) void k_rhs_flow_hz(Dims d, RhsFlowArgs one,
-                                                   const RhsFlowArgs* __restrict__ tab) {
-    using P = TwoPass<B, A>;
-    using T = ST;
-    using C = C2<T>;
-    constexpr int N = P::N;
-    constexpr int L = P::L;
-    static_assert(L * N <= P::LDS, "input tile must fit in the exchange buffer");
-    static_assert(L * A <= 64, "one pass-1 round per lane");
-    const int gx = gridDim.x;
-    const int lb = xcd_block(blockIdx.x + gx * blockIdx.y, gx * gridDim.y);
-    const int cg = lb / gx;                       // instance * 6 + component
-    const int inst = BATCH ? cg / 6 : 0;
-    const int cc = cg - inst * 6;
-    const int bx = lb - cg * gx;
-    const RhsFlowArgs& a = inst_args<BATCH>(one, tab, inst);
-    if (a.gate && *a.gate) return;
-    __shared__ C Y[P::LDS];
-    const int nrows = d.nx * d.M;
-    const int r0 = bx * 2 * L;
-    const bool vort = cc < 3;
-    const int c = vort ? cc : cc - 3;
-    const Gl<double>* uc = (const Gl<double>*)(vort ? pick(a.om, c) : pick(a.ps, c));
-    const Gl<double>* sc = (const Gl<double>*)pick(a.src, c);
-    const Gl<double>* wc = (const Gl<double>*)pick(a.om, c);
-    Gl<ST>* out = (Gl<ST>*)(vort ? pick(a.spec, c) : pick(a.spec2, c));
-#pragma unroll 4
-    for (int lr = 0; lr < 2 * L; ++lr) {
-        const int r = r0 + lr;
-        C* row = &Y[(lr >> 1) * N];
-        if (r < nrows) {
-            const int i = r / d.M;
-            const int j = 1 + (r - i * d.M);
-            const int ip = (i + 1 == d.nx) ? 0 : i + 1;
-            const int im = (i == 0) ? d.nx - 1 : i - 1;
-            const int rb = node(d, i, j, 0), xpb = node(d, ip, j, 0), xmb = node(d, im, j, 0);
-#pragma unroll
-            for (int k = threadIdx.x; k < N; k += 64) {
-                const int kp = (k + 1 == d.nz) ? 0 : k + 1;
-                const int km = (k == 0) ? d.nz - 1 : k - 1;
-                const int c0 = rb + k;
-                const double b = vort ? (double)sc[c0] : -wc[c0];
-                const double lap = (uc[xpb + k] + uc[xmb + k] + uc[c0 + d.nz] + uc[c0 - d.nz] +
-                                    uc[rb + kp] + uc[rb + km] - 6.0 * uc[c0]) * d.inv_h2;
-                reinterpret_cast<T*>(&row[k])[lr & 1] = (T)(b - lap);
-            }
-        } else {
-#pragma unroll
-            for (int k = threadIdx.x; k < N; k += 64) reinterpret_cast<T*>(&row[k])[lr & 1] = (T)0;
-        }
-    }
-    __syncthreads();
-    C xin[B];
-    const int it = threadIdx.x;
-    const bool act = it < L * A;
-    const int line = act ? it / A : 0, k1 = act ? it % A : 0;
-    if (act) {
-#pragma unroll
-        for (int k2 = 0; k2 < B; ++k2) xin[k2] = Y[line * N + k1 + A * k2];
-    }
-    __syncthreads();
-    auto prep = [&](int ln) -> RowPair {
-        return RowPair{row_base(d, r0 + 2 * ln, nrows), row_base(d, r0 + 2 * ln + 1, nrows)};
-    };
-    auto load = [&](const RowPair&, int, int k2) -> C { return xin[k2]; };
-    auto store = [&](const RowPair& rp, int p, T ha, T hb) {
-        if (rp.a >= 0) out[rp.a + p] = (ST)ha;
-        if (rp.b >= 0) out[rp.b + p] = (ST)hb;
-    };
-    two_pass_hartley<B, A, false, T>(Y, a.tw, prep, load, store);
-}
-
 // dht_x, two-pass form: block = (2L consecutive z-modes q, interior row j, component c);
 // lines are the q-pairs (q, q+1), read and written as one 16-byte value.
 // NC: the component count of the launch (3, or 6 for the vorticity and stream-vector fields
@@ -609,6 +531,12 @@ __global__ __launch_bounds__(64) void k_hz_out(Dims d, ZArgs one, const ZArgs* _
     const Gl<ST>* sc = (const Gl<ST>*)pick(a.spec, c);
     Gl<double>* uc = (Gl<double>*)pick(a.u, c);
     const int add = a.add;
+    // the refined mode's time increments: h = -1 a later cycle (accumulate), 0..2 the first
+    // cycle with that many increments held (the predictor of k_rhs_pred, same arithmetic)
+    Gl<float>* __restrict__ ic = (Gl<float>*)pick(a.inc, c);
+    const Gl<float>* __restrict__ pc = (const Gl<float>*)pick(a.pinc, c);
+    const int h = a.hist ? *a.hist : -1;
+    if (a.hist_out && blockIdx.x == 0 && c == 0 && threadIdx.x == 0) *a.hist_out = h < 2 ? h + 1 : 2;
     auto prep = [&](int line) -> RowPair {
         return RowPair{row_base(d, r0 + 2 * line, nrows), row_base(d, r0 + 2 * line + 1, nrows)};
     };
@@ -616,17 +544,47 @@ __global__ __launch_bounds__(64) void k_hz_out(Dims d, ZArgs one, const ZArgs* _
         const int k = k1 + A * k2;
         return mkc<T>(rp.a >= 0 ? ldt<T>(sc + rp.a + k) : (T)0, rp.b >= 0 ? ldt<T>(sc + rp.b + k) : (T)0);
     };
-    auto store = [&](const RowPair& rp, int p, T ha, T hb) {
-        if (rp.a >= 0) {
-            Gl<double>* dst = uc + rp.a + p;
-            *dst = add ? *dst + (double)ha : (double)ha;
-        }
-        if (rp.b >= 0) {
-            Gl<double>* dst = uc + rp.b + p;
-            *dst = add ? *dst + (double)hb : (double)hb;
-        }
+    // MODE 0: plain store or add; 1: a later cycle (u += e, inc += e); 2 + H: the first cycle
+    // with H increments held; 5: the forward z pass in place (spec to spec)
+    auto run = [&](auto mc) {
+        constexpr int MODE = decltype(mc)::value;
+        auto put = [&](int o, double e) {
+            Gl<double>* dst = uc + o;
+            if constexpr (MODE == 0) {
+                *dst = add ? *dst + e : e;
+            } else if constexpr (MODE == 1) {
+                *dst = *dst + e;
+                ic[o] = (float)((double)ic[o] + e);
+            } else {
+                double p = 0.0;
+                if constexpr (MODE == 3) p = (double)pc[o];
+                if constexpr (MODE == 4) p = 2.0 * (double)pc[o] - (double)ic[o];
+                *dst = (*dst + p) + e;
+                ic[o] = (float)(p + e);
+            }
+        };
+        auto store = [&](const RowPair& rp, int p, T ha, T hb) {
+            if constexpr (MODE == 5) {
+                Gl<ST>* sw = const_cast<Gl<ST>*>(sc);
+                if (rp.a >= 0) sw[rp.a + p] = (ST)ha;
+                if (rp.b >= 0) sw[rp.b + p] = (ST)hb;
+            } else {
+                if (rp.a >= 0) put(rp.a + p, (double)ha);
+                if (rp.b >= 0) put(rp.b + p, (double)hb);
+            }
+        };
+        two_pass_hartley<B, A, false, T>(Y, a.tw, prep, load, store);
     };
-    two_pass_hartley<B, A, false, T>(Y, a.tw, prep, load, store);
+    if constexpr (std::is_same_v<ST, float> && NC == 6) {   // the refined mode's passes
+        if (a.self) run(std::integral_constant<int, 5>{});
+        else if (!add || !ic) run(std::integral_constant<int, 0>{});
+        else if (h < 0) run(std::integral_constant<int, 1>{});
+        else if (h == 0) run(std::integral_constant<int, 2>{});
+        else if (h == 1) run(std::integral_constant<int, 3>{});
+        else run(std::integral_constant<int, 4>{});
+    } else {
+        run(std::integral_constant<int, 0>{});
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1040,23 +998,6 @@ void launch_dht_z_out(hipStream_t s, const Dims& d, const FftPlan& pz, const dou
     z.gate = gate;
     z.add = add;
     launch_hz(s, d, pz, f32, ncomp, over_one(z));
-}
-
-void launch_rhs_flow(hipStream_t s, const Dims& d, const Over<RhsFlowArgs>& a) {
-    const int nrows = d.nx * d.M;
-    const unsigned ni = a.tab ? (unsigned)a.n : 1u;
-    int B, A;
-    two_pass_shape(d.nz, B, A);
-#define VS_CASE(b, a_)                                                                         \
-    if (B == b && A == a_) {                                                                   \
-        const int rows = 2 * TwoPass<b, a_>::L;                                                \
-        const dim3 g((nrows + rows - 1) / rows, 6 * ni);                                       \
-        if (a.tab) launch_kernel((k_rhs_flow_hz<b, a_, float, true>), g, dim3(64), 0, s, d, a.one, a.tab); \
-        else launch_kernel((k_rhs_flow_hz<b, a_, float, false>), g, dim3(64), 0, s, d, a.one, a.tab); \
-        return;                                                                                \
-    }
-    VS_TWO_PASS_CASES(VS_CASE)
-#undef VS_CASE
 }
 
 }  // namespace vs

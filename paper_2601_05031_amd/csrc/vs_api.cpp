@@ -45,14 +45,15 @@ enum KClass {
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
     K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_DHT_X_PAIR, K_DHT_Z_OUT_PAIR,
     K_RHS_FLOW, K_ADJ_ADVECT, K_ADJ_WALLS, K_ADJ_SOURCE, K_ADJ_MU1, K_ADJ_MU2, K_ADJ_SUMS, K_DHT_ZX,
-    K_DHT_XZ_PAIR, K_NCLASS
+    K_DHT_XZ_PAIR, K_RHS_FLOW_Z, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
     "rhs_dht_z_field", "dht_x", "tridiag_y", "tridiag_pair", "dht_z_out", "resid_norm_omega",
     "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
     "resid_norm_flow", "dht_x_pair", "dht_z_out_pair", "rhs_flow", "adj_advect",
-    "adj_wall_couple", "adj_source", "adj_mu1", "adj_mu2", "adj_sums", "dht_zx", "dht_xz_pair"};
+    "adj_wall_couple", "adj_source", "adj_mu1", "adj_mu2", "adj_sums", "dht_zx", "dht_xz_pair",
+    "rhs_flow_z"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -76,10 +77,12 @@ struct Layout {
     size_t off_spec2;       // 3 spectral fields: the stream-vector modes
     size_t off_twx, off_twz, off_tri, off_part, off_prof, off_scal, off_istat;
     size_t off_tri2;        // the shifted vorticity pivots of the inertial variant (or 0)
+    size_t off_inc;         // refined mode: 2 x 6 FP32 fields, the last two time increments
+                            // of omega and psi (or 0)
     size_t total;
 };
 
-Layout make_layout(const vs_grid& g, bool inertial) {
+Layout make_layout(const vs_grid& g, bool inertial, bool refined) {
     const size_t N = (size_t)g.nx * g.ny * g.nz;
     const size_t fb = align_up(N * sizeof(double));
     const size_t M = (size_t)g.ny - 2;
@@ -100,6 +103,11 @@ Layout make_layout(const vs_grid& g, bool inertial) {
     if (inertial) {
         L.off_tri2 = o;
         o += align_up((size_t)(g.nx / 2 + 1) * (g.nz / 2 + 1) * (M + 1) * sizeof(double));
+    }
+    L.off_inc = 0;
+    if (refined) {
+        L.off_inc = o;
+        o += 12 * align_up(N * sizeof(float));
     }
     L.total = o;
     return L;
@@ -215,6 +223,9 @@ struct vs_state {
     double* src[3] = {};
     void* spec2[3] = {};
     bool f32 = false;         // refined mode: spectral intermediates stored as float
+    // refined mode: time increments of omega (0-2) and psi (3-5) in two FP32 buffers whose
+    // roles alternate with the step parity (the predictor of the first correction cycle)
+    float* inc[2][6] = {};
     double psi_wall_lo[3] = {0, 0, 0}, psi_wall_hi[3] = {0, 0, 0};
     double om_wall_lo[3] = {0, 0, 0}, om_wall_hi[3] = {0, 0, 0};
     double2* twx = nullptr;
@@ -404,6 +415,7 @@ struct StepArgs {
     Over<ResArgs> res;
     Over<ChkArgs> chk;
     Over<RhsFlowArgs> rf[2];
+    Over<ZArgs> zs[2];
     Over<HxArgs> hxc[2];
     Over<TriArgs> trc[2];
     Over<ZArgs> zadd[2];
@@ -412,8 +424,8 @@ struct StepArgs {
 };
 #define VS_STEP_FIELDS(X)                                                                   \
     X(adv) X(va) X(mu) X(src) X(zfwd) X(hx3) X(hx6) X(tri) X(zout6) X(res) X(chk) X(rf[0])  \
-    X(rf[1]) X(hxc[0]) X(hxc[1]) X(trc[0]) X(trc[1]) X(zadd[0]) X(zadd[1]) X(resc[0])       \
-    X(resc[1]) X(chkc[0]) X(chkc[1])
+    X(rf[1]) X(zs[0]) X(zs[1]) X(hxc[0]) X(hxc[1]) X(trc[0]) X(trc[1]) X(zadd[0]) X(zadd[1]) \
+    X(resc[0]) X(resc[1]) X(chkc[0]) X(chkc[1])
 
 // The fused refined-mode cycle and the fused FP64 pass need two-pass transform lengths and a
 // segmented tridiagonal layout; the refined mode is offered only there.
@@ -522,6 +534,11 @@ StepArgs step_args(vs_state* S, int par, double dt, bool with_ck) {
     ck.istat = S->istat;
     ck.rtol = S->p.poisson_rtol;
     A.chk = over_one(ck);
+    // the refined mode's predictor (steps only, not the initial solve): increments i1 = inc[par]
+    // (the last step's) and i2 = inc[1 - par] (the one before), which the first cycle's update
+    // overwrites with this step's increment; the held count alternates between two slots
+    const bool pred = S->f32 && par >= 0 && S->inc[0][0];
+    const int q1 = par < 0 ? 0 : par, q2 = 1 - q1;
     for (int g = 0; g < 2; ++g) {
         const int* gate = g ? S->istat + IS_CONV : nullptr;
         RhsFlowArgs rf{};
@@ -534,7 +551,23 @@ StepArgs step_args(vs_state* S, int par, double dt, bool with_ck) {
         }
         rf.tw = S->twz;
         rf.gate = gate;
+        if (pred && g == 0) {
+            for (int q = 0; q < 6; ++q) {
+                rf.i1[q] = S->inc[q1][q];
+                rf.i2[q] = S->inc[q2][q];
+            }
+            rf.hist = S->istat + IS_HIST + q1;
+        }
         A.rf[g] = over_one(rf);
+        ZArgs zsf{};
+        for (int c = 0; c < 3; ++c) {
+            zsf.spec[c] = S->spec[c];
+            zsf.spec[3 + c] = S->spec2[c];
+        }
+        zsf.tw = S->twz;
+        zsf.gate = gate;
+        zsf.self = 1;
+        A.zs[g] = over_one(zsf);
         HxArgs hc = h6;
         hc.gate = gate;
         A.hxc[g] = over_one(hc);
@@ -545,6 +578,14 @@ StepArgs step_args(vs_state* S, int par, double dt, bool with_ck) {
         ZArgs za = z6;
         za.add = 1;
         za.gate = gate;
+        if (pred) {
+            for (int q = 0; q < 6; ++q) za.inc[q] = S->inc[q2][q];
+            if (g == 0) {
+                for (int q = 0; q < 6; ++q) za.pinc[q] = S->inc[q1][q];
+                za.hist = S->istat + IS_HIST + q1;
+                za.hist_out = S->istat + IS_HIST + q2;
+            }
+        }
         A.zadd[g] = over_one(za);
         ResArgs rc = r;
         rc.gate = gate;
@@ -602,7 +643,8 @@ bool enqueue_flow_args(const StepCfg& c, const StepArgs& A, bool defer, int max_
     if (c.f32) {
         for (int cyc = 0; cyc < max_cycles; ++cyc) {
             const int g = cyc ? 1 : 0;
-            timed_cfg(c, K_RHS_FLOW, [&] { launch_rhs_flow(c.st, c.d, A.rf[g]); });
+            timed_cfg(c, K_RHS_FLOW, [&] { launch_rhs_pred(c.st, c.d, A.rf[g]); });
+            timed_cfg(c, K_RHS_FLOW_Z, [&] { launch_hz(c.st, c.d, c.pz, true, 6, A.zs[g]); });
             timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
             timed_cfg(c, K_TRIDIAG_PAIR, [&] { launch_tri_pair(c.st, c.d, true, true, A.trc[g]); });
             timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
@@ -804,7 +846,7 @@ vs_status vs_workspace_bytes(const vs_grid* grid, const vs_params* params, size_
     if (st != VS_OK) return st;
     if ((st = check_params(params)) != VS_OK) return st;
     if (!bytes) return fail(VS_E_ARG, "bytes is NULL");
-    *bytes = make_layout(*grid, params->rho > 0.0).total;
+    *bytes = make_layout(*grid, params->rho > 0.0, params->precision == VS_FP32_REFINED).total;
     return VS_OK;
 }
 
@@ -818,7 +860,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     if ((st = check_walls(walls)) != VS_OK) return st;
     if ((st = check_params(params)) != VS_OK) return st;
     if (!phi0) return fail(VS_E_ARG, "phi0 is NULL");
-    const Layout L = make_layout(*grid, params->rho > 0.0);
+    const Layout L = make_layout(*grid, params->rho > 0.0, params->precision == VS_FP32_REFINED);
     {
         Dims dd{grid->nx, grid->ny, grid->nz, grid->ny - 2, grid->h, 0.0, 0.0};
         if (params->precision == VS_FP32_REFINED && !fused_flow_ok(dd))
@@ -866,6 +908,10 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     S->twz = (double2*)(S->ws + L.off_twz);
     S->tri = (double*)(S->ws + L.off_tri);
     S->tri2 = L.off_tri2 ? (double*)(S->ws + L.off_tri2) : nullptr;
+    if (L.off_inc)
+        for (int b = 0; b < 2; ++b)
+            for (int q = 0; q < 6; ++q)
+                S->inc[b][q] = (float*)(S->ws + L.off_inc + (6 * b + q) * align_up(N * sizeof(float)));
     S->part = (double*)(S->ws + L.off_part);
     S->prof = (double*)(S->ws + L.off_prof);
     S->scal = (double*)(S->ws + L.off_scal);
@@ -899,6 +945,8 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     INIT_TRY(hipMemcpyAsync(S->phi[0], phi0, N * sizeof(double), hipMemcpyDeviceToDevice, S->stream));
     INIT_TRY(hipMemsetAsync(S->scal, 0, SC_NSCAL * sizeof(double), S->stream));
     INIT_TRY(hipMemsetAsync(S->istat, 0, IS_NSTAT * sizeof(int), S->stream));
+    // the increments' wall rows are read (as zero) by the predictor and never written
+    if (L.off_inc) INIT_TRY(hipMemsetAsync(S->ws + L.off_inc, 0, L.total - L.off_inc, S->stream));
     launch_fill_profile(S->stream, S->d, S->ps[0], S->prof);
     launch_fill_profile(S->stream, S->d, S->om[0], S->prof + grid->ny);
     for (int c = 1; c < 3; ++c) {
@@ -1394,6 +1442,9 @@ vs_status vs_load_state(vs_state* S, const void* blob, size_t bytes) {
                                dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
     HIP_TRY(hipMemcpy(S->scal, hd.scal, sizeof hd.scal, hipMemcpyHostToDevice));
+    // the checkpoint holds no time increments: the refined mode's predictor starts over
+    const int no_hist[2] = {0, 0};
+    HIP_TRY(hipMemcpy(S->istat + IS_HIST, no_hist, sizeof no_hist, hipMemcpyHostToDevice));
     S->step = hd.step;
     S->gamma_host = hd.scal[SC_GAMMA];
     if (hd.u0 != S->w.u0 || hd.u1 != S->w.u1) {

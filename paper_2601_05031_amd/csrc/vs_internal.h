@@ -80,6 +80,8 @@ enum {
     IS_FLAGS = 0,             // bit mask of ST_* below
     IS_CONV = 1,              // 1 once the running Poisson solve met rtol (gates later cycles)
     IS_CYCLES = 2,            // Poisson cycles run since the last reset
+    IS_HIST = 3,              // refined mode: time increments of omega and psi the predictor
+                              // holds (0, 1, 2), slots 3 and 4 by the parity of the step
     IS_NSTAT = 16
 };
 enum { ST_NOCONV = 1, ST_NONFINITE = 2 };
@@ -226,6 +228,15 @@ struct ZArgs {
     const double2* tw;
     const int* gate;     // skip when *gate != 0 (a converged defect-correction loop), or null
     int add;
+    // refined mode (add = 1): the time increment of each field, FP32. With hist set (the first
+    // cycle of a step): u <- u + p + e, inc <- p + e, where p is the predictor of the residual
+    // pass (see RhsFlowArgs, read from pinc and inc) and e the correction; *hist_out gets
+    // min(*hist + 1, 2). With hist null and inc set (a later cycle): u <- u + e, inc <- inc + e.
+    float* inc[6];
+    const float* pinc[6];
+    const int* hist;
+    int* hist_out;
+    int self;            // refined mode: transform FP32 spec in place (the forward z pass)
 };
 // x transforms, in place on spec[c], c < ncomp <= 6.
 struct HxArgs {
@@ -260,9 +271,8 @@ struct ChkArgs {
     double rtol;
     const int* gate;
 };
-// Residuals of both flow problems at the current fields, transformed along z into FP32
-// modes (the refined mode's defect-correction cycle): vorticity into spec, stream vector
-// into spec2.
+// Residuals of both flow problems at the current (or predicted) fields, stored in FP32 for the
+// refined mode's defect-correction cycle: vorticity into spec, stream vector into spec2.
 struct RhsFlowArgs {
     const void* src[3];
     const double* om[3];
@@ -271,7 +281,16 @@ struct RhsFlowArgs {
     void* spec2[3];
     const double2* tw;
     const int* gate;
+    // predictor of the first cycle of a step (refined mode), or hist null: the residual is
+    // taken at u + p with p = 0, i1, 2 i1 - i2 for *hist = 0, 1, 2 held increments (i1 the
+    // last step's increment u^n - u^{n-1}, i2 the one before; components 0-2 omega, 3-5 psi)
+    const float* i1[6];
+    const float* i2[6];
+    const int* hist;
 };
+// The refined mode's first-cycle residuals at the predicted fields (k_rhs_pred), in FP32 at the
+// node offsets of spec and spec2, for an in-place z pass (ZArgs::self) to transform.
+void launch_rhs_pred(hipStream_t s, const Dims& d, const Over<RhsFlowArgs>& a);
 
 // True when both periodic lengths have two-pass transforms and M a segmented solve: the forms
 // the fused flow pass, the refined mode's fused cycle and batched launches use.
@@ -290,7 +309,6 @@ void launch_hx(hipStream_t s, const Dims& d, const FftPlan& px, bool f32, int nc
                const Over<HxArgs>& a);
 // corr: the correction form (homogeneous walls, stream-vector residual modes in spec2).
 void launch_tri_pair(hipStream_t s, const Dims& d, bool f32, bool corr, const Over<TriArgs>& a);
-void launch_rhs_flow(hipStream_t s, const Dims& d, const Over<RhsFlowArgs>& a);
 // f32src: S stored as float (the refined mode).
 void launch_resid_flow_over(hipStream_t s, const Dims& d, bool f32src, const Over<ResArgs>& a);
 // last_cycle = 0: a defect-correction cycle that may be followed by another (gated).

@@ -100,6 +100,15 @@ def test_inertial_params_accepted():
     assert n1 > n0
 
 
+def test_refined_workspace_holds_the_increments():
+    # the refined mode keeps two FP32 copies of the six flow components' time increments
+    g = (64, 34, 48, 1.0)
+    n64 = P.workspace_bytes(g, P.make_params())
+    n32 = P.workspace_bytes(g, P.make_params(precision="fp32_refined"))
+    fb = -(-(64 * 34 * 48 * 4) // 256) * 256
+    assert n32 - n64 == 12 * fb
+
+
 def test_init_rejects_before_any_device_call():
     L = P.lib()
     g = V.VsGrid(32, 32, 32, 1.0)

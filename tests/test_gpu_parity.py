@@ -485,6 +485,37 @@ def test_refined_step_parity_vesicle32(seed):
     assert sc["relres"] <= w.rtol
 
 
+def test_refined_predictor_one_cycle_per_solve():
+    """The refined mode's first correction cycle of a step starts from the fields extrapolated
+    in time from the last two increments (held in FP32), so after the first steps one FP32
+    cycle per solve meets rtol, where the previous step's fields alone need two. A checkpoint
+    holds no increments: a reloaded state starts the predictor over and reaches the same fields
+    to within the solve tolerance."""
+    w = workload("droplet256", grid=GridSpec(64, 34, 64), R0=10.0, nsteps=12, max_cycles=4)
+    say(f"case refined predictor droplet {w.grid.shape}")
+    s = P.solver_for(w, precision="fp32_refined")
+    s.step(w.dt, 2)
+    first = s.scalars()["cycles"] / 4.0
+    blob = s.save()
+    s.step(w.dt, 10)
+    later = s.scalars()["cycles"] / 20.0
+    got = s.fields()
+    assert s.scalars()["relres"] <= w.rtol
+    s.close()
+    r = P.solver_for(w, precision="fp32_refined")
+    r.load(blob)
+    r.step(w.dt, 10)
+    again = r.scalars()["cycles"] / 20.0
+    rel = r.fields()
+    r.close()
+    say(f"  cycles/solve: steps 1-2 {first:.2f}, steps 3-12 {later:.2f}, after reload {again:.2f}")
+    assert first >= 1.5 and later <= 1.1 and again <= 1.3
+    g, walls, p = oracle_objs(w)
+    ref = ref_fields(O.run(g, walls, p, w.phi0(), w.dt, 12))
+    compare(got, ref, tol=TOL_REFINED, label="refined predictor 12 steps")
+    compare(rel, ref, tol=TOL_REFINED, label="refined predictor, reloaded at step 2")
+
+
 _DROPLET_REF = {}
 
 
