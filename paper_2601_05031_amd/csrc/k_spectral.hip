@@ -260,10 +260,12 @@ __global__ __launch_bounds__(kBlock) void k_dht_z_out(Dims d, FftPlan pz,
 //  pass 2: item (line, s), s < B/2, owns the mode pair p2 = {s, B - s} ({0, B/2} for s = 0):
 //          DFT_A over k1 for both, giving X[p2 + B p1]; every X_p and its partner X_{n-p}
 //          sit in the same item, so both Hartley values are formed in registers and stored.
-template <int B, int A>
+// LM > 1: LM times the lines per block, so pass 1 takes LM rounds and pass 2 (B/2 items per
+// line) fills more lanes (A = 16 leaves half the wave idle in pass 2 with LM = 1).
+template <int B, int A, int LM = 1>
 struct TwoPass {
     static constexpr int N = B * A;
-    static constexpr int L = (64 / A) > 0 ? (64 / A) : 1;
+    static constexpr int L = LM * ((64 / A) > 0 ? (64 / A) : 1);
     static constexpr int RS = A + 1;             // padded row of Y
     static constexpr int LS = B * RS + 1;        // padded line of Y
     static constexpr int LDS = L * LS;           // double2 elements
@@ -272,12 +274,12 @@ struct TwoPass {
 // Prep: Pre prep(line) (per-line row offsets, computed once per item).
 // Loader: double2 load(pre, k1, k2) -> (line a value, line b value) at position k1 + A k2.
 // Storer: void store(pre, p, ha, hb).
-template <int B, int A, bool LINE_FAST, class T, class Prep, class Load, class Store>
+template <int B, int A, bool LINE_FAST, class T, int LM = 1, class Prep, class Load, class Store>
 __device__ __forceinline__ void two_pass_hartley(C2<T>* Y, const double2* __restrict__ tw_,
                                                  Prep prep, Load load, Store store) {
     // the twiddle table is global memory (typed so, whatever the pointer's origin)
     const Gl<tw2v>* __restrict__ tw = (const Gl<tw2v>*)tw_;
-    using P = TwoPass<B, A>;
+    using P = TwoPass<B, A, LM>;
     using C = C2<T>;
     constexpr int L = P::L;
     const T half = (T)0.5;
@@ -514,11 +516,16 @@ __global__ __launch_bounds__(64) void k_hx(Dims d, HxArgs one, const HxArgs* __r
     two_pass_hartley<B, A, true, T>(Y, a.tw, prep, load, store);
 }
 
+// Lines per block of the z output pass: doubled for FP32 256-long lines (see TwoPass).
+template <int A, class ST>
+constexpr int z_out_lm() { return (A == 16 && sizeof(ST) == 4) ? 2 : 1; }
+
 // dht_z_out, two-pass form: block = (2L consecutive interior rows, component c).
 // NC as for k_hx.
 template <int B, int A, class ST, int NC, bool BATCH>
 __global__ __launch_bounds__(64) void k_hz_out(Dims d, ZArgs one, const ZArgs* __restrict__ tab) {
-    using P = TwoPass<B, A>;
+    constexpr int LM = z_out_lm<A, ST>();
+    using P = TwoPass<B, A, LM>;
     using T = ST;
     using C = C2<T>;
     const int inst = BATCH ? (int)blockIdx.y / NC : 0;
@@ -573,7 +580,7 @@ __global__ __launch_bounds__(64) void k_hz_out(Dims d, ZArgs one, const ZArgs* _
                 if (rp.b >= 0) put(rp.b + p, (double)hb);
             }
         };
-        two_pass_hartley<B, A, false, T>(Y, a.tw, prep, load, store);
+        two_pass_hartley<B, A, false, T, LM>(Y, a.tw, prep, load, store);
     };
     if constexpr (std::is_same_v<ST, float> && NC == 6) {   // the refined mode's passes
         if (a.self) run(std::integral_constant<int, 5>{});
@@ -851,7 +858,7 @@ void dht_z_out_t(hipStream_t s, const Dims& d, const FftPlan& pz, const Over<ZAr
     const unsigned ni = a.tab ? (unsigned)a.n : 1u;
 #define VS_CASE(b, a_)                                                                         \
     if (B == b && A == a_) {                                                                   \
-        const int rows = 2 * TwoPass<b, a_>::L;                                                \
+        const int rows = 2 * TwoPass<b, a_, z_out_lm<a_, ST>()>::L;                            \
         const dim3 g((nrows + rows - 1) / rows, ncomp * ni);                                   \
         if (ncomp > 3) {                                                                       \
             if (a.tab) launch_kernel((k_hz_out<b, a_, ST, 6, true>), g, dim3(64), 0, s, d, a.one, a.tab); \
