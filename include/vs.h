@@ -300,19 +300,19 @@ vs_status vs_autotune(vs_state* state, int32_t picked[7]);
 vs_status vs_set_launch_shapes(const vs_grid* grid, const int32_t shapes[7]);
 
 /* Batches (many independent instances, e.g. vesicles of different grids and parameters,
- * stepped together: one launch per kernel and instance group instead of one persistent
- * launch). vs_batch_create groups n states made by vs_init (each keeps its own
- * workspace) into grid classes (same grid, precision, model and poisson_max_cycles), and each
- * class into groups of about 2^21 nodes (all instances of a small grid, one 128^3 instance):
- * every kernel of a time step is launched once per group, each instance's pointers and
- * parameters read from a device table of argument structs (allocated by the batch: a few KB
- * per instance). Grids of a class not tuned yet are tuned first (vs_autotune on the class's
- * first instance; for an FP64 class, a grid tuned only by FP32-refined states is tuned again,
- * since its transform form was left at the default). Instances outside the fused forms (FP64 with poisson_max_cycles > 1) are
- * stepped one by one. It creates min(nstreams, groups) HIP streams (group g runs on stream
+ * stepped together: one launch per kernel and grid class instead of one persistent launch).
+ * vs_batch_create groups n states made by vs_init (each keeps its own workspace) into grid
+ * classes (same grid, precision, model and poisson_max_cycles): every kernel of a time step
+ * is launched once per class, each instance's pointers and parameters read from a device
+ * table of argument structs (allocated by the batch: a few KB per instance). Grids of a class
+ * not tuned yet are tuned first (vs_autotune on the class's first instance; for an FP64
+ * class, a grid tuned only by FP32-refined states is tuned again, since its transform form
+ * was left at the default). Instances outside the fused forms (FP64 with
+ * poisson_max_cycles > 1) are stepped one by one. It creates min(nstreams, groups) HIP
+ * streams (groups: the classes, plus one for those instances; group g runs on stream
  * g % nstreams) and moves every state onto its stream; `stream` (a hipStream_t, NULL =
  * default) is the origin the batch forks from and joins to. vs_batch_step captures two time
- * steps of every group into one HIP graph (redone when a dt or a wall speed changes) and
+ * steps of every class into one HIP graph (redone when a dt or a wall speed changes) and
  * replays it nsteps/2 times on the origin stream. nsteps must be even. dt: host array of n
  * time steps. Each instance is checked against its stability bound first; statuses are
  * collected after one synchronisation (the first failing instance's status is returned).

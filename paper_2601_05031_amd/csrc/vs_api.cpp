@@ -1657,16 +1657,17 @@ extern "C" vs_status vs_autotune(vs_state* S, int32_t picked[7]) {
 
 // ------------------------------------------------------------------------------ batches
 // Instances of one grid class (same grid, precision, model and cycle count) step together:
-// each kernel of a step is launched once for a group of instances of the class, its
-// per-instance arguments read from device tables (Over in vs_internal.h). A group holds about
-// kGroupCells nodes (all instances of the smaller grids, one 128^3 instance), the size at
-// which one launch fills the GPU and the fields one kernel hands to the next still largely
-// sit in the 256 MB Infinity Cache; larger groups would stream every hand-off from HBM. Two
-// steps of every group are captured into one HIP graph (two steps bring every instance's phi
-// buffer back to where it started), the groups spread over the batch streams, and replayed.
-// Instances outside the fused forms (FP64 with more than one cycle per solve) are stepped one
-// by one inside the same graph.
-constexpr long long kGroupCells = 1ll << 21;
+// each kernel of a step is launched once for all instances of the class, its per-instance
+// arguments read from device tables (Over in vs_internal.h). One launch per class fills the
+// GPU at every grid size and evens out the persistent plane passes, whose work comes in whole
+// (plane, component) units, one per CU at a time: a single 128^3 instance has 3 x 126 units
+// for 256 CUs in the forward pass (two rounds, the second half empty), thirteen have 4,914
+// (twenty rounds, 96% full). Measured on batch64: 1.10e10 cell-updates/s with one group per
+// class against 1.05e10 with groups of about 2^21 nodes (which kept more of each hand-off in
+// the 256 MB Infinity Cache). Two steps of every class are captured into one HIP graph (two
+// steps bring every instance's phi buffer back to where it started), the classes spread over
+// the batch streams, and replayed. Instances outside the fused forms (FP64 with more than one
+// cycle per solve) are stepped one by one inside the same graph.
 struct BatchClass {
     Dims d{};
     FftPlan px{}, pz{};
@@ -1846,31 +1847,33 @@ vs_status vs_batch_create(vs_state* const* states, int32_t n, void* stream, int3
     vs_batch* B = new vs_batch();
     B->st.assign(states, states + n);
     B->origin = (hipStream_t)stream;
+    // the instances of each class, in input order
+    std::vector<std::vector<vs_state*>> by_class;
     for (vs_state* S : B->st) {
         if (!class_eligible(S)) {
             B->loose.push_back(S);
             continue;
         }
-        const long long cells = (long long)S->g.nx * S->g.ny * S->g.nz;
-        const size_t cap = (size_t)std::max(1ll, (kGroupCells + cells / 2) / cells);
         bool placed = false;
-        for (BatchClass& C : B->cls)
-            if (same_class(C.st[0], S) && C.st.size() < cap) {
-                C.st.push_back(S);
+        for (auto& v : by_class)
+            if (same_class(v[0], S)) {
+                v.push_back(S);
                 placed = true;
                 break;
             }
-        if (!placed) {
-            BatchClass C;
-            C.d = S->d;
-            C.px = S->px;
-            C.pz = S->pz;
-            C.f32 = S->f32;
-            C.model = S->p.model;
-            C.mc = S->p.poisson_max_cycles;
-            C.st.push_back(S);
-            B->cls.push_back(C);
-        }
+        if (!placed) by_class.push_back({S});
+    }
+    for (const auto& v : by_class) {
+        const vs_state* S0 = v[0];
+        BatchClass C;
+        C.d = S0->d;
+        C.px = S0->px;
+        C.pz = S0->pz;
+        C.f32 = S0->f32;
+        C.model = S0->p.model;
+        C.mc = S0->p.poisson_max_cycles;
+        C.st = v;
+        B->cls.push_back(C);
     }
     const int groups = (int)B->cls.size() + (B->loose.empty() ? 0 : 1);
     const int ns = nstreams < groups ? nstreams : groups;

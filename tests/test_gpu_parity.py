@@ -516,6 +516,23 @@ def test_refined_predictor_one_cycle_per_solve():
     compare(rel, ref, tol=TOL_REFINED, label="refined predictor, reloaded at step 2")
 
 
+# every lane layout of the predicted-residual pass (two z per lane in row segments of 8, 16, 32
+# and 64 lanes) and of the z passes around it
+@pytest.mark.parametrize("shape", [(32, 20, 48), (32, 22, 96), (32, 18, 128), (32, 14, 256)])
+def test_refined_predictor_shapes_match_oracle(shape):
+    w = workload("droplet256", grid=GridSpec(*shape), R0=5.0, nsteps=8, max_cycles=4)
+    say(f"case refined predictor {w.grid.shape}")
+    s = P.solver_for(w, precision="fp32_refined")
+    s.step(w.dt, 8)
+    got = s.fields()
+    sc = s.scalars()
+    s.close()
+    g, walls, p = oracle_objs(w)
+    ref = ref_fields(O.run(g, walls, p, w.phi0(), w.dt, 8))
+    compare(got, ref, tol=TOL_REFINED, label=f"refined predictor {shape} 8 steps")
+    assert sc["relres"] <= w.rtol
+
+
 _DROPLET_REF = {}
 
 
