@@ -606,22 +606,27 @@ constexpr int kPlanePad = 2;
 constexpr int kPlaneThreads = 512;
 
 // One 1D Hartley transform of every line pair of the plane. ROWS: lines are x-rows (element m
-// at P[row * RS + m]); otherwise z-columns (element m at P[m * RS + col]).
-template <int B, int A, int NLP, int RS, bool ROWS>
-__device__ __forceinline__ void plane_hartley(double* __restrict__ P, const tw2v* __restrict__ tw, int it) {
-    using C = double2;
-    static_assert(NLP * A <= kPlaneThreads && NLP * (B / 2) <= kPlaneThreads, "one item per lane");
+// at P[row * RS + m]); otherwise z-columns (element m at P[m * RS + col]). T: the precision
+// of the plane (FP64, or FP32 for the refined mode's corrections).
+template <int B, int A, int NLP, int RS, bool ROWS, class T, int NT = kPlaneThreads>
+__device__ __forceinline__ void plane_hartley(T* __restrict__ P, const tw2v* __restrict__ tw, int it) {
+    using C = C2<T>;
+    static_assert(NLP * A <= NT && NLP * (B / 2) <= NT, "one item per lane");
     auto ld = [&](int lp, int m) -> C {
-        if constexpr (ROWS) return make_double2(P[(2 * lp) * RS + m], P[(2 * lp + 1) * RS + m]);
-        else return *reinterpret_cast<const double2*>(&P[m * RS + 2 * lp]);
+        if constexpr (ROWS) return mkc<T>(P[(2 * lp) * RS + m], P[(2 * lp + 1) * RS + m]);
+        else return *reinterpret_cast<const C*>(&P[m * RS + 2 * lp]);
     };
-    auto st = [&](int lp, int m, double a, double b) {
+    auto st = [&](int lp, int m, T a, T b) {
         if constexpr (ROWS) {
             P[(2 * lp) * RS + m] = a;
             P[(2 * lp + 1) * RS + m] = b;
         } else {
-            *reinterpret_cast<double2*>(&P[m * RS + 2 * lp]) = make_double2(a, b);
+            *reinterpret_cast<C*>(&P[m * RS + 2 * lp]) = mkc<T>(a, b);
         }
+    };
+    auto fma_t = [](T a, T b, T c) -> T {
+        if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+        else return __builtin_fmaf(a, b, c);
     };
     // pass 1: B-point DFTs over k2, twiddled, back to the same positions k1 + A p2
     if (it < NLP * A) {
@@ -632,7 +637,7 @@ __device__ __forceinline__ void plane_hartley(double* __restrict__ P, const tw2v
         for (int k2 = 0; k2 < B; ++k2) x[k2] = ld(lp, k1 + A * k2);
         fftr::DFT<B>::run(x);
 #pragma unroll
-        for (int p2 = 1; p2 < B; ++p2) x[p2] = cmul_tw<double>(x[p2], tw[k1 * p2]);
+        for (int p2 = 1; p2 < B; ++p2) x[p2] = cmul_tw<T>(x[p2], tw[k1 * p2]);
 #pragma unroll
         for (int p2 = 0; p2 < B; ++p2) st(lp, k1 + A * p2, x[p2].x, x[p2].y);
     }
@@ -653,13 +658,13 @@ __device__ __forceinline__ void plane_hartley(double* __restrict__ P, const tw2v
     fftr::DFT<A>::run(xb);
     __syncthreads();
     if (act) {
-        const double half = 0.5;
+        const T half = (T)0.5;
         // the partner Z_{n-p} comes from the lane's other row, except for s = 0 (rows 0 and
         // B/2, each its own partner); blended as f*u + (1-f)*v, exact for finite values (a
         // select here is turned into an indexed load from scratch memory)
-        const double f = (s == 0) ? 1.0 : 0.0, g = 1.0 - f;
+        const T f = (s == 0) ? (T)1 : (T)0, g = (T)1 - f;
         auto blend = [&](const C& u, const C& v) -> C {
-            return make_double2(__builtin_fma(f, u.x, g * v.x), __builtin_fma(f, u.y, g * v.y));
+            return mkc<T>(fma_t(f, u.x, g * v.x), fma_t(f, u.y, g * v.y));
         };
 #pragma unroll
         for (int p1 = 0; p1 < A; ++p1) {
@@ -772,6 +777,164 @@ __global__ __launch_bounds__(kPlaneThreads) void k_hxz_plane(Dims d, ZArgs zone,
                 const double2 w = *reinterpret_cast<const double2*>(&P[i * RS + 2 * k2]);
                 stc<double>(out + i * pstride + 2 * k2, w.x, w.y);
             }
+        }
+        __syncthreads();   // the plane's LDS is read out before the next one is written
+        p = pn;
+    }
+}
+
+// The refined mode's plane passes: FP32 spectral data, the (x, z) plane of one interior row
+// and component in LDS as floats (n_x (n_z + 2) floats: 66 KB at 128 x 128). ZFIRST: the forward transforms, z then x, of the FP32 residuals in place
+// (z.spec[c], c < 6: vorticity then stream vector). Otherwise the inverse transforms, x then z,
+// of the FP32 corrections (x.spec[c]) added to the FP64 fields (z.u[c]) as k_hz_out adds them:
+// the time increments of the first cycle's update (z.inc, z.pinc, z.hist, z.hist_out) or of a
+// later cycle (z.inc), or a plain add (z.add, the initial solve). Planes of an instance whose
+// z.gate is set are skipped. Persistent, with the next plane's loads in flight, as k_hxz_plane.
+template <int BX, int AX, int BZ, int AZ, bool ZFIRST, bool BATCH>
+__global__ __launch_bounds__(kPlaneThreads) void k_plane32(Dims d, ZArgs zone,
+                                                         const ZArgs* __restrict__ ztab,
+                                                         HxArgs xone,
+                                                         const HxArgs* __restrict__ xtab,
+                                                         int nplanes) {
+    constexpr int NC = 6;
+    constexpr int NX = BX * AX, NZ = BZ * AZ, RS = NZ + kPlanePad;
+    constexpr int NT = kPlaneThreads;
+    constexpr int NV = NX * NZ / 2;                          // float pairs of the plane
+    constexpr int NR = (NV + NT - 1) / NT;
+    constexpr int NR1 = (NR + 1) / 2;
+    __shared__ float P[NX * RS];
+    __shared__ tw2v TWX[NX], TWZ[NZ];
+    const size_t pstride = (size_t)d.ny * NZ;
+    {
+        const ZArgs& z0 = inst_args<BATCH>(zone, ztab, 0);
+        const HxArgs& x0 = inst_args<BATCH>(xone, xtab, 0);
+        const Gl<tw2v>* gz = (const Gl<tw2v>*)z0.tw;
+        const Gl<tw2v>* gx = (const Gl<tw2v>*)x0.tw;
+        for (int t = threadIdx.x; t < NX; t += NT) TWX[t] = gx[t];
+        for (int t = threadIdx.x; t < NZ; t += NT) TWZ[t] = gz[t];
+    }
+    struct Where {
+        int inst, c, j;
+    };
+    auto where = [&](int p) -> Where {
+        const int cg = p / d.M;
+        const int inst = BATCH ? cg / NC : 0;
+        return Where{inst, cg - inst * NC, 1 + (p - cg * d.M)};
+    };
+    auto live = [&](int q) {   // the next plane from q on (stride: the grid) not gated off
+        while (q < nplanes) {
+            const ZArgs& za = inst_args<BATCH>(zone, ztab, where(q).inst);
+            if (!(za.gate && *(const Gl<int>*)za.gate)) break;
+            q += (int)gridDim.x;
+        }
+        return q;
+    };
+    auto src_of = [&](int p) -> const Gl<float>* {
+        const Where w = where(p);
+        const ZArgs& za = inst_args<BATCH>(zone, ztab, w.inst);
+        const HxArgs& xa = inst_args<BATCH>(xone, xtab, w.inst);
+        return (const Gl<float>*)(ZFIRST ? pick(za.spec, w.c) : pick(xa.spec, w.c)) + (size_t)w.j * NZ;
+    };
+    float2 v[NR];
+    auto load = [&](int p, int r0, int r1) {
+        const Gl<float>* in = src_of(p);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r < r0 || r >= r1) continue;
+            const int t = min((int)threadIdx.x + r * NT, NV - 1);
+            const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+            const gf2v q = *reinterpret_cast<const Gl<gf2v>*>(in + i * pstride + 2 * k2);
+            v[r] = make_float2(q.x, q.y);
+        }
+    };
+    int p = live(blockIdx.x);
+    if (p < nplanes) load(p, 0, NR);
+    while (p < nplanes) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int t = threadIdx.x + r * NT;
+            if (t < NV) {
+                const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+                *reinterpret_cast<float2*>(&P[i * RS + 2 * k2]) = v[r];
+            }
+        }
+        __syncthreads();
+        const int pn = live(p + (int)gridDim.x);
+        if (pn < nplanes) load(pn, 0, NR1);
+        int it = threadIdx.x;
+        asm volatile("" : "+v"(it));
+        if constexpr (ZFIRST) {
+            plane_hartley<BZ, AZ, NX / 2, RS, true>(P, TWZ, it);
+            plane_hartley<BX, AX, NZ / 2, RS, false>(P, TWX, it);
+        } else {
+            plane_hartley<BX, AX, NZ / 2, RS, false>(P, TWX, it);
+            plane_hartley<BZ, AZ, NX / 2, RS, true>(P, TWZ, it);
+        }
+        if (pn < nplanes) load(pn, NR1, NR);
+        const Where w = where(p);
+        const ZArgs& za = inst_args<BATCH>(zone, ztab, w.inst);
+        if constexpr (ZFIRST) {
+            Gl<float>* out = (Gl<float>*)pick(za.spec, w.c) + (size_t)w.j * NZ;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int t = threadIdx.x + r * NT;
+                if (t < NV) {
+                    const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+                    const float2 e = *reinterpret_cast<const float2*>(&P[i * RS + 2 * k2]);
+                    stc<float>(out + i * pstride + 2 * k2, e.x, e.y);
+                }
+            }
+        } else {
+            Gl<double>* uc = (Gl<double>*)pick(za.u, w.c) + (size_t)w.j * NZ;
+            Gl<float>* __restrict__ ic = (Gl<float>*)pick(za.inc, w.c);
+            const Gl<float>* __restrict__ pc = (const Gl<float>*)pick(za.pinc, w.c);
+            if (ic) ic += (size_t)w.j * NZ;
+            if (pc) pc += (size_t)w.j * NZ;
+            const int h = za.hist ? *(const Gl<int>*)za.hist : -1;
+            if (za.hist_out && w.c == 0 && w.j == 1 && threadIdx.x == 0)
+                *(Gl<int>*)za.hist_out = h < 2 ? h + 1 : 2;
+            const int add = za.add;
+            // MODE as in k_hz_out: 0 plain store or add, 1 a later cycle, 2 + H the first cycle
+            auto put = [&](auto mc) {
+                constexpr int MODE = decltype(mc)::value;
+#pragma unroll 4
+                for (int r = 0; r < NR; ++r) {
+                    const int t = threadIdx.x + r * NT;
+                    if (t < NV) {
+                        const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+                        const float2 ef = *reinterpret_cast<const float2*>(&P[i * RS + 2 * k2]);
+                        const double e0 = (double)ef.x, e1 = (double)ef.y;
+                        const size_t o = i * pstride + 2 * k2;
+                        const double2 u = ldg2(uc + o);
+                        if constexpr (MODE == 0) {
+                            if (add) stc<double>(uc + o, u.x + e0, u.y + e1);
+                            else stc<double>(uc + o, e0, e1);
+                        } else if constexpr (MODE == 1) {
+                            const double2 q = ldg2(ic + o);
+                            stc<double>(uc + o, u.x + e0, u.y + e1);
+                            stc<float>(ic + o, (float)(q.x + e0), (float)(q.y + e1));
+                        } else {
+                            double p0 = 0.0, p1 = 0.0;
+                            if constexpr (MODE == 3) {
+                                const double2 a = ldg2(pc + o);
+                                p0 = a.x;
+                                p1 = a.y;
+                            } else if constexpr (MODE == 4) {
+                                const double2 a = ldg2(pc + o), b = ldg2(ic + o);
+                                p0 = 2.0 * a.x - b.x;
+                                p1 = 2.0 * a.y - b.y;
+                            }
+                            stc<double>(uc + o, (u.x + p0) + e0, (u.y + p1) + e1);
+                            stc<float>(ic + o, (float)(p0 + e0), (float)(p1 + e1));
+                        }
+                    }
+                }
+            };
+            if (!add || !ic) put(std::integral_constant<int, 0>{});
+            else if (h < 0) put(std::integral_constant<int, 1>{});
+            else if (h == 0) put(std::integral_constant<int, 2>{});
+            else if (h == 1) put(std::integral_constant<int, 3>{});
+            else put(std::integral_constant<int, 4>{});
         }
         __syncthreads();   // the plane's LDS is read out before the next one is written
         p = pn;
@@ -960,6 +1123,50 @@ bool launch_plane(hipStream_t s, const Dims& d, bool zfirst, int ncomp, const Ov
     VS_PLANE(96, 16, 6)
     VS_PLANE(128, 16, 8)
 #undef VS_PLANE
+    return false;
+}
+
+// The refined mode's FP32 plane forms: square planes of n_x = n_z in {32, 48, 64, 96, 128}.
+// (A 128 x 256 plane of floats fits in LDS too, but its 256-long transforms with the next
+// plane's loads in flight need more than the 256 registers of a lane at 512 threads.)
+bool plane32_fits(const Dims& d) {
+    int bx, ax, bz, az;
+    two_pass_shape(d.nx, bx, ax);
+    two_pass_shape(d.nz, bz, az);
+    return bx > 0 && bz > 0 && d.nx == d.nz && d.nx >= 32 && d.nx <= 128;
+}
+
+bool launch_plane32(hipStream_t s, const Dims& d, bool zfirst, const Over<ZArgs>& z,
+                    const Over<HxArgs>& x) {
+    if (!plane32_fits(d)) return false;
+    const bool batch = z.tab != nullptr;
+    if (batch != (x.tab != nullptr) || (batch && z.n != x.n)) return false;
+    const int ni = batch ? z.n : 1;
+    const int nplanes = d.M * 6 * ni;
+    // persistent: as many blocks as fit on the CUs at once (two per CU for planes up to
+    // 80 KB of LDS)
+    const size_t lds = (size_t)d.nx * (d.nz + kPlanePad) * sizeof(float) + (size_t)(d.nx + d.nz) * sizeof(tw2v);
+    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    const dim3 g((unsigned)std::min(nplanes, per_cu * plane_blocks()));
+    const dim3 blk((unsigned)kPlaneThreads);   // the kernels' launch bound
+    auto go = [&](auto kf, auto kt) {
+        if (batch) launch_kernel(kt, g, blk, 0, s, d, z.one, z.tab, x.one, x.tab, nplanes);
+        else launch_kernel(kf, g, blk, 0, s, d, z.one, z.tab, x.one, x.tab, nplanes);
+    };
+#define VS_PLANE32(nx_, nz_, bx, ax, bz, az)                                                     \
+    if (d.nx == nx_ && d.nz == nz_) {                                                            \
+        if (zfirst)                                                                              \
+            go(k_plane32<bx, ax, bz, az, true, false>, k_plane32<bx, ax, bz, az, true, true>);    \
+        else                                                                                     \
+            go(k_plane32<bx, ax, bz, az, false, false>, k_plane32<bx, ax, bz, az, false, true>);  \
+        return true;                                                                             \
+    }
+    VS_PLANE32(32, 32, 8, 4, 8, 4)
+    VS_PLANE32(48, 48, 16, 3, 16, 3)
+    VS_PLANE32(64, 64, 16, 4, 16, 4)
+    VS_PLANE32(96, 96, 16, 6, 16, 6)
+    VS_PLANE32(128, 128, 16, 8, 16, 8)
+#undef VS_PLANE32
     return false;
 }
 

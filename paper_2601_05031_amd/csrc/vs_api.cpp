@@ -45,7 +45,7 @@ enum KClass {
     K_RHS_Z_FIELD, K_DHT_X, K_TRIDIAG_Y, K_TRIDIAG_PAIR, K_DHT_Z_OUT, K_RESID_OMEGA, K_RESID_PSI,
     K_RESID_FIELD, K_CHECK, K_FILL, K_RESET, K_RESID_FLOW, K_DHT_X_PAIR, K_DHT_Z_OUT_PAIR,
     K_RHS_FLOW, K_ADJ_ADVECT, K_ADJ_WALLS, K_ADJ_SOURCE, K_ADJ_MU1, K_ADJ_MU2, K_ADJ_SUMS, K_DHT_ZX,
-    K_DHT_XZ_PAIR, K_RHS_FLOW_Z, K_NCLASS
+    K_DHT_XZ_PAIR, K_RHS_FLOW_Z, K_PLANE32_FWD, K_PLANE32_INV, K_NCLASS
 };
 const char* kClassNames[K_NCLASS] = {
     "advance", "va_partials", "mu", "source", "rhs_dht_z_omega", "rhs_dht_z_psi",
@@ -53,7 +53,7 @@ const char* kClassNames[K_NCLASS] = {
     "resid_norm_psi", "resid_norm_field", "check", "fill_profile", "reset_stats",
     "resid_norm_flow", "dht_x_pair", "dht_z_out_pair", "rhs_flow", "adj_advect",
     "adj_wall_couple", "adj_source", "adj_mu1", "adj_mu2", "adj_sums", "dht_zx", "dht_xz_pair",
-    "rhs_flow_z"};
+    "rhs_flow_z", "plane32_fwd", "plane32_inv"};
 // Which solve a Poisson call belongs to (selects the timer classes).
 enum SolveTag { TAG_OMEGA = 0, TAG_PSI = 1, TAG_FIELD = 2 };
 
@@ -641,14 +641,24 @@ void enqueue_va_mu_args(const StepCfg& c, const StepArgs& A) {
 bool enqueue_flow_args(const StepCfg& c, const StepArgs& A, bool defer, int max_cycles) {
     timed_cfg(c, K_SOURCE, [&] { launch_source(c.st, c.d, c.f32 ? P32 : P64, A.src); });
     if (c.f32) {
+        // the transforms of a cycle as two FP32 plane passes where the plane fits in LDS
+        const bool plane = plane32_fits(c.d);
         for (int cyc = 0; cyc < max_cycles; ++cyc) {
             const int g = cyc ? 1 : 0;
             timed_cfg(c, K_RHS_FLOW, [&] { launch_rhs_pred(c.st, c.d, A.rf[g]); });
-            timed_cfg(c, K_RHS_FLOW_Z, [&] { launch_hz(c.st, c.d, c.pz, true, 6, A.zs[g]); });
-            timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
+            if (plane) {
+                timed_cfg(c, K_PLANE32_FWD, [&] { launch_plane32(c.st, c.d, true, A.zs[g], A.hxc[g]); });
+            } else {
+                timed_cfg(c, K_RHS_FLOW_Z, [&] { launch_hz(c.st, c.d, c.pz, true, 6, A.zs[g]); });
+                timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
+            }
             timed_cfg(c, K_TRIDIAG_PAIR, [&] { launch_tri_pair(c.st, c.d, true, true, A.trc[g]); });
-            timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
-            timed_cfg(c, K_DHT_Z_OUT_PAIR, [&] { launch_hz(c.st, c.d, c.pz, true, 6, A.zadd[g]); });
+            if (plane) {
+                timed_cfg(c, K_PLANE32_INV, [&] { launch_plane32(c.st, c.d, false, A.zadd[g], A.hxc[g]); });
+            } else {
+                timed_cfg(c, K_DHT_X_PAIR, [&] { launch_hx(c.st, c.d, c.px, true, 6, A.hxc[g]); });
+                timed_cfg(c, K_DHT_Z_OUT_PAIR, [&] { launch_hz(c.st, c.d, c.pz, true, 6, A.zadd[g]); });
+            }
             timed_cfg(c, K_RESID_FLOW, [&] { launch_resid_flow_over(c.st, c.d, false, A.resc[g]); });
             if (max_cycles == 1 && defer) return true;
             timed_cfg(c, K_CHECK, [&] {

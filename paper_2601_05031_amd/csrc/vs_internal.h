@@ -294,6 +294,13 @@ void launch_rhs_pred(hipStream_t s, const Dims& d, const Over<RhsFlowArgs>& a);
 
 // True when both periodic lengths have two-pass transforms and M a segmented solve: the forms
 // the fused flow pass, the refined mode's fused cycle and batched launches use.
+// The refined mode's cycle transforms as FP32 plane passes (k_plane32): forward in place on
+// z.spec, or inverse from x.spec added to z.u with the increments of ZArgs; gated per instance.
+// plane32_fits: n_x = n_z in {32, 48, 64, 96, 128}. Returns false (nothing launched) for other
+// grids.
+bool plane32_fits(const Dims& d);
+bool launch_plane32(hipStream_t s, const Dims& d, bool zfirst, const Over<ZArgs>& z,
+                    const Over<HxArgs>& x);
 bool fused_flow_ok(const Dims& d);
 // Both transform directions in one pass per (interior row, component), the (x, z) plane in
 // LDS: zfirst, z then x from z.spec into x.spec (the source's forward transform); otherwise x
