@@ -802,6 +802,11 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane32(Dims d, ZArgs zone,
     constexpr int NV = NX * NZ / 2;                          // float pairs of the plane
     constexpr int NR = (NV + NT - 1) / NT;
     constexpr int NR1 = (NR + 1) / 2;
+    // planes of more than 16 pairs per lane (128 x 256): transforms over halves of the lines
+    // (one item per lane), and no prefetch (its registers would spill)
+    constexpr bool PF = NR <= 16;
+    constexpr int ZH = (NX / 2) * AZ > NT ? 2 : 1;
+    constexpr int XH = (NZ / 2) * AX > NT ? 2 : 1;
     __shared__ float P[NX * RS];
     __shared__ tw2v TWX[NX], TWZ[NZ];
     const size_t pstride = (size_t)d.ny * NZ;
@@ -848,29 +853,50 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane32(Dims d, ZArgs zone,
         }
     };
     int p = live(blockIdx.x);
-    if (p < nplanes) load(p, 0, NR);
+    if (PF && p < nplanes) load(p, 0, NR);
     while (p < nplanes) {
+        if constexpr (PF) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int t = threadIdx.x + r * NT;
-            if (t < NV) {
+            for (int r = 0; r < NR; ++r) {
+                const int t = threadIdx.x + r * NT;
+                if (t < NV) {
+                    const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
+                    *reinterpret_cast<float2*>(&P[i * RS + 2 * k2]) = v[r];
+                }
+            }
+        } else {
+            const Gl<float>* in = src_of(p);
+#pragma unroll 8
+            for (int r = 0; r < NR; ++r) {
+                const int t = threadIdx.x + r * NT;
                 const int i = t / (NZ / 2), k2 = t - i * (NZ / 2);
-                *reinterpret_cast<float2*>(&P[i * RS + 2 * k2]) = v[r];
+                const gf2v q = *reinterpret_cast<const Gl<gf2v>*>(in + i * pstride + 2 * k2);
+                *reinterpret_cast<float2*>(&P[i * RS + 2 * k2]) = make_float2(q.x, q.y);
             }
         }
         __syncthreads();
         const int pn = live(p + (int)gridDim.x);
-        if (pn < nplanes) load(pn, 0, NR1);
+        if (PF && pn < nplanes) load(pn, 0, NR1);
         int it = threadIdx.x;
         asm volatile("" : "+v"(it));
+        auto zpass = [&] {
+#pragma unroll
+            for (int q = 0; q < ZH; ++q)
+                plane_hartley<BZ, AZ, NX / 2 / ZH, RS, true>(P + q * (NX / ZH) * RS, TWZ, it);
+        };
+        auto xpass = [&] {
+#pragma unroll
+            for (int q = 0; q < XH; ++q)
+                plane_hartley<BX, AX, NZ / 2 / XH, RS, false>(P + q * (NZ / XH), TWX, it);
+        };
         if constexpr (ZFIRST) {
-            plane_hartley<BZ, AZ, NX / 2, RS, true>(P, TWZ, it);
-            plane_hartley<BX, AX, NZ / 2, RS, false>(P, TWX, it);
+            zpass();
+            xpass();
         } else {
-            plane_hartley<BX, AX, NZ / 2, RS, false>(P, TWX, it);
-            plane_hartley<BZ, AZ, NX / 2, RS, true>(P, TWZ, it);
+            xpass();
+            zpass();
         }
-        if (pn < nplanes) load(pn, NR1, NR);
+        if (PF && pn < nplanes) load(pn, NR1, NR);
         const Where w = where(p);
         const ZArgs& za = inst_args<BATCH>(zone, ztab, w.inst);
         if constexpr (ZFIRST) {
@@ -1126,14 +1152,14 @@ bool launch_plane(hipStream_t s, const Dims& d, bool zfirst, int ncomp, const Ov
     return false;
 }
 
-// The refined mode's FP32 plane forms: square planes of n_x = n_z in {32, 48, 64, 96, 128}.
-// (A 128 x 256 plane of floats fits in LDS too, but its 256-long transforms with the next
-// plane's loads in flight need more than the 256 registers of a lane at 512 threads.)
+// The refined mode's FP32 plane forms: square planes of n_x = n_z in {32, 48, 64, 96, 128}
+// and the 128 x 256 plane (132 KB of floats).
 bool plane32_fits(const Dims& d) {
     int bx, ax, bz, az;
     two_pass_shape(d.nx, bx, ax);
     two_pass_shape(d.nz, bz, az);
-    return bx > 0 && bz > 0 && d.nx == d.nz && d.nx >= 32 && d.nx <= 128;
+    if (!bx || !bz) return false;
+    return (d.nx == d.nz && d.nx >= 32 && d.nx <= 128) || (d.nx == 128 && d.nz == 256);
 }
 
 bool launch_plane32(hipStream_t s, const Dims& d, bool zfirst, const Over<ZArgs>& z,
@@ -1166,6 +1192,7 @@ bool launch_plane32(hipStream_t s, const Dims& d, bool zfirst, const Over<ZArgs>
     VS_PLANE32(64, 64, 16, 4, 16, 4)
     VS_PLANE32(96, 96, 16, 6, 16, 6)
     VS_PLANE32(128, 128, 16, 8, 16, 8)
+    VS_PLANE32(128, 256, 16, 8, 16, 16)
 #undef VS_PLANE32
     return false;
 }
