@@ -523,9 +523,10 @@ def main():
                      if kernel_bytes(k, nx, ny, nz)) / args.profile_steps
     step_kernel_ms = sum(v["total_ms"] for v in kern.values()) / args.profile_steps
 
-    # ---- the same three instances replayed as one captured graph (one stream each), so the
-    # small reduction kernels and launch gaps of one instance overlap the others' work; an
-    # extra figure, `value` stays the plain sequential vs_step path above
+    # ---- the same three instances as one batch: one grid class, so every kernel of a step is
+    # launched once for all three (the plane passes' last rounds fill better) and two steps are
+    # replayed as one captured graph; an extra figure, `value` stays the plain sequential
+    # vs_step path above
     headline_graph = None
     gsteps = args.steps if args.graph_steps < 0 else args.graph_steps
     if gsteps >= 2:
