@@ -247,25 +247,24 @@ def batched_run(P, torch, steps: int, nstreams: int) -> dict:
         print(f"bench: batch64 {prec}: {1e3 * tb / steps:.2f} ms/batch step "
               f"({cells * steps / tb:.3e} cell-updates/s), sequential {1e3 * ts / steps:.2f} ms",
               file=sys.stderr, flush=True)
-        if prec == "fp64":
-            # each grid class alone as a batch: the per-cell rate of the class's kernels
-            per = {}
-            for n in sorted({w.grid.nx for w in ws}):
-                sel = [s for s, w in zip(solvers, ws) if w.grid.nx == n]
-                dsel = [dt for dt, w in zip(dts, ws) if w.grid.nx == n]
-                bc = P.Batch(sel, nstreams=nstreams)
-                bc.step(dsel, 2)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                bc.step(dsel, steps)
-                tc = time.perf_counter() - t0
-                bc.close()
-                per[f"{n}^3"] = {"instances": len(sel),
-                                 "cell_updates_per_s": sum(x.grid.N for x in ws if x.grid.nx == n) * steps / tc}
-            out[prec]["per_class"] = per
-            print("bench: batch64 fp64 per class: " +
-                  ", ".join(f"{k} {v['cell_updates_per_s']:.3e}" for k, v in per.items()),
-                  file=sys.stderr, flush=True)
+        # each grid class alone as a batch: the per-cell rate of the class's kernels
+        per = {}
+        for n in sorted({w.grid.nx for w in ws}):
+            sel = [s for s, w in zip(solvers, ws) if w.grid.nx == n]
+            dsel = [dt for dt, w in zip(dts, ws) if w.grid.nx == n]
+            bc = P.Batch(sel, nstreams=nstreams)
+            bc.step(dsel, 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bc.step(dsel, steps)
+            tc = time.perf_counter() - t0
+            bc.close()
+            per[f"{n}^3"] = {"instances": len(sel),
+                             "cell_updates_per_s": sum(x.grid.N for x in ws if x.grid.nx == n) * steps / tc}
+        out[prec]["per_class"] = per
+        print(f"bench: batch64 {prec} per class: " +
+              ", ".join(f"{k} {v['cell_updates_per_s']:.3e}" for k, v in per.items()),
+              file=sys.stderr, flush=True)
         for s in solvers:
             s.close()
         del solvers, b
