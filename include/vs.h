@@ -89,6 +89,16 @@ enum {
     VS_S_CYCLES = 8,   /* Poisson refinement cycles run by the last vs_step call (all solves)      */
     VS_NSCALARS = 9
 };
+/* Per-step log records (vs_log_read): fields of one record */
+enum {
+    VS_L_INDEX = 0,    /* record number since vs_init (0: the initial solve, n: time step n)       */
+    VS_L_CYCLES = 1,   /* Poisson cycles counted so far in the vs_step call that ran the step      */
+    VS_L_RELRES = 2,   /* the larger final relative residual of the step's two flow solves        */
+    VS_L_V = 3, VS_L_A = 4, VS_L_LAMBDA_V = 5, VS_L_GAMMA_A = 6,   /* of the step's new phi      */
+    VS_L_CONV = 7,     /* 1 if both solves met poisson_rtol                                        */
+    VS_LOG_FIELDS = 8,
+    VS_LOG_CAP = 4096  /* records kept (a ring in the workspace: the oldest are overwritten)        */
+};
 
 /* Grid ("Numerical implementation"). ny counts both wall rows; ny >= 3.
  * nx, nz >= 4, even, of the form 2^a 3^b, at most 512 (the periodic directions are
@@ -256,6 +266,14 @@ vs_status vs_field_offset(const vs_state* state, int32_t field, size_t* byte_off
 
 /* Copy the VS_NSCALARS global scalars (slots VS_S_*) to host memory `out`. Synchronises. */
 vs_status vs_get_scalars(vs_state* state, double out[VS_NSCALARS]);
+
+/* The per-step log: the device appends one record (VS_L_* fields) per time step, written by
+ * the step's final flow check (and one for the initial solve of vs_init), in every mode, single
+ * states and batches alike. The last VS_LOG_CAP records are kept. vs_log_read copies the
+ * most recent min(cap, kept) records, oldest first, to host memory out (cap * VS_LOG_FIELDS
+ * doubles) and sets *n to their count. Synchronises. With the environment variable VS_LOG set
+ * (to anything), vs_step prints the records of its steps to stderr, one line per step. */
+vs_status vs_log_read(vs_state* state, double* out, int32_t cap, int32_t* n);
 
 /* Checkpoint: write phi, mu, omega, psi, the scalars, the wall speeds and the step count into
  * blob, which may be host memory or device memory (device allocations are detected; then the

@@ -17,10 +17,11 @@ __device__ __forceinline__ double fc_wave_sum(double v) {
 
 // Call from every thread of one block (a multiple of 64 threads, at most 1024); sh holds
 // 4 * 16 doubles. last_cycle = 0 (a defect-correction cycle that may be followed by another):
-// the convergence flag gates the next cycle and the miss is not yet an error.
+// the convergence flag gates the next cycle and the miss is not yet an error. log (or null):
+// the step's final check (converged, or the last cycle) appends a record to the per-step log.
 __device__ inline void flow_check_block(const double* __restrict__ partials, int nblocks,
                                         double rtol, double* scal, int* istat, double* sh,
-                                        int last_cycle = 1) {
+                                        int last_cycle = 1, double* log = nullptr) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
@@ -63,6 +64,19 @@ __device__ inline void flow_check_block(const double* __restrict__ partials, int
             for (int sidx = 0; sidx < 2; ++sidx) {
                 const double prev = scal[SC_RELRES_MAX];
                 scal[SC_RELRES_MAX] = (rel[sidx] != rel[sidx] || rel[sidx] > prev) ? rel[sidx] : prev;
+            }
+            if (log) {
+                const int n = istat[IS_LOGN];
+                double* r = log + (size_t)(n % kLogCap) * kLogFields;
+                r[0] = (double)n;
+                r[1] = (double)istat[IS_CYCLES];
+                r[2] = (rel[0] != rel[0] || rel[0] > rel[1]) ? rel[0] : rel[1];
+                r[3] = scal[SC_V];
+                r[4] = scal[SC_A];
+                r[5] = scal[SC_LAMV];
+                r[6] = scal[SC_GAMMA];
+                r[7] = (double)(conv ? 1 : 0);
+                istat[IS_LOGN] = n + 1;
             }
         }
         if (!conv && last_cycle) istat[IS_FLAGS] |= ST_NOCONV;

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_advance_x(Dims d, SlabGrid sg, AdvAr
     if (a.ck_part && lb == 0) {
         // the previous step's flow check, off the critical path of this kernel's other blocks
         __shared__ double shc[4 * 16];
-        flow_check_block(a.ck_part, a.ck_nb, a.ck_rtol, a.scal, a.ck_istat, shc);
+        flow_check_block(a.ck_part, a.ck_nb, a.ck_rtol, a.scal, a.ck_istat, shc, 1, a.ck_log);
     }
     const Gl<double>* __restrict__ phi = (const Gl<double>*)a.phi;
     const Gl<T>* __restrict__ mu = (const Gl<T>*)a.mu;
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_advance_x2(Dims d, SlabGrid sg, AdvA
     const AdvArgs a = inst_args<BATCH>(one, tab, inst);
     if (a.ck_part && lb == 0) {
         __shared__ double shc[4 * 16];
-        flow_check_block(a.ck_part, a.ck_nb, a.ck_rtol, a.scal, a.ck_istat, shc);
+        flow_check_block(a.ck_part, a.ck_nb, a.ck_rtol, a.scal, a.ck_istat, shc, 1, a.ck_log);
     }
     const Gl<double>* __restrict__ phi = (const Gl<double>*)a.phi;
     const Gl<T>* __restrict__ mu = (const Gl<T>*)a.mu;

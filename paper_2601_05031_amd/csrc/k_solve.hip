@@ -908,7 +908,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_pred(Dims d, SlabGrid sg, RhsFlo
 __global__ __launch_bounds__(1024) void k_check(const double* __restrict__ partials,
                                                int nblocks, double rtol, int last_cycle,
                                                double* scal, int* istat, const int* gate,
-                                               int slot0) {
+                                               int slot0, int role, double* log) {
     if (gate && *gate) return;
     __shared__ double sh[2 * 16];
     double rr = 0.0, bb = 0.0;
@@ -945,6 +945,21 @@ __global__ __launch_bounds__(1024) void k_check(const double* __restrict__ parti
     if (conv || last_cycle) {
         const double prev = scal[SC_RELRES_MAX];
         scal[SC_RELRES_MAX] = (rel != rel || rel > prev) ? rel : prev;
+        if (role == 1) scal[SC_RELRES_W] = rel;
+        if (role == 2 && log) {   // the step's record (the per-step log; see flow_check.h)
+            const double rw = scal[SC_RELRES_W];
+            const int n = istat[IS_LOGN];
+            double* r = log + (size_t)(n % kLogCap) * kLogFields;
+            r[0] = (double)n;
+            r[1] = (double)istat[IS_CYCLES];
+            r[2] = (rw != rw || rw > rel) ? rw : rel;
+            r[3] = scal[SC_V];
+            r[4] = scal[SC_A];
+            r[5] = scal[SC_LAMV];
+            r[6] = scal[SC_GAMMA];
+            r[7] = (double)((conv && rw <= rtol) ? 1 : 0);
+            istat[IS_LOGN] = n + 1;
+        }
     }
     if (!conv && last_cycle) istat[IS_FLAGS] |= ST_NOCONV;
     if (!isfinite(rr) || !isfinite(bb)) istat[IS_FLAGS] |= ST_NONFINITE;
@@ -958,7 +973,7 @@ __global__ __launch_bounds__(1024) void k_check_flow(int nblocks, int last_cycle
     const ChkArgs& a = inst_args<BATCH>(one, tab, (int)blockIdx.x);
     if (a.gate && *a.gate) return;
     __shared__ double sh[4 * 16];
-    flow_check_block(a.part, nblocks, a.rtol, a.scal, a.istat, sh, last_cycle);
+    flow_check_block(a.part, nblocks, a.rtol, a.scal, a.istat, sh, last_cycle, a.log);
 }
 
 }  // namespace
@@ -1223,10 +1238,11 @@ void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, dou
 }
 
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
-                  int last_cycle, double* scal, int* istat, const int* gate, int slot0) {
+                  int last_cycle, double* scal, int* istat, const int* gate, int slot0, int role,
+                  double* log) {
     (void)cycle;
     launch_kernel(k_check, dim3(1), dim3(1024), 0, s, partials, nblocks, rtol,
-                       last_cycle, scal, istat, gate, slot0);
+                       last_cycle, scal, istat, gate, slot0, role, log);
 }
 
 }  // namespace vs

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -79,6 +80,7 @@ struct Layout {
     size_t off_tri2;        // the shifted vorticity pivots of the inertial variant (or 0)
     size_t off_inc;         // refined mode: 2 x 6 FP32 fields, the last two time increments
                             // of omega and psi (or 0)
+    size_t off_log;         // the per-step log: kLogCap records of kLogFields doubles
     size_t total;
 };
 
@@ -99,6 +101,7 @@ Layout make_layout(const vs_grid& g, bool inertial, bool refined) {
     L.off_prof = o;   o += align_up(4 * (size_t)g.ny * sizeof(double));   // tables + a change
     L.off_scal = o;   o += align_up(SC_NSCAL * sizeof(double));
     L.off_istat = o;  o += align_up(IS_NSTAT * sizeof(int));
+    L.off_log = o;    o += align_up((size_t)kLogCap * kLogFields * sizeof(double));
     L.off_tri2 = 0;
     if (inertial) {
         L.off_tri2 = o;
@@ -226,6 +229,8 @@ struct vs_state {
     // refined mode: time increments of omega (0-2) and psi (3-5) in two FP32 buffers whose
     // roles alternate with the step parity (the predictor of the first correction cycle)
     float* inc[2][6] = {};
+    double* log = nullptr;    // the per-step log (device ring, kLogCap records)
+    long long log_shown = 0;  // records of it already printed (VS_LOG)
     double psi_wall_lo[3] = {0, 0, 0}, psi_wall_hi[3] = {0, 0, 0};
     double om_wall_lo[3] = {0, 0, 0}, om_wall_hi[3] = {0, 0, 0};
     double2* twx = nullptr;
@@ -362,8 +367,12 @@ void enqueue_verify(vs_state* S, const RhsArgs& rhs, double* const u[3], int nco
     const int nb = resid_blocks(d);
     const int k_res = tag == TAG_OMEGA ? K_RESID_OMEGA : tag == TAG_PSI ? K_RESID_PSI : K_RESID_FIELD;
     timed(S, k_res, [&] { launch_resid_norm(S->stream, d, rhs, cu, ncomp, S->part, gate); });
+    // the two solves of a time step (FP64, more than one cycle per solve): the stream-vector
+    // check logs the step
+    const int role = tag == TAG_OMEGA ? 1 : tag == TAG_PSI ? 2 : 0;
     timed(S, K_CHECK, [&] {
-        launch_check(S->stream, S->part, nb, rtol, cyc, last, S->scal, S->istat, gate);
+        launch_check(S->stream, S->part, nb, rtol, cyc, last, S->scal, S->istat, gate, 0, role,
+                     S->log);
     });
 }
 
@@ -454,6 +463,7 @@ StepArgs step_args(vs_state* S, int par, double dt, bool with_ck) {
         ad.ck_istat = S->istat;
         ad.ck_rtol = S->p.poisson_rtol;
         ad.ck_nb = resid_flow_blocks(S->d);
+        ad.ck_log = S->log;
     }
     A.adv = over_one(ad);
     A.va = over_one(VaArgs{phi_new, S->part, S->p.eps});
@@ -533,6 +543,7 @@ StepArgs step_args(vs_state* S, int par, double dt, bool with_ck) {
     ck.scal = S->scal;
     ck.istat = S->istat;
     ck.rtol = S->p.poisson_rtol;
+    ck.log = S->log;
     A.chk = over_one(ck);
     // the refined mode's predictor (steps only, not the initial solve): increments i1 = inc[par]
     // (the last step's) and i2 = inc[1 - par] (the one before), which the first cycle's update
@@ -836,6 +847,43 @@ vs_status collect(vs_state* S, const char* what) {
     return VS_OK;
 }
 
+// The per-step log's records, oldest first (at most kLogCap), and the count written since
+// vs_init. Synchronises.
+vs_status read_log(vs_state* S, std::vector<double>& recs, long long& total) {
+    int ist[IS_NSTAT];
+    const vs_status rs = read_status(S, nullptr, ist);
+    if (rs != VS_OK) return rs;
+    total = ist[IS_LOGN];
+    const long long kept = total < kLogCap ? total : kLogCap;
+    std::vector<double> ring((size_t)kLogCap * kLogFields);
+    HIP_TRY(hipMemcpy(ring.data(), S->log, ring.size() * sizeof(double), hipMemcpyDeviceToHost));
+    recs.resize((size_t)kept * kLogFields);
+    for (long long q = 0; q < kept; ++q) {
+        const long long idx = total - kept + q;
+        std::memcpy(&recs[(size_t)q * kLogFields], &ring[(size_t)(idx % kLogCap) * kLogFields],
+                    kLogFields * sizeof(double));
+    }
+    return VS_OK;
+}
+
+// VS_LOG: the records of the steps just run, one line each, on stderr.
+void print_log(vs_state* S) {
+    static const bool on = std::getenv("VS_LOG") != nullptr;
+    if (!on) return;
+    std::vector<double> recs;
+    long long total = 0;
+    if (read_log(S, recs, total) != VS_OK) return;
+    const long long kept = (long long)(recs.size() / kLogFields);
+    for (long long q = 0; q < kept; ++q) {
+        const double* r = &recs[(size_t)q * kLogFields];
+        if ((long long)r[VS_L_INDEX] < S->log_shown) continue;
+        std::fprintf(stderr, "vs step %lld: cycles %d relres %.3e V %.10g A %.10g lambda_V %.6g gamma_A %.6g%s\n",
+                     (long long)r[VS_L_INDEX], (int)r[VS_L_CYCLES], r[VS_L_RELRES], r[VS_L_V], r[VS_L_A],
+                     r[VS_L_LAMBDA_V], r[VS_L_GAMMA_A], r[VS_L_CONV] != 0.0 ? "" : " (not converged)");
+    }
+    S->log_shown = total;
+}
+
 double stability_rate(const vs_state* S) {
     const double h2 = S->g.h * S->g.h;
     const double lmax = 12.0 / h2;
@@ -926,6 +974,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     S->prof = (double*)(S->ws + L.off_prof);
     S->scal = (double*)(S->ws + L.off_scal);
     S->istat = (int*)(S->ws + L.off_istat);
+    S->log = (double*)(S->ws + L.off_log);
 
     // Host tables: twiddles exp(-2 pi i m/n), Thomas pivots per Hartley mode class, and the
     // no-body channel profiles of psi_x and omega_x (main text "Boundary conditions").
@@ -955,6 +1004,7 @@ vs_status vs_init(const vs_grid* grid, const vs_walls* walls, const vs_params* p
     INIT_TRY(hipMemcpyAsync(S->phi[0], phi0, N * sizeof(double), hipMemcpyDeviceToDevice, S->stream));
     INIT_TRY(hipMemsetAsync(S->scal, 0, SC_NSCAL * sizeof(double), S->stream));
     INIT_TRY(hipMemsetAsync(S->istat, 0, IS_NSTAT * sizeof(int), S->stream));
+    INIT_TRY(hipMemsetAsync(S->log, 0, (size_t)kLogCap * kLogFields * sizeof(double), S->stream));
     // the increments' wall rows are read (as zero) by the predictor and never written
     if (L.off_inc) INIT_TRY(hipMemsetAsync(S->ws + L.off_inc, 0, L.total - L.off_inc, S->stream));
     launch_fill_profile(S->stream, S->d, S->ps[0], S->prof);
@@ -1157,7 +1207,9 @@ vs_status vs_step(vs_state* S, double dt, int32_t nsteps) {
     for (int s = 0; s < nsteps; ++s) enqueue_step(S, dt, s + 1 < nsteps);
     HIP_TRY(hipGetLastError());
     S->step += nsteps;
-    return collect(S, "vs_step");
+    const vs_status cs = collect(S, "vs_step");
+    print_log(S);
+    return cs;
 }
 
 vs_status vs_grad_step(vs_state* S, double dt, const double* adj_next, double* adj_prev,
@@ -1351,6 +1403,22 @@ vs_status vs_field_offset(const vs_state* S, int32_t field, size_t* byte_offset)
         default: return fail(VS_E_ARG, "unknown field id %d", field);
     }
     *byte_offset = (size_t)((const char*)p - S->ws);
+    return VS_OK;
+}
+
+vs_status vs_log_read(vs_state* S, double* out, int32_t cap, int32_t* n) {
+    if (!S) return fail(VS_E_STATE, "state is NULL");
+    if (!out || !n) return fail(VS_E_ARG, "out and n are required");
+    if (cap < 1) return fail(VS_E_ARG, "cap must be >= 1");
+    std::vector<double> recs;
+    long long total = 0;
+    const vs_status rs = read_log(S, recs, total);
+    if (rs != VS_OK) return rs;
+    const long long kept = (long long)(recs.size() / kLogFields);
+    const long long m = kept < cap ? kept : cap;
+    if (m > 0)
+        std::memcpy(out, &recs[(size_t)(kept - m) * kLogFields], (size_t)m * kLogFields * sizeof(double));
+    *n = (int32_t)m;
     return VS_OK;
 }
 

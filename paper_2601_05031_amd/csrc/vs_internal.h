@@ -66,6 +66,8 @@ enum {
     SC_ADJ_OMC = 12,          // wall coupling of the second adjoint solve with the omega walls
     SC_ADJ_KAPPA = 13,        // sum mu_bar d mu / d kappa
     SC_ADJ_GAMMA = 14,        // sum mu_bar d mu / d gamma_A = -sum mu_bar L_h phi
+    SC_RELRES_W = 15,         // final relative residual of the step's vorticity solve (checks
+                              // of one solve at a time: the stream-vector check logs the step)
     // diagnostics: sums over the nodes with trapezoid weights, and the largest sigma_t
     SC_DG_OMEGA = 16,         // sum_w |omega - omega_0|^2
     SC_DG_PSI = 17,           // sum_w |psi - psi_0|^2
@@ -82,9 +84,14 @@ enum {
     IS_CYCLES = 2,            // Poisson cycles run since the last reset
     IS_HIST = 3,              // refined mode: time increments of omega and psi the predictor
                               // holds (0, 1, 2), slots 3 and 4 by the parity of the step
+    IS_LOGN = 5,              // records written to the per-step log since vs_init
     IS_NSTAT = 16
 };
 enum { ST_NOCONV = 1, ST_NONFINITE = 2 };
+// The per-step log: a ring of kLogCap records of kLogFields doubles (VS_L_* in include/vs.h),
+// one per time step (and one for the initial solve), written by the step's final flow check.
+constexpr int kLogCap = VS_LOG_CAP;
+constexpr int kLogFields = VS_LOG_FIELDS;
 
 // Source of the right-hand side b of a Poisson solve.
 enum RhsMode {
@@ -171,6 +178,7 @@ struct AdvArgs {
     int* ck_istat;
     double ck_rtol;
     int ck_nb;               // residual partial blocks of that check
+    double* ck_log;          // the per-step log that check appends to
 };
 void launch_advance(hipStream_t s, const Dims& d, Prec pr, const Over<AdvArgs>& a);
 int resid_flow_blocks(const Dims& d);
@@ -270,6 +278,7 @@ struct ChkArgs {
     int* istat;
     double rtol;
     const int* gate;
+    double* log;         // the per-step log (the step's final check appends a record), or null
 };
 // Residuals of both flow problems at the current (or predicted) fields, stored in FP32 for the
 // refined mode's defect-correction cycle: vorticity into spec, stream vector into spec2.
@@ -413,8 +422,11 @@ void launch_resid_norm(hipStream_t s, const Dims& d, const RhsArgs& rhs,
 // stream vector in 6-11).
 void launch_check_flow(hipStream_t s, const Dims& d, const double* partials, double rtol,
                        double* scal, int* istat);
+// role: 0 a lone solve; 1 the vorticity solve of a step (its final relres kept); 2 the
+// stream-vector solve of a step (its final check appends the step's record to log).
 void launch_check(hipStream_t s, const double* partials, int nblocks, double rtol, int cycle,
-                  int last_cycle, double* scal, int* istat, const int* gate, int slot0 = 0);
+                  int last_cycle, double* scal, int* istat, const int* gate, int slot0 = 0,
+                  int role = 0, double* log = nullptr);
 
 
 }  // namespace vs

@@ -32,6 +32,8 @@ VS_ALLOW_UNSTABLE = 1
 
 FIELDS = {"phi": 0, "mu": 1, "omega_x": 2, "omega_y": 3, "omega_z": 4, "psi_x": 5, "psi_y": 6, "psi_z": 7}
 SCALARS = ["V", "A", "V0", "A0", "lambda_V", "gamma_A", "relres", "step", "cycles"]
+LOG_FIELDS = ["index", "cycles", "relres", "V", "A", "lambda_V", "gamma_A", "conv"]
+VS_LOG_CAP = 4096
 
 _WALL_KINDS = {"poiseuille": VS_POISEUILLE, "couette": VS_COUETTE}
 _MODELS = {"bending": VS_BENDING, "cahn_hilliard": VS_CAHN_HILLIARD}
@@ -74,6 +76,14 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_05031_amd.build`")
+    # PyTorch provides the device memory and streams, and ships its own HIP runtime (soname
+    # libamdhip64.so.7, loaded by its libraries under another name). Loaded first, that runtime
+    # also serves libvs; loaded after libvs, it would be a second runtime beside the system one
+    # and the first of them to be used does not see the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, sz, i32, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
@@ -87,6 +97,7 @@ def lib() -> ctypes.CDLL:
         "vs_grad_step": (i32, [vp, dbl, vp, vp, P(dbl)]),
         "vs_field_offset": (i32, [vp, i32, P(sz)]),
         "vs_get_scalars": (i32, [vp, P(dbl)]),
+        "vs_log_read": (i32, [vp, P(dbl), i32, P(i32)]),
         "vs_save_state": (i32, [vp, vp, P(sz)]),
         "vs_load_state": (i32, [vp, vp, sz]),
         "vs_profile": (i32, [vp, i32]),
@@ -251,6 +262,16 @@ class Solver:
         out = (ctypes.c_double * len(SCALARS))()
         _check(lib().vs_get_scalars(self._st, out), "vs_get_scalars")
         return dict(zip(SCALARS, list(out)))
+
+    def log(self, cap: int = VS_LOG_CAP):
+        """The per-step log (vs_log_read): up to cap most recent records, oldest first, as an
+        array of shape (n, len(LOG_FIELDS))."""
+        import numpy as np
+        out = (ctypes.c_double * (cap * len(LOG_FIELDS)))()
+        n = ctypes.c_int32(0)
+        _check(lib().vs_log_read(self._st, out, cap, ctypes.byref(n)), "vs_log_read")
+        return np.frombuffer(out, dtype=np.float64, count=n.value * len(LOG_FIELDS)).reshape(
+            n.value, len(LOG_FIELDS)).copy()
 
     def set_walls(self, u0: float, u1: float = 0.0):
         """New wall speeds (same kind) from now on: the time-dependent-walls hook."""

@@ -143,6 +143,9 @@ def test_null_state_calls():
     assert L.vs_set_walls(None, ctypes.byref(w)) == V.VS_E_STATE
     out = (ctypes.c_double * 6)()
     assert L.vs_diagnostics(None, None, out) == V.VS_E_STATE
+    n = ctypes.c_int32(0)
+    rec = (ctypes.c_double * 8)()
+    assert L.vs_log_read(None, rec, 1, ctypes.byref(n)) == V.VS_E_STATE
     assert L.vs_batch_step(None, None, 2) == V.VS_E_STATE
     b = ctypes.c_void_p(0)
     assert L.vs_batch_create(None, 0, None, 1, ctypes.byref(b)) == V.VS_E_ARG

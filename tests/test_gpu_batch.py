@@ -64,19 +64,29 @@ def test_batch_bitwise_equals_single_instances(precision, mc, plane):
     for w in ws:
         s = P.solver_for(w, precision=precision)
         s.step(w.dt, nsteps)
-        singles.append((s.fields(), s.scalars()))
+        singles.append((s.fields(), s.scalars(), s.log()))
         s.close()
     solvers = [P.solver_for(w, precision=precision) for w in ws]
     b = V.Batch(solvers, nstreams=4)
     b.step([w.dt for w in ws], 2)
     b.step([w.dt for w in ws], nsteps - 2)      # replays the captured graph
     b.close()
-    for w, s, (ref, rsc) in zip(ws, solvers, singles):
+    # log fields compared bit for bit: all but the cycles (counted per call) and the relative
+    # residual (its partial sums are added in a block of the size of the kernel that runs the
+    # check: the next step's advance, or the check kernel after a call's or a graph's last step)
+    keep = [i for i, k in enumerate(V.LOG_FIELDS) if k not in ("cycles", "relres")]
+    ir = V.LOG_FIELDS.index("relres")
+    for w, s, (ref, rsc, rlog) in zip(ws, solvers, singles):
         got = s.fields()
         sc = s.scalars()
         for k in FIELD_NAMES:
             assert np.array_equal(got[k], ref[k]), (w.name, k)
         assert sc["step"] == nsteps and sc["V"] == rsc["V"] and sc["A"] == rsc["A"]
+        # the per-step log: the same records, written by the batch's checks
+        glog = s.log()
+        assert glog.shape == rlog.shape == (nsteps + 1, len(V.LOG_FIELDS)), (glog.shape, rlog.shape)
+        assert np.array_equal(glog[:, keep], rlog[:, keep]), w.name
+        assert np.allclose(glog[:, ir], rlog[:, ir], rtol=1e-12, atol=0.0), w.name
         # the states keep working after the batch is gone
         s.step(w.dt, 1)
         s.close()

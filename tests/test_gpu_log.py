@@ -1,0 +1,73 @@
+"""The per-step device log (vs_log_read): one record per time step, written by the step's final
+flow check on the device, against the oracle's scalars of the same steps (V, A and the
+penalty multipliers of SM eq. (37), (38), at the bounds of the scalar parity tests)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import workload
+from workloads.shapes import GridSpec
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_2601_05031_amd as P  # noqa: E402
+from paper_2601_05031_amd import vs as V  # noqa: E402
+
+L = {k: i for i, k in enumerate(V.LOG_FIELDS)}
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def oracle_steps(w, nsteps):
+    g = O.Grid(*w.grid.shape, h=w.grid.h)
+    walls = O.Walls(w.wall_kind, w.u0, w.u1)
+    p = O.Params(model=w.model, eta=w.eta, mobility=w.mobility, eps=w.eps, kappa=w.kappa,
+                 sigma=w.sigma, gamma0=w.gamma0, rate_V=w.rate_V, k_A=w.k_A, bend_scale=w.bend_scale)
+    s = O.init_state(g, walls, p, w.phi0())
+    out = [s]
+    for _ in range(nsteps):
+        s = O.step(s, w.dt, g, walls, p)
+        out.append(s)
+    return g, p, out
+
+
+@pytest.mark.parametrize("precision,mc", [("fp64", 1), ("fp64", 3), ("fp32_refined", 3)])
+def test_log_records_every_step(precision, mc):
+    w = workload("vesicle32", grid=GridSpec(32, 21, 32), wall_kind="couette", u0=-0.03, u1=0.05,
+                 R0=6.0, gamma0=0.2, rate_V=10.0, k_A=1.0, kappa=0.5, seed=4, dt=5e-4, max_cycles=mc)
+    say(f"case log {precision} max_cycles={mc} grid={w.grid.shape}")
+    s = P.solver_for(w, precision=precision)
+    s.step(w.dt, 3)
+    first = s.log()
+    s.step(w.dt, 2)
+    log = s.log()
+    sc = s.scalars()
+    last3 = s.log(cap=3)
+    s.close()
+    assert first.shape == (4, len(V.LOG_FIELDS)) and log.shape == (6, len(V.LOG_FIELDS))
+    assert np.array_equal(log[:4], first)
+    assert list(log[:, L["index"]]) == [0, 1, 2, 3, 4, 5]
+    assert np.array_equal(last3, log[3:])
+    assert (log[:, L["conv"]] == 1).all() and (log[:, L["relres"]] <= w.rtol).all()
+    # cycles counted within each vs_step call: two checks per cycle, one or more cycles a step
+    cyc = log[:, L["cycles"]]
+    assert cyc[1] >= 2 and cyc[2] > cyc[1] and cyc[3] > cyc[2] and cyc[4] >= 2 and cyc[5] > cyc[4]
+    if precision == "fp64":   # one cycle per solve (the direct solve meets rtol at once)
+        assert list(cyc[1:]) == [2, 4, 6, 2, 4]
+    last = log[-1]
+    assert last[L["V"]] == sc["V"] and last[L["A"]] == sc["A"]
+    assert last[L["lambda_V"]] == sc["lambda_V"] and last[L["gamma_A"]] == sc["gamma_A"]
+    g, p, ref = oracle_steps(w, 5)
+    rv, ra = (1e-12, 1e-11) if precision == "fp64" else (1e-9, 1e-8)
+    for r, o in zip(log, ref):
+        assert r[L["V"]] == pytest.approx(o.V, rel=rv)
+        assert r[L["A"]] == pytest.approx(o.A, rel=ra)
+        lam_bound = 2.0 * p.rate_V * rv * (abs(o.V) + abs(o.V0)) / (p.mobility * g.domain_volume)
+        assert abs(r[L["lambda_V"]] - o.lam_V) <= max(lam_bound, 1e-300), (r[L["lambda_V"]], o.lam_V)
+        assert r[L["gamma_A"]] == pytest.approx(o.gamma_A, rel=ra * 100, abs=1e-14)
+    say("  " + "; ".join(f"{int(r[0])}: cyc {int(r[1])} rel {r[2]:.1e}" for r in log))
