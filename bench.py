@@ -437,8 +437,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design note, not built)", file=sys.stderr)
+        print(f"bench.py: the library runs one simulation per GPU on one GPU; --gpus {args.gpus} "
+              "is not supported (the multi-GPU decomposition is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
