@@ -71,3 +71,22 @@ def test_log_records_every_step(precision, mc):
         assert abs(r[L["lambda_V"]] - o.lam_V) <= max(lam_bound, 1e-300), (r[L["lambda_V"]], o.lam_V)
         assert r[L["gamma_A"]] == pytest.approx(o.gamma_A, rel=ra * 100, abs=1e-14)
     say("  " + "; ".join(f"{int(r[0])}: cyc {int(r[1])} rel {r[2]:.1e}" for r in log))
+
+
+def test_log_ring_keeps_the_last_records():
+    """More steps than the ring holds: the oldest records are overwritten, the newest kept in
+    order, and a short read returns the most recent ones."""
+    w = workload("vesicle32", grid=GridSpec(32, 10, 32), R0=3.0, max_cycles=1)
+    say(f"case log ring grid={w.grid.shape}")
+    s = P.solver_for(w)
+    nsteps = V.VS_LOG_CAP + 4
+    s.step(w.dt, nsteps)
+    log = s.log()
+    tail = s.log(cap=10)
+    s.close()
+    assert log.shape == (V.VS_LOG_CAP, len(V.LOG_FIELDS))
+    idx = log[:, L["index"]]
+    assert idx[0] == nsteps + 1 - V.VS_LOG_CAP and idx[-1] == nsteps
+    assert np.array_equal(np.diff(idx), np.ones(V.VS_LOG_CAP - 1))
+    assert np.array_equal(tail, log[-10:])
+    assert (log[:, L["conv"]] == 1).all()
