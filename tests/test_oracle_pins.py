@@ -70,6 +70,32 @@ def test_central_difference_closed_form():
     assert np.all(dy[:, 0, :] == 0) and np.all(dy[:, -1, :] == 0)
 
 
+def test_vorticity_source_closed_form():
+    """S = (1/eta) grad phi x grad mu (main text eq. (5b)) on the interior rows, by central
+    differences: phi varying along x only and mu along z only give S = (0, -phi_x mu_z, 0)/eta;
+    phi along y (an even wall mode) and mu along x give S = (0, 0, -phi_y mu_x)/eta. Swapping
+    the factors of the cross product flips both signs; dropping 1/eta scales them."""
+    eta = 1.7
+    g = O.Grid(8, 9, 6, h=0.5)
+    i, j, k = np.meshgrid(np.arange(8), np.arange(9), np.arange(6), indexing="ij")
+    cx, cz, cy = 2 * math.pi * 3 / 8, 2 * math.pi * 1 / 6, math.pi * 2 / 8
+    phi = np.sin(cx * i) + 0.0 * j
+    mu = np.sin(cz * k) + 0.0 * j
+    S = O.vorticity_source(phi, mu, g, eta)
+    fx = math.sin(cx) / g.h * np.cos(cx * i)
+    mz = math.sin(cz) / g.h * np.cos(cz * k)
+    assert S.shape == (3, 8, 7, 6)
+    assert np.allclose(S[0], 0.0, atol=1e-13) and np.allclose(S[2], 0.0, atol=1e-13)
+    assert np.allclose(S[1], (-fx * mz / eta)[:, 1:-1, :], atol=1e-12)
+    phi = np.cos(cy * j) + 0.0 * i
+    mu = np.sin(cx * i) + 0.0 * k
+    S = O.vorticity_source(phi, mu, g, eta)
+    fy = -math.sin(cy) / g.h * np.sin(cy * j)
+    mx = math.sin(cx) / g.h * np.cos(cx * i)
+    assert np.allclose(S[0], 0.0, atol=1e-13) and np.allclose(S[1], 0.0, atol=1e-13)
+    assert np.allclose(S[2], (-fy * mx / eta)[:, 1:-1, :], atol=1e-12)
+
+
 def test_curl_closed_form_and_divergence_free():
     """curl (0, 0, sin(2 pi i/nx)) = (0, -sin(2 pi/nx)/h cos(2 pi i/nx), 0); and the discrete
     divergence of a central-difference curl vanishes (central differences commute)."""
