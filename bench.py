@@ -395,6 +395,31 @@ def copy_ceiling(torch) -> float:
     return 2.0 * (1 << 30) / t / 1e9
 
 
+def system_info(torch) -> dict:
+    """The device, the software versions and the clocks the run saw (each None if unreadable)."""
+    info = {"device": None, "arch": None, "compute_units": None, "hip": torch.version.hip,
+            "torch": torch.__version__, "rocm": None, "clocks": None}
+    try:
+        pr = torch.cuda.get_device_properties(0)
+        info.update(device=pr.name, arch=pr.gcnArchName, compute_units=pr.multi_processor_count)
+    except Exception:
+        pass
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            info["rocm"] = f.read().strip()
+    except OSError:
+        pass
+    try:
+        import subprocess
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=30)
+        card = next(iter(json.loads(r.stdout).values()))
+        info["clocks"] = {k.rstrip(": "): v for k, v in card.items() if "clk" in k.lower()}
+    except Exception:
+        pass
+    return info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -426,6 +451,8 @@ def main():
                          "adv_slab=8,va_maxb=512,... (profiler runs: no candidate launches)")
     ap.add_argument("--cpu-single-only", action="store_true",
                     help="time the CPU oracle on one thread only")
+    ap.add_argument("--repeats", type=int, default=4,
+                    help="further timed regions like the first, reported beside `value` (0 = none)")
     ap.add_argument("--cpu-worker", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
     args.profile_steps = max(1, args.profile_steps)   # the roofline needs one profiled step
@@ -492,6 +519,19 @@ def main():
     relres = max(s.scalars()["relres"] for s in solvers)
     print(f"bench: timed {args.steps} steps x {len(KAPPAS)} instances in {wall:.3f} s "
           f"(events {gpu_ms:.1f} ms), max relres {relres:.2e}", file=sys.stderr, flush=True)
+    # the same timed region again (the run-to-run spread; `value` is the first)
+    repeats = [value]
+    for _ in range(max(0, args.repeats)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in solvers:
+            s.step(base.dt, args.steps)
+        torch.cuda.synchronize()
+        repeats.append(total_cells / (time.perf_counter() - t0))
+    relres = max(relres, max(s.scalars()["relres"] for s in solvers))
+    if len(repeats) > 1:
+        print(f"bench: {len(repeats)} timed regions: " + " ".join(f"{v:.4e}" for v in repeats),
+              file=sys.stderr, flush=True)
 
     # ---- per-kernel event timing on the kappa = 1 instance (a separate pass)
     s1 = solvers[1]
@@ -593,6 +633,9 @@ def main():
                    "flow": "poiseuille u0=0.05", "penalties": {"rate_V": base.rate_V, "k_A": base.k_A}},
         "steps_per_s_per_instance": len(KAPPAS) * args.steps / wall,
         "max_relres": relres,
+        "timed_regions": {"values": repeats, "median": sorted(repeats)[len(repeats) // 2],
+                          "note": "value is the first; each region is the same K steps of every instance"},
+        "system": system_info(torch),
         "per_kappa_cell_updates_per_s": {k: N * args.steps / t for k, t in per_kappa.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
