@@ -48,6 +48,14 @@ def test_log_records_every_step(precision, mc):
     log = s.log()
     sc = s.scalars()
     last3 = s.log(cap=3)
+    # argument errors on a live state: no output array, no count, a capacity below one
+    import ctypes
+    n = ctypes.c_int32(-7)
+    buf = (ctypes.c_double * len(V.LOG_FIELDS))()
+    assert V.lib().vs_log_read(s._st, None, 1, ctypes.byref(n)) == V.VS_E_ARG
+    assert V.lib().vs_log_read(s._st, buf, 1, None) == V.VS_E_ARG
+    assert V.lib().vs_log_read(s._st, buf, 0, ctypes.byref(n)) == V.VS_E_ARG
+    assert n.value == -7
     s.close()
     assert first.shape == (4, len(V.LOG_FIELDS)) and log.shape == (6, len(V.LOG_FIELDS))
     assert np.array_equal(log[:4], first)
