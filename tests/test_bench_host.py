@@ -26,3 +26,13 @@ def test_kernel_bytes_model():
     assert bench.kernel_bytes("dht_x", nx, ny, nz) == 48 * ni
     # both flow residuals: omega, S and psi, three components each
     assert bench.kernel_bytes("resid_norm_flow", nx, ny, nz) == 72 * ni
+
+
+def test_system_info_without_a_device():
+    # every field is present; what cannot be read here (no GPU) is None, not an exception
+    import torch
+    info = bench.system_info(torch)
+    assert set(info) == {"device", "arch", "compute_units", "hip", "torch", "rocm", "clocks"}
+    assert info["torch"] == torch.__version__
+    if not torch.cuda.is_available():
+        assert info["device"] is None and info["compute_units"] is None
