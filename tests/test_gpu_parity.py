@@ -378,6 +378,26 @@ def test_unstable_dt_rejected_before_enqueue():
     s.close()
 
 
+def test_step_argument_errors_leave_the_state():
+    """No step (nsteps < 1) and a time step that is not a positive finite number are argument
+    errors, found on the host: nothing runs, the fields and the step count stay."""
+    w = workload("vesicle32", grid=GridSpec(16, 12, 16), R0=3.0)
+    say("case step argument errors")
+    s = P.solver_for(w)
+    before = s.fields()
+    for dt, n in [(w.dt, 0), (w.dt, -3), (0.0, 1), (-w.dt, 1), (float("nan"), 1), (float("inf"), 1)]:
+        with pytest.raises(V.VsError) as e:
+            s.step(dt, n)
+        assert e.value.code == V.VS_E_ARG, (dt, n)
+    after = s.fields()
+    assert s.scalars()["step"] == 0
+    for k in before:
+        assert np.array_equal(after[k], before[k]), k
+    s.step(w.dt, 1)
+    assert s.scalars()["step"] == 1
+    s.close()
+
+
 def test_unreachable_tolerance_reports_noconv():
     w = workload("vesicle32")
     say("case noconv")
