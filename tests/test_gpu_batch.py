@@ -131,6 +131,10 @@ def test_batch_rejects_odd_steps_and_unstable_dt():
     with pytest.raises(V.VsError) as e:
         b.step([ws[0].dt, 10.0], 2)
     assert e.value.code == V.VS_E_UNSTABLE
+    for dts, n in [([w.dt for w in ws], 0), ([float("nan"), ws[1].dt], 2), ([ws[0].dt, 0.0], 2)]:
+        with pytest.raises(V.VsError) as e:
+            b.step(dts, n)
+        assert e.value.code == V.VS_E_ARG, (dts, n)
     b.close()
     for s in solvers:
         assert s.scalars()["step"] == 0
