@@ -439,7 +439,7 @@ def main():
     ap.add_argument("--batch-streams", type=int, default=2)
     ap.add_argument("--adjoint-steps", type=int, default=50,
                     help="steps of the 96^3 rollout gradient (0 = skip)")
-    ap.add_argument("--inertial-steps", type=int, default=20,
+    ap.add_argument("--inertial-steps", type=int, default=200,
                     help="steps of the 128^3 vesicle with the inertial vorticity equation (0 = skip)")
     ap.add_argument("--no-diagnostics", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
