@@ -396,7 +396,7 @@ def copy_ceiling(torch) -> float:
 
 
 def system_info(torch) -> dict:
-    """The device, the software versions and the clocks the run saw (each None if unreadable)."""
+    """The device, the software versions and the current clocks (each None if unreadable)."""
     info = {"device": None, "arch": None, "compute_units": None, "hip": torch.version.hip,
             "torch": torch.__version__, "rocm": None, "clocks": None}
     try:
@@ -529,6 +529,7 @@ def main():
         torch.cuda.synchronize()
         repeats.append(total_cells / (time.perf_counter() - t0))
     relres = max(relres, max(s.scalars()["relres"] for s in solvers))
+    sysinfo = system_info(torch)   # the clocks just after the timed regions
     if len(repeats) > 1:
         print(f"bench: {len(repeats)} timed regions: " + " ".join(f"{v:.4e}" for v in repeats),
               file=sys.stderr, flush=True)
@@ -635,7 +636,7 @@ def main():
         "max_relres": relres,
         "timed_regions": {"values": repeats, "median": sorted(repeats)[len(repeats) // 2],
                           "note": "value is the first; each region is the same K steps of every instance"},
-        "system": system_info(torch),
+        "system": sysinfo,
         "per_kappa_cell_updates_per_s": {k: N * args.steps / t for k, t in per_kappa.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
