@@ -36,3 +36,18 @@ def test_system_info_without_a_device():
     assert info["torch"] == torch.__version__
     if not torch.cuda.is_available():
         assert info["device"] is None and info["compute_units"] is None
+
+
+def test_more_than_one_gpu_is_refused():
+    # one simulation per GPU on one GPU: --gpus above 1 (or a multi-rank launch) exits with
+    # status 2 and says so, before touching a device
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for args, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(root, "bench.py")] + args,
+                           capture_output=True, text=True, timeout=120,
+                           env=dict(os.environ, **env))
+        assert r.returncode == 2, (args, env, r.stderr)
+        assert "not supported" in r.stderr and r.stdout == ""
