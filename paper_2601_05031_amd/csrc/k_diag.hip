@@ -18,10 +18,29 @@ namespace vs {
 
 namespace {
 
+// The velocity on every node into three scratch fields (curl psi inside, the wall velocity on
+// the walls), so that the shear stress reads each neighbour's velocity once instead of
+// evaluating the curl there again.
+__global__ __launch_bounds__(kBlock) void k_diag_vel(Vel vel, Dims d, double* __restrict__ v0,
+                                                    double* __restrict__ v1,
+                                                    double* __restrict__ v2) {
+    int i, j, k;
+    bool ok;
+    plane_index(d, i, j, k, ok);
+    if (!ok) return;
+    const int c = node(d, i, j, k);
+    v0[c] = vx_at(vel, d, i, j, k);
+    v1[c] = vy_at(vel, d, i, j, k);
+    v2[c] = vz_at(vel, d, i, j, k);
+}
+
 __global__ __launch_bounds__(kBlock) void k_diag(const double* __restrict__ phi,
                                                 const double* __restrict__ o0,
                                                 const double* __restrict__ o1,
                                                 const double* __restrict__ o2, Vel vel,
+                                                const double* __restrict__ V0,
+                                                const double* __restrict__ V1,
+                                                const double* __restrict__ V2,
                                                 const double* __restrict__ prof, Dims d, double eta,
                                                 int model, double eps, double sigma, SlabGrid sg,
                                                 double* __restrict__ sigma_t,
@@ -56,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(const double* __restrict__ phi,
             }
             double st = 0.0;
             {
-                const double vx = vx_at(vel, d, i, j, k), vy = vy_at(vel, d, i, j, k), vz = vz_at(vel, d, i, j, k);
+                const double vx = V0[n.c], vy = V1[n.c], vz = V2[n.c];
                 vmax = fmax(vmax, sqrt(vx * vx + vy * vy + vz * vz));
             }
             if (interior(d, j)) {
@@ -65,12 +84,12 @@ __global__ __launch_bounds__(kBlock) void k_diag(const double* __restrict__ phi,
                                   (vel.py[node(d, i, j + 1, k)] - vel.py[node(d, i, j - 1, k)]) * d.inv_2h +
                                   (vel.pz[node(d, i, j, kp)] - vel.pz[node(d, i, j, km)]) * d.inv_2h;
                 acc[3] += dv * dv;
-                const double sxy = (vx_at(vel, d, i, j + 1, k) - vx_at(vel, d, i, j - 1, k)) +
-                                   (vy_at(vel, d, ip, j, k) - vy_at(vel, d, im, j, k));
-                const double syz = (vy_at(vel, d, i, j, kp) - vy_at(vel, d, i, j, km)) +
-                                   (vz_at(vel, d, i, j + 1, k) - vz_at(vel, d, i, j - 1, k));
-                const double sxz = (vx_at(vel, d, i, j, kp) - vx_at(vel, d, i, j, km)) +
-                                   (vz_at(vel, d, ip, j, k) - vz_at(vel, d, im, j, k));
+                const int cjp = node(d, i, j + 1, k), cjm = node(d, i, j - 1, k);
+                const int ckp = n.c - k + kp, ckm = n.c - k + km;
+                const int cip = node(d, ip, j, k), cim = node(d, im, j, k);
+                const double sxy = (V0[cjp] - V0[cjm]) + (V1[cip] - V1[cim]);
+                const double syz = (V1[ckp] - V1[ckm]) + (V2[cjp] - V2[cjm]);
+                const double sxz = (V0[ckp] - V0[ckm]) + (V2[cip] - V2[cim]);
                 st = eta * d.inv_2h * sqrt(sxy * sxy + syz * syz + sxz * sxz);
             }
             if (sigma_t) sigma_t[n.c] = st;
@@ -159,13 +178,16 @@ __global__ __launch_bounds__(kBlock) void k_shift_profiles(double* __restrict__ 
 void launch_diagnostics(hipStream_t s, const Dims& d, const double* phi, double* const omega[3],
                         double* const psi[3], const double* prof, double vz_lo, double vz_hi,
                         double eta, int model, double eps, double sigma, double* sigma_t,
-                        double* part, double* scal) {
+                        double* part, double* scal, double* const vscratch[3]) {
     const SlabGrid g = slab_grid(d.ny * d.nz, d.nx, kMaxPartialBlocks);
     const Vel vel{psi[0], psi[1], psi[2], vz_lo, vz_hi};
     const int nb = g.gx * g.gi;
+    launch_kernel(k_diag_vel, plane_grid(d), dim3(kBlock), 0, s, vel, d, vscratch[0], vscratch[1],
+                  vscratch[2]);
     launch_kernel(k_diag, dim3(nb), dim3(kBlock), 0, s, phi, (const double*)omega[0],
-                  (const double*)omega[1], (const double*)omega[2], vel, prof, d, eta, model, eps,
-                  sigma, g, sigma_t, part);
+                  (const double*)omega[1], (const double*)omega[2], vel,
+                  (const double*)vscratch[0], (const double*)vscratch[1],
+                  (const double*)vscratch[2], prof, d, eta, model, eps, sigma, g, sigma_t, part);
     launch_kernel(k_diag_finalize, dim3(1), dim3(1024), 0, s, (const double*)part, nb, scal);
 }
 

@@ -1374,8 +1374,10 @@ vs_status vs_diagnostics(vs_state* S, double* sigma_t, double out[6]) {
     if (!S) return fail(VS_E_STATE, "state is NULL");
     if (!out) return fail(VS_E_ARG, "out is NULL");
     const Dims& d = S->d;
+    // the source fields are free between calls: the velocity goes there first
     launch_diagnostics(S->stream, d, S->phi[S->cur], S->om, S->ps, S->prof, S->vz_lo, S->vz_hi,
-                       S->p.eta, S->p.model, S->p.eps, S->p.sigma, sigma_t, S->part, S->scal);
+                       S->p.eta, S->p.model, S->p.eps, S->p.sigma, sigma_t, S->part, S->scal,
+                       S->src);
     HIP_TRY(hipGetLastError());
     double sc[SC_NSCAL];
     const vs_status rs = read_status(S, sc, nullptr);

@@ -398,11 +398,12 @@ void launch_adj_source(hipStream_t s, const Dims& d, const double* phi, const do
 void launch_adj_mu1(hipStream_t s, const Dims& d, const double* phi, const double* mubar,
                     double C_b, double dCb_dkappa, double eps, double* gbar, double* part);
 int resid_flow_blocks(const Dims& d);
-// Diagnostics (k_diag.hip): sigma_t (device field or NULL) and SC_DG_* sums.
+// Diagnostics (k_diag.hip): sigma_t (device field or NULL) and SC_DG_* sums; vscratch: three
+// full fields the velocity is stored in first (scratch: overwritten).
 void launch_diagnostics(hipStream_t s, const Dims& d, const double* phi, double* const omega[3],
                         double* const psi[3], const double* prof, double vz_lo, double vz_hi,
                         double eta, int model, double eps, double sigma, double* sigma_t,
-                        double* part, double* scal);
+                        double* part, double* scal, double* const vscratch[3]);
 // omega_x += dprof[ny + j], psi_x += dprof[j] at every node (a wall-speed change).
 void launch_shift_profiles(hipStream_t s, const Dims& d, double* omega_x, double* psi_x,
                            const double* dprof);
