@@ -529,7 +529,6 @@ def main():
         torch.cuda.synchronize()
         repeats.append(total_cells / (time.perf_counter() - t0))
     relres = max(relres, max(s.scalars()["relres"] for s in solvers))
-    sysinfo = system_info(torch)   # the clocks just after the timed regions
     if len(repeats) > 1:
         print(f"bench: {len(repeats)} timed regions: " + " ".join(f"{v:.4e}" for v in repeats),
               file=sys.stderr, flush=True)
@@ -540,6 +539,9 @@ def main():
     s1.step(base.dt, args.profile_steps)
     prof = s1.profile_read()
     s1.profile(False)
+    # the clocks just after the timed and profiled steps (rocm-smi runs for a while with the
+    # GPU idle, so not between the two)
+    sysinfo = system_info(torch)
     kern = {}
     for name, (ms, n) in prof.items():
         if n == 0:
